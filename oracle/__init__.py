@@ -1,0 +1,18 @@
+"""FP64 CPU oracle for the reduced-basis hierarchical matched filter.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  The product library
+(HIP kernels behind the C ABI) never calls it, and it shares no code with the
+library: plain numpy/scipy (and torch CPU float64 for autograd) only.
+
+Modules
+-------
+mf      the template method: strain FFT, sigma, complex SNR series, triggers,
+        peaks (Sec. II, Eqs. MF_def, SNR_def, hf_eqn, IFFT).
+basis   PCA/SVD basis of the whitened unit-norm bank, rank rule, coefficients,
+        reduced-basis SNR (Sec. II.A, Eqs. Eq-PCA/Eq-SVD, basis_SNR,
+        Beta_eqn, SNR_loss; Sec. III.B).
+grad    loss sum g |rho|^2 over a frozen trigger set and its gradients with
+        respect to the coefficients and the strain (torch CPU float64
+        autograd through an independent plain forward).
+"""
