@@ -1,0 +1,259 @@
+/*
+ * rbmf.h -- C ABI of the reduced-basis hierarchical matched filter for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The search it implements (Dhurkunde, Fehrmann & Nitz, "A hierarchical
+ * approach to matched filtering using a reduced basis", arXiv:2110.13115):
+ *
+ *   - the noise-weighted inner product <s|h> = 4 int s~ h~* / Sn df
+ *     (Sec. II, Eq. MF_def) and the SNR normalised by <h|h>^{1/2} with the
+ *     unknown phase maximised by the modulus (Eq. SNR_def and the text after
+ *     Eq. hf_eqn);
+ *   - the SNR time series of one template by an inverse FFT of the weighted
+ *     correlation (Eq. IFFT); a trigger is a sample whose SNR reaches a
+ *     threshold (Sec. II);
+ *   - an orthonormal basis of the whitened, unit-norm bank from its
+ *     covariance / SVD (Sec. II.A, Eqs. Eq-PCA, Eq-SVD; Sec. III.B), truncated
+ *     by the retained energy (Eq. SNR_loss);
+ *   - per-basis filter outputs beta_k = IFFT(<s|p_k>) and the reconstruction
+ *     rho_j = sum_k c*_{jk} beta_k (Eqs. basis_SNR, Beta_eqn);
+ *   - a two-stage hierarchy (Sec. III.C): a first stage over the whole bank
+ *     with a lowered threshold, and an exact second stage restricted to what
+ *     the first stage selected.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *   Grid      N samples (a power of two, 2^12..2^21) at fs Hz; dt = 1/fs,
+ *             df = fs/N.  Band: bins k_lo = ceil(f_low/df) .. N/2-1
+ *             inclusive (DC and Nyquist excluded).
+ *   Spectra   s~[k] = dt * sum_n s[n] e^{-2 pi i k n/N}.
+ *   Filter    rho_j[n] = 4 df sum_{k in band} s~[k] conj(h_j[k]) / Sn[k]
+ *                        e^{+2 pi i k n/N} / sigma_j,
+ *             sigma_j^2 = 4 df sum_{k in band} |h_j[k]|^2 / Sn[k];
+ *             SNR = |rho_j[n]|, phase = arg rho_j[n].
+ *   Pointers  "host or device" arguments are classified with
+ *             hipPointerGetAttributes; device pointers must belong to the
+ *             context's device.  Host arrays are read/written synchronously.
+ *   Streams   all device work of a context is ordered on the stream given to
+ *             rb_ctx_create (NULL = the null stream).  Calls that return
+ *             counts synchronise that stream before returning.
+ *   Errors    every call returns rb_status and never aborts; argument checks
+ *             run on the host before any device work.  rb_last_error() gives a
+ *             thread-local message for the last failure.
+ *   Ownership the caller owns every array it passes; the library copies what
+ *             it keeps into handles.  Handles own their device memory and are
+ *             freed explicitly; free banks and bases before their context.
+ *   Threads   one context per host thread; handles are not thread-safe.
+ */
+#ifndef RBMF_H
+#define RBMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RB_OK = 0,
+  RB_ERR_ARG = 1,          /* invalid argument (shape, range, null, PSD)      */
+  RB_ERR_OOM = 2,          /* device or host allocation failed                 */
+  RB_ERR_DEVICE = 3,       /* a HIP runtime call failed                        */
+  RB_ERR_CAPACITY = 4,     /* output buffer too small; *n_out = required size  */
+  RB_ERR_NUMERIC = 5,      /* non-finite input or degenerate numerics          */
+  RB_ERR_UNSUPPORTED = 6,  /* valid but not supported by this build            */
+  RB_ERR_CALLBACK = 7      /* the bank fill callback returned non-zero         */
+} rb_status;
+
+/* Storage type of the reconstruction operands C and Z (accumulation is FP32
+ * in every case; basis construction, sigma and PSD products are FP64). */
+typedef enum { RB_F32 = 0, RB_BF16 = 1, RB_F16 = 2 } rb_dtype;
+
+/* Second-stage variant of rb_filter. */
+typedef enum {
+  RB_STAGE2_FULL = 0,      /* full matched filter (all N samples) of every
+                              template with a first-stage crossing            */
+  RB_STAGE2_SPARSE = 1     /* exact SNR evaluated only at the first-stage
+                              crossing samples (direct frequency sums)        */
+} rb_stage2_mode;
+
+typedef struct rb_ctx_s*   rb_ctx;
+typedef struct rb_bank_s*  rb_bank;
+typedef struct rb_basis_s* rb_basis;
+
+typedef struct {
+  int64_t N;               /* samples per segment, power of two 2^12..2^21   */
+  double  fs;              /* sampling rate, Hz (> 0)                        */
+  double  f_low;           /* lower band edge, Hz, 0 < f_low < fs/2          */
+} rb_grid;
+
+/* One trigger: a (template, sample) pair whose SNR reaches the threshold. */
+typedef struct {
+  int32_t tmpl;            /* template index in the bank                     */
+  int32_t sample;          /* sample index n in [0, N) (natural time order)  */
+  float   snr;             /* |rho|                                          */
+  float   phase;           /* arg rho in (-pi, pi]                           */
+} rb_trigger;
+
+/* Per-template maximum of |rho| over the samples a call evaluated. */
+typedef struct {
+  float   snr;             /* max |rho|; -1 if the template was not evaluated
+                              by the exact filter in this call               */
+  int32_t sample;          /* argmax (ties to the lowest n); -1 if none       */
+} rb_peak;
+
+typedef struct {
+  int64_t n_stage1;        /* first-stage crossings (rb_filter)              */
+  int32_t n_refiltered;    /* templates passed to the second stage           */
+  int32_t rank;            /* basis rank used                                */
+  float   ms[8];           /* device time per stage, ms: [0] strain FFT,
+                              [1] correlation + basis IFFTs, [2] reconstruction
+                              GEMM + first-stage threshold, [3] selection,
+                              [4] second stage / full MF, [5] sort + output,
+                              [6] total, [7] reserved                        */
+} rb_stats;
+
+typedef struct {
+  double  thr1;            /* first-stage threshold on |rho_RB| (> 0)        */
+  double  thr2;            /* final threshold on the exact |rho| (>= thr1)   */
+  int32_t stage2;          /* rb_stage2_mode                                 */
+  int32_t reserved;        /* must be 0                                      */
+} rb_filter_opts;
+
+/* Bank source.  Fills out[(t1-t0) * (k1-k0) * 2] with the complex128 values
+ * h_j[k] (interleaved re, im; row-major over templates) of templates
+ * [t0, t1) at rfft bins [k0, k1).  Returns 0 on success.  Called from the
+ * thread that called rb_bank_create, never concurrently. */
+typedef int (*rb_bank_fill_fn)(void* user, int32_t t0, int32_t t1, int64_t k0, int64_t k1,
+                               double* out);
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`, ordering all work on `hip_stream`
+ * (a hipStream_t, or NULL for the null stream; the stream stays owned by the
+ * caller and must outlive the context).  RB_ERR_DEVICE if the device does not
+ * exist or is not gfx950. */
+rb_status rb_ctx_create(int device, void* hip_stream, rb_ctx* out);
+
+/* Destroy a context.  RB_ERR_ARG if banks or bases created on it are still
+ * alive. */
+rb_status rb_ctx_destroy(rb_ctx ctx);
+
+/* Thread-local text of the last failure ("" if none). */
+const char* rb_last_error(void);
+
+/* ------------------------------------------------------------------ bank */
+
+/* Whiten and normalise a template bank and upload it (Sec. III.B: templates
+ * whitened with the PSD and normalised to unity).
+ *   grid  segment grid; psd: host, N/2+1 one-sided PSD values Sn[k] (1/Hz),
+ *         finite and > 0 on the band (other bins are not read).
+ *   T     number of templates, 1..2^24.
+ *   fill  template source, called with chunks of templates over the bins
+ *         [k_base, N/2) where k_base <= k_lo.
+ * In FP64 on the host: sigma_j, the whitened unit templates
+ * w_j[k] = h_j[k] sqrt(4 df/Sn[k]) / sigma_j; then rounded to complex64 and
+ * uploaded.  RB_ERR_ARG for a bad grid or PSD, or a template with sigma = 0;
+ * RB_ERR_CALLBACK if fill fails. */
+rb_status rb_bank_create(rb_ctx ctx, const rb_grid* grid, const double* psd, int32_t T,
+                         rb_bank_fill_fn fill, void* user, rb_bank* out);
+
+rb_status rb_bank_free(rb_bank bank);
+
+/* Bank facts.  Any output may be NULL.  sigma: host, T doubles (FP64 sigma_j
+ * of the unwhitened templates, i.e. their optimal-SNR normalisation). */
+rb_status rb_bank_info(rb_bank bank, int32_t* T, int64_t* k_lo, int64_t* k_hi, double* sigma);
+
+/* ------------------------------------------------------------------ basis */
+
+/* Reduced basis of a bank (Sec. II.A, III.B; Eqs. Eq-SVD, SNR_loss).
+ *   rank  > 0: keep exactly min(rank, T) vectors;  0: the smallest K whose
+ *         retained energy sum_{k<K} lambda_k / sum lambda is >= 1 - tol.
+ *   tol   in (0, 1) when rank == 0.
+ *   dtype storage of C and Z in rb_filter (RB_F32, RB_BF16, RB_F16).
+ * FP64 throughout: Gram products of the stored templates, subspace iteration
+ * with Rayleigh-Ritz, basis rows v_k = lambda_k^{-1/2} sum_j conj(U_jk) w_j,
+ * coefficients c_jk = <w_j, v_k>.  The basis is stored complex64, the
+ * coefficients as C = conj(c) in `dtype` (with power-of-two row scales for
+ * the 16-bit types).  rank_out / energy_out: host, may be NULL. */
+rb_status rb_build_basis(rb_ctx ctx, rb_bank bank, int32_t rank, double tol, rb_dtype dtype,
+                         rb_basis* out, int32_t* rank_out, double* energy_out);
+
+rb_status rb_basis_free(rb_basis basis);
+
+/* Copy the basis out (host arrays, any may be NULL): V: K x nb complex128
+ * (rows over bins k_lo..k_hi), c: T x K complex128 coefficients (FP64, before
+ * storage rounding), lambda: K eigenvalues (FP64, descending). */
+rb_status rb_basis_export(rb_basis basis, double* V, double* c, double* lambda);
+
+/* ------------------------------------------------------------------ search */
+
+/* Hierarchical reduced-basis search of one segment (Sec. III.C):
+ *   1. s~ of the strain (forward FFT), whitened on the band;
+ *   2. beta_k = IFFT(d conj(v_k)) for every basis vector;
+ *   3. rho_RB = C beta (MFMA GEMM), first-stage crossings |rho_RB| >= thr1;
+ *   4. second stage (opts->stage2): the exact |rho| of the selected templates,
+ *      final triggers |rho| >= thr2.
+ *   strain  host or device, N floats.
+ *   out     host or device, cap entries; triggers sorted by (tmpl, sample).
+ *   n_out   host; number of final triggers.  If it exceeds cap the call
+ *           returns RB_ERR_CAPACITY with the required count in *n_out.
+ *   peaks   host or device, T entries, or NULL.
+ *   stats   host or NULL. */
+rb_status rb_filter(rb_ctx ctx, rb_basis basis, rb_bank bank, const float* strain,
+                    const rb_filter_opts* opts, rb_trigger* out, int64_t cap, int64_t* n_out,
+                    rb_peak* peaks, rb_stats* stats);
+
+/* Template method (Sec. II, Eq. IFFT): the full SNR series of every template
+ * by an inverse FFT, thresholded at thr (> 0).  Arguments as for rb_filter. */
+rb_status mf_full(rb_ctx ctx, rb_bank bank, const float* strain, double thr, rb_trigger* out,
+                  int64_t cap, int64_t* n_out, rb_peak* peaks, rb_stats* stats);
+
+/* First-stage reconstruction at given (template, sample) points:
+ *   rho_i = sum_k C_{j_i k} beta_k[n_i]      (Eq. Beta_eqn, C = conj(c))
+ * with beta from `strain` (FP32 path whatever the basis storage type).
+ *   S    host or device, n triggers (only tmpl and sample are read; tmpl in
+ *        [0, T), sample in [0, N), else RB_ERR_ARG).
+ *   C    host or device, T x K complex64 coefficients replacing the basis's
+ *        own conj(c), or NULL to use them.
+ *   rho  host or device, n complex64 (interleaved). */
+rb_status rb_rho_at(rb_ctx ctx, rb_basis basis, const float* strain, const rb_trigger* S,
+                    int64_t n, const float* C, float* rho);
+
+/* Adjoint of correlation plus reconstruction.  For the loss
+ *   L = sum_i g_i |rho_{j_i}[n_i]|^2      (S = {(j_i, n_i)} frozen, rho as in
+ *                                          rb_rho_at)
+ * computes dL/dC (T x K complex64, interleaved, torch's convention for a
+ * complex leaf: dL/dRe + i dL/dIm; rows without triggers are zero) and dL/ds
+ * (N floats).  Reductions run in a fixed order (bitwise reproducible).
+ *   S, C     as for rb_rho_at.
+ *   seed     host or device, n floats g_i, or NULL for all ones.
+ *   grad_C   host or device or NULL; grad_strain host or device or NULL.
+ *   loss     host or NULL: L. */
+rb_status rb_backward(rb_ctx ctx, rb_basis basis, const float* strain, const rb_trigger* S,
+                      const float* seed, int64_t n, const float* C, float* grad_C,
+                      float* grad_strain, double* loss);
+
+/* Clustered peaks of a (tmpl, sample)-sorted trigger list: is_peak[i] = 1 if
+ * no trigger of the same template within +-W samples (circular over N) has a
+ * larger SNR, or an equal SNR at a lower sample.  trig / is_peak: host or
+ * device. */
+rb_status rb_cluster_peaks(rb_ctx ctx, const rb_trigger* trig, int64_t n, int32_t W, int64_t N,
+                           uint8_t* is_peak);
+
+/* ------------------------------------------------------------------ debug */
+
+/* Dump the complex SNR series (small T*N only): rho (host or device,
+ * T x N x 2 floats, natural time order).  basis == NULL: exact template
+ * method; otherwise the first-stage reconstruction rho_RB = C beta. */
+rb_status rb_debug_rho(rb_ctx ctx, rb_basis basis, rb_bank bank, const float* strain, float* rho);
+
+/* Dump the per-basis filter outputs beta (K x N x 2 floats, natural time
+ * order, host or device) as stored for the reconstruction (after any 16-bit
+ * rounding and with its scale removed). */
+rb_status rb_debug_basis_outputs(rb_ctx ctx, rb_basis basis, const float* strain, float* beta);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBMF_H */

@@ -1,0 +1,1327 @@
+// C-ABI host layer: argument validation, handles, device buffers, and the
+// orchestration of the kernels for each entry point of include/rbmf.h.
+#include "../../include/rbmf.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <memory>
+#include <random>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+#include "linalg.h"
+
+namespace rbmf {
+
+hipError_t launch_pack_c(const float2* C, int T, int Tp, int K, int Kp, int dtype, const float* row_scale,
+                         void* cpk, hipStream_t stream);
+int gemm_tile_templates();
+
+namespace {
+thread_local std::string g_err;
+}
+void set_error(const std::string& msg) { g_err = msg; }
+const char* last_error_cstr() { return g_err.c_str(); }
+
+}  // namespace rbmf
+
+using namespace rbmf;
+using cd = std::complex<double>;
+
+// ====================================================================== helpers
+namespace {
+
+#define RB_CHECK(cond, code, msg)       \
+  do {                                  \
+    if (!(cond)) {                      \
+      set_error(msg);                   \
+      return code;                      \
+    }                                   \
+  } while (0)
+
+#define RB_TRY(expr)                    \
+  do {                                  \
+    rb_status st_ = (expr);             \
+    if (st_ != RB_OK) return st_;       \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  rb_status ensure(size_t need) {
+    if (need <= bytes && p) return RB_OK;
+    release();
+    if (need == 0) need = 256;
+    if (hipMalloc(&p, need) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      set_error("device allocation of " + std::to_string(need) + " bytes failed");
+      return RB_ERR_OOM;
+    }
+    bytes = need;
+    return RB_OK;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+struct HostPinned {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~HostPinned() {
+    if (p) (void)hipHostFree(p);
+  }
+  rb_status ensure(size_t need) {
+    if (need <= bytes && p) return RB_OK;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    if (hipHostMalloc(&p, need, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("pinned host allocation failed");
+      return RB_ERR_OOM;
+    }
+    bytes = need;
+    return RB_OK;
+  }
+};
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+template <class F>
+void parallel_for(int64_t n, F&& f) {
+  int nt = (int)std::min<int64_t>(n, std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+  if (nt <= 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int64_t> next(0);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&]() {
+      for (int64_t i; (i = next.fetch_add(1)) < n;) f(i);
+    });
+  for (auto& t : th) t.join();
+}
+
+struct TwTables {
+  DevBuf pyr, tlo, thi, pyr64, tlo64, thi64;
+};
+
+}  // namespace
+
+// ====================================================================== handles
+struct rb_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int live = 0;
+  std::map<int64_t, std::unique_ptr<TwTables>> tw;
+  // scratch
+  DevBuf work, work64, dspec, strain, z, z32, adjA, adjAhat, adjB, adjT, adjS, adjRho, adjG, adjC, adjGC,
+      adjOrd, adjSeg, trig1, trig2, recs, tmp, final_out, cnt1, cnt2, off1, off2, fill1, fill2,
+      list1, list2, tmax, summary, counters, thr_row, peaks, flag, rho_tmp, zws;
+  hipEvent_t ev[8] = {};
+};
+
+struct rb_bank_s {
+  rb_ctx ctx = nullptr;
+  rb_grid grid{};
+  int32_t T = 0;
+  int64_t k_lo = 0, k_hi = 0, kb = 0, nbs = 0;
+  std::vector<double> sigma;
+  DevBuf w;          // T x nbs complex64 whitened unit templates
+  DevBuf wd;         // nbs double: dt * sqrt(4 df / Sn) (0 below k_lo)
+  DevBuf sup_lo, sup_hi;
+  int live_bases = 0;
+};
+
+struct rb_basis_s {
+  rb_ctx ctx = nullptr;
+  rb_bank bank = nullptr;
+  int32_t K = 0, Kp = 0, Tp = 0;
+  rb_dtype dtype = RB_F32;
+  double energy = 0.0, trace = 0.0;
+  std::vector<double> lambda;
+  std::vector<cd> c;           // T x K FP64 coefficients
+  std::vector<float> row_scale;  // per-template power-of-two scale (16-bit), 1 otherwise
+  DevBuf P;                    // K x nbs complex64
+  DevBuf cpk;                  // packed realified C
+  DevBuf C32;                  // T x K complex64 (conj(c)), unscaled, for the adjoint
+  DevBuf row_inv;              // Tp floats 1/row_scale
+  DevBuf row_scale_dev;        // Tp floats
+  DevBuf thr_row;              // Tp floats: squared first-stage threshold per template
+  float thr_cached = -1.f;
+};
+
+// ====================================================================== shared steps
+namespace {
+
+rb_status get_tables(rb_ctx ctx, const FftGeom& g, FftTables& out, FftTables64* out64 = nullptr) {
+  auto it = ctx->tw.find(g.N);
+  if (it == ctx->tw.end()) {
+    auto t = std::make_unique<TwTables>();
+    std::vector<float2> pyr(4096, make_float2(0.f, 0.f));
+    for (int L = 2; L <= 2048; L <<= 1)
+      for (int i = 0; i < L; ++i) {
+        const double a = 2.0 * M_PI * (double)i / (double)L;
+        pyr[L + i] = make_float2((float)std::cos(a), (float)std::sin(a));
+      }
+    const int64_t nlo = int64_t(1) << g.s_lo, nhi = g.N >> g.s_lo;
+    std::vector<float2> tlo(nlo), thi(std::max<int64_t>(nhi, 1));
+    for (int64_t e = 0; e < nlo; ++e) {
+      const double a = 2.0 * M_PI * (double)e / (double)g.N;
+      tlo[e] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    for (int64_t e = 0; e < nhi; ++e) {
+      const double a = 2.0 * M_PI * (double)(e << g.s_lo) / (double)g.N;
+      thi[e] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    std::vector<double2> pyr64(4096, make_double2(0.0, 0.0)), tlo64(nlo), thi64(thi.size());
+    for (int L = 2; L <= 2048; L <<= 1)
+      for (int i = 0; i < L; ++i) {
+        const double a = 2.0 * M_PI * (double)i / (double)L;
+        pyr64[L + i] = make_double2(std::cos(a), std::sin(a));
+      }
+    for (int64_t e = 0; e < nlo; ++e) {
+      const double a = 2.0 * M_PI * (double)e / (double)g.N;
+      tlo64[e] = make_double2(std::cos(a), std::sin(a));
+    }
+    for (int64_t e = 0; e < nhi; ++e) {
+      const double a = 2.0 * M_PI * (double)(e << g.s_lo) / (double)g.N;
+      thi64[e] = make_double2(std::cos(a), std::sin(a));
+    }
+    RB_TRY(t->pyr64.ensure(pyr64.size() * sizeof(double2)));
+    RB_TRY(t->tlo64.ensure(tlo64.size() * sizeof(double2)));
+    RB_TRY(t->thi64.ensure(thi64.size() * sizeof(double2)));
+    RB_HIP(hipMemcpy(t->pyr64.p, pyr64.data(), pyr64.size() * sizeof(double2), hipMemcpyHostToDevice));
+    RB_HIP(hipMemcpy(t->tlo64.p, tlo64.data(), tlo64.size() * sizeof(double2), hipMemcpyHostToDevice));
+    RB_HIP(hipMemcpy(t->thi64.p, thi64.data(), thi64.size() * sizeof(double2), hipMemcpyHostToDevice));
+    RB_TRY(t->pyr.ensure(pyr.size() * sizeof(float2)));
+    RB_TRY(t->tlo.ensure(tlo.size() * sizeof(float2)));
+    RB_TRY(t->thi.ensure(thi.size() * sizeof(float2)));
+    RB_HIP(hipMemcpy(t->pyr.p, pyr.data(), pyr.size() * sizeof(float2), hipMemcpyHostToDevice));
+    RB_HIP(hipMemcpy(t->tlo.p, tlo.data(), tlo.size() * sizeof(float2), hipMemcpyHostToDevice));
+    RB_HIP(hipMemcpy(t->thi.p, thi.data(), thi.size() * sizeof(float2), hipMemcpyHostToDevice));
+    it = ctx->tw.emplace(g.N, std::move(t)).first;
+  }
+  out.pyr = it->second->pyr.as<float2>();
+  out.tlo = it->second->tlo.as<float2>();
+  out.thi = it->second->thi.as<float2>();
+  if (out64) {
+    out64->pyr = it->second->pyr64.as<double2>();
+    out64->tlo = it->second->tlo64.as<double2>();
+    out64->thi = it->second->thi64.as<double2>();
+  }
+  return RB_OK;
+}
+
+rb_status fill32(rb_ctx ctx, void* p, uint32_t v, int64_t n) {
+  RB_HIP(launch_fill_u32(static_cast<uint32_t*>(p), v, n, ctx->stream));
+  return RB_OK;
+}
+
+// vectors per FFT batch: keep the [B][N] intermediate near 256 MB so the
+// pass-1 -> pass-2 round trip can stay in the Infinity Cache.
+int batch_vectors(int64_t N, int64_t nvec) {
+  int64_t b = (int64_t(256) << 20) / (N * 8);
+  b = std::max<int64_t>(1, std::min<int64_t>(b, 1024));
+  return (int)std::min<int64_t>(b, std::max<int64_t>(nvec, 1));
+}
+
+PassArgs base_args(rb_bank bank, const FftGeom& g, const FftTables& tw) {
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.g = g;
+  a.tw = tw;
+  a.kb = bank->kb;
+  a.nbs = bank->nbs;
+  a.band_lo = (int32_t)bank->k_lo;
+  a.band_hi = (int32_t)bank->k_hi;
+  a.k_lo = (int32_t)bank->k_lo;
+  a.k_hi = (int32_t)bank->k_hi;
+  a.wd64 = bank->wd.as<double>();
+  a.zscale = 1.f;
+  return a;
+}
+
+// strain -> device pointer (copied into ctx scratch if it is a host array)
+rb_status strain_device(rb_ctx ctx, const float* strain, int64_t N, const float** out) {
+  RB_CHECK(strain != nullptr, RB_ERR_ARG, "strain is NULL");
+  if (is_device_ptr(strain)) {
+    *out = strain;
+    return RB_OK;
+  }
+  RB_TRY(ctx->strain.ensure(N * sizeof(float)));
+  RB_HIP(hipMemcpyAsync(ctx->strain.p, strain, N * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+  *out = ctx->strain.as<float>();
+  return RB_OK;
+}
+
+// a1: whitened band spectrum d[k - kb] = dt w[k] DFT(s)[k] (zero below k_lo)
+rb_status step_spectrum(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTables& tw, const float* s) {
+  FftTables tw32;
+  FftTables64 tw64;
+  RB_TRY(get_tables(ctx, g, tw32, &tw64));
+  RB_TRY(ctx->work64.ensure((size_t)g.N * 16));
+  RB_TRY(ctx->dspec.ensure((size_t)bank->nbs * 8));
+  RB_TRY(fill32(ctx, ctx->dspec.p, 0u, bank->nbs * 2));
+  PassArgs a = base_args(bank, g, tw);
+  a.sign = -1;
+  a.nvec = 1;
+  a.real_in = s;
+  a.tw64 = tw64;
+  a.work64 = ctx->work64.as<double2>();
+  RB_HIP(launch_pass1(a, IN_REAL, ctx->stream));
+  a.cout = ctx->dspec.as<float2>();
+  RB_HIP(launch_pass2(a, OUT_SPECTRUM, ctx->stream));
+  return RB_OK;
+}
+
+// a2 + a3: Z = IFFT(d conj(P_k)) for all basis vectors, planar storage
+// (the basis's storage type, or FP32 into ctx->z32 when force_f32)
+rb_status step_basis_outputs(rb_ctx ctx, rb_basis basis, const FftGeom& g, const FftTables& tw,
+                             bool force_f32 = false) {
+  rb_bank bank = basis->bank;
+  const int K = basis->K, Kp = force_f32 ? basis->K : basis->Kp;
+  const rb_dtype dt = force_f32 ? RB_F32 : basis->dtype;
+  DevBuf& zb = force_f32 ? ctx->z32 : ctx->z;
+  const size_t esz = dt == RB_F32 ? 4 : 2;
+  RB_TRY(zb.ensure((size_t)2 * Kp * g.N * esz));
+  if (Kp > K) {   // zero the padded rows so that 0 * pad never produces NaN
+    const size_t off = (size_t)2 * K * g.N * esz, bytes = (size_t)2 * (Kp - K) * g.N * esz;
+    RB_TRY(fill32(ctx, static_cast<char*>(zb.p) + off, 0u, (int64_t)(bytes / 4)));
+  }
+  const int B = batch_vectors(g.N, K);
+  RB_TRY(ctx->work.ensure((size_t)B * g.N * 8));
+  PassArgs a = base_args(bank, g, tw);
+  a.sign = +1;
+  a.d = ctx->dspec.as<float2>();
+  a.src = basis->P.as<float2>();
+  a.work = ctx->work.as<float2>();
+  a.zout = zb.as<float>();
+  a.zdtype = (int)dt;
+  for (int v0 = 0; v0 < K; v0 += B) {
+    a.vec_base = v0;
+    a.nvec = std::min(B, K - v0);
+    RB_HIP(launch_pass1(a, IN_CORR, ctx->stream));
+    RB_HIP(launch_pass2(a, dt == RB_F32 ? OUT_Z32 : OUT_Z16, ctx->stream));
+  }
+  return RB_OK;
+}
+
+rb_status ensure_trigger_scratch(rb_ctx ctx, int T) {
+  RB_TRY(ctx->cnt1.ensure((size_t)T * 4));
+  RB_TRY(ctx->cnt2.ensure((size_t)T * 4));
+  RB_TRY(ctx->off1.ensure((size_t)T * 4));
+  RB_TRY(ctx->off2.ensure((size_t)T * 4));
+  RB_TRY(ctx->fill1.ensure((size_t)T * 4));
+  RB_TRY(ctx->fill2.ensure((size_t)T * 4));
+  RB_TRY(ctx->list1.ensure((size_t)T * 4));
+  RB_TRY(ctx->list2.ensure((size_t)T * 4));
+  RB_TRY(ctx->tmax.ensure((size_t)T * 8));
+  RB_TRY(ctx->summary.ensure(8 * 8));
+  RB_TRY(ctx->counters.ensure(4 * 8));
+  RB_TRY(ctx->flag.ensure(8));
+  if (ctx->trig1.bytes == 0) RB_TRY(ctx->trig1.ensure((size_t)1 << 22 << 4));
+  if (ctx->trig2.bytes == 0) RB_TRY(ctx->trig2.ensure((size_t)1 << 20 << 4));
+  return RB_OK;
+}
+
+int64_t trig_capacity(const DevBuf& b) { return (int64_t)(b.bytes / sizeof(TrigRec)); }
+
+// Full matched filter of a template list (or all templates) with the
+// threshold epilogue; counts in cnt2, records in trig2, maxima in tmax.
+rb_status step_mf(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTables& tw, const int32_t* list,
+                  int64_t nlist, float thr2sq) {
+  const int B = batch_vectors(g.N, nlist);
+  RB_TRY(ctx->work.ensure((size_t)B * g.N * 8));
+  PassArgs a = base_args(bank, g, tw);
+  a.sign = +1;
+  a.d = ctx->dspec.as<float2>();
+  a.src = bank->w.as<float2>();
+  a.sup_lo = bank->sup_lo.as<int32_t>();
+  a.sup_hi = bank->sup_hi.as<int32_t>();
+  a.work = ctx->work.as<float2>();
+  a.vec_list = list;
+  a.thr2 = thr2sq;
+  a.trig = ctx->trig2.as<TrigRec>();
+  a.trig_cap = trig_capacity(ctx->trig2);
+  a.trig_count = ctx->counters.as<unsigned long long>() + 1;
+  a.tmpl_count = ctx->cnt2.as<int32_t>();
+  a.tmpl_max = ctx->tmax.as<unsigned long long>();
+  for (int64_t i0 = 0; i0 < nlist; i0 += B) {
+    a.vec_base = (int)i0;
+    a.nvec = (int)std::min<int64_t>(B, nlist - i0);
+    RB_HIP(launch_pass1(a, IN_CORR, ctx->stream));
+    RB_HIP(launch_pass2(a, OUT_THRESH, ctx->stream));
+  }
+  return RB_OK;
+}
+
+// scan cnt -> offsets/list and read the summary {total, nlist, maxcount, flag}
+rb_status scan_and_read(rb_ctx ctx, int T, DevBuf& cnt, DevBuf& off, DevBuf& fill, DevBuf& list,
+                        int64_t sum_host[3]) {
+  RB_HIP(launch_scan_counts(cnt.as<int32_t>(), T, off.as<int32_t>(), fill.as<int32_t>(), list.as<int32_t>(),
+                            ctx->summary.as<int64_t>(), ctx->stream));
+  RB_HIP(hipMemcpyAsync(sum_host, ctx->summary.p, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  return RB_OK;
+}
+
+// Stage-2 records (trig2, cnt2, off2, list2) -> sorted rb_trigger in final_out
+rb_status step_sort(rb_ctx ctx, int T, int64_t total, int64_t nlist) {
+  RB_TRY(ctx->recs.ensure(std::max<size_t>(16, (size_t)total * sizeof(TrigRec))));
+  RB_TRY(ctx->tmp.ensure(std::max<size_t>(16, (size_t)total * sizeof(TrigRec))));
+  RB_TRY(ctx->final_out.ensure(std::max<size_t>(16, (size_t)total * sizeof(rb_trigger))));
+  RB_HIP(launch_scatter_triggers(ctx->trig2.as<TrigRec>(), total, ctx->off2.as<int32_t>(), ctx->fill2.as<int32_t>(),
+                                 ctx->recs.as<TrigRec>(), ctx->stream));
+  RB_HIP(launch_segment_sort(ctx->recs.as<TrigRec>(), ctx->tmp.as<TrigRec>(), ctx->off2.as<int32_t>(),
+                             ctx->cnt2.as<int32_t>(), ctx->list2.as<int32_t>(), (int)nlist, ctx->final_out.p,
+                             ctx->stream));
+  (void)T;
+  return RB_OK;
+}
+
+rb_status copy_out(rb_ctx ctx, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return RB_OK;
+  const hipMemcpyKind kind = is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  RB_HIP(hipMemcpyAsync(dst, src, bytes, kind, ctx->stream));
+  return RB_OK;
+}
+
+void record(rb_ctx ctx, rb_stats* st, int i) {
+  if (st) (void)hipEventRecord(ctx->ev[i], ctx->stream);
+}
+
+rb_status validate_ctx(rb_ctx ctx) {
+  RB_CHECK(ctx != nullptr, RB_ERR_ARG, "context is NULL");
+  RB_HIP(hipSetDevice(ctx->device));
+  return RB_OK;
+}
+
+// Second stage + sort + output shared by rb_filter and mf_full.
+rb_status finish_stage2(rb_ctx ctx, rb_bank bank, rb_trigger* out, int64_t cap, int64_t* n_out, rb_peak* peaks,
+                        int64_t sum2[3]) {
+  const int T = bank->T;
+  const int64_t total = sum2[0];
+  *n_out = total;
+  if (peaks) {
+    RB_TRY(ctx->peaks.ensure((size_t)T * sizeof(rb_peak)));
+    RB_HIP(launch_peaks_from_max(ctx->tmax.as<unsigned long long>(), T, ctx->peaks.p, ctx->stream));
+    RB_TRY(copy_out(ctx, peaks, ctx->peaks.p, (size_t)T * sizeof(rb_peak)));
+  }
+  if (total > cap) {
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+    set_error("trigger capacity " + std::to_string(cap) + " < required " + std::to_string(total));
+    return RB_ERR_CAPACITY;
+  }
+  RB_CHECK(out != nullptr || total == 0, RB_ERR_ARG, "out is NULL");
+  RB_TRY(step_sort(ctx, T, total, sum2[1]));
+  RB_TRY(copy_out(ctx, out, ctx->final_out.p, (size_t)total * sizeof(rb_trigger)));
+  return RB_OK;
+}
+
+}  // namespace
+
+// ====================================================================== context
+extern "C" const char* rb_last_error(void) { return rbmf::last_error_cstr(); }
+
+extern "C" rb_status rb_ctx_create(int device, void* hip_stream, rb_ctx* out) {
+  RB_CHECK(out != nullptr, RB_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  RB_HIP(hipGetDeviceCount(&n));
+  RB_CHECK(device >= 0 && device < n, RB_ERR_DEVICE, "no HIP device " + std::to_string(device));
+  hipDeviceProp_t prop;
+  RB_HIP(hipGetDeviceProperties(&prop, device));
+  RB_CHECK(std::strncmp(prop.gcnArchName, "gfx950", 6) == 0, RB_ERR_DEVICE,
+           std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+  RB_HIP(hipSetDevice(device));
+  auto c = new (std::nothrow) rb_ctx_s;
+  RB_CHECK(c != nullptr, RB_ERR_OOM, "host allocation failed");
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  for (auto& e : c->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete c;
+      set_error("hipEventCreate failed");
+      return RB_ERR_DEVICE;
+    }
+  }
+  *out = c;
+  return RB_OK;
+}
+
+extern "C" rb_status rb_ctx_destroy(rb_ctx ctx) {
+  RB_CHECK(ctx != nullptr, RB_ERR_ARG, "context is NULL");
+  RB_CHECK(ctx->live == 0, RB_ERR_ARG, "context still has live banks or bases");
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& e : ctx->ev) (void)hipEventDestroy(e);
+  delete ctx;
+  return RB_OK;
+}
+
+// ====================================================================== bank
+extern "C" rb_status rb_bank_create(rb_ctx ctx, const rb_grid* grid, const double* psd, int32_t T,
+                                    rb_bank_fill_fn fill, void* user, rb_bank* out) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(out != nullptr && grid != nullptr && psd != nullptr && fill != nullptr, RB_ERR_ARG,
+           "NULL argument");
+  *out = nullptr;
+  const int64_t N = grid->N;
+  RB_CHECK(N >= 4096 && N <= (int64_t(1) << 21) && (N & (N - 1)) == 0, RB_ERR_ARG,
+           "N must be a power of two in [2^12, 2^21]");
+  RB_CHECK(std::isfinite(grid->fs) && grid->fs > 0, RB_ERR_ARG, "fs must be > 0");
+  RB_CHECK(std::isfinite(grid->f_low) && grid->f_low > 0 && grid->f_low < grid->fs / 2, RB_ERR_ARG,
+           "f_low must be in (0, fs/2)");
+  RB_CHECK(T >= 1 && T <= (1 << 24), RB_ERR_ARG, "T must be in [1, 2^24]");
+  const double df = grid->fs / (double)N, dt = 1.0 / grid->fs;
+  const int64_t k_lo = (int64_t)std::ceil(grid->f_low / df - 1e-9), k_hi = N / 2 - 1;
+  RB_CHECK(k_lo >= 1 && k_lo <= k_hi, RB_ERR_ARG, "empty band");
+  for (int64_t k = k_lo; k <= k_hi; ++k)
+    RB_CHECK(std::isfinite(psd[k]) && psd[k] > 0, RB_ERR_ARG,
+             "PSD must be finite and positive on the band (bin " + std::to_string(k) + ")");
+  std::unique_ptr<rb_bank_s> b(new (std::nothrow) rb_bank_s);
+  RB_CHECK(b != nullptr, RB_ERR_OOM, "host allocation failed");
+  b->ctx = ctx;
+  b->grid = *grid;
+  b->T = T;
+  b->k_lo = k_lo;
+  b->k_hi = k_hi;
+  b->kb = (k_lo / 16) * 16;
+  b->nbs = N / 2 - b->kb;
+  const int64_t nbs = b->nbs, kb = b->kb;
+  std::vector<double> w(nbs, 0.0);
+  std::vector<double> wd(nbs, 0.0);
+  for (int64_t k = k_lo; k <= k_hi; ++k) {
+    w[k - kb] = std::sqrt(4.0 * df / psd[k]);
+    wd[k - kb] = dt * w[k - kb];
+  }
+  RB_TRY(b->wd.ensure(nbs * sizeof(double)));
+  RB_HIP(hipMemcpy(b->wd.p, wd.data(), nbs * sizeof(double), hipMemcpyHostToDevice));
+  RB_TRY(b->w.ensure((size_t)T * nbs * sizeof(float2)));
+  RB_TRY(b->sup_lo.ensure((size_t)T * 4));
+  RB_TRY(b->sup_hi.ensure((size_t)T * 4));
+  b->sigma.assign(T, 0.0);
+  std::vector<int32_t> slo(T), shi(T);
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(T, (int64_t(64) << 20) / (nbs * 16)));
+  std::vector<double> hbuf((size_t)chunk * nbs * 2);
+  HostPinned stage;
+  RB_TRY(stage.ensure((size_t)chunk * nbs * sizeof(float2)));
+  std::string bad;
+  for (int64_t t0 = 0; t0 < T; t0 += chunk) {
+    const int64_t t1 = std::min<int64_t>(T, t0 + chunk);
+    RB_HIP(hipStreamSynchronize(ctx->stream));   // staging buffer reuse
+    const int rc = fill(user, (int32_t)t0, (int32_t)t1, kb, N / 2, hbuf.data());
+    RB_CHECK(rc == 0, RB_ERR_CALLBACK, "bank fill callback returned " + std::to_string(rc));
+    float2* st = static_cast<float2*>(stage.p);
+    std::atomic<int> nbad(0);
+    parallel_for(t1 - t0, [&](int64_t i) {
+      const double* h = &hbuf[(size_t)i * nbs * 2];
+      double s2 = 0.0;
+      int64_t lo = -1, hi = -1;
+      for (int64_t k = k_lo; k <= k_hi; ++k) {
+        const double re = h[2 * (k - kb)], im = h[2 * (k - kb) + 1];
+        const double a2 = (re * re + im * im) * w[k - kb] * w[k - kb];
+        s2 += a2;
+        if (a2 > 0.0) {
+          if (lo < 0) lo = k;
+          hi = k;
+        }
+      }
+      const double sg = std::sqrt(s2);
+      b->sigma[t0 + i] = sg;
+      if (!(sg > 0.0) || !std::isfinite(sg)) {
+        nbad++;
+        return;
+      }
+      float2* o = st + (size_t)i * nbs;
+      for (int64_t k = kb; k < k_lo; ++k) o[k - kb] = make_float2(0.f, 0.f);
+      for (int64_t k = k_lo; k <= k_hi; ++k) {
+        const double f = w[k - kb] / sg;
+        o[k - kb] = make_float2((float)(h[2 * (k - kb)] * f), (float)(h[2 * (k - kb) + 1] * f));
+      }
+      slo[t0 + i] = (int32_t)lo;
+      shi[t0 + i] = (int32_t)hi;
+    });
+    RB_CHECK(nbad.load() == 0, RB_ERR_ARG, "a template has zero or non-finite norm on the band");
+    RB_HIP(hipMemcpyAsync(b->w.as<float2>() + (size_t)t0 * nbs, st, (size_t)(t1 - t0) * nbs * sizeof(float2),
+                          hipMemcpyHostToDevice, ctx->stream));
+  }
+  RB_HIP(hipMemcpy(b->sup_lo.p, slo.data(), (size_t)T * 4, hipMemcpyHostToDevice));
+  RB_HIP(hipMemcpy(b->sup_hi.p, shi.data(), (size_t)T * 4, hipMemcpyHostToDevice));
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->live++;
+  *out = b.release();
+  return RB_OK;
+}
+
+extern "C" rb_status rb_bank_free(rb_bank bank) {
+  RB_CHECK(bank != nullptr, RB_ERR_ARG, "bank is NULL");
+  RB_CHECK(bank->live_bases == 0, RB_ERR_ARG, "bank still has live bases");
+  (void)hipSetDevice(bank->ctx->device);
+  (void)hipStreamSynchronize(bank->ctx->stream);
+  bank->ctx->live--;
+  delete bank;
+  return RB_OK;
+}
+
+extern "C" rb_status rb_bank_info(rb_bank bank, int32_t* T, int64_t* k_lo, int64_t* k_hi, double* sigma) {
+  RB_CHECK(bank != nullptr, RB_ERR_ARG, "bank is NULL");
+  if (T) *T = bank->T;
+  if (k_lo) *k_lo = bank->k_lo;
+  if (k_hi) *k_hi = bank->k_hi;
+  if (sigma) {
+    // sigma of the unwhitened templates (the bank stores w_j = h_j w / sigma_j)
+    std::memcpy(sigma, bank->sigma.data(), bank->sigma.size() * sizeof(double));
+  }
+  return RB_OK;
+}
+
+// ====================================================================== basis
+namespace {
+
+struct BasisWork {
+  DevBuf Q, Y, B, M, R, ws, norms, scale;
+};
+
+// Orthonormalise the columns of Y (T x L, complex128, row-major ld = L) in
+// place of Q: twice "scale, Gram, eigen-decompose" (SVQB).  Returns the kept
+// column count in *Lout.
+rb_status svqb(rb_ctx ctx, BasisWork& bw, const double2* Y, int64_t T, int L, double2* Qout, int* Lout) {
+  const double2* src = Y;
+  int Lc = L;
+  for (int pass = 0; pass < 2; ++pass) {
+    RB_TRY(bw.M.ensure((size_t)Lc * Lc * 16));
+    ZOperand A{src, 0, 1, Lc, 1};
+    ZOperand Bo{src, 0, Lc, 1, 0};
+    RB_HIP(launch_zgemm(Lc, Lc, T, A, Bo, bw.M.as<double2>(), Lc, 0, bw.ws.as<double2>(),
+                        (int64_t)(bw.ws.bytes / 16), ctx->stream));
+    std::vector<cd> G((size_t)Lc * Lc);
+    RB_HIP(hipMemcpyAsync(G.data(), bw.M.p, G.size() * 16, hipMemcpyDeviceToHost, ctx->stream));
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+    std::vector<double> dsc(Lc);
+    for (int i = 0; i < Lc; ++i) {
+      const double g = G[(size_t)i * Lc + i].real();
+      dsc[i] = g > 0 ? 1.0 / std::sqrt(g) : 0.0;
+    }
+    for (int i = 0; i < Lc; ++i)
+      for (int j = 0; j < Lc; ++j) G[(size_t)i * Lc + j] *= dsc[i] * dsc[j];
+    std::vector<double> th;
+    std::vector<cd> W;
+    RB_CHECK(herm_eig_desc(Lc, G, th, W), RB_ERR_NUMERIC, "eigensolver did not converge");
+    int keep = 0;
+    while (keep < Lc && th[keep] > 1e-12 * th[0]) ++keep;
+    RB_CHECK(keep > 0, RB_ERR_NUMERIC, "rank-zero subspace");
+    std::vector<cd> Rm((size_t)Lc * keep);
+    for (int i = 0; i < Lc; ++i)
+      for (int j = 0; j < keep; ++j) Rm[(size_t)i * keep + j] = dsc[i] * W[(size_t)i * Lc + j] / std::sqrt(th[j]);
+    RB_TRY(bw.R.ensure(Rm.size() * 16));
+    RB_HIP(hipMemcpyAsync(bw.R.p, Rm.data(), Rm.size() * 16, hipMemcpyHostToDevice, ctx->stream));
+    RB_HIP(hipStreamSynchronize(ctx->stream));   // Rm is pageable and local
+    // pass 0: Y -> Qout; pass 1: Qout -> Y (then copied back to Qout)
+    double2* outp = (pass == 0) ? Qout : bw.Y.as<double2>();
+    ZOperand A2{src, 0, Lc, 1, 0};
+    ZOperand B2{bw.R.p, 0, keep, 1, 0};
+    RB_HIP(launch_zgemm(T, keep, Lc, A2, B2, outp, keep, 0, bw.ws.as<double2>(), (int64_t)(bw.ws.bytes / 16),
+                        ctx->stream));
+    src = outp;
+    Lc = keep;
+  }
+  // result of pass 2 is in Y; copy to Qout
+  RB_HIP(hipMemcpyAsync(Qout, bw.Y.p, (size_t)T * Lc * 16, hipMemcpyDeviceToDevice, ctx->stream));
+  *Lout = Lc;
+  return RB_OK;
+}
+
+}  // namespace
+
+extern "C" rb_status rb_build_basis(rb_ctx ctx, rb_bank bank, int32_t rank, double tol, rb_dtype dtype,
+                                    rb_basis* out, int32_t* rank_out, double* energy_out) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(bank != nullptr && out != nullptr, RB_ERR_ARG, "NULL argument");
+  RB_CHECK(bank->ctx == ctx, RB_ERR_ARG, "bank belongs to another context");
+  RB_CHECK(rank >= 0, RB_ERR_ARG, "rank must be >= 0");
+  RB_CHECK(rank > 0 || (tol > 0 && tol < 1), RB_ERR_ARG, "tol must be in (0, 1) when rank == 0");
+  RB_CHECK(dtype == RB_F32 || dtype == RB_BF16 || dtype == RB_F16, RB_ERR_ARG, "bad dtype");
+  *out = nullptr;
+  const int64_t T = bank->T;
+  const int64_t nb = bank->k_hi - bank->k_lo + 1, off = bank->k_lo - bank->kb, nbs = bank->nbs;
+  hipStream_t s = ctx->stream;
+  BasisWork bw;
+  RB_TRY(bw.ws.ensure((size_t)64 << 20 << 4));   // 64 Mi complex128 split-K partials (1 GiB)
+  // trace of the Gram = sum of stored squared norms
+  RB_TRY(bw.norms.ensure((size_t)T * 8));
+  const float2* W = bank->w.as<float2>() + off;
+  RB_HIP(launch_row_norms(W, T, nb, nbs, bw.norms.as<double>(), s));
+  std::vector<double> norms(T);
+  RB_HIP(hipMemcpyAsync(norms.data(), bw.norms.p, T * 8, hipMemcpyDeviceToHost, s));
+  RB_HIP(hipStreamSynchronize(s));
+  double trace = 0.0;
+  for (double v : norms) trace += v;
+
+  const ZOperand Wop{W, 1, nbs, 1, 0};    // T x nb
+  const ZOperand WHop{W, 1, 1, nbs, 1};   // nb x T  (conjugate transpose)
+  const int over = 32;
+  int L = (int)std::min<int64_t>(T, rank > 0 ? (int64_t)rank + std::max(over, rank / 4) : 160);
+  const int q = 4;
+  std::vector<double> theta;
+  std::vector<cd> S;
+  int Lc = 0, K = 0;
+  std::mt19937_64 rng(0x2110131150ull);
+  std::normal_distribution<double> nd;
+  for (;;) {
+    // random start, orthonormalised
+    std::vector<cd> Om((size_t)T * L);
+    for (auto& v : Om) v = cd(nd(rng), nd(rng));
+    RB_TRY(bw.Q.ensure((size_t)T * L * 16));
+    RB_TRY(bw.Y.ensure((size_t)T * L * 16));
+    RB_HIP(hipMemcpyAsync(bw.Y.p, Om.data(), Om.size() * 16, hipMemcpyHostToDevice, s));
+    RB_TRY(svqb(ctx, bw, bw.Y.as<double2>(), T, L, bw.Q.as<double2>(), &Lc));
+    RB_TRY(bw.B.ensure((size_t)nb * Lc * 16));
+    if (Lc < T) {
+      for (int it = 0; it < q; ++it) {
+        ZOperand Qop{bw.Q.p, 0, Lc, 1, 0};
+        RB_HIP(launch_zgemm(nb, Lc, T, WHop, Qop, bw.B.as<double2>(), Lc, 0, bw.ws.as<double2>(),
+                            (int64_t)(bw.ws.bytes / 16), s));
+        ZOperand Bop{bw.B.p, 0, Lc, 1, 0};
+        RB_HIP(launch_zgemm(T, Lc, nb, Wop, Bop, bw.Y.as<double2>(), Lc, 0, bw.ws.as<double2>(),
+                            (int64_t)(bw.ws.bytes / 16), s));
+        int Ln = 0;
+        RB_TRY(svqb(ctx, bw, bw.Y.as<double2>(), T, Lc, bw.Q.as<double2>(), &Ln));
+        Lc = Ln;
+      }
+    }
+    // Rayleigh-Ritz: B = W^H Q, M = B^H B = Q^H G Q
+    {
+      ZOperand Qop{bw.Q.p, 0, Lc, 1, 0};
+      RB_HIP(launch_zgemm(nb, Lc, T, WHop, Qop, bw.B.as<double2>(), Lc, 0, bw.ws.as<double2>(),
+                          (int64_t)(bw.ws.bytes / 16), s));
+      RB_TRY(bw.M.ensure((size_t)Lc * Lc * 16));
+      ZOperand BH{bw.B.p, 0, 1, Lc, 1};
+      ZOperand Bo{bw.B.p, 0, Lc, 1, 0};
+      RB_HIP(launch_zgemm(Lc, Lc, nb, BH, Bo, bw.M.as<double2>(), Lc, 0, bw.ws.as<double2>(),
+                          (int64_t)(bw.ws.bytes / 16), s));
+      std::vector<cd> Mh((size_t)Lc * Lc);
+      RB_HIP(hipMemcpyAsync(Mh.data(), bw.M.p, Mh.size() * 16, hipMemcpyDeviceToHost, s));
+      RB_HIP(hipStreamSynchronize(s));
+      RB_CHECK(herm_eig_desc(Lc, Mh, theta, S), RB_ERR_NUMERIC, "eigensolver did not converge");
+    }
+    int npos = 0;
+    while (npos < Lc && theta[npos] > 1e-14 * theta[0]) ++npos;
+    if (rank > 0) {
+      K = std::min(rank, npos);
+      break;
+    }
+    double cum = 0.0;
+    K = 0;
+    while (K < npos && cum < (1.0 - tol) * trace) cum += theta[K++];
+    if (cum >= (1.0 - tol) * trace && (K + over <= Lc || Lc >= T)) break;
+    if (Lc >= T || L >= T) break;   // cannot grow further
+    L = (int)std::min<int64_t>(T, 2 * (int64_t)L);
+  }
+  RB_CHECK(K >= 1, RB_ERR_NUMERIC, "basis has rank zero");
+  std::unique_ptr<rb_basis_s> bs(new (std::nothrow) rb_basis_s);
+  RB_CHECK(bs != nullptr, RB_ERR_OOM, "host allocation failed");
+  bs->ctx = ctx;
+  bs->bank = bank;
+  bs->K = K;
+  bs->Kp = (dtype == RB_F32) ? K : ((K + 7) / 8) * 8;
+  const int tile = gemm_tile_templates();
+  bs->Tp = (int)(((T + tile - 1) / tile) * tile);
+  bs->dtype = dtype;
+  bs->trace = trace;
+  bs->lambda.assign(theta.begin(), theta.begin() + K);
+  double e = 0.0;
+  for (int k = 0; k < K; ++k) e += theta[k];
+  bs->energy = e / trace;
+  // BS = B S[:, :K]  (nb x K)
+  std::vector<cd> Sk((size_t)Lc * K);
+  for (int i = 0; i < Lc; ++i)
+    for (int k = 0; k < K; ++k) Sk[(size_t)i * K + k] = S[(size_t)i * Lc + k];
+  DevBuf Sd, BS, cdev, scale;
+  RB_TRY(Sd.ensure(Sk.size() * 16));
+  RB_HIP(hipMemcpyAsync(Sd.p, Sk.data(), Sk.size() * 16, hipMemcpyHostToDevice, s));
+  RB_TRY(BS.ensure((size_t)nb * K * 16));
+  {
+    ZOperand Bo{bw.B.p, 0, Lc, 1, 0};
+    ZOperand So{Sd.p, 0, K, 1, 0};
+    RB_HIP(launch_zgemm(nb, K, Lc, Bo, So, BS.as<double2>(), K, 0, bw.ws.as<double2>(),
+                        (int64_t)(bw.ws.bytes / 16), s));
+  }
+  std::vector<double> sc(K);
+  for (int k = 0; k < K; ++k) sc[k] = 1.0 / std::sqrt(theta[k]);
+  RB_TRY(scale.ensure(K * 8));
+  RB_HIP(hipMemcpyAsync(scale.p, sc.data(), K * 8, hipMemcpyHostToDevice, s));
+  RB_TRY(bs->P.ensure((size_t)K * nbs * sizeof(float2)));
+  RB_HIP(launch_basis_rows(BS.as<double2>(), nb, K, K, scale.as<double>(), off, nbs, bs->P.as<float2>(), s));
+  // c = W BS diag(theta^-1/2)  (T x K)
+  RB_TRY(cdev.ensure((size_t)T * K * 16));
+  {
+    ZOperand BSo{BS.p, 0, K, 1, 0};
+    RB_HIP(launch_zgemm(T, K, nb, Wop, BSo, cdev.as<double2>(), K, 0, bw.ws.as<double2>(),
+                        (int64_t)(bw.ws.bytes / 16), s));
+  }
+  bs->c.resize((size_t)T * K);
+  RB_HIP(hipMemcpyAsync(bs->c.data(), cdev.p, bs->c.size() * 16, hipMemcpyDeviceToHost, s));
+  RB_HIP(hipStreamSynchronize(s));
+  for (int64_t j = 0; j < T; ++j)
+    for (int k = 0; k < K; ++k) bs->c[(size_t)j * K + k] *= sc[k];
+  // C = conj(c) as complex64 (unscaled), row scales for FP16
+  std::vector<float2> C32((size_t)T * K);
+  bs->row_scale.assign(bs->Tp, 1.f);
+  for (int64_t j = 0; j < T; ++j) {
+    double mx = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const cd v = std::conj(bs->c[(size_t)j * K + k]);
+      C32[(size_t)j * K + k] = make_float2((float)v.real(), (float)v.imag());
+      mx = std::max(mx, std::max(std::fabs(v.real()), std::fabs(v.imag())));
+    }
+    if (dtype == RB_F16 && mx > 0) {
+      int ex;
+      (void)std::frexp(mx, &ex);      // mx = m 2^ex, m in [0.5, 1)
+      bs->row_scale[j] = (float)std::ldexp(1.0, -ex);
+    }
+  }
+  std::vector<float> rinv(bs->Tp);
+  for (int j = 0; j < bs->Tp; ++j) rinv[j] = 1.f / bs->row_scale[j];
+  RB_TRY(bs->C32.ensure(C32.size() * sizeof(float2)));
+  RB_HIP(hipMemcpyAsync(bs->C32.p, C32.data(), C32.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+  RB_TRY(bs->row_inv.ensure((size_t)bs->Tp * 4));
+  RB_TRY(bs->row_scale_dev.ensure((size_t)bs->Tp * 4));
+  RB_HIP(hipMemcpyAsync(bs->row_inv.p, rinv.data(), (size_t)bs->Tp * 4, hipMemcpyHostToDevice, s));
+  RB_HIP(hipMemcpyAsync(bs->row_scale_dev.p, bs->row_scale.data(), (size_t)bs->Tp * 4, hipMemcpyHostToDevice, s));
+  const size_t cpk_bytes = (dtype == RB_F32) ? (size_t)(bs->Tp / 16) * K * 64 * 4
+                                             : (size_t)(bs->Tp / 16) * (bs->Kp / 8) * 64 * 8 * 2;
+  RB_TRY(bs->cpk.ensure(cpk_bytes));
+  RB_HIP(launch_pack_c(bs->C32.as<float2>(), (int)T, bs->Tp, K, bs->Kp, (int)dtype,
+                       dtype == RB_F16 ? bs->row_scale_dev.as<float>() : nullptr, bs->cpk.p, s));
+  RB_HIP(hipStreamSynchronize(s));
+  if (rank_out) *rank_out = K;
+  if (energy_out) *energy_out = bs->energy;
+  bank->live_bases++;
+  ctx->live++;
+  *out = bs.release();
+  return RB_OK;
+}
+
+extern "C" rb_status rb_basis_free(rb_basis basis) {
+  RB_CHECK(basis != nullptr, RB_ERR_ARG, "basis is NULL");
+  (void)hipSetDevice(basis->ctx->device);
+  (void)hipStreamSynchronize(basis->ctx->stream);
+  basis->bank->live_bases--;
+  basis->ctx->live--;
+  delete basis;
+  return RB_OK;
+}
+
+extern "C" rb_status rb_basis_export(rb_basis basis, double* V, double* c, double* lambda) {
+  RB_CHECK(basis != nullptr, RB_ERR_ARG, "basis is NULL");
+  RB_HIP(hipSetDevice(basis->ctx->device));
+  rb_bank bank = basis->bank;
+  const int K = basis->K;
+  const int64_t nb = bank->k_hi - bank->k_lo + 1, off = bank->k_lo - bank->kb;
+  if (V) {
+    std::vector<float2> P((size_t)K * bank->nbs);
+    RB_HIP(hipMemcpy(P.data(), basis->P.p, P.size() * sizeof(float2), hipMemcpyDeviceToHost));
+    for (int k = 0; k < K; ++k)
+      for (int64_t f = 0; f < nb; ++f) {
+        const float2 v = P[(size_t)k * bank->nbs + off + f];
+        V[2 * ((size_t)k * nb + f)] = v.x;
+        V[2 * ((size_t)k * nb + f) + 1] = v.y;
+      }
+  }
+  if (c) std::memcpy(c, basis->c.data(), basis->c.size() * 16);
+  if (lambda) std::memcpy(lambda, basis->lambda.data(), basis->lambda.size() * 8);
+  return RB_OK;
+}
+
+// ====================================================================== search
+namespace {
+
+rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq, float2* rho_out) {
+  rb_bank bank = basis->bank;
+  const int T = bank->T;
+  const float want = rho_out ? std::numeric_limits<float>::infinity() : thr1sq;
+  if (!(basis->thr_cached == want)) {
+    RB_TRY(basis->thr_row.ensure((size_t)basis->Tp * 4));
+    std::vector<float> thr(basis->Tp);
+    for (int j = 0; j < basis->Tp; ++j) {
+      const float a = basis->row_scale[j];
+      thr[j] = want * a * a;
+    }
+    RB_HIP(hipMemcpyAsync(basis->thr_row.p, thr.data(), thr.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+    basis->thr_cached = want;
+  }
+  GemmArgs ga;
+  std::memset(&ga, 0, sizeof(ga));
+  ga.N = g.N;
+  ga.T = T;
+  ga.Tp = basis->Tp;
+  ga.K = basis->K;
+  ga.Kp = basis->Kp;
+  ga.dtype = (int)basis->dtype;
+  ga.cpk = basis->cpk.p;
+  ga.z = ctx->z.p;
+  ga.thr2_row = basis->thr_row.as<float>();
+  ga.N1 = g.N1;
+  ga.N2 = g.N2;
+  ga.trig = ctx->trig1.as<TrigRec>();
+  ga.trig_cap = trig_capacity(ctx->trig1);
+  ga.trig_count = ctx->counters.as<unsigned long long>();
+  ga.tmpl_count = ctx->cnt1.as<int32_t>();
+  ga.rho_out = rho_out;
+  ga.row_inv = basis->row_inv.as<float>();
+  RB_HIP(launch_recon_gemm(ga, ctx->stream));
+  return RB_OK;
+}
+
+}  // namespace
+
+extern "C" rb_status rb_filter(rb_ctx ctx, rb_basis basis, rb_bank bank, const float* strain,
+                               const rb_filter_opts* opts, rb_trigger* out, int64_t cap, int64_t* n_out,
+                               rb_peak* peaks, rb_stats* stats) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(basis != nullptr && bank != nullptr && opts != nullptr && n_out != nullptr, RB_ERR_ARG,
+           "NULL argument");
+  RB_CHECK(basis->bank == bank && bank->ctx == ctx, RB_ERR_ARG, "basis/bank/context mismatch");
+  RB_CHECK(std::isfinite(opts->thr1) && opts->thr1 > 0, RB_ERR_ARG, "thr1 must be > 0");
+  RB_CHECK(std::isfinite(opts->thr2) && opts->thr2 >= opts->thr1, RB_ERR_ARG, "thr2 must be >= thr1");
+  RB_CHECK(opts->stage2 == RB_STAGE2_FULL || opts->stage2 == RB_STAGE2_SPARSE, RB_ERR_ARG, "bad stage2 mode");
+  RB_CHECK(opts->reserved == 0, RB_ERR_ARG, "reserved must be 0");
+  RB_CHECK(cap >= 0, RB_ERR_ARG, "cap must be >= 0");
+  RB_CHECK(opts->stage2 == RB_STAGE2_FULL, RB_ERR_UNSUPPORTED, "sparse second stage not available");
+  const int T = bank->T;
+  const FftGeom g = make_geom(bank->grid.N);
+  FftTables tw;
+  RB_TRY(get_tables(ctx, g, tw));
+  const float* s;
+  RB_TRY(strain_device(ctx, strain, g.N, &s));
+  RB_TRY(ensure_trigger_scratch(ctx, T));
+  record(ctx, stats, 0);
+  RB_TRY(fill32(ctx, ctx->flag.p, 0u, 2));
+  RB_HIP(launch_check_finite(s, g.N, ctx->flag.as<int64_t>(), ctx->stream));
+  RB_TRY(step_spectrum(ctx, bank, g, tw, s));
+  record(ctx, stats, 1);
+  RB_TRY(step_basis_outputs(ctx, basis, g, tw));
+  record(ctx, stats, 2);
+  int64_t sum1[3];
+  for (;;) {
+    RB_TRY(fill32(ctx, ctx->counters.p, 0u, 2));
+    RB_TRY(fill32(ctx, ctx->cnt1.p, 0u, T));
+    RB_TRY(stage1_gemm(ctx, basis, g, (float)(opts->thr1 * opts->thr1), nullptr));
+    record(ctx, stats, 3);
+    RB_TRY(scan_and_read(ctx, T, ctx->cnt1, ctx->off1, ctx->fill1, ctx->list1, sum1));
+    if (sum1[0] <= trig_capacity(ctx->trig1)) break;
+    RB_TRY(ctx->trig1.ensure((size_t)(sum1[0] + sum1[0] / 4) * sizeof(TrigRec)));
+  }
+  int64_t flag = 0;
+  RB_HIP(hipMemcpyAsync(&flag, ctx->flag.p, 8, hipMemcpyDeviceToHost, ctx->stream));
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  RB_CHECK(flag == 0, RB_ERR_NUMERIC, "strain contains non-finite values");
+  record(ctx, stats, 4);
+  int64_t sum2[3];
+  for (;;) {
+    RB_TRY(fill32(ctx, ctx->counters.p, 0u, 4));
+    RB_TRY(fill32(ctx, ctx->cnt2.p, 0u, T));
+    RB_TRY(fill32(ctx, ctx->tmax.p, 0u, 2 * (int64_t)T));
+    RB_TRY(step_mf(ctx, bank, g, tw, ctx->list1.as<int32_t>(), sum1[1], (float)(opts->thr2 * opts->thr2)));
+    record(ctx, stats, 5);
+    RB_TRY(scan_and_read(ctx, T, ctx->cnt2, ctx->off2, ctx->fill2, ctx->list2, sum2));
+    if (sum2[0] <= trig_capacity(ctx->trig2)) break;
+    RB_TRY(ctx->trig2.ensure((size_t)(sum2[0] + sum2[0] / 4) * sizeof(TrigRec)));
+  }
+  const rb_status st = finish_stage2(ctx, bank, out, cap, n_out, peaks, sum2);
+  record(ctx, stats, 6);
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->n_stage1 = sum1[0];
+    stats->n_refiltered = (int32_t)sum1[1];
+    stats->rank = basis->K;
+    float ms;
+    const int pairs[7][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {0, 6}};
+    for (int i = 0; i < 7; ++i)
+      if (hipEventElapsedTime(&ms, ctx->ev[pairs[i][0]], ctx->ev[pairs[i][1]]) == hipSuccess) stats->ms[i] = ms;
+    (void)hipGetLastError();
+  }
+  return st;
+}
+
+extern "C" rb_status mf_full(rb_ctx ctx, rb_bank bank, const float* strain, double thr, rb_trigger* out,
+                             int64_t cap, int64_t* n_out, rb_peak* peaks, rb_stats* stats) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(bank != nullptr && n_out != nullptr, RB_ERR_ARG, "NULL argument");
+  RB_CHECK(bank->ctx == ctx, RB_ERR_ARG, "bank belongs to another context");
+  RB_CHECK(std::isfinite(thr) && thr > 0, RB_ERR_ARG, "thr must be > 0");
+  RB_CHECK(cap >= 0, RB_ERR_ARG, "cap must be >= 0");
+  const int T = bank->T;
+  const FftGeom g = make_geom(bank->grid.N);
+  FftTables tw;
+  RB_TRY(get_tables(ctx, g, tw));
+  const float* s;
+  RB_TRY(strain_device(ctx, strain, g.N, &s));
+  RB_TRY(ensure_trigger_scratch(ctx, T));
+  record(ctx, stats, 0);
+  RB_TRY(fill32(ctx, ctx->flag.p, 0u, 2));
+  RB_HIP(launch_check_finite(s, g.N, ctx->flag.as<int64_t>(), ctx->stream));
+  RB_TRY(step_spectrum(ctx, bank, g, tw, s));
+  record(ctx, stats, 1);
+  int64_t sum2[3];
+  for (;;) {
+    RB_TRY(fill32(ctx, ctx->counters.p, 0u, 4));
+    RB_TRY(fill32(ctx, ctx->cnt2.p, 0u, T));
+    RB_TRY(fill32(ctx, ctx->tmax.p, 0u, 2 * (int64_t)T));
+    RB_TRY(step_mf(ctx, bank, g, tw, nullptr, T, (float)(thr * thr)));
+    record(ctx, stats, 2);
+    RB_TRY(scan_and_read(ctx, T, ctx->cnt2, ctx->off2, ctx->fill2, ctx->list2, sum2));
+    if (sum2[0] <= trig_capacity(ctx->trig2)) break;
+    RB_TRY(ctx->trig2.ensure((size_t)(sum2[0] + sum2[0] / 4) * sizeof(TrigRec)));
+  }
+  int64_t flag = 0;
+  RB_HIP(hipMemcpyAsync(&flag, ctx->flag.p, 8, hipMemcpyDeviceToHost, ctx->stream));
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  RB_CHECK(flag == 0, RB_ERR_NUMERIC, "strain contains non-finite values");
+  const rb_status st = finish_stage2(ctx, bank, out, cap, n_out, peaks, sum2);
+  record(ctx, stats, 3);
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->n_refiltered = T;
+    float ms;
+    if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) stats->ms[0] = ms;
+    if (hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]) == hipSuccess) stats->ms[4] = ms;
+    if (hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]) == hipSuccess) stats->ms[5] = ms;
+    if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]) == hipSuccess) stats->ms[6] = ms;
+    (void)hipGetLastError();
+  }
+  return st;
+}
+
+extern "C" rb_status rb_cluster_peaks(rb_ctx ctx, const rb_trigger* trig, int64_t n, int32_t W, int64_t N,
+                                      uint8_t* is_peak) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(n >= 0 && W >= 0 && N > 0, RB_ERR_ARG, "bad sizes");
+  if (n == 0) return RB_OK;
+  RB_CHECK(trig != nullptr && is_peak != nullptr, RB_ERR_ARG, "NULL argument");
+  DevBuf tdev, pdev;
+  const void* tp = trig;
+  if (!is_device_ptr(trig)) {
+    RB_TRY(tdev.ensure((size_t)n * sizeof(rb_trigger)));
+    RB_HIP(hipMemcpyAsync(tdev.p, trig, (size_t)n * sizeof(rb_trigger), hipMemcpyHostToDevice, ctx->stream));
+    tp = tdev.p;
+  }
+  uint8_t* pp = is_peak;
+  const bool dev_out = is_device_ptr(is_peak);
+  if (!dev_out) {
+    RB_TRY(pdev.ensure((size_t)n));
+    pp = pdev.as<uint8_t>();
+  }
+  RB_HIP(launch_cluster_peaks(tp, n, W, N, pp, ctx->stream));
+  if (!dev_out) RB_HIP(hipMemcpyAsync(is_peak, pp, (size_t)n, hipMemcpyDeviceToHost, ctx->stream));
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  return RB_OK;
+}
+
+// ====================================================================== debug
+extern "C" rb_status rb_debug_rho(rb_ctx ctx, rb_basis basis, rb_bank bank, const float* strain, float* rho) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(bank != nullptr && rho != nullptr, RB_ERR_ARG, "NULL argument");
+  RB_CHECK(bank->ctx == ctx && (basis == nullptr || basis->bank == bank), RB_ERR_ARG, "handle mismatch");
+  const int T = bank->T;
+  const FftGeom g = make_geom(bank->grid.N);
+  RB_CHECK((double)T * g.N <= 4e9, RB_ERR_ARG, "T * N too large for a dump");
+  FftTables tw;
+  RB_TRY(get_tables(ctx, g, tw));
+  const float* s;
+  RB_TRY(strain_device(ctx, strain, g.N, &s));
+  RB_TRY(ensure_trigger_scratch(ctx, T));
+  float2* dst = reinterpret_cast<float2*>(rho);
+  const bool dev = is_device_ptr(rho);
+  if (!dev) {
+    RB_TRY(ctx->rho_tmp.ensure((size_t)T * g.N * 8));
+    dst = ctx->rho_tmp.as<float2>();
+  }
+  RB_TRY(step_spectrum(ctx, bank, g, tw, s));
+  if (basis == nullptr) {
+    const int B = batch_vectors(g.N, T);
+    RB_TRY(ctx->work.ensure((size_t)B * g.N * 8));
+    PassArgs a = base_args(bank, g, tw);
+    a.sign = +1;
+    a.d = ctx->dspec.as<float2>();
+    a.src = bank->w.as<float2>();
+    a.sup_lo = bank->sup_lo.as<int32_t>();
+    a.sup_hi = bank->sup_hi.as<int32_t>();
+    a.work = ctx->work.as<float2>();
+    a.cout = dst;
+    for (int i0 = 0; i0 < T; i0 += B) {
+      a.vec_base = i0;
+      a.nvec = std::min(B, T - i0);
+      RB_HIP(launch_pass1(a, IN_CORR, ctx->stream));
+      RB_HIP(launch_pass2(a, OUT_NATURAL, ctx->stream));
+    }
+  } else {
+    RB_TRY(step_basis_outputs(ctx, basis, g, tw));
+    RB_TRY(fill32(ctx, ctx->counters.p, 0u, 2));
+    RB_TRY(fill32(ctx, ctx->cnt1.p, 0u, T));
+    RB_TRY(stage1_gemm(ctx, basis, g, 0.f, dst));
+  }
+  if (!dev) RB_HIP(hipMemcpyAsync(rho, dst, (size_t)T * g.N * 8, hipMemcpyDeviceToHost, ctx->stream));
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  return RB_OK;
+}
+
+extern "C" rb_status rb_debug_basis_outputs(rb_ctx ctx, rb_basis basis, const float* strain, float* beta) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(basis != nullptr && beta != nullptr, RB_ERR_ARG, "NULL argument");
+  rb_bank bank = basis->bank;
+  const FftGeom g = make_geom(bank->grid.N);
+  const int K = basis->K;
+  FftTables tw;
+  RB_TRY(get_tables(ctx, g, tw));
+  const float* s;
+  RB_TRY(strain_device(ctx, strain, g.N, &s));
+  RB_TRY(step_spectrum(ctx, bank, g, tw, s));
+  RB_TRY(step_basis_outputs(ctx, basis, g, tw));
+  float2* dst = reinterpret_cast<float2*>(beta);
+  const bool dev = is_device_ptr(beta);
+  if (!dev) {
+    RB_TRY(ctx->rho_tmp.ensure((size_t)K * g.N * 8));
+    dst = ctx->rho_tmp.as<float2>();
+  }
+  RB_HIP(launch_z_to_natural(ctx->z.p, (int)basis->dtype, 1.f, g.N, K, g.N1, g.N2, dst, ctx->stream));
+  if (!dev) RB_HIP(hipMemcpyAsync(beta, dst, (size_t)K * g.N * 8, hipMemcpyDeviceToHost, ctx->stream));
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  return RB_OK;
+}
+
+namespace {
+
+// Copies the trigger list (host or device) to host arrays and validates it.
+rb_status host_triggers(rb_ctx ctx, const rb_trigger* S, int64_t n, int T, int64_t N, std::vector<int32_t>& tm,
+                        std::vector<int32_t>& sp) {
+  std::vector<rb_trigger> h((size_t)n);
+  if (n > 0) {
+    if (is_device_ptr(S)) {
+      RB_HIP(hipMemcpyAsync(h.data(), S, (size_t)n * sizeof(rb_trigger), hipMemcpyDeviceToHost, ctx->stream));
+      RB_HIP(hipStreamSynchronize(ctx->stream));
+    } else {
+      std::memcpy(h.data(), S, (size_t)n * sizeof(rb_trigger));
+    }
+  }
+  tm.resize(n);
+  sp.resize(n);
+  for (int64_t i = 0; i < n; ++i) {
+    RB_CHECK(h[i].tmpl >= 0 && h[i].tmpl < T && h[i].sample >= 0 && h[i].sample < N, RB_ERR_ARG,
+             "trigger " + std::to_string(i) + " out of range");
+    tm[i] = h[i].tmpl;
+    sp[i] = h[i].sample;
+  }
+  return RB_OK;
+}
+
+rb_status upload(rb_ctx ctx, DevBuf& b, const void* src, size_t bytes) {
+  RB_TRY(b.ensure(std::max<size_t>(bytes, 16)));
+  if (bytes) RB_HIP(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+  return RB_OK;
+}
+
+// Uploads C (host or device, T x K complex64) or points at the basis's own.
+rb_status coeffs(rb_ctx ctx, rb_basis basis, const float* C, const float2** out) {
+  if (C == nullptr) {
+    *out = basis->C32.as<float2>();
+    return RB_OK;
+  }
+  if (is_device_ptr(C)) {
+    *out = reinterpret_cast<const float2*>(C);
+    return RB_OK;
+  }
+  const size_t bytes = (size_t)basis->bank->T * basis->K * sizeof(float2);
+  RB_TRY(ctx->adjC.ensure(bytes));
+  RB_HIP(hipMemcpyAsync(ctx->adjC.p, C, bytes, hipMemcpyHostToDevice, ctx->stream));
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  *out = ctx->adjC.as<float2>();
+  return RB_OK;
+}
+
+// Groups trigger indices by key (stable): order and segment offsets.
+void group_by(const std::vector<int32_t>& key, std::vector<int32_t>& order, std::vector<int32_t>& seg) {
+  const int64_t n = (int64_t)key.size();
+  order.resize(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  seg.clear();
+  for (int64_t s = 0; s < n; ++s)
+    if (s == 0 || key[order[s]] != key[order[s - 1]]) seg.push_back((int32_t)s);
+  seg.push_back((int32_t)n);
+}
+
+// d, FP32 Z, uploaded triggers and rho at the trigger points.
+rb_status adjoint_forward(rb_ctx ctx, rb_basis basis, const float* strain, const rb_trigger* S, int64_t n,
+                          const float* C, const FftGeom& g, std::vector<int32_t>& tm, std::vector<int32_t>& sp,
+                          const float2** Cd) {
+  rb_bank bank = basis->bank;
+  FftTables tw;
+  RB_TRY(get_tables(ctx, g, tw));
+  RB_TRY(host_triggers(ctx, S, n, bank->T, g.N, tm, sp));
+  const float* s;
+  RB_TRY(strain_device(ctx, strain, g.N, &s));
+  RB_TRY(coeffs(ctx, basis, C, Cd));
+  RB_TRY(step_spectrum(ctx, bank, g, tw, s));
+  RB_TRY(step_basis_outputs(ctx, basis, g, tw, true));
+  RB_TRY(upload(ctx, ctx->adjT, tm.data(), tm.size() * 4));
+  RB_TRY(upload(ctx, ctx->adjS, sp.data(), sp.size() * 4));
+  RB_TRY(ctx->adjRho.ensure(std::max<size_t>(16, (size_t)n * sizeof(float2))));
+  RB_HIP(launch_rho_at(ctx->z32.as<float>(), g.N, basis->K, g.N1, g.N2, *Cd, ctx->adjT.as<int32_t>(),
+                       ctx->adjS.as<int32_t>(), n, ctx->adjRho.as<float2>(), ctx->stream));
+  return RB_OK;
+}
+
+}  // namespace
+
+extern "C" rb_status rb_rho_at(rb_ctx ctx, rb_basis basis, const float* strain, const rb_trigger* S, int64_t n,
+                               const float* C, float* rho) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(basis != nullptr && basis->ctx == ctx, RB_ERR_ARG, "basis is NULL or from another context");
+  RB_CHECK(n >= 0, RB_ERR_ARG, "n must be >= 0");
+  if (n == 0) return RB_OK;
+  RB_CHECK(S != nullptr && rho != nullptr, RB_ERR_ARG, "NULL argument");
+  const FftGeom g = make_geom(basis->bank->grid.N);
+  std::vector<int32_t> tm, sp;
+  const float2* Cd;
+  RB_TRY(adjoint_forward(ctx, basis, strain, S, n, C, g, tm, sp, &Cd));
+  RB_TRY(copy_out(ctx, rho, ctx->adjRho.p, (size_t)n * sizeof(float2)));
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  return RB_OK;
+}
+
+extern "C" rb_status rb_backward(rb_ctx ctx, rb_basis basis, const float* strain, const rb_trigger* S,
+                                 const float* seed, int64_t n, const float* C, float* grad_C, float* grad_strain,
+                                 double* loss) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(basis != nullptr && basis->ctx == ctx, RB_ERR_ARG, "basis is NULL or from another context");
+  RB_CHECK(n >= 0, RB_ERR_ARG, "n must be >= 0");
+  RB_CHECK(n == 0 || S != nullptr, RB_ERR_ARG, "S is NULL");
+  rb_bank bank = basis->bank;
+  const int T = bank->T, K = basis->K;
+  const FftGeom g = make_geom(bank->grid.N);
+  const int64_t N = g.N;
+  hipStream_t st = ctx->stream;
+  std::vector<int32_t> tm, sp;
+  const float2* Cd = nullptr;
+  RB_TRY(adjoint_forward(ctx, basis, strain, S, n, C, g, tm, sp, &Cd));
+  std::vector<float> gh((size_t)n, 1.f);
+  const float* gd = nullptr;
+  if (seed) {
+    if (is_device_ptr(seed)) {
+      RB_HIP(hipMemcpyAsync(gh.data(), seed, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+      RB_HIP(hipStreamSynchronize(st));
+    } else {
+      std::memcpy(gh.data(), seed, (size_t)n * 4);
+    }
+    RB_TRY(upload(ctx, ctx->adjG, gh.data(), (size_t)n * 4));
+    gd = ctx->adjG.as<float>();
+  }
+  if (loss) {
+    std::vector<float2> rh((size_t)n);
+    if (n) RB_HIP(hipMemcpyAsync(rh.data(), ctx->adjRho.p, (size_t)n * sizeof(float2), hipMemcpyDeviceToHost, st));
+    RB_HIP(hipStreamSynchronize(st));
+    double L = 0.0;
+    for (int64_t i = 0; i < n; ++i) L += (double)gh[i] * ((double)rh[i].x * rh[i].x + (double)rh[i].y * rh[i].y);
+    *loss = L;
+  }
+  if (grad_C) {
+    const size_t bytes = (size_t)T * K * sizeof(float2);
+    RB_TRY(ctx->adjGC.ensure(bytes));
+    RB_TRY(fill32(ctx, ctx->adjGC.p, 0u, (int64_t)(bytes / 4)));
+    std::vector<int32_t> order, seg;
+    group_by(tm, order, seg);
+    RB_TRY(upload(ctx, ctx->adjOrd, order.data(), order.size() * 4));
+    RB_TRY(upload(ctx, ctx->adjSeg, seg.data(), seg.size() * 4));
+    RB_HIP(launch_grad_c(ctx->z32.as<float>(), N, K, g.N1, g.N2, ctx->adjOrd.as<int32_t>(), ctx->adjSeg.as<int32_t>(),
+                         (int)seg.size() - 1, ctx->adjT.as<int32_t>(), ctx->adjS.as<int32_t>(),
+                         ctx->adjRho.as<float2>(), gd, ctx->adjGC.as<float2>(), st));
+    RB_TRY(copy_out(ctx, grad_C, ctx->adjGC.p, bytes));
+    RB_HIP(hipStreamSynchronize(st));   // order/seg host vectors die here
+  }
+  if (grad_strain) {
+    FftTables tw;
+    RB_TRY(get_tables(ctx, g, tw));
+    RB_TRY(ctx->adjA.ensure((size_t)K * N * sizeof(float2)));
+    RB_TRY(ctx->adjAhat.ensure((size_t)K * N * sizeof(float2)));
+    RB_TRY(fill32(ctx, ctx->adjA.p, 0u, (int64_t)K * N * 2));
+    std::vector<int32_t> order, seg;
+    group_by(sp, order, seg);
+    RB_TRY(upload(ctx, ctx->adjOrd, order.data(), order.size() * 4));
+    RB_TRY(upload(ctx, ctx->adjSeg, seg.data(), seg.size() * 4));
+    RB_HIP(launch_scatter_a(K, N, ctx->adjOrd.as<int32_t>(), ctx->adjSeg.as<int32_t>(), (int)seg.size() - 1,
+                            ctx->adjT.as<int32_t>(), ctx->adjS.as<int32_t>(), ctx->adjRho.as<float2>(), gd, Cd,
+                            ctx->adjA.as<float2>(), st));
+    // Ahat_k[f] = sum_n A_k[n] e^{+2 pi i f n / N}, natural frequency order
+    const int B = batch_vectors(N, K);
+    RB_TRY(ctx->work.ensure((size_t)B * N * 8));
+    PassArgs a = base_args(bank, g, tw);
+    a.sign = +1;
+    a.src = ctx->adjA.as<float2>();
+    a.work = ctx->work.as<float2>();
+    a.cout = ctx->adjAhat.as<float2>();
+    for (int v0 = 0; v0 < K; v0 += B) {
+      a.vec_base = v0;
+      a.nvec = std::min(B, K - v0);
+      RB_HIP(launch_pass1(a, IN_DENSE, st));
+      RB_HIP(launch_pass2(a, OUT_NATURAL, st));
+    }
+    // B[f] on the band, then dL/ds = 2 Re FFT_-(B)
+    RB_TRY(ctx->adjB.ensure((size_t)N * sizeof(float2)));
+    RB_TRY(fill32(ctx, ctx->adjB.p, 0u, N * 2));
+    RB_HIP(launch_bsum(ctx->adjAhat.as<float2>(), basis->P.as<float2>(), bank->wd.as<double>(), K, N, bank->kb,
+                       bank->nbs, bank->k_lo, bank->k_hi, ctx->adjB.as<float2>(), st));
+    PassArgs b = base_args(bank, g, tw);
+    b.sign = -1;
+    b.nvec = 1;
+    b.src = ctx->adjB.as<float2>();
+    b.work = ctx->work.as<float2>();
+    b.cout = ctx->adjAhat.as<float2>();     // reuse: first N entries
+    RB_HIP(launch_pass1(b, IN_DENSE, st));
+    RB_HIP(launch_pass2(b, OUT_NATURAL, st));
+    float* gs = grad_strain;
+    DevBuf tmp;
+    const bool dev = is_device_ptr(grad_strain);
+    if (!dev) {
+      RB_TRY(tmp.ensure((size_t)N * 4));
+      gs = tmp.as<float>();
+    }
+    RB_HIP(launch_real2(ctx->adjAhat.as<float2>(), N, gs, st));
+    if (!dev) RB_HIP(hipMemcpyAsync(grad_strain, gs, (size_t)N * 4, hipMemcpyDeviceToHost, st));
+    RB_HIP(hipStreamSynchronize(st));
+  }
+  RB_HIP(hipStreamSynchronize(st));
+  return RB_OK;
+}

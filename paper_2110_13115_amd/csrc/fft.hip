@@ -1,0 +1,530 @@
+// Batched LDS-staged radix FFT passes for gfx950.
+//
+// An N-point transform is split N = N1 * N2 (four-step).  Pass 1 runs
+// N2-point FFTs down adjacent columns (16 for FP32, 8 for FP64, so every
+// global access is a 128-byte row segment), multiplies by the inter-pass
+// twiddle and writes the [N2][N1] intermediate.  Pass 2 runs N1-point FFTs along rows.
+// The result stays in the four-step (transposed) order: position
+// q = n2 * N1 + n1 holds index n = n2 + N2 * n1; consumers that need natural
+// order map q -> n themselves.
+//
+// Inside a workgroup each FFT is a self-sorting mixed-radix Stockham
+// factorisation (radix 8/16 butterflies in registers, LDS exchanges between
+// stages).  The first stage reads global memory directly and the last stage
+// writes global memory directly, so an FFT of length L with s stages costs
+// s - 1 LDS round trips.
+//
+// Fused prologues (pass 1):  IN_CORR  X[f] = d[f] conj(src_v[f]) on the
+//   vector's support (Sec. III.C: filter the whitened data with every basis
+//   vector / template); negative frequencies are zero, so only the first half
+//   of every column is read.  IN_REAL: the real strain.  IN_DENSE: complex.
+// The batched passes run in FP32.  The one forward transform of the strain
+// runs in FP64: raw strain carries out-of-band (low-frequency) power many
+// orders of magnitude above the band, and FP32 rounding relative to the total
+// energy would swamp the whitened in-band bins.
+// Fused epilogues (pass 2): planar FP32 / 16-bit Z for the reconstruction
+//   GEMM, threshold + trigger append + per-template max (template method,
+//   Eq. IFFT and the trigger definition of Sec. II), whitened band spectrum
+//   of the strain, natural-order dumps.
+#include "internal.h"
+
+#include <hip/hip_fp16.h>
+
+namespace rbmf {
+
+namespace {
+
+constexpr int NT = 256;      // threads per workgroup
+constexpr int ROW_ELEMS = 4096;  // elements per pass-2 workgroup
+
+// Complex helpers generic over float2 / double2.
+template <class V> struct Re;
+template <> struct Re<float2> { using T = float; };
+template <> struct Re<double2> { using T = double; };
+template <class V>
+__device__ __forceinline__ V mk(typename Re<V>::T x, typename Re<V>::T y) {
+  V v;
+  v.x = x;
+  v.y = y;
+  return v;
+}
+template <class V>
+__device__ __forceinline__ V cadd(V a, V b) { return mk<V>(a.x + b.x, a.y + b.y); }
+template <class V>
+__device__ __forceinline__ V csub(V a, V b) { return mk<V>(a.x - b.x, a.y - b.y); }
+template <class V>
+__device__ __forceinline__ V cmul(V a, V b) { return mk<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// a * conj(b)
+template <class V>
+__device__ __forceinline__ V cmulc(V a, V b) { return mk<V>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+template <int S, class V>
+__device__ __forceinline__ V signed_tw(V w) { return S > 0 ? w : mk<V>(w.x, -w.y); }
+
+// x * e^{S 2 pi i k / R} for 0 <= k < R/2, R <= 16 (k is a compile-time
+// constant after unrolling, so the switch folds away).
+template <int R, int S, class V>
+__device__ __forceinline__ V rot(V x, int k) {
+  using T = typename Re<V>::T;
+  const int k16 = k * (16 / R);
+  if (k16 == 0) return x;
+  if (k16 == 4) return S > 0 ? mk<V>(-x.y, x.x) : mk<V>(x.y, -x.x);
+  const T C1 = (T)0.92387953251128674, S1 = (T)0.38268343236508978, H2 = (T)0.70710678118654752;
+  T c = 1, s = 0;
+  switch (k16) {
+    case 1: c = C1; s = S1; break;
+    case 2: c = H2; s = H2; break;
+    case 3: c = S1; s = C1; break;
+    case 5: c = -S1; s = C1; break;
+    case 6: c = -H2; s = H2; break;
+    case 7: c = -C1; s = S1; break;
+    default: break;
+  }
+  if (S < 0) s = -s;
+  return mk<V>(x.x * c - x.y * s, x.x * s + x.y * c);
+}
+
+// In-register DFT of size R (radix-2 decimation in time, recursively).
+template <int R, int S>
+struct Dft {
+  template <class V>
+  static __device__ __forceinline__ void run(V* v) {
+    constexpr int H = R / 2;
+    V e[H], o[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      e[i] = v[2 * i];
+      o[i] = v[2 * i + 1];
+    }
+    Dft<H, S>::run(e);
+    Dft<H, S>::run(o);
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const V t = rot<R, S>(o[k], k);
+      v[k] = cadd(e[k], t);
+      v[k + H] = csub(e[k], t);
+    }
+  }
+};
+template <int S>
+struct Dft<1, S> {
+  template <class V>
+  static __device__ __forceinline__ void run(V*) {}
+};
+
+// Stage twiddles: input r of a butterfly with k = j mod Ns gets
+// e^{S 2 pi i r k / (Ns R)} = pyr[Ns R + r k].
+template <int R, int Ns, int S, class V>
+__device__ __forceinline__ void apply_stage_tw(V* v, int k, const V* __restrict__ pyr) {
+  if (Ns == 1) return;
+#pragma unroll
+  for (int r = 1; r < R; ++r) v[r] = cmul(v[r], signed_tw<S>(pyr[Ns * R + r * k]));
+}
+
+// ------------------------------------------------------------------ layouts
+// Column layout (pass 1): C FFTs, element (c, pos) at pos * C + c.
+template <int L, int C>
+struct ColLayout {
+  static constexpr int NF = C;
+  static constexpr int SIZE = L * C;
+  template <int R>
+  static __device__ __forceinline__ void split(int b, int& f, int& j) {
+    f = b % C;
+    j = b / C;
+  }
+  static __device__ __forceinline__ int addr(int f, int pos) { return pos * C + f; }
+};
+// columns per pass-1 workgroup: one 128-byte row segment
+template <class V> struct Cols { static constexpr int value = 128 / sizeof(V); };
+// Row layout (pass 2): F FFTs, element (f, pos) at f * (L + L/8) + pos + pos/8
+// (one pad slot every 8 elements keeps the radix-8/16 scatter conflict-free).
+template <int L>
+struct RowLayout {
+  static constexpr int NF = (ROW_ELEMS / L) > 0 ? (ROW_ELEMS / L) : 1;
+  static constexpr int LP = L + L / 8;
+  static constexpr int SIZE = NF * LP;
+  template <int R>
+  static __device__ __forceinline__ void split(int b, int& f, int& j) {
+    f = b / (L / R);
+    j = b % (L / R);
+  }
+  static __device__ __forceinline__ int addr(int f, int pos) { return f * LP + pos + (pos >> 3); }
+};
+
+// One LDS-to-LDS Stockham stage (radix R, Ns already-combined length).
+template <class Lay, int L, int R, int Ns, int S, class V>
+__device__ __forceinline__ void lds_stage(V* lds, const V* __restrict__ pyr, int tid) {
+  constexpr int NB = Lay::NF * L / R;
+  constexpr int PER = (NB + NT - 1) / NT;
+  V v[PER][R];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int b = tid + i * NT;
+    if (b < NB) {
+      int f, j;
+      Lay::template split<R>(b, f, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = lds[Lay::addr(f, j + r * (L / R))];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int b = tid + i * NT;
+    if (b < NB) {
+      int f, j;
+      Lay::template split<R>(b, f, j);
+      const int k = j % Ns;
+      apply_stage_tw<R, Ns, S>(v[i], k, pyr);
+      Dft<R, S>::run(v[i]);
+      const int idxD = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[Lay::addr(f, idxD + m * Ns)] = v[i][m];
+    }
+  }
+  __syncthreads();
+}
+
+// Reads the R inputs of the final stage's butterflies and applies the stage
+// twiddles and DFT; the caller stores.  Output m of butterfly j is position
+// j + m * (L / R).
+template <class Lay, int L, int R, int S, class V, class Store>
+__device__ __forceinline__ void final_stage(const V* lds, const V* __restrict__ pyr, int tid,
+                                            Store&& store) {
+  constexpr int Ns = L / R;
+  constexpr int NB = Lay::NF * L / R;
+  constexpr int PER = (NB + NT - 1) / NT;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int b = tid + i * NT;
+    if (b < NB) {
+      int f, j;
+      Lay::template split<R>(b, f, j);
+      V v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = lds[Lay::addr(f, j + r * (L / R))];
+      apply_stage_tw<R, Ns, S>(v, j, pyr);
+      Dft<R, S>::run(v);
+#pragma unroll
+      for (int m = 0; m < R; ++m) store(f, j + m * Ns, v[m], m);
+    }
+  }
+}
+
+__device__ __forceinline__ int resolve_vec(const PassArgs& a, int bv, bool& skip) {
+  skip = false;
+  if (a.d_count != nullptr && a.vec_base + bv >= *a.d_count) {
+    skip = true;
+    return 0;
+  }
+  return a.vec_list ? a.vec_list[a.vec_base + bv] : a.vec_base + bv;
+}
+
+// Pointers of the FP32 (batched) or FP64 (strain spectrum) variant.
+template <class V> struct PassPtr;
+template <> struct PassPtr<float2> {
+  static __device__ __forceinline__ const float2* pyr(const PassArgs& a) { return a.tw.pyr; }
+  static __device__ __forceinline__ const float2* tlo(const PassArgs& a) { return a.tw.tlo; }
+  static __device__ __forceinline__ const float2* thi(const PassArgs& a) { return a.tw.thi; }
+  static __device__ __forceinline__ float2* work(const PassArgs& a) { return a.work; }
+};
+template <> struct PassPtr<double2> {
+  static __device__ __forceinline__ const double2* pyr(const PassArgs& a) { return a.tw64.pyr; }
+  static __device__ __forceinline__ const double2* tlo(const PassArgs& a) { return a.tw64.tlo; }
+  static __device__ __forceinline__ const double2* thi(const PassArgs& a) { return a.tw64.thi; }
+  static __device__ __forceinline__ double2* work(const PassArgs& a) { return a.work64; }
+};
+
+// ------------------------------------------------------------------ pass 1
+template <class V, int L, int R1, int R2, int R3, int IN, int S>
+__global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
+  using T = typename Re<V>::T;
+  constexpr int C = Cols<V>::value;
+  using Lay = ColLayout<L, C>;
+  __shared__ V lds[Lay::SIZE];
+  const int tid = threadIdx.x;
+  bool skip;
+  const int v = resolve_vec(a, blockIdx.y, skip);
+  if (skip) return;
+  const int bv = blockIdx.y;
+  const int N1 = a.g.N1;
+  const int f1_0 = blockIdx.x * C;
+  const V* __restrict__ pyr = PassPtr<V>::pyr(a);
+
+  int lo = a.band_lo, hi = a.band_hi;
+  if (IN == IN_CORR && a.sup_lo != nullptr) {
+    lo = a.sup_lo[v];
+    hi = a.sup_hi[v];
+  }
+  // ---- stage 1: global -> registers -> LDS (Ns = 1, no twiddles)
+  {
+    constexpr int NB = C * L / R1;
+    constexpr int PER = (NB + NT - 1) / NT;
+    constexpr bool HALF = (IN == IN_CORR);   // one-sided input: rows >= L/2 are zero
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int b = tid + i * NT;
+      if (b < NB) {
+        const int c = b % C, j = b / C;
+        const int f1 = f1_0 + c;
+        V x[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+          x[r] = mk<V>(0, 0);
+          if (HALF && r >= R1 / 2) continue;
+          const int f2 = j + r * (L / R1);
+          const int64_t f = (int64_t)f1 + (int64_t)N1 * f2;
+          if (IN == IN_CORR) {
+            if (f >= lo && f <= hi) {
+              const float2 dv = a.d[f - a.kb];
+              const float2 pv = a.src[(int64_t)v * a.nbs + (f - a.kb)];
+              x[r] = mk<V>(dv.x * pv.x + dv.y * pv.y, dv.y * pv.x - dv.x * pv.y);
+            }
+          } else if (IN == IN_REAL) {
+            x[r] = mk<V>((T)a.real_in[f], 0);
+          } else {
+            const float2 in = a.src[(int64_t)v * a.g.N + f];
+            x[r] = mk<V>(in.x, in.y);
+          }
+        }
+        Dft<R1, S>::run(x);
+#pragma unroll
+        for (int m = 0; m < R1; ++m) lds[Lay::addr(c, j * R1 + m)] = x[m];
+      }
+    }
+  }
+  __syncthreads();
+  if (R3 > 1) lds_stage<Lay, L, R2, R1, S>(lds, pyr, tid);
+  constexpr int RL = (R3 > 1) ? R3 : R2;
+  // ---- final stage: LDS -> inter-pass twiddle -> global [n2][N1]
+  const int s_lo = a.g.s_lo;
+  const int mask = (1 << s_lo) - 1;
+  const V* __restrict__ thi = PassPtr<V>::thi(a);
+  const V* __restrict__ tlo = PassPtr<V>::tlo(a);
+  V* __restrict__ outv = PassPtr<V>::work(a) + (int64_t)bv * a.g.N;
+  final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int c, int n2, V val, int) {
+    const int f1 = f1_0 + c;
+    const int64_t e = (int64_t)f1 * n2;
+    const V w = cmul(thi[e >> s_lo], tlo[e & mask]);
+    outv[(int64_t)n2 * N1 + f1] = cmul(val, signed_tw<S>(w));
+  });
+}
+
+// ------------------------------------------------------------------ pass 2
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ uint16_t f32_to_f16_rne(float x) {
+  __half h = __float2half_rn(x);
+  return *reinterpret_cast<uint16_t*>(&h);
+}
+
+template <class V, int L, int R1, int R2, int R3, int OUT, int S>
+__global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
+  using Lay = RowLayout<L>;
+  constexpr int F = Lay::NF;
+  __shared__ V lds[Lay::SIZE];
+  const int tid = threadIdx.x;
+  bool skip;
+  const int v = resolve_vec(a, blockIdx.y, skip);
+  if (skip) return;
+  const int bv = blockIdx.y;
+  const int N2 = a.g.N2;
+  const int row0 = blockIdx.x * F;
+  const V* __restrict__ pyr = PassPtr<V>::pyr(a);
+  const V* __restrict__ inv = PassPtr<V>::work(a) + (int64_t)bv * a.g.N;
+  // ---- stage 1: global rows -> LDS
+  {
+    constexpr int NB = F * L / R1;
+    constexpr int PER = (NB + NT - 1) / NT;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int b = tid + i * NT;
+      if (b < NB) {
+        int f, j;
+        Lay::template split<R1>(b, f, j);
+        V x[R1];
+        const V* rowp = inv + (int64_t)(row0 + f) * L;
+#pragma unroll
+        for (int r = 0; r < R1; ++r) x[r] = rowp[j + r * (L / R1)];
+        Dft<R1, S>::run(x);
+#pragma unroll
+        for (int m = 0; m < R1; ++m) lds[Lay::addr(f, j * R1 + m)] = x[m];
+      }
+    }
+  }
+  __syncthreads();
+  if (R3 > 1) lds_stage<Lay, L, R2, R1, S>(lds, pyr, tid);
+  constexpr int RL = (R3 > 1) ? R3 : R2;
+  const int64_t N = a.g.N;
+
+  if constexpr (OUT == OUT_Z32) {
+    float* __restrict__ zr = a.zout + (int64_t)(2 * v) * N;
+    float* __restrict__ zi = zr + N;
+    final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int f, int n1, V val, int) {
+      const int64_t q = (int64_t)(row0 + f) * L + n1;
+      zr[q] = val.x;
+      zi[q] = val.y;
+    });
+  } else if constexpr (OUT == OUT_Z16) {
+    uint16_t* __restrict__ zr = reinterpret_cast<uint16_t*>(a.zout) + (int64_t)(2 * v) * N;
+    uint16_t* __restrict__ zi = zr + N;
+    const float sc = a.zscale;
+    const bool bf = (a.zdtype == 1);
+    final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int f, int n1, V val, int) {
+      const int64_t q = (int64_t)(row0 + f) * L + n1;
+      const float xr = val.x * sc, xi = val.y * sc;
+      zr[q] = bf ? f32_to_bf16_rne(xr) : f32_to_f16_rne(xr);
+      zi[q] = bf ? f32_to_bf16_rne(xi) : f32_to_f16_rne(xi);
+    });
+  } else if constexpr (OUT == OUT_THRESH) {
+    const float thr2 = a.thr2;
+    const int lane = __lane_id();
+    unsigned long long best = 0ull;   // packed (p bits << 32 | ~n)
+    final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int f, int n1, V val, int) {
+      const int n2 = row0 + f;
+      const int n = n2 + N2 * n1;
+      const float p = val.x * val.x + val.y * val.y;
+      const unsigned long long key =
+          ((unsigned long long)__float_as_uint(p) << 32) | (unsigned long long)(0xffffffffu - (uint32_t)n);
+      best = key > best ? key : best;
+      const bool hit = p >= thr2;
+      const unsigned long long mask = __ballot(hit);
+      if (mask) {
+        const int cnt = __popcll(mask);
+        const int leader = __ffsll((long long)mask) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) {
+          base = atomicAdd(a.trig_count, (unsigned long long)cnt);
+          atomicAdd(&a.tmpl_count[v], cnt);
+        }
+        base = __shfl(base, leader);
+        if (hit) {
+          const unsigned long long idx = base + __popcll(mask & ((1ull << lane) - 1ull));
+          if ((int64_t)idx < a.trig_cap) {
+            TrigRec t;
+            t.tmpl = v;
+            t.sample = n;
+            t.re = val.x;
+            t.im = val.y;
+            a.trig[idx] = t;
+          }
+        }
+      }
+    });
+    // wave-reduce the running maximum, one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(best, off);
+      best = o > best ? o : best;
+    }
+    if (lane == 0 && best != 0ull) atomicMax(&a.tmpl_max[v], best);
+  } else if constexpr (OUT == OUT_NATURAL) {
+    float2* __restrict__ o = a.cout + (int64_t)v * N;
+    final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int f, int n1, V val, int) {
+      const int64_t n = (int64_t)(row0 + f) + (int64_t)N2 * n1;
+      o[n] = make_float2(val.x, val.y);
+    });
+  } else if constexpr (OUT == OUT_TRANSPOSED) {
+    float2* __restrict__ o = a.cout + (int64_t)v * N;
+    final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int f, int n1, V val, int) {
+      o[(int64_t)(row0 + f) * L + n1] = make_float2(val.x, val.y);
+    });
+  } else {   // OUT_SPECTRUM: whitening in the pass's own precision, then FP32
+    final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int f, int n1, V val, int) {
+      const int64_t k = (int64_t)(row0 + f) + (int64_t)N2 * n1;
+      if (k >= a.k_lo && k <= a.k_hi) {
+        const double w = a.wd64[k - a.kb];
+        a.cout[k - a.kb] = make_float2((float)(val.x * w), (float)(val.y * w));
+      }
+    });
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+template <int L>
+struct Radices;
+template <> struct Radices<64> { static constexpr int r1 = 8, r2 = 8, r3 = 1; };
+template <> struct Radices<128> { static constexpr int r1 = 16, r2 = 8, r3 = 1; };
+template <> struct Radices<256> { static constexpr int r1 = 16, r2 = 16, r3 = 1; };
+template <> struct Radices<512> { static constexpr int r1 = 8, r2 = 8, r3 = 8; };
+template <> struct Radices<1024> { static constexpr int r1 = 16, r2 = 8, r3 = 8; };
+template <> struct Radices<2048> { static constexpr int r1 = 16, r2 = 16, r3 = 8; };
+
+template <class V, int L, int IN, int S>
+hipError_t go1(const PassArgs& a, hipStream_t st) {
+  using Rd = Radices<L>;
+  dim3 grid(a.g.N1 / Cols<V>::value, a.nvec);
+  hipLaunchKernelGGL((k_pass1<V, L, Rd::r1, Rd::r2, Rd::r3, IN, S>), grid, dim3(NT), 0, st, a);
+  return hipGetLastError();
+}
+template <class V, int L, int OUT, int S>
+hipError_t go2(const PassArgs& a, hipStream_t st) {
+  using Rd = Radices<L>;
+  dim3 grid(a.g.N2 / RowLayout<L>::NF, a.nvec);
+  hipLaunchKernelGGL((k_pass2<V, L, Rd::r1, Rd::r2, Rd::r3, OUT, S>), grid, dim3(NT), 0, st, a);
+  return hipGetLastError();
+}
+
+template <class V, int IN, int S>
+hipError_t disp1(const PassArgs& a, hipStream_t st) {
+  switch (a.g.N2) {   // N2 <= 1024 for N <= 2^21
+    case 64: return go1<V, 64, IN, S>(a, st);
+    case 128: return go1<V, 128, IN, S>(a, st);
+    case 256: return go1<V, 256, IN, S>(a, st);
+    case 512: return go1<V, 512, IN, S>(a, st);
+    case 1024: return go1<V, 1024, IN, S>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+template <class V, int OUT, int S>
+hipError_t disp2(const PassArgs& a, hipStream_t st) {
+  switch (a.g.N1) {
+    case 64: return go2<V, 64, OUT, S>(a, st);
+    case 128: return go2<V, 128, OUT, S>(a, st);
+    case 256: return go2<V, 256, OUT, S>(a, st);
+    case 512: return go2<V, 512, OUT, S>(a, st);
+    case 1024: return go2<V, 1024, OUT, S>(a, st);
+    case 2048: return go2<V, 2048, OUT, S>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+FftGeom make_geom(int64_t N) {
+  FftGeom g;
+  g.N = N;
+  int m = 0;
+  while ((int64_t(1) << m) < N) ++m;
+  g.log2N = m;
+  g.N2 = 1 << (m / 2);
+  g.N1 = 1 << (m - m / 2);
+  g.s_lo = (m + 1) / 2;
+  return g;
+}
+
+hipError_t launch_pass1(const PassArgs& a, InKind in, hipStream_t st) {
+  if (a.nvec <= 0) return hipSuccess;
+  if (in == IN_CORR) return a.sign > 0 ? disp1<float2, IN_CORR, 1>(a, st) : disp1<float2, IN_CORR, -1>(a, st);
+  if (in == IN_REAL) return disp1<double2, IN_REAL, -1>(a, st);     // strain spectrum: FP64
+  return a.sign > 0 ? disp1<float2, IN_DENSE, 1>(a, st) : disp1<float2, IN_DENSE, -1>(a, st);
+}
+
+hipError_t launch_pass2(const PassArgs& a, OutKind out, hipStream_t st) {
+  if (a.nvec <= 0) return hipSuccess;
+  switch (out) {
+    case OUT_Z32: return disp2<float2, OUT_Z32, 1>(a, st);
+    case OUT_Z16: return disp2<float2, OUT_Z16, 1>(a, st);
+    case OUT_THRESH: return disp2<float2, OUT_THRESH, 1>(a, st);
+    case OUT_NATURAL:
+      return a.sign > 0 ? disp2<float2, OUT_NATURAL, 1>(a, st) : disp2<float2, OUT_NATURAL, -1>(a, st);
+    case OUT_TRANSPOSED:
+      return a.sign > 0 ? disp2<float2, OUT_TRANSPOSED, 1>(a, st) : disp2<float2, OUT_TRANSPOSED, -1>(a, st);
+    case OUT_SPECTRUM: return disp2<double2, OUT_SPECTRUM, -1>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace rbmf

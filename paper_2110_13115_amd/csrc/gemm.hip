@@ -1,0 +1,269 @@
+// Reconstruction GEMM rho = C * Z on MFMA with a fused first-stage threshold
+// (Sec. II.A Eq. Beta_eqn: rho_j = sum_k c*_{jk} beta_k; Sec. III.C: first
+// stage over the whole bank).  rho is never written to memory.
+//
+// The complex product is realified: output row 2j is Re rho_j, row 2j+1 is
+// Im rho_j, reduction index 2k / 2k+1 runs over Re / Im of beta_k, with
+//   A[2j  ][2k] =  Re C_jk   A[2j  ][2k+1] = -Im C_jk
+//   A[2j+1][2k] =  Im C_jk   A[2j+1][2k+1] =  Re C_jk
+// so that Re rho and Im rho of one (template, sample) land in the same lane
+// of the 32x32 MFMA accumulator (rows 4g..4g+3 of a lane are consecutive).
+//
+// FP32 path: v_mfma_f32_32x32x2_f32, one complex k per instruction.
+// 16-bit path: v_mfma_f32_32x32x16_{bf16,f16}, eight complex k per
+// instruction, FP32 accumulation.
+#include "internal.h"
+
+namespace rbmf {
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int WAVES = 4;
+constexpr int WT_ROWB = 2;       // 32-row MFMA blocks per wave (= 32 templates)
+constexpr int WT_COLB = 2;       // 32-column MFMA blocks per wave (= 64 samples)
+constexpr int TILE_T = WAVES * WT_ROWB * 16;   // templates per workgroup (128)
+constexpr int TILE_N = WT_COLB * 32;           // samples per workgroup (64)
+
+__device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[WT_ROWB][WT_COLB],
+                                         int rb0, int64_t q0) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int rb = 0; rb < WT_ROWB; ++rb) {
+#pragma unroll
+    for (int cb = 0; cb < WT_COLB; ++cb) {
+      const int64_t q = q0 + cb * 32 + (lane & 31);
+      const int n = (int)(q / a.N1) + a.N2 * (int)(q % a.N1);
+#pragma unroll
+      for (int i = 0; i < 16; i += 2) {
+        const int m = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);   // even: Re row
+        const int j = (rb0 + rb) * 16 + (m >> 1);
+        const float re = acc[rb][cb][i], im = acc[rb][cb][i + 1];
+        const float p = re * re + im * im;
+        if (a.rho_out != nullptr && j < a.T) {
+          const float s = a.row_inv ? a.row_inv[j] : 1.f;
+          a.rho_out[(int64_t)j * a.N + n] = make_float2(re * s, im * s);
+        }
+        const bool hit = (j < a.T) && (p >= a.thr2_row[j]);
+        const unsigned long long mask = __ballot(hit);
+        if (mask) {
+          const int cnt = __popcll(mask);
+          const int leader = __ffsll((long long)mask) - 1;
+          unsigned long long base = 0;
+          if (lane == leader) base = atomicAdd(a.trig_count, (unsigned long long)cnt);
+          base = __shfl(base, leader);
+          if (hit) {
+            atomicAdd(&a.tmpl_count[j], 1);
+            const unsigned long long idx = base + __popcll(mask & ((1ull << lane) - 1ull));
+            if ((int64_t)idx < a.trig_cap) {
+              TrigRec t;
+              t.tmpl = j;
+              t.sample = n;
+              t.re = re;
+              t.im = im;
+              a.trig[idx] = t;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// Maps a linear workgroup id to (template tile, sample tile) so that the
+// template tiles sharing one sample tile run on the same XCD (workgroups are
+// dispatched round-robin over the 8 XCDs): Z is then fetched into each L2 once.
+__device__ __forceinline__ bool xcd_tile(int ntt, int64_t nwg, int& tt, int64_t& st) {
+  const int64_t per = (nwg + 7) / 8;
+  const int64_t bid = blockIdx.x;
+  const int64_t L = (bid % 8) * per + bid / 8;
+  if (L >= nwg) return false;
+  tt = (int)(L % ntt);
+  st = L / ntt;
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
+  const int ntt = a.Tp / TILE_T;
+  const int64_t nwg = (int64_t)ntt * (a.N / TILE_N);
+  int tt;
+  int64_t st;
+  if (!xcd_tile(ntt, nwg, tt, st)) return;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int rb0 = tt * (TILE_T / 16) + wave * WT_ROWB;     // first 16-template row block
+  const int64_t q0 = st * TILE_N;
+  const float* __restrict__ cpk = static_cast<const float*>(a.cpk);
+  const float* __restrict__ z = static_cast<const float*>(a.z);
+  const int K = a.K;
+  const int64_t N = a.N;
+  // lane's operand addresses
+  const float* ap[WT_ROWB];
+#pragma unroll
+  for (int rb = 0; rb < WT_ROWB; ++rb) ap[rb] = cpk + ((int64_t)(rb0 + rb) * K) * 64 + lane;
+  const float* bp = z + (int64_t)(lane >> 5) * N + q0 + (lane & 31);
+
+  f32x16 acc[WT_ROWB][WT_COLB];
+#pragma unroll
+  for (int rb = 0; rb < WT_ROWB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < WT_COLB; ++cb) acc[rb][cb] = (f32x16){};
+
+#pragma unroll 4
+  for (int k = 0; k < K; ++k) {
+    float av[WT_ROWB], bv[WT_COLB];
+#pragma unroll
+    for (int rb = 0; rb < WT_ROWB; ++rb) av[rb] = ap[rb][(int64_t)k * 64];
+#pragma unroll
+    for (int cb = 0; cb < WT_COLB; ++cb) bv[cb] = bp[(int64_t)(2 * k) * N + cb * 32];
+#pragma unroll
+    for (int rb = 0; rb < WT_ROWB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < WT_COLB; ++cb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
+  }
+  epilogue(a, acc, rb0, q0);
+}
+
+// 16-bit operands: one instruction reduces over 16 realified entries = 8
+// complex k.  A lane l holds entries [8 (l/32), 8 (l/32) + 8) of row l%32
+// (4 complex k, Re/Im interleaved); B lane l holds the same 8 reduction rows
+// of column l%32.  C is pre-packed so each lane loads 16 contiguous bytes; Z is planar
+// (row 2k = Re, 2k+1 = Im) and gathered into the interleaved order here.
+template <int DT>
+__global__ __launch_bounds__(256) void k_recon_16(GemmArgs a) {
+  const int ntt = a.Tp / TILE_T;
+  const int64_t nwg = (int64_t)ntt * (a.N / TILE_N);
+  int tt;
+  int64_t st;
+  if (!xcd_tile(ntt, nwg, tt, st)) return;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int rb0 = tt * (TILE_T / 16) + wave * WT_ROWB;
+  const int64_t q0 = st * TILE_N;
+  const u16x8* __restrict__ cpk = static_cast<const u16x8*>(a.cpk);
+  const uint16_t* __restrict__ z = static_cast<const uint16_t*>(a.z);
+  const int KB = a.Kp / 8;        // k-steps of 8 complex values (16 reduction rows)
+  const int64_t N = a.N;
+  f32x16 acc[WT_ROWB][WT_COLB];
+#pragma unroll
+  for (int rb = 0; rb < WT_ROWB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < WT_COLB; ++cb) acc[rb][cb] = (f32x16){};
+#pragma unroll 2
+  for (int kb = 0; kb < KB; ++kb) {
+    u16x8 av[WT_ROWB], bv[WT_COLB];
+#pragma unroll
+    for (int rb = 0; rb < WT_ROWB; ++rb) av[rb] = cpk[((int64_t)(rb0 + rb) * KB + kb) * 64 + lane];
+#pragma unroll
+    for (int cb = 0; cb < WT_COLB; ++cb) {
+      const int64_t col = q0 + cb * 32 + (lane & 31);
+      const int64_t row = 16 * kb + 8 * (lane >> 5);   // planar rows 2k+t of complex k = 8kb + 4h + ..
+      u16x8 b;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) b[e] = z[(row + e) * N + col];
+      bv[cb] = b;
+    }
+#pragma unroll
+    for (int rb = 0; rb < WT_ROWB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < WT_COLB; ++cb) {
+        if (DT == 1)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              __builtin_bit_cast(bf16x8, av[rb]), __builtin_bit_cast(bf16x8, bv[cb]), acc[rb][cb], 0, 0, 0);
+        else
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+              __builtin_bit_cast(f16x8, av[rb]), __builtin_bit_cast(f16x8, bv[cb]), acc[rb][cb], 0, 0, 0);
+      }
+  }
+  epilogue(a, acc, rb0, q0);
+}
+
+// ------------------------------------------------------------------ packing
+__device__ __forceinline__ uint16_t to16(float x, int dtype) {
+  if (dtype == 1) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+  }
+  _Float16 h = (_Float16)x;
+  return __builtin_bit_cast(uint16_t, h);
+}
+
+// Realified A entry for lane-row r (0..31) within a 16-template block and
+// reduction index t (0 = Re beta_k, 1 = Im beta_k).
+__device__ __forceinline__ float a_entry(const float2* C, int T, int K, int rb, int r, int k,
+                                         int t, const float* row_scale) {
+  const int j = rb * 16 + (r >> 1);
+  if (j >= T || k >= K) return 0.f;
+  float2 c = C[(int64_t)j * K + k];
+  if (row_scale) {
+    c.x *= row_scale[j];
+    c.y *= row_scale[j];
+  }
+  const int part = r & 1;
+  if (part == 0) return t == 0 ? c.x : -c.y;
+  return t == 0 ? c.y : c.x;
+}
+
+__global__ void k_pack_f32(const float2* C, int T, int Tp, int K, float* out) {
+  const int64_t total = (int64_t)(Tp / 16) * K * 64;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(i & 63);
+    const int64_t rk = i >> 6;
+    const int k = (int)(rk % K);
+    const int rb = (int)(rk / K);
+    out[i] = a_entry(C, T, K, rb, l & 31, k, l >> 5, nullptr);
+  }
+}
+
+__global__ void k_pack_16(const float2* C, int T, int Tp, int K, int Kp, int dtype,
+                          const float* row_scale, uint16_t* out) {
+  const int KB = Kp / 8;
+  const int64_t total = (int64_t)(Tp / 16) * KB * 64 * 8;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(i & 7);
+    const int l = (int)((i >> 3) & 63);
+    const int64_t rkb = i >> 9;
+    const int kb = (int)(rkb % KB);
+    const int rb = (int)(rkb / KB);
+    const int red = 8 * (l >> 5) + e;          // reduction index within the 16-step
+    const int k = kb * 8 + (red >> 1);
+    out[i] = to16(a_entry(C, T, K, rb, l & 31, k, red & 1, row_scale), dtype);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
+  if (a.Tp % TILE_T != 0 || a.N % TILE_N != 0) return hipErrorInvalidValue;
+  const int64_t nwg = (int64_t)(a.Tp / TILE_T) * (a.N / TILE_N);
+  const int64_t launch = ((nwg + 7) / 8) * 8;
+  if (a.dtype == 0)
+    hipLaunchKernelGGL(k_recon_f32, dim3((unsigned)launch), dim3(256), 0, st, a);
+  else if (a.dtype == 1)
+    hipLaunchKernelGGL(k_recon_16<1>, dim3((unsigned)launch), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_recon_16<2>, dim3((unsigned)launch), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_c(const float2* C, int T, int Tp, int K, int Kp, int dtype,
+                         const float* row_scale, void* cpk, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_pack_f32, dim3(1024), dim3(256), 0, st, C, T, Tp, K, static_cast<float*>(cpk));
+  else
+    hipLaunchKernelGGL(k_pack_16, dim3(1024), dim3(256), 0, st, C, T, Tp, K, Kp, dtype, row_scale,
+                       static_cast<uint16_t*>(cpk));
+  return hipGetLastError();
+}
+
+int gemm_tile_templates() { return TILE_T; }
+
+}  // namespace rbmf

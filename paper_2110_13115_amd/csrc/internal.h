@@ -1,0 +1,195 @@
+// Internal interfaces between the C-ABI host layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace rbmf {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+#define RB_HIP(call)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      ::rbmf::set_error(std::string(#call " failed: ") + hipGetErrorString(e_));        \
+      return RB_ERR_DEVICE;                                                             \
+    }                                                                                   \
+  } while (0)
+
+// ---------------------------------------------------------------- FFT plan
+// N = N1 * N2.  Pass 1: N2-point FFTs down the N1 columns of the [N2][N1]
+// array (input index f = f1 + N1 f2), twiddle w_N^{f1 n2}, stored at
+// n2 * N1 + f1.  Pass 2: N1-point FFTs along each row; the output at position
+// q = n2 * N1 + n1 is time (or frequency) index n = n2 + N2 n1.
+struct FftGeom {
+  int64_t N;
+  int log2N;
+  int N1, N2;      // row length, column length
+  int s_lo;        // split of the inter-pass twiddle exponent: lo table 2^s_lo entries
+};
+
+struct FftTables {   // device pointers, FP32 values from FP64 host math
+  const float2* pyr;   // pyr[L + i] = e^{+2 pi i i / L}, L = 2..2048
+  const float2* tlo;   // e^{+2 pi i e / N}, e < 2^s_lo
+  const float2* thi;   // e^{+2 pi i (e << s_lo) / N}, e < N >> s_lo
+};
+
+struct FftTables64 {
+  const double2* pyr;
+  const double2* tlo;
+  const double2* thi;
+};
+
+FftGeom make_geom(int64_t N);
+
+// Pass-1 input variants.
+enum InKind { IN_CORR = 0, IN_REAL = 1, IN_DENSE = 2 };
+// Pass-2 output variants.
+enum OutKind {
+  OUT_Z32 = 0,       // planar FP32 Z: row 2v = Re, row 2v+1 = Im, row stride N
+  OUT_Z16 = 1,       // planar 16-bit Z (bf16 or f16), same layout, values * zscale
+  OUT_THRESH = 2,    // |x|^2 >= thr2: append trigger, per-vector count and max
+  OUT_NATURAL = 3,   // complex64 natural order out[v][n]
+  OUT_SPECTRUM = 4,  // forward transform of the strain: d[k - kb] = wd[k] X[k], band only
+  OUT_TRANSPOSED = 5 // complex64 in the pass order out[v][q] (adjoint)
+};
+
+struct TrigRec {     // device trigger record before sorting
+  int32_t tmpl;
+  int32_t sample;
+  float re;
+  float im;
+};
+
+struct PassArgs {
+  FftGeom g;
+  FftTables tw;
+  FftTables64 tw64;          // FP64 tables (strain spectrum)
+  double2* work64;           // FP64 intermediate (strain spectrum)
+  const double* wd64;        // OUT_SPECTRUM: dt * sqrt(4 df / Sn[k]) from kb, FP64
+  int sign;                  // +1 inverse (e^{+}), -1 forward
+  int nvec;                  // vectors in this launch
+  int vec_base;              // first vector (or first list entry)
+  const int32_t* vec_list;   // optional gather list (device)
+  const int32_t* d_count;    // optional device count: entries >= *d_count are skipped
+  // pass-1 inputs
+  const float2* d;           // IN_CORR: whitened data, band-packed from kb
+  const float2* src;         // IN_CORR: vectors (stride nbs) / IN_DENSE: vectors (stride N)
+  const float* real_in;      // IN_REAL
+  int64_t kb;                // first stored bin
+  int64_t nbs;               // stored bins per vector
+  const int32_t* sup_lo;     // IN_CORR: per-vector first non-zero bin (absolute)
+  const int32_t* sup_hi;     // IN_CORR: per-vector last non-zero bin
+  int32_t band_lo, band_hi;  // IN_CORR when sup_* are NULL
+  // intermediate [nvec][N] complex64
+  float2* work;
+  // pass-2 outputs
+  float* zout;               // OUT_Z32 / OUT_Z16 (as raw bytes for 16-bit)
+  int zdtype;                // 0 f32, 1 bf16, 2 f16
+  float zscale;
+  float thr2;                // OUT_THRESH: squared threshold
+  TrigRec* trig;             // OUT_THRESH
+  int64_t trig_cap;
+  unsigned long long* trig_count;
+  int32_t* tmpl_count;       // per template crossing counts
+  unsigned long long* tmpl_max;  // per template packed (|x|^2 bits << 32 | ~n)
+  float2* cout;              // OUT_NATURAL / OUT_SPECTRUM / OUT_TRANSPOSED
+  int32_t k_lo;              // OUT_SPECTRUM band
+  int32_t k_hi;
+};
+
+// Launch pass 1 / pass 2 on `stream`.  Return hipSuccess or the launch error.
+hipError_t launch_pass1(const PassArgs& a, InKind in, hipStream_t stream);
+hipError_t launch_pass2(const PassArgs& a, OutKind out, hipStream_t stream);
+
+// ---------------------------------------------------------------- GEMM
+struct GemmArgs {
+  int64_t N;
+  int T, Tp;                 // templates, padded to the row tile
+  int K, Kp;                 // basis rank, padded
+  int dtype;                 // 0 f32, 1 bf16, 2 f16
+  const void* cpk;           // packed realified coefficients
+  const void* z;             // planar Z [2Kp][N]
+  const float* thr2_row;     // per-template squared threshold (16-bit scales folded in)
+  int N1, N2;                // position q -> n = q / N1 + N2 * (q % N1)
+  TrigRec* trig;
+  int64_t trig_cap;
+  unsigned long long* trig_count;
+  int32_t* tmpl_count;
+  float2* rho_out;           // debug: natural order T x N, or NULL
+  const float* row_inv;      // per-template 1/scale applied to rho_out (16-bit), or NULL
+};
+hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t stream);
+// Packs C (T x K complex, FP32 interleaved, device) into the kernel's layout.
+hipError_t launch_pack_c(const float2* C, int T, int Tp, int K, int Kp, int dtype,
+                         const float* row_scale, void* cpk, hipStream_t stream);
+
+// ---------------------------------------------------------------- triggers
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+// summary (device, 3 x int64): total, number of listed templates, max count
+hipError_t launch_scan_counts(const int32_t* counts, int T, int32_t* offsets, int32_t* fill,
+                              int32_t* list, int64_t* summary, hipStream_t s);
+hipError_t launch_scatter_triggers(const TrigRec* in, int64_t n, const int32_t* offsets,
+                                   int32_t* fill, TrigRec* out, hipStream_t s);
+hipError_t launch_segment_sort(TrigRec* recs, TrigRec* tmp, const int32_t* offsets,
+                               const int32_t* counts, const int32_t* list, int nlist, void* out,
+                               hipStream_t s);
+hipError_t launch_peaks_from_max(const unsigned long long* tmax, int T, void* out_peaks,
+                                 hipStream_t s);
+hipError_t launch_cluster_peaks(const void* trig, int64_t n, int W, int64_t N, uint8_t* is_peak,
+                                hipStream_t s);
+hipError_t launch_sparse_exact(const TrigRec* cand, int64_t ncand, const int32_t* offsets,
+                               const int32_t* counts, const int32_t* list, const int32_t* nlist,
+                               int T, const float2* d, const float2* tmpl, int64_t kb, int64_t nbs,
+                               const int32_t* sup_lo, const int32_t* sup_hi, int64_t N,
+                               float thr2, TrigRec* out, int64_t cap,
+                               unsigned long long* out_count, int32_t* tmpl_count,
+                               unsigned long long* tmpl_max, hipStream_t s);
+
+// ---------------------------------------------------------------- FP64 complex GEMM
+// C[m][n] (+)= sum_k opA(A)[m][k] * opB(B)[k][n], complex128 accumulation.
+// Operands are complex64 or complex128 with arbitrary row/col strides (in
+// elements) and an optional conjugation.  `workspace` (workspace_elems
+// complex128) holds split-reduction partials; it may be NULL (no split).
+struct ZOperand {
+  const void* p;
+  int is_c64;        // 1: complex64 elements, 0: complex128
+  int64_t rs, cs;    // strides of (row, col) of the *logical* operand
+  int conj;
+};
+hipError_t launch_zgemm(int64_t M, int64_t Nn, int64_t Kd, ZOperand A, ZOperand B, double2* C,
+                        int64_t ldc, int accumulate, double2* workspace, int64_t workspace_elems,
+                        hipStream_t s);
+hipError_t launch_c128_to_c64_rows(const double2* in, int64_t rows, int64_t cols, int64_t ld_in,
+                                   const double* row_scale, int conj, float2* out, int64_t ld_out,
+                                   hipStream_t s);
+hipError_t launch_basis_rows(const double2* BS, int64_t nb, int K, int64_t ld, const double* scale,
+                             int64_t off, int64_t nbs, float2* out, hipStream_t s);
+hipError_t launch_row_norms(const float2* w, int64_t rows, int64_t len, int64_t ld, double* out,
+                            hipStream_t s);
+
+// ---------------------------------------------------------------- misc
+hipError_t launch_check_finite(const float* x, int64_t n, int64_t* flag, hipStream_t s);
+hipError_t launch_z_to_natural(const void* z, int dtype, float inv_scale, int64_t N, int K, int N1,
+                               int N2, float2* out, hipStream_t s);
+
+// ---------------------------------------------------------------- adjoint
+hipError_t launch_rho_at(const float* z, int64_t N, int K, int N1, int N2, const float2* C,
+                         const int32_t* tmpl, const int32_t* samp, int64_t n, float2* rho,
+                         hipStream_t s);
+hipError_t launch_grad_c(const float* z, int64_t N, int K, int N1, int N2, const int32_t* order,
+                         const int32_t* seg_off, int nseg, const int32_t* tmpl,
+                         const int32_t* samp, const float2* rho, const float* g, float2* gC,
+                         hipStream_t s);
+hipError_t launch_scatter_a(int K, int64_t N, const int32_t* order, const int32_t* seg_off, int nseg,
+                            const int32_t* tmpl, const int32_t* samp, const float2* rho,
+                            const float* g, const float2* C, float2* A, hipStream_t s);
+hipError_t launch_bsum(const float2* Ahat, const float2* P, const double* wd, int K, int64_t N,
+                       int64_t kb, int64_t nbs, int64_t k_lo, int64_t k_hi, float2* B,
+                       hipStream_t s);
+hipError_t launch_real2(const float2* x, int64_t N, float* out, hipStream_t s);
+
+}  // namespace rbmf

@@ -1,0 +1,173 @@
+// Host FP64 dense linear algebra for the basis construction: eigen-
+// decomposition of small complex Hermitian matrices (the Rayleigh-Ritz and
+// orthonormalisation problems of size L x L, L ~ rank + oversampling).
+//
+// Method: unitary Householder reduction to Hermitian tridiagonal form, a
+// diagonal phase scaling that makes the tridiagonal real, the implicit QL
+// iteration with Wilkinson-type shifts on the real tridiagonal (accumulating
+// the plane rotations), and back-transformation of the eigenvectors.
+#include "linalg.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace rbmf {
+
+using cd = std::complex<double>;
+
+namespace {
+
+// Implicit QL on a real symmetric tridiagonal (d: diagonal, e[i] = T[i+1][i],
+// e[n-1] unused).  Z (n x n, column-major: Z[i + n*j]) accumulates rotations.
+bool tql_implicit(int n, std::vector<double>& d, std::vector<double>& e, std::vector<double>& Z) {
+  if (n == 1) return true;
+  e[n - 1] = 0.0;
+  const double eps = std::numeric_limits<double>::epsilon();
+  for (int l = 0; l < n; ++l) {
+    int iter = 0;
+    int m;
+    do {
+      for (m = l; m < n - 1; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= eps * dd) break;
+      }
+      if (m != l) {
+        if (++iter > 100) return false;
+        double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+        double r = std::hypot(g, 1.0);
+        g = d[m] - d[l] + e[l] / (g + (g >= 0 ? std::fabs(r) : -std::fabs(r)));
+        double s = 1.0, c = 1.0, p = 0.0;
+        int i;
+        bool deflated = false;
+        for (i = m - 1; i >= l; --i) {
+          double f = s * e[i];
+          const double b = c * e[i];
+          r = std::hypot(f, g);
+          e[i + 1] = r;
+          if (r == 0.0) {
+            d[i + 1] -= p;
+            e[m] = 0.0;
+            deflated = true;
+            break;
+          }
+          s = f / r;
+          c = g / r;
+          g = d[i + 1] - p;
+          r = (d[i] - g) * s + 2.0 * c * b;
+          p = s * r;
+          d[i + 1] = g + p;
+          g = c * r - b;
+          double* zi = &Z[(size_t)n * i];
+          double* zi1 = &Z[(size_t)n * (i + 1)];
+          for (int k = 0; k < n; ++k) {
+            f = zi1[k];
+            zi1[k] = s * zi[k] + c * f;
+            zi[k] = c * zi[k] - s * f;
+          }
+        }
+        if (deflated) continue;
+        d[l] -= p;
+        e[l] = g;
+        e[m] = 0.0;
+      }
+    } while (m != l);
+  }
+  return true;
+}
+
+}  // namespace
+
+bool herm_eig_desc(int n, const std::vector<cd>& Ain, std::vector<double>& w, std::vector<cd>& V) {
+  // A row-major n x n Hermitian (only the lower triangle is read).
+  std::vector<cd> A(Ain);
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) A[(size_t)i * n + j] = std::conj(A[(size_t)j * n + i]);
+  for (int i = 0; i < n; ++i) A[(size_t)i * n + i] = cd(A[(size_t)i * n + i].real(), 0.0);
+
+  std::vector<double> d(n), e(n, 0.0);
+  std::vector<cd> sub(n, cd(0.0, 0.0));
+  std::vector<std::vector<cd>> refl;   // Householder vectors v_k (length n-k-1), H = I - 2 v v^H
+  refl.reserve(n > 2 ? n - 2 : 0);
+  std::vector<cd> p(n), wv(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    // x = A[k+1:, k]
+    double xn2 = 0.0;
+    for (int i = 0; i < m; ++i) xn2 += std::norm(A[(size_t)(k + 1 + i) * n + k]);
+    const double xn = std::sqrt(xn2);
+    std::vector<cd> v(m, cd(0.0, 0.0));
+    if (xn == 0.0) {
+      refl.push_back(v);
+      sub[k] = cd(0.0, 0.0);
+      continue;
+    }
+    const cd x0 = A[(size_t)(k + 1) * n + k];
+    const cd ph = (std::abs(x0) > 0.0) ? x0 / std::abs(x0) : cd(1.0, 0.0);
+    const cd alpha = -ph * xn;
+    for (int i = 0; i < m; ++i) v[i] = A[(size_t)(k + 1 + i) * n + k];
+    v[0] -= alpha;
+    double vn2 = 0.0;
+    for (int i = 0; i < m; ++i) vn2 += std::norm(v[i]);
+    const double vn = std::sqrt(vn2);
+    for (int i = 0; i < m; ++i) v[i] /= vn;
+    // p = A22 v ; Kv = v^H p ; w = p - Kv v ; A22 -= 2 (v w^H + w v^H)
+    for (int i = 0; i < m; ++i) {
+      cd s(0.0, 0.0);
+      const cd* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
+      for (int j = 0; j < m; ++j) s += row[j] * v[j];
+      p[i] = s;
+    }
+    cd Kv(0.0, 0.0);
+    for (int i = 0; i < m; ++i) Kv += std::conj(v[i]) * p[i];
+    const double kr = Kv.real();
+    for (int i = 0; i < m; ++i) wv[i] = p[i] - kr * v[i];
+    for (int i = 0; i < m; ++i) {
+      cd* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
+      for (int j = 0; j < m; ++j) row[j] -= 2.0 * (v[i] * std::conj(wv[j]) + wv[i] * std::conj(v[j]));
+    }
+    sub[k] = alpha;
+    for (int i = 0; i < m; ++i) {
+      A[(size_t)(k + 1 + i) * n + k] = (i == 0) ? alpha : cd(0.0, 0.0);
+      A[(size_t)k * n + (k + 1 + i)] = (i == 0) ? std::conj(alpha) : cd(0.0, 0.0);
+    }
+    refl.push_back(v);
+  }
+  for (int k = 0; k < n; ++k) d[k] = A[(size_t)k * n + k].real();
+  if (n >= 2) sub[n - 2] = A[(size_t)(n - 1) * n + (n - 2)];
+  // phase scaling: T = D T' D^H with T' real
+  std::vector<cd> delta(n, cd(1.0, 0.0));
+  for (int k = 0; k + 1 < n; ++k) {
+    const double a = std::abs(sub[k]);
+    e[k] = a;
+    delta[k + 1] = (a > 0.0) ? delta[k] * (sub[k] / a) : delta[k];
+  }
+  std::vector<double> Z((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Z[(size_t)n * i + i] = 1.0;
+  if (!tql_implicit(n, d, e, Z)) return false;
+  // order descending
+  std::vector<int> ord(n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] > d[b]; });
+  w.resize(n);
+  V.assign((size_t)n * n, cd(0.0, 0.0));   // row-major, column j = eigenvector j
+  for (int jj = 0; jj < n; ++jj) {
+    const int j = ord[jj];
+    w[jj] = d[j];
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + jj] = delta[i] * Z[(size_t)n * j + i];
+  }
+  // back-transform: U = H_0 H_1 ... H_{n-3} Y
+  for (int k = (int)refl.size() - 1; k >= 0; --k) {
+    const std::vector<cd>& v = refl[k];
+    const int m = (int)v.size();
+    for (int col = 0; col < n; ++col) {
+      cd s(0.0, 0.0);
+      for (int i = 0; i < m; ++i) s += std::conj(v[i]) * V[(size_t)(k + 1 + i) * n + col];
+      s *= 2.0;
+      for (int i = 0; i < m; ++i) V[(size_t)(k + 1 + i) * n + col] -= v[i] * s;
+    }
+  }
+  return true;
+}
+
+}  // namespace rbmf

@@ -30,6 +30,8 @@ Seeds: ``numpy.random.default_rng([13115, cfg, purpose])`` with purpose
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence, Tuple
 
@@ -127,6 +129,68 @@ def taylorf2(f: np.ndarray, m1: float, m2: float, order: int = 7,
     return out
 
 
+class _FreqPowers:
+    """Frequency-only factors of the TaylorF2 expression, shared by a chunk."""
+
+    def __init__(self, f: np.ndarray):
+        self.f = f
+        pos = f > 0
+        self.pos = pos
+        self.amp = np.zeros_like(f)
+        self.amp[pos] = f[pos] ** (-7.0 / 6.0)
+        self.f13 = np.zeros_like(f)
+        self.f13[pos] = np.cbrt(f[pos])
+        self.logf = np.zeros_like(f)
+        self.logf[pos] = np.log(f[pos])
+
+
+def _taylorf2_pre(pre: _FreqPowers, m1: float, m2: float, order: int, f_low: float) -> np.ndarray:
+    """taylorf2() on a precomputed grid (same expression, shared powers of f)."""
+    f = pre.f
+    out = np.zeros(f.shape, dtype=np.complex128)
+    lo = np.searchsorted(f, max(f_low, 0.0), side="left")
+    hi = np.searchsorted(f, f_isco(m1, m2), side="right")
+    lo = max(lo, int(np.argmax(pre.pos)) if pre.pos.any() else f.shape[0])
+    if hi <= lo:
+        return out
+    sl = slice(lo, hi)
+    M = (m1 + m2) * MSUN_S
+    eta = m1 * m2 / (m1 + m2) ** 2
+    cM = np.cbrt(np.pi * M)
+    v = cM * pre.f13[sl]
+    series = _pn_phase_series_pre(v, np.log(cM) + pre.logf[sl] / 3.0, eta, order)
+    v2 = v * v
+    v5 = v2 * v2 * v
+    psi = -np.pi / 4.0 + 3.0 / (128.0 * eta) * series / v5
+    out[sl] = pre.amp[sl] * (np.cos(psi) - 1j * np.sin(psi))
+    return out
+
+
+def _pn_phase_series_pre(v: np.ndarray, logv: np.ndarray, eta: float, order: int) -> np.ndarray:
+    pi = np.pi
+    out = np.ones_like(v)
+    if order < 2:
+        return out
+    v2 = v * v
+    out += 20.0 / 9.0 * (743.0 / 336.0 + 11.0 / 4.0 * eta) * v2
+    if order >= 3:
+        out += -16.0 * pi * v2 * v
+    if order >= 4:
+        out += 10.0 * (3058673.0 / 1016064.0 + 5429.0 / 1008.0 * eta + 617.0 / 144.0 * eta ** 2) * v2 * v2
+    if order >= 5:
+        lvlso = np.log(1.0 / np.sqrt(6.0))
+        out += pi * (38645.0 / 756.0 - 65.0 / 9.0 * eta) * (1.0 + 3.0 * (logv - lvlso)) * v2 * v2 * v
+    if order >= 6:
+        c6 = (11583231236531.0 / 4694215680.0 - 640.0 / 3.0 * pi ** 2 - 6848.0 / 21.0 * EULER_GAMMA
+              + eta * (-15737765635.0 / 3048192.0 + 2255.0 / 12.0 * pi ** 2)
+              + 76055.0 / 1728.0 * eta ** 2 - 127825.0 / 1296.0 * eta ** 3)
+        out += (c6 - 6848.0 / 21.0 * (np.log(4.0) + logv)) * v2 * v2 * v2
+    if order >= 7:
+        out += pi * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta
+                     - 74045.0 / 756.0 * eta ** 2) * v2 * v2 * v2 * v
+    return out
+
+
 def taylorf2_0pn_closed_form(f: np.ndarray, m1: float, m2: float, f_low: float = 0.0,
                              tc: float = 0.0) -> np.ndarray:
     """The 0PN SPA template written with the chirp mass, as a check of the
@@ -165,9 +229,20 @@ class Bank:
     def fill(self, t0: int, t1: int, k0: int, k1: int) -> np.ndarray:
         """Templates [t0, t1) on bins [k0, k1): complex128 (t1-t0, k1-k0)."""
         f = np.arange(k0, k1, dtype=np.float64) * self.df
-        out = np.empty((t1 - t0, k1 - k0), dtype=np.complex128)
-        for i, t in enumerate(range(t0, t1)):
-            out[i] = taylorf2(f, float(self.m1[t]), float(self.m2[t]), self.order, self.f_low)
+        out = np.zeros((t1 - t0, k1 - k0), dtype=np.complex128)
+        pre = _FreqPowers(f)
+
+        def one(i):
+            t = t0 + i
+            out[i] = _taylorf2_pre(pre, float(self.m1[t]), float(self.m2[t]), self.order, self.f_low)
+
+        n = t1 - t0
+        if n >= 8:
+            with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+                list(ex.map(one, range(n)))
+        else:
+            for i in range(n):
+                one(i)
         return out
 
     def full(self) -> np.ndarray:

@@ -1,0 +1,311 @@
+"""Thin ctypes binding of the C ABI in include/rbmf.h (argument marshalling
+only: every step of the search runs in the HIP library).
+
+Arrays may be numpy arrays (host) or torch tensors (host or device); device
+tensors are passed by pointer and stay on the GPU.  The library fails loudly
+if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Callable, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbmf.so")
+
+RB_OK, RB_ERR_ARG, RB_ERR_OOM, RB_ERR_DEVICE, RB_ERR_CAPACITY, RB_ERR_NUMERIC, RB_ERR_UNSUPPORTED, \
+    RB_ERR_CALLBACK = range(8)
+RB_F32, RB_BF16, RB_F16 = 0, 1, 2
+RB_STAGE2_FULL, RB_STAGE2_SPARSE = 0, 1
+DTYPES = {"f32": RB_F32, "bf16": RB_BF16, "f16": RB_F16}
+
+FUNCTIONS = ["rb_ctx_create", "rb_ctx_destroy", "rb_last_error", "rb_bank_create", "rb_bank_free",
+             "rb_bank_info", "rb_build_basis", "rb_basis_free", "rb_basis_export", "rb_filter",
+             "mf_full", "rb_rho_at", "rb_backward", "rb_cluster_peaks", "rb_debug_rho",
+             "rb_debug_basis_outputs"]
+
+
+class Grid(C.Structure):
+    _fields_ = [("N", C.c_int64), ("fs", C.c_double), ("f_low", C.c_double)]
+
+
+class Trigger(C.Structure):
+    _fields_ = [("tmpl", C.c_int32), ("sample", C.c_int32), ("snr", C.c_float), ("phase", C.c_float)]
+
+
+class Peak(C.Structure):
+    _fields_ = [("snr", C.c_float), ("sample", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_stage1", C.c_int64), ("n_refiltered", C.c_int32), ("rank", C.c_int32),
+                ("ms", C.c_float * 8)]
+
+
+class FilterOpts(C.Structure):
+    _fields_ = [("thr1", C.c_double), ("thr2", C.c_double), ("stage2", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+TRIGGER_NP = np.dtype([("tmpl", np.int32), ("sample", np.int32), ("snr", np.float32),
+                       ("phase", np.float32)])
+PEAK_NP = np.dtype([("snr", np.float32), ("sample", np.int32)])
+
+FILL_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int64,
+                      C.POINTER(C.c_double))
+
+_lib = None
+
+
+class RbError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is missing: run __graft_entry__.build() "
+                               "(or python -m paper_2110_13115_amd.build) first")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.rb_ctx_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+        L.rb_ctx_destroy.argtypes = [vp]
+        L.rb_last_error.restype = C.c_char_p
+        L.rb_bank_create.argtypes = [vp, C.POINTER(Grid), vp, i32, FILL_FN, vp, C.POINTER(vp)]
+        L.rb_bank_free.argtypes = [vp]
+        L.rb_bank_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i64), vp]
+        L.rb_build_basis.argtypes = [vp, vp, i32, dbl, C.c_int, C.POINTER(vp), C.POINTER(i32),
+                                     C.POINTER(dbl)]
+        L.rb_basis_free.argtypes = [vp]
+        L.rb_basis_export.argtypes = [vp, vp, vp, vp]
+        L.rb_filter.argtypes = [vp, vp, vp, vp, C.POINTER(FilterOpts), vp, i64, C.POINTER(i64), vp,
+                                C.POINTER(Stats)]
+        L.mf_full.argtypes = [vp, vp, vp, dbl, vp, i64, C.POINTER(i64), vp, C.POINTER(Stats)]
+        L.rb_rho_at.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+        L.rb_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, C.POINTER(dbl)]
+        L.rb_cluster_peaks.argtypes = [vp, vp, i64, i32, i64, vp]
+        L.rb_debug_rho.argtypes = [vp, vp, vp, vp, vp]
+        L.rb_debug_basis_outputs.argtypes = [vp, vp, vp, vp]
+        for f in FUNCTIONS:
+            if f != "rb_last_error":
+                getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int, where: str):
+    if st != RB_OK:
+        raise RbError(st, where, lib().rb_last_error().decode())
+
+
+def _ptr(x) -> Optional[int]:
+    """Raw pointer of a numpy array or torch tensor (None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr()
+    raise TypeError(f"unsupported array type {type(x)}")
+
+
+def current_stream_handle() -> Optional[int]:
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+class Context:
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        self.h = C.c_void_p()
+        if stream is None:
+            stream = current_stream_handle()
+        _check(lib().rb_ctx_create(device, stream, C.byref(self.h)), "rb_ctx_create")
+
+    def close(self):
+        if self.h:
+            _check(lib().rb_ctx_destroy(self.h), "rb_ctx_destroy")
+            self.h = C.c_void_p()
+
+
+class Bank:
+    """Whitened unit-norm bank on the device.  fill(t0, t1, k0, k1) must return
+    the complex128 templates [t0, t1) on rfft bins [k0, k1)."""
+
+    def __init__(self, ctx: Context, N: int, fs: float, f_low: float, psd: np.ndarray, T: int,
+                 fill: Callable[[int, int, int, int], np.ndarray]):
+        self.ctx, self.N, self.fs, self.f_low, self.T = ctx, int(N), float(fs), float(f_low), int(T)
+        self.h = C.c_void_p()
+        psd = np.ascontiguousarray(psd, dtype=np.float64)
+        self._err = None
+
+        def cb(user, t0, t1, k0, k1, out):
+            try:
+                a = np.asarray(fill(int(t0), int(t1), int(k0), int(k1)), dtype=np.complex128)
+                n = (t1 - t0) * (k1 - k0)
+                dst = np.ctypeslib.as_array(out, shape=(2 * n,))
+                dst[:] = a.reshape(-1).view(np.float64)
+                return 0
+            except Exception as e:        # reported after the call returns
+                self._err = e
+                return 1
+
+        self._cb = FILL_FN(cb)
+        g = Grid(self.N, self.fs, self.f_low)
+        st = lib().rb_bank_create(ctx.h, C.byref(g), _ptr(psd), self.T, self._cb, None, C.byref(self.h))
+        if self._err is not None:
+            raise self._err
+        _check(st, "rb_bank_create")
+
+    def info(self) -> Tuple[int, int, int, np.ndarray]:
+        T = C.c_int32()
+        klo, khi = C.c_int64(), C.c_int64()
+        sig = np.empty(self.T, dtype=np.float64)
+        _check(lib().rb_bank_info(self.h, C.byref(T), C.byref(klo), C.byref(khi), _ptr(sig)),
+               "rb_bank_info")
+        return T.value, klo.value, khi.value, sig
+
+    def close(self):
+        if self.h:
+            _check(lib().rb_bank_free(self.h), "rb_bank_free")
+            self.h = C.c_void_p()
+
+
+class Basis:
+    def __init__(self, ctx: Context, bank: Bank, rank: int = 0, tol: float = 1e-3, dtype="f32"):
+        self.ctx, self.bank = ctx, bank
+        self.h = C.c_void_p()
+        K = C.c_int32()
+        e = C.c_double()
+        dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        _check(lib().rb_build_basis(ctx.h, bank.h, int(rank), float(tol), dt, C.byref(self.h),
+                                    C.byref(K), C.byref(e)), "rb_build_basis")
+        self.K, self.energy, self.dtype = K.value, e.value, dt
+
+    def export(self):
+        _, klo, khi, _ = self.bank.info()
+        nb = khi - klo + 1
+        V = np.empty((self.K, nb), dtype=np.complex128)
+        c = np.empty((self.bank.T, self.K), dtype=np.complex128)
+        lam = np.empty(self.K, dtype=np.float64)
+        _check(lib().rb_basis_export(self.h, _ptr(V), _ptr(c), _ptr(lam)), "rb_basis_export")
+        return V, c, lam
+
+    def close(self):
+        if self.h:
+            _check(lib().rb_basis_free(self.h), "rb_basis_free")
+            self.h = C.c_void_p()
+
+
+def _triggers_out(cap: int, like_device: bool):
+    if like_device:
+        import torch
+        return torch.empty((max(cap, 1), 4), dtype=torch.int32, device="cuda")
+    return np.empty(max(cap, 1), dtype=TRIGGER_NP)
+
+
+def _as_np_triggers(buf, n: int) -> np.ndarray:
+    if isinstance(buf, np.ndarray):
+        return buf[:n].copy()
+    return buf[:n].cpu().numpy().view(TRIGGER_NP).reshape(-1)
+
+
+def rb_filter(ctx: Context, basis: Basis, bank: Bank, strain, thr1: float, thr2: float,
+              stage2: int = RB_STAGE2_FULL, cap: int = 1 << 20, peaks: bool = False,
+              out=None):
+    """Returns (triggers as a TRIGGER_NP array, peaks or None, Stats)."""
+    o = FilterOpts(thr1, thr2, stage2, 0)
+    dev = out is not None and not isinstance(out, np.ndarray)
+    buf = out if out is not None else _triggers_out(cap, False)
+    cap = buf.shape[0]
+    n = C.c_int64()
+    pk = np.empty(bank.T, dtype=PEAK_NP) if peaks else None
+    st = Stats()
+    _check(lib().rb_filter(ctx.h, basis.h, bank.h, _ptr(strain), C.byref(o), _ptr(buf), cap, C.byref(n),
+                           _ptr(pk), C.byref(st)), "rb_filter")
+    return _as_np_triggers(buf, n.value) if not dev else n.value, pk, st
+
+
+def mf_full(ctx: Context, bank: Bank, strain, thr: float, cap: int = 1 << 20, peaks: bool = False,
+            out=None):
+    dev = out is not None and not isinstance(out, np.ndarray)
+    buf = out if out is not None else _triggers_out(cap, False)
+    cap = buf.shape[0]
+    n = C.c_int64()
+    pk = np.empty(bank.T, dtype=PEAK_NP) if peaks else None
+    st = Stats()
+    _check(lib().mf_full(ctx.h, bank.h, _ptr(strain), float(thr), _ptr(buf), cap, C.byref(n), _ptr(pk),
+                         C.byref(st)), "mf_full")
+    return _as_np_triggers(buf, n.value) if not dev else n.value, pk, st
+
+
+def _trig_arg(S):
+    if isinstance(S, np.ndarray):
+        return np.ascontiguousarray(S, dtype=TRIGGER_NP)
+    return S          # device tensor of rb_trigger records (n x 4 int32)
+
+
+def rho_at(ctx: Context, basis: Basis, strain, S, coeffs=None, out=None):
+    """First-stage rho at trigger points (complex64, host array or `out`);
+    coeffs: T x K complex64 replacing the basis's conj(c), or None."""
+    S = _trig_arg(S)
+    n = S.shape[0]
+    rho = out if out is not None else np.empty(n, dtype=np.complex64)
+    _check(lib().rb_rho_at(ctx.h, basis.h, _ptr(strain), _ptr(S), n, _ptr(coeffs), _ptr(rho)),
+           "rb_rho_at")
+    return rho
+
+
+def rb_backward(ctx: Context, basis: Basis, strain, S, seed=None, coeffs=None, want_C=True,
+                want_strain=True, grad_C=None, grad_strain=None):
+    """Returns (loss, grad_C (T x K complex64) or None, grad_strain (N) or None).
+    Outputs are host arrays unless device buffers are passed in."""
+    S = _trig_arg(S)
+    n = S.shape[0]
+    gC = grad_C if grad_C is not None else (
+        np.zeros((basis.bank.T, basis.K), dtype=np.complex64) if want_C else None)
+    gs = grad_strain if grad_strain is not None else (
+        np.zeros(basis.bank.N, dtype=np.float32) if want_strain else None)
+    loss = C.c_double()
+    sd = seed
+    if isinstance(seed, np.ndarray) or isinstance(seed, (list, tuple)):
+        sd = np.ascontiguousarray(seed, dtype=np.float32)
+    _check(lib().rb_backward(ctx.h, basis.h, _ptr(strain), _ptr(S), _ptr(sd), n, _ptr(coeffs),
+                             _ptr(gC), _ptr(gs), C.byref(loss)), "rb_backward")
+    return loss.value, gC, gs
+
+
+def cluster_peaks(ctx: Context, trig: np.ndarray, W: int, N: int) -> np.ndarray:
+    trig = np.ascontiguousarray(trig, dtype=TRIGGER_NP)
+    out = np.zeros(trig.shape[0], dtype=np.uint8)
+    _check(lib().rb_cluster_peaks(ctx.h, _ptr(trig), trig.shape[0], int(W), int(N), _ptr(out)),
+           "rb_cluster_peaks")
+    return out.astype(bool)
+
+
+def debug_rho(ctx: Context, bank: Bank, strain, basis: Optional[Basis] = None) -> np.ndarray:
+    rho = np.empty((bank.T, bank.N), dtype=np.complex64)
+    _check(lib().rb_debug_rho(ctx.h, basis.h if basis else None, bank.h, _ptr(strain), _ptr(rho)),
+           "rb_debug_rho")
+    return rho
+
+
+def debug_basis_outputs(ctx: Context, basis: Basis, strain) -> np.ndarray:
+    z = np.empty((basis.K, basis.bank.N), dtype=np.complex64)
+    _check(lib().rb_debug_basis_outputs(ctx.h, basis.h, _ptr(strain), _ptr(z)), "rb_debug_basis_outputs")
+    return z
