@@ -175,34 +175,76 @@ rb_status rb_bank_info(rb_bank bank, int32_t* T, int64_t* k_lo, int64_t* k_hi, d
  * with Rayleigh-Ritz, basis rows v_k = lambda_k^{-1/2} sum_j conj(U_jk) w_j,
  * coefficients c_jk = <w_j, v_k>.  The basis is stored complex64, the
  * coefficients as C = conj(c) in `dtype` (with power-of-two row scales for
- * the 16-bit types).  rank_out / energy_out: host, may be NULL. */
+ * FP16).  rank_out / energy_out: host, may be NULL.  Equivalent to
+ * rb_build_basis_range over [0, T). */
 rb_status rb_build_basis(rb_ctx ctx, rb_bank bank, int32_t rank, double tol, rb_dtype dtype,
                          rb_basis* out, int32_t* rank_out, double* energy_out);
+
+/* Basis of the sub-bank of templates [t0, t1) (0 <= t0 < t1 <= T): the
+ * paper splits a bank into sub-banks (along tau0) and builds one basis per
+ * sub-bank (Sec. III.B).  Template indices stay global everywhere (triggers,
+ * rb_rho_at / rb_backward trigger lists); per-template arrays of a range basis
+ * (coefficients, gradients, dumps) have t1 - t0 rows. */
+rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, int32_t t1, int32_t rank,
+                               double tol, rb_dtype dtype, rb_basis* out, int32_t* rank_out,
+                               double* energy_out);
+
+/* Basis facts (outputs may be NULL). */
+rb_status rb_basis_info(rb_basis basis, int32_t* t0, int32_t* t1, int32_t* rank, double* energy);
 
 rb_status rb_basis_free(rb_basis basis);
 
 /* Copy the basis out (host arrays, any may be NULL): V: K x nb complex128
- * (rows over bins k_lo..k_hi), c: T x K complex128 coefficients (FP64, before
- * storage rounding), lambda: K eigenvalues (FP64, descending). */
+ * (rows over bins k_lo..k_hi), c: (t1-t0) x K complex128 coefficients (FP64,
+ * before storage rounding), lambda: K eigenvalues (FP64, descending). */
 rb_status rb_basis_export(rb_basis basis, double* V, double* c, double* lambda);
 
 /* ------------------------------------------------------------------ search */
 
 /* Hierarchical reduced-basis search of one segment (Sec. III.C):
  *   1. s~ of the strain (forward FFT), whitened on the band;
- *   2. beta_k = IFFT(d conj(v_k)) for every basis vector;
+ *   2. beta_k = IFFT(d conj(v_k)) for every basis vector of every sub-bank;
  *   3. rho_RB = C beta (MFMA GEMM), first-stage crossings |rho_RB| >= thr1;
  *   4. second stage (opts->stage2): the exact |rho| of the selected templates,
  *      final triggers |rho| >= thr2.
+ *   bases   nbases (>= 1) bases of this bank whose template ranges partition
+ *           [0, T) (one basis of the whole bank, or one per sub-bank).
  *   strain  host or device, N floats.
  *   out     host or device, cap entries; triggers sorted by (tmpl, sample).
  *   n_out   host; number of final triggers.  If it exceeds cap the call
  *           returns RB_ERR_CAPACITY with the required count in *n_out.
  *   peaks   host or device, T entries, or NULL.
  *   stats   host or NULL. */
-rb_status rb_filter(rb_ctx ctx, rb_basis basis, rb_bank bank, const float* strain,
-                    const rb_filter_opts* opts, rb_trigger* out, int64_t cap, int64_t* n_out,
-                    rb_peak* peaks, rb_stats* stats);
+rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases, rb_bank bank,
+                    const float* strain, const rb_filter_opts* opts, rb_trigger* out, int64_t cap,
+                    int64_t* n_out, rb_peak* peaks, rb_stats* stats);
+
+/* One work item of a batched search: a segment and the bank (on that
+ * segment's grid) with the bases of its sub-banks. */
+typedef struct {
+  const float* strain;       /* device pointer, N floats of the bank's grid     */
+  rb_bank bank;
+  const rb_basis* bases;     /* bases partitioning the bank's templates         */
+  int32_t nbases;
+} rb_batch_item;
+
+/* Batched hierarchical search (Sec. III.B sub-banks x segments of any length;
+ * one item per (segment, bank)).  Each item runs the same steps as rb_filter
+ * (full second stage only) with device-side counts, so the whole batch is a
+ * sequence of kernel launches with no host synchronisation inside.
+ *   use_graph  1: the batch is captured once into a hipGraph (keyed by the
+ *              item pointers, thresholds and capacities) and replayed on later
+ *              calls with the same key: refill the strain buffers and call
+ *              again.  0: launched eagerly.
+ *   out        host or device, nitems x cap_item triggers; item i's sorted
+ *              triggers start at out + i * cap_item.
+ *   n_out      host, nitems counts.  RB_ERR_CAPACITY (with every count set)
+ *              if some item has more than cap_item triggers.
+ *   stats      host or NULL: summed counts and ms[6] = device time of the
+ *              batch. */
+rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_item* items,
+                          const rb_filter_opts* opts, int32_t use_graph, rb_trigger* out,
+                          int64_t cap_item, int64_t* n_out, rb_stats* stats);
 
 /* Template method (Sec. II, Eq. IFFT): the full SNR series of every template
  * by an inverse FFT, thresholded at thr (> 0).  Arguments as for rb_filter. */
@@ -213,9 +255,9 @@ rb_status mf_full(rb_ctx ctx, rb_bank bank, const float* strain, double thr, rb_
  *   rho_i = sum_k C_{j_i k} beta_k[n_i]      (Eq. Beta_eqn, C = conj(c))
  * with beta from `strain` (FP32 path whatever the basis storage type).
  *   S    host or device, n triggers (only tmpl and sample are read; tmpl in
- *        [0, T), sample in [0, N), else RB_ERR_ARG).
- *   C    host or device, T x K complex64 coefficients replacing the basis's
- *        own conj(c), or NULL to use them.
+ *        the basis's range [t0, t1), sample in [0, N), else RB_ERR_ARG).
+ *   C    host or device, (t1-t0) x K complex64 coefficients replacing the
+ *        basis's own conj(c), or NULL to use them.
  *   rho  host or device, n complex64 (interleaved). */
 rb_status rb_rho_at(rb_ctx ctx, rb_basis basis, const float* strain, const rb_trigger* S,
                     int64_t n, const float* C, float* rho);
@@ -223,7 +265,7 @@ rb_status rb_rho_at(rb_ctx ctx, rb_basis basis, const float* strain, const rb_tr
 /* Adjoint of correlation plus reconstruction.  For the loss
  *   L = sum_i g_i |rho_{j_i}[n_i]|^2      (S = {(j_i, n_i)} frozen, rho as in
  *                                          rb_rho_at)
- * computes dL/dC (T x K complex64, interleaved, torch's convention for a
+ * computes dL/dC ((t1-t0) x K complex64, interleaved, torch's convention for a
  * complex leaf: dL/dRe + i dL/dIm; rows without triggers are zero) and dL/ds
  * (N floats).  Reductions run in a fixed order (bitwise reproducible).
  *   S, C     as for rb_rho_at.
@@ -244,8 +286,9 @@ rb_status rb_cluster_peaks(rb_ctx ctx, const rb_trigger* trig, int64_t n, int32_
 /* ------------------------------------------------------------------ debug */
 
 /* Dump the complex SNR series (small T*N only): rho (host or device,
- * T x N x 2 floats, natural time order).  basis == NULL: exact template
- * method; otherwise the first-stage reconstruction rho_RB = C beta. */
+ * rows x N x 2 floats, natural time order).  basis == NULL: exact template
+ * method for all T templates; otherwise the first-stage reconstruction
+ * rho_RB = C beta for the basis's t1 - t0 templates. */
 rb_status rb_debug_rho(rb_ctx ctx, rb_basis basis, rb_bank bank, const float* strain, float* rho);
 
 /* Dump the per-basis filter outputs beta (K x N x 2 floats, natural time

@@ -142,10 +142,21 @@ struct rb_ctx_s {
   int live = 0;
   std::map<int64_t, std::unique_ptr<TwTables>> tw;
   // scratch
-  DevBuf work, work64, dspec, strain, z, z32, adjA, adjAhat, adjB, adjT, adjS, adjRho, adjG, adjC, adjGC,
+  DevBuf work, work64, dspec, strain, z, z32, recs1, adjA, adjAhat, adjB, adjT, adjS, adjRho, adjG, adjC, adjGC,
       adjOrd, adjSeg, trig1, trig2, recs, tmp, final_out, cnt1, cnt2, off1, off2, fill1, fill2,
       list1, list2, tmax, summary, counters, thr_row, peaks, flag, rho_tmp, zws;
   hipEvent_t ev[8] = {};
+  std::vector<hipEvent_t> evs;
+  // batch search: per-item summaries and outputs, captured graph
+  DevBuf bsum, bout;
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::string gkey;
+  ~rb_ctx_s() {
+    for (auto e : evs) (void)hipEventDestroy(e);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (gstream) (void)hipStreamDestroy(gstream);
+  }
 };
 
 struct rb_bank_s {
@@ -163,6 +174,7 @@ struct rb_bank_s {
 struct rb_basis_s {
   rb_ctx ctx = nullptr;
   rb_bank bank = nullptr;
+  int32_t t0 = 0, T = 0;       // template range [t0, t0 + T) of the bank
   int32_t K = 0, Kp = 0, Tp = 0;
   rb_dtype dtype = RB_F32;
   double energy = 0.0, trace = 0.0;
@@ -356,8 +368,10 @@ int64_t trig_capacity(const DevBuf& b) { return (int64_t)(b.bytes / sizeof(TrigR
 
 // Full matched filter of a template list (or all templates) with the
 // threshold epilogue; counts in cnt2, records in trig2, maxima in tmax.
+// With d_count (graph mode) nlist is an upper bound and list entries at or
+// beyond *d_count are skipped on the device.
 rb_status step_mf(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTables& tw, const int32_t* list,
-                  int64_t nlist, float thr2sq) {
+                  int64_t nlist, float thr2sq, const int32_t* d_count = nullptr) {
   const int B = batch_vectors(g.N, nlist);
   RB_TRY(ctx->work.ensure((size_t)B * g.N * 8));
   PassArgs a = base_args(bank, g, tw);
@@ -368,6 +382,7 @@ rb_status step_mf(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTables& t
   a.sup_hi = bank->sup_hi.as<int32_t>();
   a.work = ctx->work.as<float2>();
   a.vec_list = list;
+  a.d_count = d_count;
   a.thr2 = thr2sq;
   a.trig = ctx->trig2.as<TrigRec>();
   a.trig_cap = trig_capacity(ctx->trig2);
@@ -398,11 +413,11 @@ rb_status step_sort(rb_ctx ctx, int T, int64_t total, int64_t nlist) {
   RB_TRY(ctx->recs.ensure(std::max<size_t>(16, (size_t)total * sizeof(TrigRec))));
   RB_TRY(ctx->tmp.ensure(std::max<size_t>(16, (size_t)total * sizeof(TrigRec))));
   RB_TRY(ctx->final_out.ensure(std::max<size_t>(16, (size_t)total * sizeof(rb_trigger))));
-  RB_HIP(launch_scatter_triggers(ctx->trig2.as<TrigRec>(), total, ctx->off2.as<int32_t>(), ctx->fill2.as<int32_t>(),
-                                 ctx->recs.as<TrigRec>(), ctx->stream));
+  RB_HIP(launch_scatter_triggers(ctx->trig2.as<TrigRec>(), total, nullptr, ctx->off2.as<int32_t>(),
+                                 ctx->fill2.as<int32_t>(), ctx->recs.as<TrigRec>(), ctx->stream));
   RB_HIP(launch_segment_sort(ctx->recs.as<TrigRec>(), ctx->tmp.as<TrigRec>(), ctx->off2.as<int32_t>(),
                              ctx->cnt2.as<int32_t>(), ctx->list2.as<int32_t>(), (int)nlist, ctx->final_out.p,
-                             ctx->stream));
+                             nullptr, 0, ctx->stream));
   (void)T;
   return RB_OK;
 }
@@ -664,21 +679,38 @@ rb_status svqb(rb_ctx ctx, BasisWork& bw, const double2* Y, int64_t T, int L, do
 
 extern "C" rb_status rb_build_basis(rb_ctx ctx, rb_bank bank, int32_t rank, double tol, rb_dtype dtype,
                                     rb_basis* out, int32_t* rank_out, double* energy_out) {
+  RB_CHECK(bank != nullptr, RB_ERR_ARG, "bank is NULL");
+  return rb_build_basis_range(ctx, bank, 0, bank->T, rank, tol, dtype, out, rank_out, energy_out);
+}
+
+extern "C" rb_status rb_basis_info(rb_basis basis, int32_t* t0, int32_t* t1, int32_t* rank, double* energy) {
+  RB_CHECK(basis != nullptr, RB_ERR_ARG, "basis is NULL");
+  if (t0) *t0 = basis->t0;
+  if (t1) *t1 = basis->t0 + basis->T;
+  if (rank) *rank = basis->K;
+  if (energy) *energy = basis->energy;
+  return RB_OK;
+}
+
+extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, int32_t t1, int32_t rank,
+                                          double tol, rb_dtype dtype, rb_basis* out, int32_t* rank_out,
+                                          double* energy_out) {
   RB_TRY(validate_ctx(ctx));
   RB_CHECK(bank != nullptr && out != nullptr, RB_ERR_ARG, "NULL argument");
   RB_CHECK(bank->ctx == ctx, RB_ERR_ARG, "bank belongs to another context");
+  RB_CHECK(t0 >= 0 && t0 < t1 && t1 <= bank->T, RB_ERR_ARG, "template range must satisfy 0 <= t0 < t1 <= T");
   RB_CHECK(rank >= 0, RB_ERR_ARG, "rank must be >= 0");
   RB_CHECK(rank > 0 || (tol > 0 && tol < 1), RB_ERR_ARG, "tol must be in (0, 1) when rank == 0");
   RB_CHECK(dtype == RB_F32 || dtype == RB_BF16 || dtype == RB_F16, RB_ERR_ARG, "bad dtype");
   *out = nullptr;
-  const int64_t T = bank->T;
+  const int64_t T = t1 - t0;
   const int64_t nb = bank->k_hi - bank->k_lo + 1, off = bank->k_lo - bank->kb, nbs = bank->nbs;
   hipStream_t s = ctx->stream;
   BasisWork bw;
   RB_TRY(bw.ws.ensure((size_t)64 << 20 << 4));   // 64 Mi complex128 split-K partials (1 GiB)
   // trace of the Gram = sum of stored squared norms
   RB_TRY(bw.norms.ensure((size_t)T * 8));
-  const float2* W = bank->w.as<float2>() + off;
+  const float2* W = bank->w.as<float2>() + (size_t)t0 * nbs + off;
   RB_HIP(launch_row_norms(W, T, nb, nbs, bw.norms.as<double>(), s));
   std::vector<double> norms(T);
   RB_HIP(hipMemcpyAsync(norms.data(), bw.norms.p, T * 8, hipMemcpyDeviceToHost, s));
@@ -751,6 +783,8 @@ extern "C" rb_status rb_build_basis(rb_ctx ctx, rb_bank bank, int32_t rank, doub
   RB_CHECK(bs != nullptr, RB_ERR_OOM, "host allocation failed");
   bs->ctx = ctx;
   bs->bank = bank;
+  bs->t0 = t0;
+  bs->T = (int32_t)T;
   bs->K = K;
   bs->Kp = (dtype == RB_F32) ? K : ((K + 7) / 8) * 8;
   const int tile = gemm_tile_templates();
@@ -866,8 +900,6 @@ extern "C" rb_status rb_basis_export(rb_basis basis, double* V, double* c, doubl
 namespace {
 
 rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq, float2* rho_out) {
-  rb_bank bank = basis->bank;
-  const int T = bank->T;
   const float want = rho_out ? std::numeric_limits<float>::infinity() : thr1sq;
   if (!(basis->thr_cached == want)) {
     RB_TRY(basis->thr_row.ensure((size_t)basis->Tp * 4));
@@ -883,7 +915,7 @@ rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq
   GemmArgs ga;
   std::memset(&ga, 0, sizeof(ga));
   ga.N = g.N;
-  ga.T = T;
+  ga.T = basis->T;
   ga.Tp = basis->Tp;
   ga.K = basis->K;
   ga.Kp = basis->Kp;
@@ -896,28 +928,66 @@ rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq
   ga.trig = ctx->trig1.as<TrigRec>();
   ga.trig_cap = trig_capacity(ctx->trig1);
   ga.trig_count = ctx->counters.as<unsigned long long>();
-  ga.tmpl_count = ctx->cnt1.as<int32_t>();
+  ga.tmpl_base = basis->t0;
+  ga.tmpl_count = ctx->cnt1.as<int32_t>() + basis->t0;
   ga.rho_out = rho_out;
   ga.row_inv = basis->row_inv.as<float>();
   RB_HIP(launch_recon_gemm(ga, ctx->stream));
   return RB_OK;
 }
 
+rb_status event(rb_ctx ctx, size_t i) {
+  while (ctx->evs.size() <= i) {
+    hipEvent_t e;
+    RB_HIP(hipEventCreate(&e));
+    ctx->evs.push_back(e);
+  }
+  RB_HIP(hipEventRecord(ctx->evs[i], ctx->stream));
+  return RB_OK;
+}
+
+float elapsed(rb_ctx ctx, size_t a, size_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, ctx->evs[a], ctx->evs[b]) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.f;
+  }
+  return ms;
+}
+
+// The bases must belong to `bank` and their ranges must partition [0, T).
+rb_status check_partition(rb_ctx ctx, const rb_basis* bases, int32_t nb, rb_bank bank) {
+  RB_CHECK(bases != nullptr && nb >= 1, RB_ERR_ARG, "need at least one basis");
+  std::vector<std::pair<int32_t, int32_t>> r;
+  for (int32_t i = 0; i < nb; ++i) {
+    RB_CHECK(bases[i] != nullptr, RB_ERR_ARG, "basis is NULL");
+    RB_CHECK(bases[i]->bank == bank && bases[i]->ctx == ctx, RB_ERR_ARG, "basis/bank/context mismatch");
+    r.push_back({bases[i]->t0, bases[i]->t0 + bases[i]->T});
+  }
+  std::sort(r.begin(), r.end());
+  int32_t at = 0;
+  for (auto& x : r) {
+    RB_CHECK(x.first == at, RB_ERR_ARG, "basis template ranges must partition [0, T)");
+    at = x.second;
+  }
+  RB_CHECK(at == bank->T, RB_ERR_ARG, "basis template ranges must partition [0, T)");
+  return RB_OK;
+}
+
 }  // namespace
 
-extern "C" rb_status rb_filter(rb_ctx ctx, rb_basis basis, rb_bank bank, const float* strain,
-                               const rb_filter_opts* opts, rb_trigger* out, int64_t cap, int64_t* n_out,
-                               rb_peak* peaks, rb_stats* stats) {
+extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases, rb_bank bank,
+                               const float* strain, const rb_filter_opts* opts, rb_trigger* out, int64_t cap,
+                               int64_t* n_out, rb_peak* peaks, rb_stats* stats) {
   RB_TRY(validate_ctx(ctx));
-  RB_CHECK(basis != nullptr && bank != nullptr && opts != nullptr && n_out != nullptr, RB_ERR_ARG,
-           "NULL argument");
-  RB_CHECK(basis->bank == bank && bank->ctx == ctx, RB_ERR_ARG, "basis/bank/context mismatch");
+  RB_CHECK(bank != nullptr && opts != nullptr && n_out != nullptr, RB_ERR_ARG, "NULL argument");
+  RB_CHECK(bank->ctx == ctx, RB_ERR_ARG, "bank belongs to another context");
+  RB_TRY(check_partition(ctx, bases, nbases, bank));
   RB_CHECK(std::isfinite(opts->thr1) && opts->thr1 > 0, RB_ERR_ARG, "thr1 must be > 0");
   RB_CHECK(std::isfinite(opts->thr2) && opts->thr2 >= opts->thr1, RB_ERR_ARG, "thr2 must be >= thr1");
   RB_CHECK(opts->stage2 == RB_STAGE2_FULL || opts->stage2 == RB_STAGE2_SPARSE, RB_ERR_ARG, "bad stage2 mode");
   RB_CHECK(opts->reserved == 0, RB_ERR_ARG, "reserved must be 0");
   RB_CHECK(cap >= 0, RB_ERR_ARG, "cap must be >= 0");
-  RB_CHECK(opts->stage2 == RB_STAGE2_FULL, RB_ERR_UNSUPPORTED, "sparse second stage not available");
   const int T = bank->T;
   const FftGeom g = make_geom(bank->grid.N);
   FftTables tw;
@@ -925,52 +995,96 @@ extern "C" rb_status rb_filter(rb_ctx ctx, rb_basis basis, rb_bank bank, const f
   const float* s;
   RB_TRY(strain_device(ctx, strain, g.N, &s));
   RB_TRY(ensure_trigger_scratch(ctx, T));
-  record(ctx, stats, 0);
+  const bool tm = stats != nullptr;
+  // events: 0 start, 1 spectrum, 2+2m Z of basis m, 3+2m GEMM of basis m, then scan, stage 2, end
+  const size_t e_scan = 2 + 2 * (size_t)nbases, e_s2 = e_scan + 1, e_end = e_s2 + 1;
+  if (tm) RB_TRY(event(ctx, 0));
   RB_TRY(fill32(ctx, ctx->flag.p, 0u, 2));
   RB_HIP(launch_check_finite(s, g.N, ctx->flag.as<int64_t>(), ctx->stream));
   RB_TRY(step_spectrum(ctx, bank, g, tw, s));
-  record(ctx, stats, 1);
-  RB_TRY(step_basis_outputs(ctx, basis, g, tw));
-  record(ctx, stats, 2);
+  if (tm) RB_TRY(event(ctx, 1));
   int64_t sum1[3];
+  const float thr1sq = (float)(opts->thr1 * opts->thr1);
   for (;;) {
     RB_TRY(fill32(ctx, ctx->counters.p, 0u, 2));
     RB_TRY(fill32(ctx, ctx->cnt1.p, 0u, T));
-    RB_TRY(stage1_gemm(ctx, basis, g, (float)(opts->thr1 * opts->thr1), nullptr));
-    record(ctx, stats, 3);
+    for (int32_t m = 0; m < nbases; ++m) {
+      RB_TRY(step_basis_outputs(ctx, bases[m], g, tw));
+      if (tm) RB_TRY(event(ctx, 2 + 2 * (size_t)m));
+      RB_TRY(stage1_gemm(ctx, bases[m], g, thr1sq, nullptr));
+      if (tm) RB_TRY(event(ctx, 3 + 2 * (size_t)m));
+    }
     RB_TRY(scan_and_read(ctx, T, ctx->cnt1, ctx->off1, ctx->fill1, ctx->list1, sum1));
     if (sum1[0] <= trig_capacity(ctx->trig1)) break;
     RB_TRY(ctx->trig1.ensure((size_t)(sum1[0] + sum1[0] / 4) * sizeof(TrigRec)));
   }
+  if (tm) RB_TRY(event(ctx, e_scan));
   int64_t flag = 0;
   RB_HIP(hipMemcpyAsync(&flag, ctx->flag.p, 8, hipMemcpyDeviceToHost, ctx->stream));
   RB_HIP(hipStreamSynchronize(ctx->stream));
   RB_CHECK(flag == 0, RB_ERR_NUMERIC, "strain contains non-finite values");
-  record(ctx, stats, 4);
   int64_t sum2[3];
+  const bool sparse = opts->stage2 == RB_STAGE2_SPARSE;
+  if (sparse) {   // stage-1 records grouped by template (off1 / fill1 from the scan)
+    RB_TRY(ctx->recs1.ensure(std::max<size_t>(16, (size_t)sum1[0] * sizeof(TrigRec))));
+    RB_HIP(launch_scatter_triggers(ctx->trig1.as<TrigRec>(), sum1[0], nullptr, ctx->off1.as<int32_t>(),
+                                   ctx->fill1.as<int32_t>(), ctx->recs1.as<TrigRec>(), ctx->stream));
+  }
   for (;;) {
     RB_TRY(fill32(ctx, ctx->counters.p, 0u, 4));
     RB_TRY(fill32(ctx, ctx->cnt2.p, 0u, T));
     RB_TRY(fill32(ctx, ctx->tmax.p, 0u, 2 * (int64_t)T));
-    RB_TRY(step_mf(ctx, bank, g, tw, ctx->list1.as<int32_t>(), sum1[1], (float)(opts->thr2 * opts->thr2)));
-    record(ctx, stats, 5);
+    if (sparse) {
+      SparseArgs sa;
+      std::memset(&sa, 0, sizeof(sa));
+      sa.N = g.N;
+      sa.s_lo = g.s_lo;
+      sa.tlo = tw.tlo;
+      sa.thi = tw.thi;
+      sa.list = ctx->list1.as<int32_t>();
+      sa.offsets = ctx->off1.as<int32_t>();
+      sa.counts = ctx->cnt1.as<int32_t>();
+      sa.recs = ctx->recs1.as<TrigRec>();
+      sa.d = ctx->dspec.as<float2>();
+      sa.tmpl = bank->w.as<float2>();
+      sa.kb = bank->kb;
+      sa.nbs = bank->nbs;
+      sa.sup_lo = bank->sup_lo.as<int32_t>();
+      sa.sup_hi = bank->sup_hi.as<int32_t>();
+      sa.thr2 = (float)(opts->thr2 * opts->thr2);
+      sa.out = ctx->trig2.as<TrigRec>();
+      sa.out_cap = trig_capacity(ctx->trig2);
+      sa.out_count = ctx->counters.as<unsigned long long>() + 1;
+      sa.tmpl_count = ctx->cnt2.as<int32_t>();
+      sa.tmpl_max = ctx->tmax.as<unsigned long long>();
+      RB_HIP(launch_sparse_exact(sa, (int)sum1[1], ctx->stream));
+    } else {
+      RB_TRY(step_mf(ctx, bank, g, tw, ctx->list1.as<int32_t>(), sum1[1], (float)(opts->thr2 * opts->thr2)));
+    }
+    if (tm) RB_TRY(event(ctx, e_s2));
     RB_TRY(scan_and_read(ctx, T, ctx->cnt2, ctx->off2, ctx->fill2, ctx->list2, sum2));
     if (sum2[0] <= trig_capacity(ctx->trig2)) break;
     RB_TRY(ctx->trig2.ensure((size_t)(sum2[0] + sum2[0] / 4) * sizeof(TrigRec)));
   }
   const rb_status st = finish_stage2(ctx, bank, out, cap, n_out, peaks, sum2);
-  record(ctx, stats, 6);
+  if (tm) RB_TRY(event(ctx, e_end));
   RB_HIP(hipStreamSynchronize(ctx->stream));
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     stats->n_stage1 = sum1[0];
     stats->n_refiltered = (int32_t)sum1[1];
-    stats->rank = basis->K;
-    float ms;
-    const int pairs[7][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {0, 6}};
-    for (int i = 0; i < 7; ++i)
-      if (hipEventElapsedTime(&ms, ctx->ev[pairs[i][0]], ctx->ev[pairs[i][1]]) == hipSuccess) stats->ms[i] = ms;
-    (void)hipGetLastError();
+    int kmax = 0;
+    for (int32_t m = 0; m < nbases; ++m) kmax = std::max(kmax, (int)bases[m]->K);
+    stats->rank = kmax;
+    stats->ms[0] = elapsed(ctx, 0, 1);
+    for (int32_t m = 0; m < nbases; ++m) {
+      stats->ms[1] += elapsed(ctx, m == 0 ? 1 : 3 + 2 * (size_t)(m - 1), 2 + 2 * (size_t)m);
+      stats->ms[2] += elapsed(ctx, 2 + 2 * (size_t)m, 3 + 2 * (size_t)m);
+    }
+    stats->ms[3] = elapsed(ctx, 3 + 2 * (size_t)(nbases - 1), e_scan);
+    stats->ms[4] = elapsed(ctx, e_scan, e_s2);
+    stats->ms[5] = elapsed(ctx, e_s2, e_end);
+    stats->ms[6] = elapsed(ctx, 0, e_end);
   }
   return st;
 }
@@ -1056,8 +1170,9 @@ extern "C" rb_status rb_debug_rho(rb_ctx ctx, rb_basis basis, rb_bank bank, cons
   RB_CHECK(bank != nullptr && rho != nullptr, RB_ERR_ARG, "NULL argument");
   RB_CHECK(bank->ctx == ctx && (basis == nullptr || basis->bank == bank), RB_ERR_ARG, "handle mismatch");
   const int T = bank->T;
+  const int rows = basis ? basis->T : T;
   const FftGeom g = make_geom(bank->grid.N);
-  RB_CHECK((double)T * g.N <= 4e9, RB_ERR_ARG, "T * N too large for a dump");
+  RB_CHECK((double)rows * g.N <= 4e9, RB_ERR_ARG, "rows * N too large for a dump");
   FftTables tw;
   RB_TRY(get_tables(ctx, g, tw));
   const float* s;
@@ -1066,7 +1181,7 @@ extern "C" rb_status rb_debug_rho(rb_ctx ctx, rb_basis basis, rb_bank bank, cons
   float2* dst = reinterpret_cast<float2*>(rho);
   const bool dev = is_device_ptr(rho);
   if (!dev) {
-    RB_TRY(ctx->rho_tmp.ensure((size_t)T * g.N * 8));
+    RB_TRY(ctx->rho_tmp.ensure((size_t)rows * g.N * 8));
     dst = ctx->rho_tmp.as<float2>();
   }
   RB_TRY(step_spectrum(ctx, bank, g, tw, s));
@@ -1091,9 +1206,9 @@ extern "C" rb_status rb_debug_rho(rb_ctx ctx, rb_basis basis, rb_bank bank, cons
     RB_TRY(step_basis_outputs(ctx, basis, g, tw));
     RB_TRY(fill32(ctx, ctx->counters.p, 0u, 2));
     RB_TRY(fill32(ctx, ctx->cnt1.p, 0u, T));
-    RB_TRY(stage1_gemm(ctx, basis, g, 0.f, dst));
+    RB_TRY(stage1_gemm(ctx, basis, g, 0.f, dst));   // rows [t0, t0 + T) of the basis
   }
-  if (!dev) RB_HIP(hipMemcpyAsync(rho, dst, (size_t)T * g.N * 8, hipMemcpyDeviceToHost, ctx->stream));
+  if (!dev) RB_HIP(hipMemcpyAsync(rho, dst, (size_t)rows * g.N * 8, hipMemcpyDeviceToHost, ctx->stream));
   RB_HIP(hipStreamSynchronize(ctx->stream));
   return RB_OK;
 }
@@ -1125,8 +1240,8 @@ extern "C" rb_status rb_debug_basis_outputs(rb_ctx ctx, rb_basis basis, const fl
 namespace {
 
 // Copies the trigger list (host or device) to host arrays and validates it.
-rb_status host_triggers(rb_ctx ctx, const rb_trigger* S, int64_t n, int T, int64_t N, std::vector<int32_t>& tm,
-                        std::vector<int32_t>& sp) {
+rb_status host_triggers(rb_ctx ctx, const rb_trigger* S, int64_t n, int t0, int T, int64_t N,
+                        std::vector<int32_t>& tm, std::vector<int32_t>& sp) {
   std::vector<rb_trigger> h((size_t)n);
   if (n > 0) {
     if (is_device_ptr(S)) {
@@ -1139,9 +1254,9 @@ rb_status host_triggers(rb_ctx ctx, const rb_trigger* S, int64_t n, int T, int64
   tm.resize(n);
   sp.resize(n);
   for (int64_t i = 0; i < n; ++i) {
-    RB_CHECK(h[i].tmpl >= 0 && h[i].tmpl < T && h[i].sample >= 0 && h[i].sample < N, RB_ERR_ARG,
-             "trigger " + std::to_string(i) + " out of range");
-    tm[i] = h[i].tmpl;
+    RB_CHECK(h[i].tmpl >= t0 && h[i].tmpl < t0 + T && h[i].sample >= 0 && h[i].sample < N, RB_ERR_ARG,
+             "trigger " + std::to_string(i) + " outside the basis's templates or the segment");
+    tm[i] = h[i].tmpl - t0;     // local row
     sp[i] = h[i].sample;
   }
   return RB_OK;
@@ -1163,7 +1278,7 @@ rb_status coeffs(rb_ctx ctx, rb_basis basis, const float* C, const float2** out)
     *out = reinterpret_cast<const float2*>(C);
     return RB_OK;
   }
-  const size_t bytes = (size_t)basis->bank->T * basis->K * sizeof(float2);
+  const size_t bytes = (size_t)basis->T * basis->K * sizeof(float2);
   RB_TRY(ctx->adjC.ensure(bytes));
   RB_HIP(hipMemcpyAsync(ctx->adjC.p, C, bytes, hipMemcpyHostToDevice, ctx->stream));
   RB_HIP(hipStreamSynchronize(ctx->stream));
@@ -1190,7 +1305,7 @@ rb_status adjoint_forward(rb_ctx ctx, rb_basis basis, const float* strain, const
   rb_bank bank = basis->bank;
   FftTables tw;
   RB_TRY(get_tables(ctx, g, tw));
-  RB_TRY(host_triggers(ctx, S, n, bank->T, g.N, tm, sp));
+  RB_TRY(host_triggers(ctx, S, n, basis->t0, basis->T, g.N, tm, sp));
   const float* s;
   RB_TRY(strain_device(ctx, strain, g.N, &s));
   RB_TRY(coeffs(ctx, basis, C, Cd));
@@ -1230,7 +1345,7 @@ extern "C" rb_status rb_backward(rb_ctx ctx, rb_basis basis, const float* strain
   RB_CHECK(n >= 0, RB_ERR_ARG, "n must be >= 0");
   RB_CHECK(n == 0 || S != nullptr, RB_ERR_ARG, "S is NULL");
   rb_bank bank = basis->bank;
-  const int T = bank->T, K = basis->K;
+  const int T = basis->T, K = basis->K;     // rows of C / grad_C: the basis's templates
   const FftGeom g = make_geom(bank->grid.N);
   const int64_t N = g.N;
   hipStream_t st = ctx->stream;
@@ -1323,5 +1438,195 @@ extern "C" rb_status rb_backward(rb_ctx ctx, rb_basis basis, const float* strain
     RB_HIP(hipStreamSynchronize(st));
   }
   RB_HIP(hipStreamSynchronize(st));
+  return RB_OK;
+}
+
+// ====================================================================== batch
+namespace {
+
+// Enqueues the whole search of one item with device-side counts only (no
+// host synchronisation), so that it can be captured into a graph.  Results:
+// sm[0..2] stage-1 summary, sm[3] non-finite flag, sm[4..6] stage-2 summary,
+// triggers in out (cap_item entries, written only if they all fit).
+rb_status enqueue_item(rb_ctx ctx, const rb_batch_item& it, const rb_filter_opts* opts, int64_t* sm,
+                       rb_trigger* out, int64_t cap_item) {
+  rb_bank bank = it.bank;
+  const int T = bank->T;
+  const FftGeom g = make_geom(bank->grid.N);
+  FftTables tw;
+  RB_TRY(get_tables(ctx, g, tw));
+  const float* s = it.strain;
+  RB_TRY(fill32(ctx, sm, 0u, 16));
+  RB_HIP(launch_check_finite(s, g.N, sm + 3, ctx->stream));
+  RB_TRY(step_spectrum(ctx, bank, g, tw, s));
+  RB_TRY(fill32(ctx, ctx->counters.p, 0u, 4));
+  RB_TRY(fill32(ctx, ctx->cnt1.p, 0u, T));
+  const float thr1sq = (float)(opts->thr1 * opts->thr1);
+  for (int32_t m = 0; m < it.nbases; ++m) {
+    RB_TRY(step_basis_outputs(ctx, it.bases[m], g, tw));
+    RB_TRY(stage1_gemm(ctx, it.bases[m], g, thr1sq, nullptr));
+  }
+  RB_HIP(launch_scan_counts(ctx->cnt1.as<int32_t>(), T, ctx->off1.as<int32_t>(), ctx->fill1.as<int32_t>(),
+                            ctx->list1.as<int32_t>(), sm, ctx->stream));
+  RB_TRY(fill32(ctx, ctx->cnt2.p, 0u, T));
+  RB_TRY(fill32(ctx, ctx->tmax.p, 0u, 2 * (int64_t)T));
+  // the low word of sm[1] (little-endian int64, < 2^31) is the stage-1 template count
+  RB_TRY(step_mf(ctx, bank, g, tw, ctx->list1.as<int32_t>(), T, (float)(opts->thr2 * opts->thr2),
+                 reinterpret_cast<const int32_t*>(sm + 1)));
+  RB_HIP(launch_scan_counts(ctx->cnt2.as<int32_t>(), T, ctx->off2.as<int32_t>(), ctx->fill2.as<int32_t>(),
+                            ctx->list2.as<int32_t>(), sm + 4, ctx->stream));
+  const int64_t cap2 = trig_capacity(ctx->trig2);
+  RB_HIP(launch_scatter_triggers(ctx->trig2.as<TrigRec>(), cap2, sm + 4, ctx->off2.as<int32_t>(),
+                                 ctx->fill2.as<int32_t>(), ctx->recs.as<TrigRec>(), ctx->stream));
+  RB_HIP(launch_segment_sort(ctx->recs.as<TrigRec>(), ctx->tmp.as<TrigRec>(), ctx->off2.as<int32_t>(),
+                             ctx->cnt2.as<int32_t>(), ctx->list2.as<int32_t>(), T, out, sm + 4, cap_item,
+                             ctx->stream));
+  return RB_OK;
+}
+
+rb_status enqueue_all(rb_ctx ctx, int32_t n, const rb_batch_item* items, const rb_filter_opts* opts,
+                      int64_t cap_item) {
+  for (int32_t i = 0; i < n; ++i)
+    RB_TRY(enqueue_item(ctx, items[i], opts, ctx->bsum.as<int64_t>() + 8 * (size_t)i,
+                        ctx->bout.as<rb_trigger>() + (size_t)i * cap_item, cap_item));
+  return RB_OK;
+}
+
+std::string batch_key(int32_t n, const rb_batch_item* items, const rb_filter_opts* opts, int64_t cap_item,
+                      rb_ctx ctx) {
+  std::string k;
+  auto add = [&](const void* p, size_t b) { k.append(static_cast<const char*>(p), b); };
+  add(&n, sizeof(n));
+  add(opts, sizeof(*opts));
+  add(&cap_item, sizeof(cap_item));
+  for (int32_t i = 0; i < n; ++i) {
+    add(&items[i].strain, sizeof(void*));
+    add(&items[i].bank, sizeof(void*));
+    add(&items[i].nbases, sizeof(int32_t));
+    for (int32_t m = 0; m < items[i].nbases; ++m) add(&items[i].bases[m], sizeof(void*));
+  }
+  const void* bufs[] = {ctx->work.p, ctx->work64.p, ctx->dspec.p, ctx->z.p, ctx->trig1.p, ctx->trig2.p,
+                        ctx->recs.p, ctx->tmp.p, ctx->bsum.p, ctx->bout.p, ctx->cnt1.p, ctx->cnt2.p};
+  add(bufs, sizeof(bufs));
+  return k;
+}
+
+}  // namespace
+
+extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_item* items,
+                                     const rb_filter_opts* opts, int32_t use_graph, rb_trigger* out,
+                                     int64_t cap_item, int64_t* n_out, rb_stats* stats) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(nitems >= 1 && items != nullptr && opts != nullptr && n_out != nullptr, RB_ERR_ARG, "NULL argument");
+  RB_CHECK(cap_item >= 0 && (out != nullptr || cap_item == 0), RB_ERR_ARG, "bad output buffer");
+  RB_CHECK(std::isfinite(opts->thr1) && opts->thr1 > 0, RB_ERR_ARG, "thr1 must be > 0");
+  RB_CHECK(std::isfinite(opts->thr2) && opts->thr2 >= opts->thr1, RB_ERR_ARG, "thr2 must be >= thr1");
+  RB_CHECK(opts->stage2 == RB_STAGE2_FULL && opts->reserved == 0, RB_ERR_ARG,
+           "batch search supports the full second stage only");
+  int Tmax = 0;
+  for (int32_t i = 0; i < nitems; ++i) {
+    const rb_batch_item& it = items[i];
+    RB_CHECK(it.bank != nullptr && it.bank->ctx == ctx, RB_ERR_ARG, "item bank is NULL or from another context");
+    RB_TRY(check_partition(ctx, it.bases, it.nbases, it.bank));
+    RB_CHECK(it.strain != nullptr && is_device_ptr(it.strain), RB_ERR_ARG,
+             "item " + std::to_string(i) + ": strain must be a device pointer");
+    Tmax = std::max(Tmax, it.bank->T);
+  }
+  RB_TRY(ensure_trigger_scratch(ctx, Tmax));
+  RB_TRY(ctx->bsum.ensure((size_t)nitems * 8 * 8));
+  RB_TRY(ctx->bout.ensure(std::max<size_t>(16, (size_t)nitems * cap_item * sizeof(rb_trigger))));
+  const size_t cap2 = (size_t)trig_capacity(ctx->trig2);
+  RB_TRY(ctx->recs.ensure(cap2 * sizeof(TrigRec)));
+  RB_TRY(ctx->tmp.ensure(cap2 * sizeof(TrigRec)));
+  std::vector<int64_t> sm((size_t)nitems * 8);
+  const bool tm = stats != nullptr;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    if (tm) RB_TRY(event(ctx, 0));
+    if (use_graph) {
+      std::string key = batch_key(nitems, items, opts, cap_item, ctx);
+      if (ctx->gkey != key || !ctx->gexec) {
+        // eager pass: sizes every buffer and fills every cache outside the capture
+        RB_TRY(enqueue_all(ctx, nitems, items, opts, cap_item));
+        RB_HIP(hipStreamSynchronize(ctx->stream));
+        key = batch_key(nitems, items, opts, cap_item, ctx);
+        if (!ctx->gstream) RB_HIP(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+        if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+        ctx->gexec = nullptr;
+        hipStream_t user = ctx->stream;
+        ctx->stream = ctx->gstream;
+        hipGraph_t graph = nullptr;
+        rb_status rs = RB_OK;
+        if (hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+          ctx->stream = user;
+          set_error("hipStreamBeginCapture failed");
+          return RB_ERR_DEVICE;
+        }
+        rs = enqueue_all(ctx, nitems, items, opts, cap_item);
+        const hipError_t ec = hipStreamEndCapture(ctx->gstream, &graph);
+        ctx->stream = user;
+        if (rs != RB_OK) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return rs;
+        }
+        RB_CHECK(ec == hipSuccess && graph != nullptr, RB_ERR_DEVICE, "graph capture failed");
+        const hipError_t ei = hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        RB_CHECK(ei == hipSuccess, RB_ERR_DEVICE, "hipGraphInstantiate failed");
+        ctx->gkey = key;
+      }
+      // order the replay after the caller's stream and the caller's stream after it
+      RB_TRY(event(ctx, 1));
+      RB_HIP(hipStreamWaitEvent(ctx->gstream, ctx->evs[1], 0));
+      RB_HIP(hipGraphLaunch(ctx->gexec, ctx->gstream));
+      RB_HIP(hipEventRecord(ctx->evs[1], ctx->gstream));
+      RB_HIP(hipStreamWaitEvent(ctx->stream, ctx->evs[1], 0));
+    } else {
+      RB_TRY(enqueue_all(ctx, nitems, items, opts, cap_item));
+    }
+    if (tm) RB_TRY(event(ctx, 2));
+    RB_HIP(hipMemcpyAsync(sm.data(), ctx->bsum.p, sm.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+    bool grow = false;
+    for (int32_t i = 0; i < nitems; ++i) {
+      const int64_t* q = &sm[8 * (size_t)i];
+      RB_CHECK(q[3] == 0, RB_ERR_NUMERIC, "item " + std::to_string(i) + ": strain contains non-finite values");
+      if (q[0] > trig_capacity(ctx->trig1)) {
+        RB_TRY(ctx->trig1.ensure((size_t)(q[0] + q[0] / 4) * sizeof(TrigRec)));
+        grow = true;
+      }
+      if (q[4] > trig_capacity(ctx->trig2)) {
+        const size_t c = (size_t)(q[4] + q[4] / 4);
+        RB_TRY(ctx->trig2.ensure(c * sizeof(TrigRec)));
+        RB_TRY(ctx->recs.ensure(c * sizeof(TrigRec)));
+        RB_TRY(ctx->tmp.ensure(c * sizeof(TrigRec)));
+        grow = true;
+      }
+    }
+    if (!grow) break;
+    ctx->gkey.clear();   // buffers moved: re-record
+  }
+  bool over = false;
+  for (int32_t i = 0; i < nitems; ++i) {
+    n_out[i] = sm[8 * (size_t)i + 4];
+    if (n_out[i] > cap_item) over = true;
+  }
+  if (!over) {
+    for (int32_t i = 0; i < nitems; ++i)
+      RB_TRY(copy_out(ctx, out + (size_t)i * cap_item, ctx->bout.as<rb_trigger>() + (size_t)i * cap_item,
+                      (size_t)n_out[i] * sizeof(rb_trigger)));
+  }
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    for (int32_t i = 0; i < nitems; ++i) {
+      stats->n_stage1 += sm[8 * (size_t)i];
+      stats->n_refiltered += (int32_t)sm[8 * (size_t)i + 1];
+    }
+    stats->ms[6] = elapsed(ctx, 0, 2);
+  }
+  if (over) {
+    set_error("per-item trigger capacity " + std::to_string(cap_item) + " exceeded");
+    return RB_ERR_CAPACITY;
+  }
   return RB_OK;
 }

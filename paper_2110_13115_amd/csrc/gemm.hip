@@ -28,6 +28,7 @@ constexpr int WT_ROWB = 2;       // 32-row MFMA blocks per wave (= 32 templates)
 constexpr int WT_COLB = 2;       // 32-column MFMA blocks per wave (= 64 samples)
 constexpr int TILE_T = WAVES * WT_ROWB * 16;   // templates per workgroup (128)
 constexpr int TILE_N = WT_COLB * 32;           // samples per workgroup (64)
+constexpr size_t kLdsMax = 160 * 1024;         // gfx950 LDS per workgroup
 
 __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[WT_ROWB][WT_COLB],
                                          int rb0, int64_t q0) {
@@ -61,7 +62,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[
             const unsigned long long idx = base + __popcll(mask & ((1ull << lane) - 1ull));
             if ((int64_t)idx < a.trig_cap) {
               TrigRec t;
-              t.tmpl = j;
+              t.tmpl = a.tmpl_base + j;
               t.sample = n;
               t.re = re;
               t.im = im;
@@ -183,6 +184,62 @@ __global__ __launch_bounds__(256) void k_recon_16(GemmArgs a) {
   epilogue(a, acc, rb0, q0);
 }
 
+// 16-bit operands, Z tile staged in LDS.  One workgroup owns 64 samples and
+// loops over every 128-template tile of the (sub-)bank: the planar Z tile
+// (2Kp rows x 64 samples) is read from HBM once with 16-byte loads and stored
+// transposed (sample-major, reduction index contiguous, rows padded by 16 B)
+// so each lane's B fragment is a single 16-byte LDS read; the packed C tiles
+// come from L2.
+template <int DT>
+__global__ __launch_bounds__(256) void k_recon_16_lds(GemmArgs a) {
+  extern __shared__ uint16_t zs[];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t q0 = (int64_t)blockIdx.x * TILE_N;
+  const int Kp = a.Kp, KB = Kp / 8, R2 = 2 * Kp;
+  const int RS = R2 + 8;            // LDS row stride (u16) of one sample
+  const int64_t N = a.N;
+  const uint16_t* __restrict__ z = static_cast<const uint16_t*>(a.z);
+  for (int idx = threadIdx.x; idx < R2 * (TILE_N / 8); idx += 256) {
+    const int r = idx / (TILE_N / 8), c8 = (idx % (TILE_N / 8)) * 8;
+    const u16x8 v = *reinterpret_cast<const u16x8*>(z + (int64_t)r * N + q0 + c8);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) zs[(c8 + e) * RS + r] = v[e];
+  }
+  __syncthreads();
+  const u16x8* __restrict__ cpk = static_cast<const u16x8*>(a.cpk);
+  const int ntt = a.Tp / TILE_T;
+  for (int tt = 0; tt < ntt; ++tt) {
+    const int rb0 = tt * (TILE_T / 16) + wave * WT_ROWB;
+    f32x16 acc[WT_ROWB][WT_COLB];
+#pragma unroll
+    for (int rb = 0; rb < WT_ROWB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < WT_COLB; ++cb) acc[rb][cb] = (f32x16){};
+#pragma unroll 2
+    for (int kb = 0; kb < KB; ++kb) {
+      u16x8 av[WT_ROWB], bv[WT_COLB];
+#pragma unroll
+      for (int rb = 0; rb < WT_ROWB; ++rb) av[rb] = cpk[((int64_t)(rb0 + rb) * KB + kb) * 64 + lane];
+#pragma unroll
+      for (int cb = 0; cb < WT_COLB; ++cb)
+        bv[cb] = *reinterpret_cast<const u16x8*>(zs + (cb * 32 + (lane & 31)) * RS + 16 * kb + 8 * (lane >> 5));
+#pragma unroll
+      for (int rb = 0; rb < WT_ROWB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < WT_COLB; ++cb) {
+          if (DT == 1)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, av[rb]), __builtin_bit_cast(bf16x8, bv[cb]), acc[rb][cb], 0, 0, 0);
+          else
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                __builtin_bit_cast(f16x8, av[rb]), __builtin_bit_cast(f16x8, bv[cb]), acc[rb][cb], 0, 0, 0);
+        }
+    }
+    epilogue(a, acc, rb0, q0);
+  }
+}
+
 // ------------------------------------------------------------------ packing
 __device__ __forceinline__ uint16_t to16(float x, int dtype) {
   if (dtype == 1) {
@@ -245,9 +302,30 @@ hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
   if (a.Tp % TILE_T != 0 || a.N % TILE_N != 0) return hipErrorInvalidValue;
   const int64_t nwg = (int64_t)(a.Tp / TILE_T) * (a.N / TILE_N);
   const int64_t launch = ((nwg + 7) / 8) * 8;
-  if (a.dtype == 0)
+  if (a.dtype == 0) {
     hipLaunchKernelGGL(k_recon_f32, dim3((unsigned)launch), dim3(256), 0, st, a);
-  else if (a.dtype == 1)
+    return hipGetLastError();
+  }
+  const size_t lds = (size_t)TILE_N * (2 * a.Kp + 8) * 2;
+  if (lds <= kLdsMax) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_recon_16_lds<1>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_recon_16_lds<2>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+    const unsigned grid = (unsigned)(a.N / TILE_N);
+    if (a.dtype == 1)
+      hipLaunchKernelGGL(k_recon_16_lds<1>, dim3(grid), dim3(256), lds, st, a);
+    else
+      hipLaunchKernelGGL(k_recon_16_lds<2>, dim3(grid), dim3(256), lds, st, a);
+    return hipGetLastError();
+  }
+  if (a.dtype == 1)
     hipLaunchKernelGGL(k_recon_16<1>, dim3((unsigned)launch), dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL(k_recon_16<2>, dim3((unsigned)launch), dim3(256), 0, st, a);

@@ -118,7 +118,8 @@ struct GemmArgs {
   TrigRec* trig;
   int64_t trig_cap;
   unsigned long long* trig_count;
-  int32_t* tmpl_count;
+  int tmpl_base;             // global index of local template 0 (sub-bank bases)
+  int32_t* tmpl_count;       // per local template (already offset by tmpl_base)
   float2* rho_out;           // debug: natural order T x N, or NULL
   const float* row_inv;      // per-template 1/scale applied to rho_out (16-bit), or NULL
 };
@@ -132,22 +133,41 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 // summary (device, 3 x int64): total, number of listed templates, max count
 hipError_t launch_scan_counts(const int32_t* counts, int T, int32_t* offsets, int32_t* fill,
                               int32_t* list, int64_t* summary, hipStream_t s);
-hipError_t launch_scatter_triggers(const TrigRec* in, int64_t n, const int32_t* offsets,
-                                   int32_t* fill, TrigRec* out, hipStream_t s);
+// n_dev / summary_dev: optional device-side counts (graph-capturable form);
+// n / nlist are then upper bounds used to size the launch.
+hipError_t launch_scatter_triggers(const TrigRec* in, int64_t n, const int64_t* n_dev,
+                                   const int32_t* offsets, int32_t* fill, TrigRec* out,
+                                   hipStream_t s);
 hipError_t launch_segment_sort(TrigRec* recs, TrigRec* tmp, const int32_t* offsets,
                                const int32_t* counts, const int32_t* list, int nlist, void* out,
-                               hipStream_t s);
+                               const int64_t* summary_dev, int64_t out_cap, hipStream_t s);
 hipError_t launch_peaks_from_max(const unsigned long long* tmax, int T, void* out_peaks,
                                  hipStream_t s);
 hipError_t launch_cluster_peaks(const void* trig, int64_t n, int W, int64_t N, uint8_t* is_peak,
                                 hipStream_t s);
-hipError_t launch_sparse_exact(const TrigRec* cand, int64_t ncand, const int32_t* offsets,
-                               const int32_t* counts, const int32_t* list, const int32_t* nlist,
-                               int T, const float2* d, const float2* tmpl, int64_t kb, int64_t nbs,
-                               const int32_t* sup_lo, const int32_t* sup_hi, int64_t N,
-                               float thr2, TrigRec* out, int64_t cap,
-                               unsigned long long* out_count, int32_t* tmpl_count,
-                               unsigned long long* tmpl_max, hipStream_t s);
+struct SparseArgs {
+  int64_t N;
+  int s_lo;
+  const float2* tlo;          // FP32 inter-pass twiddle tables (as the FFT's)
+  const float2* thi;
+  const int32_t* list;        // selected templates
+  const int32_t* d_count;     // optional device count of `list`
+  const int32_t* offsets;     // stage-1 records grouped by template: offsets / counts
+  const int32_t* counts;
+  const TrigRec* recs;
+  const float2* d;            // whitened data from kb
+  const float2* tmpl;         // bank templates (stride nbs, from kb)
+  int64_t kb, nbs;
+  const int32_t* sup_lo;
+  const int32_t* sup_hi;
+  float thr2;                 // squared final threshold
+  TrigRec* out;
+  int64_t out_cap;
+  unsigned long long* out_count;
+  int32_t* tmpl_count;
+  unsigned long long* tmpl_max;
+};
+hipError_t launch_sparse_exact(const SparseArgs& a, int grid, hipStream_t s);
 
 // ---------------------------------------------------------------- FP64 complex GEMM
 // C[m][n] (+)= sum_k opA(A)[m][k] * opB(B)[k][n], complex128 accumulation.

@@ -1,0 +1,132 @@
+// Sparse exact second stage: for every template j selected by the first stage,
+// the exact complex SNR (Eq. IFFT, discretised as in the template method)
+//   rho_j[n] = sum_{f in support_j} d[f] conj(w_j[f]) e^{+2 pi i f n / N}
+// evaluated only at the samples n where the first stage crossed (direct
+// frequency sums instead of a full inverse FFT).  Every final trigger
+// (|rho| >= thr2 >= thr1) is a first-stage crossing as long as the first-stage
+// reconstruction error stays below thr2 - thr1, so the final trigger set equals
+// the template method's.
+//
+// One workgroup per selected template streams w_j once per group of up to
+// SP_M crossings.  A thread owns 8 consecutive bins of each 2048-bin tile:
+// the twiddle of its first bin comes exactly from the two-level table
+// (e = f n mod N), the next seven by multiplication with e^{2 pi i n / N}
+// (error <= 8 ulp).
+#include "internal.h"
+
+namespace rbmf {
+
+namespace {
+
+constexpr int SP_T = 256;      // threads
+constexpr int SP_R = 8;        // consecutive bins per thread and tile
+constexpr int SP_M = 8;        // crossings per pass
+
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
+  __shared__ float2 tlo[2048];
+  __shared__ float2 thi[1024];
+  __shared__ float2 red[SP_M][SP_T / 64];
+  if (a.d_count != nullptr && (int)blockIdx.x >= *a.d_count) return;
+  const int j = a.list[blockIdx.x];
+  const int nlo = 1 << a.s_lo, nhi = (int)(a.N >> a.s_lo);
+  for (int i = threadIdx.x; i < nlo; i += SP_T) tlo[i] = a.tlo[i];
+  for (int i = threadIdx.x; i < nhi; i += SP_T) thi[i] = a.thi[i];
+  __syncthreads();
+  const int mask = nlo - 1;
+  const int64_t Nm = a.N - 1;
+  auto tw = [&](int64_t e) { return cmulf(thi[(e & Nm) >> a.s_lo], tlo[e & mask]); };
+  const int lo = a.sup_lo[j], hi = a.sup_hi[j];
+  const int off = a.offsets[j], cnt = a.counts[j];
+  const float2* __restrict__ wj = a.tmpl + (int64_t)j * a.nbs - a.kb;   // indexed by absolute bin
+  const float2* __restrict__ d = a.d - a.kb;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned long long best = 0ull;
+  for (int c0 = 0; c0 < cnt; c0 += SP_M) {
+    const int m = min(SP_M, cnt - c0);
+    int ns[SP_M];
+    float2 step[SP_M], acc[SP_M];
+#pragma unroll
+    for (int i = 0; i < SP_M; ++i) {
+      ns[i] = i < m ? a.recs[off + c0 + i].sample : 0;
+      step[i] = tw(ns[i]);
+      acc[i] = make_float2(0.f, 0.f);
+    }
+    for (int f0 = lo + threadIdx.x * SP_R; f0 <= hi; f0 += SP_T * SP_R) {
+      float2 x[SP_R];
+#pragma unroll
+      for (int r = 0; r < SP_R; ++r) {
+        const int f = f0 + r;
+        if (f <= hi) {
+          const float2 dv = d[f], wv = wj[f];
+          x[r] = make_float2(dv.x * wv.x + dv.y * wv.y, dv.y * wv.x - dv.x * wv.y);   // d conj(w)
+        } else {
+          x[r] = make_float2(0.f, 0.f);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < SP_M; ++i) {
+        if (i < m) {
+          float2 w = tw((int64_t)f0 * ns[i]);
+#pragma unroll
+          for (int r = 0; r < SP_R; ++r) {
+            acc[i].x += x[r].x * w.x - x[r].y * w.y;
+            acc[i].y += x[r].x * w.y + x[r].y * w.x;
+            w = cmulf(w, step[i]);
+          }
+        }
+      }
+    }
+    // workgroup reduction of the m accumulators
+#pragma unroll
+    for (int i = 0; i < SP_M; ++i) {
+      float re = acc[i].x, im = acc[i].y;
+      for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_xor(re, o);
+        im += __shfl_xor(im, o);
+      }
+      if (lane == 0) red[i][wave] = make_float2(re, im);
+    }
+    __syncthreads();
+    if (threadIdx.x < SP_M && (int)threadIdx.x < m) {
+      const int i = threadIdx.x;
+      float re = 0.f, im = 0.f;
+      for (int w = 0; w < SP_T / 64; ++w) {
+        re += red[i][w].x;
+        im += red[i][w].y;
+      }
+      const float p = re * re + im * im;
+      const int n = ns[i];
+      const unsigned long long key =
+          ((unsigned long long)__float_as_uint(p) << 32) | (unsigned long long)(0xffffffffu - (uint32_t)n);
+      best = key > best ? key : best;
+      if (p >= a.thr2) {
+        const unsigned long long idx = atomicAdd(a.out_count, 1ull);
+        atomicAdd(&a.tmpl_count[j], 1);
+        if ((int64_t)idx < a.out_cap) {
+          TrigRec t;
+          t.tmpl = j;
+          t.sample = n;
+          t.re = re;
+          t.im = im;
+          a.out[idx] = t;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < SP_M && best != 0ull) atomicMax(&a.tmpl_max[j], best);
+}
+
+}  // namespace
+
+hipError_t launch_sparse_exact(const SparseArgs& a, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sparse_exact, dim3(grid), dim3(SP_T), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace rbmf

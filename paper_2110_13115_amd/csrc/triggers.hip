@@ -84,8 +84,14 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_counts(const int32_t* counts, i
   }
 }
 
-__global__ void k_scatter(const TrigRec* in, int64_t n, const int32_t* offsets, int32_t* fill,
-                          TrigRec* out) {
+// n_dev (optional): device record count; nothing is scattered when it exceeds
+// n (records were dropped at capacity; the caller reports it).
+__global__ void k_scatter(const TrigRec* in, int64_t n, const int64_t* n_dev, const int32_t* offsets,
+                          int32_t* fill, TrigRec* out) {
+  if (n_dev != nullptr) {
+    if (*n_dev > n) return;
+    n = *n_dev;
+  }
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const TrigRec r = in[i];
     const int pos = offsets[r.tmpl] + atomicAdd(&fill[r.tmpl], 1);
@@ -126,10 +132,15 @@ __device__ void lds_bitonic(int2* s, int n2) {
 // sorted in LDS; longer ones are sorted in runs of SEG_LDS and merged in
 // global memory (ping-pong between recs and tmp, merge by rank: keys are
 // distinct samples).
+// summary_dev (optional, graph mode): {total, nlist, ...} on the device; the
+// grid then covers every template, workgroups beyond nlist exit, and nothing
+// is written when total exceeds out_cap.
 __global__ __launch_bounds__(1024) void k_segment_sort(TrigRec* recs, TrigRec* tmp, const int32_t* offsets,
                                                        const int32_t* counts, const int32_t* list,
-                                                       rb_trigger* out) {
+                                                       rb_trigger* out, const int64_t* summary_dev,
+                                                       int64_t out_cap) {
   __shared__ int2 s[SEG_LDS];
+  if (summary_dev != nullptr && (blockIdx.x >= summary_dev[1] || summary_dev[0] > out_cap)) return;
   const int j = list[blockIdx.x];
   const int off = offsets[j];
   const int c = counts[j];
@@ -255,20 +266,21 @@ hipError_t launch_scan_counts(const int32_t* counts, int T, int32_t* offsets, in
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_triggers(const TrigRec* in, int64_t n, const int32_t* offsets, int32_t* fill,
-                                   TrigRec* out, hipStream_t s) {
+hipError_t launch_scatter_triggers(const TrigRec* in, int64_t n, const int64_t* n_dev, const int32_t* offsets,
+                                   int32_t* fill, TrigRec* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int64_t g = (n + 255) / 256;
   if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)g), dim3(256), 0, s, in, n, offsets, fill, out);
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)g), dim3(256), 0, s, in, n, n_dev, offsets, fill, out);
   return hipGetLastError();
 }
 
 hipError_t launch_segment_sort(TrigRec* recs, TrigRec* tmp, const int32_t* offsets, const int32_t* counts,
-                               const int32_t* list, int nlist, void* out, hipStream_t s) {
+                               const int32_t* list, int nlist, void* out, const int64_t* summary_dev,
+                               int64_t out_cap, hipStream_t s) {
   if (nlist <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_segment_sort, dim3(nlist), dim3(1024), 0, s, recs, tmp, offsets, counts, list,
-                     static_cast<rb_trigger*>(out));
+                     static_cast<rb_trigger*>(out), summary_dev, out_cap);
   return hipGetLastError();
 }
 

@@ -255,10 +255,15 @@ class Bank:
 
 
 def random_bank(cfg: int, T: int, N: int, fs: float, f_low: float, mmin: float, mmax: float,
-                order: int) -> Bank:
-    """m1, m2 i.i.d. uniform in [mmin, mmax] (seed purpose 0)."""
+                order: int, sort_tau0: bool = False) -> Bank:
+    """m1, m2 i.i.d. uniform in [mmin, mmax] (seed purpose 0); optionally
+    ordered by tau0 at f_low so that sub-banks are contiguous tau0 slices (the
+    split of Sec. III.B)."""
     rng = rng_for(cfg, PURPOSE_BANK)
     m = rng.uniform(mmin, mmax, size=(T, 2))
+    if sort_tau0:
+        t0 = np.array([tau0(a, b, f_low) for a, b in m])
+        m = m[np.argsort(t0, kind="stable")]
     return Bank(N, fs, f_low, m[:, 0].copy(), m[:, 1].copy(), order)
 
 
@@ -330,6 +335,8 @@ class Workload:
     thr2: float = 6.0
     inj_snrs: Tuple[float, ...] = ()
     on_bank: bool = True
+    subbanks: int = 1              # equal tau0-ordered sub-banks, one basis each
+    ranks: Tuple[int, ...] = ()    # fixed rank per sub-bank (empty: by energy / `rank`)
 
     @property
     def seconds(self) -> float:
@@ -337,17 +344,26 @@ class Workload:
 
     def bank(self) -> Bank:
         return random_bank(self.cfg, self.T, self.N, self.fs, self.f_low, self.mmin, self.mmax,
-                           self.order)
+                           self.order, sort_tau0=self.subbanks > 1)
+
+    def bounds(self) -> List[int]:
+        """Sub-bank template boundaries [0, ..., T]."""
+        return [int(round(i * self.T / self.subbanks)) for i in range(self.subbanks + 1)]
+
+    def sub_ranks(self) -> List[int]:
+        return list(self.ranks) if self.ranks else [self.rank] * self.subbanks
 
 
 WORKLOADS = {
     # 64 templates, 0PN, 16 s at 2048 Hz, f_low 30 Hz, one on-bank injection at SNR 10
     "full_mf_16s_64t": Workload("full_mf_16s_64t", 1, 32768, 2048.0, 30.0, 64, 5.0, 20.0, 0,
                                 thr1=5.0, thr2=6.0, inj_snrs=(10.0,)),
-    # 2000 templates, 3.5PN, 256 s, f_low 20 Hz, >= 0.999 energy basis, 8 off-bank injections
+    # 2000 templates, 3.5PN, 256 s, f_low 20 Hz, 8 off-bank injections; split along tau0
+    # into 10 sub-banks of 200, each basis keeping >= 0.999 of its energy
     "rb_256s_2000t": Workload("rb_256s_2000t", 2, 524288, 2048.0, 20.0, 2000, 1.0, 3.0, 7,
                               tol=1e-3, thr1=5.0, thr2=6.0,
-                              inj_snrs=(5.0, 6.0, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0), on_bank=False),
+                              inj_snrs=(5.0, 6.0, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0), on_bank=False,
+                              subbanks=10),
     # 10000 templates, 0PN, 16 s, f_low 30 Hz, m in [1, 20]
     "rb_16s_10000t": Workload("rb_16s_10000t", 3, 32768, 2048.0, 30.0, 10000, 1.0, 20.0, 0,
                               tol=1e-3, thr1=5.0, thr2=6.0, inj_snrs=(10.0,)),

@@ -23,8 +23,9 @@ RB_STAGE2_FULL, RB_STAGE2_SPARSE = 0, 1
 DTYPES = {"f32": RB_F32, "bf16": RB_BF16, "f16": RB_F16}
 
 FUNCTIONS = ["rb_ctx_create", "rb_ctx_destroy", "rb_last_error", "rb_bank_create", "rb_bank_free",
-             "rb_bank_info", "rb_build_basis", "rb_basis_free", "rb_basis_export", "rb_filter",
-             "mf_full", "rb_rho_at", "rb_backward", "rb_cluster_peaks", "rb_debug_rho",
+             "rb_bank_info", "rb_build_basis", "rb_build_basis_range", "rb_basis_info",
+             "rb_basis_free", "rb_basis_export", "rb_filter",
+             "rb_filter_batch", "mf_full", "rb_rho_at", "rb_backward", "rb_cluster_peaks", "rb_debug_rho",
              "rb_debug_basis_outputs"]
 
 
@@ -83,11 +84,16 @@ def lib():
         L.rb_bank_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i64), vp]
         L.rb_build_basis.argtypes = [vp, vp, i32, dbl, C.c_int, C.POINTER(vp), C.POINTER(i32),
                                      C.POINTER(dbl)]
+        L.rb_build_basis_range.argtypes = [vp, vp, i32, i32, i32, dbl, C.c_int, C.POINTER(vp),
+                                           C.POINTER(i32), C.POINTER(dbl)]
+        L.rb_basis_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl)]
         L.rb_basis_free.argtypes = [vp]
         L.rb_basis_export.argtypes = [vp, vp, vp, vp]
-        L.rb_filter.argtypes = [vp, vp, vp, vp, C.POINTER(FilterOpts), vp, i64, C.POINTER(i64), vp,
-                                C.POINTER(Stats)]
+        L.rb_filter.argtypes = [vp, C.POINTER(vp), i32, vp, vp, C.POINTER(FilterOpts), vp, i64,
+                                C.POINTER(i64), vp, C.POINTER(Stats)]
         L.mf_full.argtypes = [vp, vp, vp, dbl, vp, i64, C.POINTER(i64), vp, C.POINTER(Stats)]
+        L.rb_filter_batch.argtypes = [vp, i32, vp, C.POINTER(FilterOpts), i32, vp, i64, C.POINTER(i64),
+                                      C.POINTER(Stats)]
         L.rb_rho_at.argtypes = [vp, vp, vp, vp, i64, vp, vp]
         L.rb_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, C.POINTER(dbl)]
         L.rb_cluster_peaks.argtypes = [vp, vp, i64, i32, i64, vp]
@@ -187,21 +193,27 @@ class Bank:
 
 
 class Basis:
-    def __init__(self, ctx: Context, bank: Bank, rank: int = 0, tol: float = 1e-3, dtype="f32"):
+    """Reduced basis of templates [t0, t1) of a bank (default: the whole bank)."""
+
+    def __init__(self, ctx: Context, bank: Bank, rank: int = 0, tol: float = 1e-3, dtype="f32",
+                 t0: int = 0, t1: Optional[int] = None):
         self.ctx, self.bank = ctx, bank
+        self.t0 = int(t0)
+        self.t1 = bank.T if t1 is None else int(t1)
+        self.T = self.t1 - self.t0
         self.h = C.c_void_p()
         K = C.c_int32()
         e = C.c_double()
         dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
-        _check(lib().rb_build_basis(ctx.h, bank.h, int(rank), float(tol), dt, C.byref(self.h),
-                                    C.byref(K), C.byref(e)), "rb_build_basis")
+        _check(lib().rb_build_basis_range(ctx.h, bank.h, self.t0, self.t1, int(rank), float(tol), dt,
+                                          C.byref(self.h), C.byref(K), C.byref(e)), "rb_build_basis_range")
         self.K, self.energy, self.dtype = K.value, e.value, dt
 
     def export(self):
         _, klo, khi, _ = self.bank.info()
         nb = khi - klo + 1
         V = np.empty((self.K, nb), dtype=np.complex128)
-        c = np.empty((self.bank.T, self.K), dtype=np.complex128)
+        c = np.empty((self.T, self.K), dtype=np.complex128)
         lam = np.empty(self.K, dtype=np.float64)
         _check(lib().rb_basis_export(self.h, _ptr(V), _ptr(c), _ptr(lam)), "rb_basis_export")
         return V, c, lam
@@ -225,10 +237,22 @@ def _as_np_triggers(buf, n: int) -> np.ndarray:
     return buf[:n].cpu().numpy().view(TRIGGER_NP).reshape(-1)
 
 
-def rb_filter(ctx: Context, basis: Basis, bank: Bank, strain, thr1: float, thr2: float,
+def subbank_bases(ctx: Context, bank: Bank, bounds, rank=0, tol: float = 1e-3, dtype="f32"):
+    """One basis per sub-bank; bounds = [0, b1, ..., T]; rank an int or a list."""
+    ranks = rank if isinstance(rank, (list, tuple)) else [rank] * (len(bounds) - 1)
+    return [Basis(ctx, bank, rank=r, tol=tol, dtype=dtype, t0=a, t1=b)
+            for a, b, r in zip(bounds[:-1], bounds[1:], ranks)]
+
+
+def rb_filter(ctx: Context, bases, bank: Bank, strain, thr1: float, thr2: float,
               stage2: int = RB_STAGE2_FULL, cap: int = 1 << 20, peaks: bool = False,
               out=None):
-    """Returns (triggers as a TRIGGER_NP array, peaks or None, Stats)."""
+    """bases: one Basis or a list partitioning the bank.  Returns (triggers as a
+    TRIGGER_NP array, or their count when `out` is a device buffer; peaks or
+    None; Stats)."""
+    if isinstance(bases, Basis):
+        bases = [bases]
+    arr = (C.c_void_p * len(bases))(*[b.h.value for b in bases])
     o = FilterOpts(thr1, thr2, stage2, 0)
     dev = out is not None and not isinstance(out, np.ndarray)
     buf = out if out is not None else _triggers_out(cap, False)
@@ -236,8 +260,8 @@ def rb_filter(ctx: Context, basis: Basis, bank: Bank, strain, thr1: float, thr2:
     n = C.c_int64()
     pk = np.empty(bank.T, dtype=PEAK_NP) if peaks else None
     st = Stats()
-    _check(lib().rb_filter(ctx.h, basis.h, bank.h, _ptr(strain), C.byref(o), _ptr(buf), cap, C.byref(n),
-                           _ptr(pk), C.byref(st)), "rb_filter")
+    _check(lib().rb_filter(ctx.h, arr, len(bases), bank.h, _ptr(strain), C.byref(o), _ptr(buf), cap,
+                           C.byref(n), _ptr(pk), C.byref(st)), "rb_filter")
     return _as_np_triggers(buf, n.value) if not dev else n.value, pk, st
 
 
@@ -309,3 +333,35 @@ def debug_basis_outputs(ctx: Context, basis: Basis, strain) -> np.ndarray:
     z = np.empty((basis.K, basis.bank.N), dtype=np.complex64)
     _check(lib().rb_debug_basis_outputs(ctx.h, basis.h, _ptr(strain), _ptr(z)), "rb_debug_basis_outputs")
     return z
+
+
+class BatchItem(C.Structure):
+    _fields_ = [("strain", C.c_void_p), ("bank", C.c_void_p), ("bases", C.POINTER(C.c_void_p)),
+                ("nbases", C.c_int32)]
+
+
+def rb_filter_batch(ctx: Context, items, thr1: float, thr2: float, use_graph: bool = True,
+                    cap_item: int = 1 << 16, out=None):
+    """items: list of (device strain tensor, Bank, [Basis, ...]).  Returns
+    (list of per-item TRIGGER_NP arrays, Stats); with a device `out` buffer
+    (nitems * cap_item x 4 int32) returns (counts, Stats) instead."""
+    n = len(items)
+    keep = []
+    arr = (BatchItem * n)()
+    for i, (s, bank, bases) in enumerate(items):
+        if isinstance(bases, Basis):
+            bases = [bases]
+        bp = (C.c_void_p * len(bases))(*[b.h.value for b in bases])
+        keep.append(bp)
+        arr[i] = BatchItem(_ptr(s), bank.h.value, C.cast(bp, C.POINTER(C.c_void_p)), len(bases))
+    o = FilterOpts(thr1, thr2, RB_STAGE2_FULL, 0)
+    dev = out is not None and not isinstance(out, np.ndarray)
+    buf = out if out is not None else np.empty(max(1, n * cap_item), dtype=TRIGGER_NP)
+    counts = (C.c_int64 * n)()
+    st = Stats()
+    _check(lib().rb_filter_batch(ctx.h, n, arr, C.byref(o), int(use_graph), _ptr(buf), cap_item, counts,
+                                 C.byref(st)), "rb_filter_batch")
+    cnt = [counts[i] for i in range(n)]
+    if dev:
+        return cnt, st
+    return [buf[i * cap_item:i * cap_item + cnt[i]].copy() for i in range(n)], st

@@ -58,7 +58,7 @@ def test_error_paths_without_gpu():
     assert st == rbmf.RB_ERR_DEVICE
     assert len(L.rb_last_error()) > 0
     n = C.c_int64()
-    assert L.rb_filter(None, None, None, None, None, None, 0, C.byref(n), None, None) == rbmf.RB_ERR_ARG
+    assert L.rb_filter(None, None, 0, None, None, None, None, 0, C.byref(n), None, None) == rbmf.RB_ERR_ARG
     assert L.mf_full(None, None, None, 5.0, None, 0, C.byref(n), None, None) == rbmf.RB_ERR_ARG
 
 

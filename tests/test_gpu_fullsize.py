@@ -1,6 +1,6 @@
 """Parity at the benchmark's full size (256 s at 2048 Hz, N = 2^19, 2000
-3.5PN templates, >= 0.999-energy basis, thresholds 5.0 / 6.0), in the launch
-configuration bench.py times.  The oracle cannot hold all 2000 SNR series, so
+3.5PN templates in 10 tau0-ordered sub-banks, one >= 0.999-energy basis per
+sub-bank, thresholds 5.0 / 6.0), in the launch configuration bench.py times.  The oracle cannot hold all 2000 SNR series, so
 it is evaluated template by template on:
   * every template that appears in either GPU trigger list (exact set and SNR
     comparison over all N samples of those templates), and
@@ -61,12 +61,12 @@ def check_against_oracle(trig, rows, thr):
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_fullsize_rb_and_mf_vs_oracle(full, dtype):
     wl, bank_def, psd, strain, inj, ctx, bank = full
-    basis = rbmf.Basis(ctx, bank, rank=0, tol=wl.tol, dtype=dtype)
-    log(dtype, "K", basis.K, "energy", basis.energy)
-    assert basis.energy >= 1 - wl.tol
+    bases = rbmf.subbank_bases(ctx, bank, wl.bounds(), rank=wl.sub_ranks(), tol=wl.tol, dtype=dtype)
+    log(dtype, "K per sub-bank", [b.K for b in bases])
+    assert all(b.energy >= 1 - wl.tol for b in bases)
     import torch
     sd = torch.from_numpy(strain).cuda()
-    rb, _, st = rbmf.rb_filter(ctx, basis, bank, sd, wl.thr1, wl.thr2)
+    rb, _, st = rbmf.rb_filter(ctx, bases, bank, sd, wl.thr1, wl.thr2)
     mf, _, _ = rbmf.mf_full(ctx, bank, sd, wl.thr2)
     log("rb final", len(rb), "stage1", st.n_stage1, "refiltered", st.n_refiltered, "mf", len(mf))
     templates = set(rb["tmpl"].tolist()) | set(mf["tmpl"].tolist())
@@ -78,9 +78,14 @@ def test_fullsize_rb_and_mf_vs_oracle(full, dtype):
     log("rb vs oracle", n_o, n_g, "band", n_b)
     n_o2, n_g2, _ = check_against_oracle(mf, rows, wl.thr2)
     log("mf vs oracle", n_o2, n_g2)
+    sp, _, _ = rbmf.rb_filter(ctx, bases, bank, sd, wl.thr1, wl.thr2, stage2=rbmf.RB_STAGE2_SPARSE)
+    assert set(sp["tmpl"].tolist()) <= set(rows)
+    check_against_oracle(sp, rows, wl.thr2)
+    log("sparse vs oracle ok", len(sp))
     # report how the off-bank injections are recovered by this (random, sparse) bank
     for i in inj:
         near = rb[np.abs(((rb["sample"].astype(np.int64) - i.n0 + wl.N // 2) % wl.N) - wl.N // 2) < 2048]
         log(f"  injection SNR {i.snr:.1f} at {i.n0}: {len(near)} final triggers within 1 s, "
             f"max {near['snr'].max() if len(near) else 0:.2f}")
-    basis.close()
+    for b in bases:
+        b.close()

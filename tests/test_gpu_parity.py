@@ -192,6 +192,14 @@ def test_rb_filter_final_triggers(ctx, rb_case):
     assert np.all(peaks["snr"][~ev] == -1)
     t2, _, _ = rbmf.rb_filter(ctx, basis, bank, case.strain, 5.0, 6.0)
     assert t2.tobytes() == trig.tobytes()
+    # sparse exact second stage: same final set, SNRs to 1e-4, peaks over evaluated samples
+    ts, pks, sts = rbmf.rb_filter(ctx, basis, bank, case.strain, 5.0, 6.0, stage2=rbmf.RB_STAGE2_SPARSE,
+                                  peaks=True)
+    compare_triggers(ts, case.rho, 6.0)
+    assert np.array_equal(ts[["tmpl", "sample"]], trig[["tmpl", "sample"]])
+    assert sts.n_refiltered == st.n_refiltered
+    ev = pks["snr"] >= 0
+    assert ev.sum() == st.n_refiltered
     with pytest.raises(rbmf.RbError) as ei:
         rbmf.rb_filter(ctx, basis, bank, case.strain, 6.0, 5.0)
     assert ei.value.status == rbmf.RB_ERR_ARG
