@@ -91,7 +91,22 @@ def main():
     ap.add_argument("--workload", default="rb_256s_2000t")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-16bit", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline rb_filter call (for profiler runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run one plain device-to-device copy of MIB MiB and exit (scales HBM byte "
+                         "counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 18            # float32 elements in MIB MiB
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 4}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); the path "
               "shards by segment / sub-bank / template with no exchange on the forward path, but no "
@@ -137,6 +152,10 @@ def main():
     log(f"rb_filter f32: {t_rb * 1e3:.2f} ms/step, final {n_rb}, stage-1 {s1[-1]}, refiltered "
         f"{nref[-1]}, stage ms {[round(x, 3) for x in st_rb.ms[:7]]}")
 
+    if args.headline_only:
+        print(json.dumps({"rb_filter_ms_per_step": t_rb * 1e3, "gemm_ms": float(np.mean(gemm_ms)),
+                          "stage_ms": [round(x, 4) for x in st_rb.ms[:7]], "ranks": ranks}), flush=True)
+        return
     # --- comparator: full matched filter on the same GPU
     t_mf, (n_mf, _, st_mf) = time_calls(mf_step, args.steps, args.warmup, torch)
     mf_trig = out[:n_mf].cpu().numpy().view(rbmf.TRIGGER_NP).reshape(-1).copy()

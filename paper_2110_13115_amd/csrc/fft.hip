@@ -111,13 +111,33 @@ struct Dft<1, S> {
   static __device__ __forceinline__ void run(V*) {}
 };
 
+// Powers w^r, r = 0..R-1 (R <= 16), from the table entries w^1, w^2, w^4, w^8
+// and at most three products each (a few ulp), instead of R-1 table gathers.
+// base(p) must return the table entry for exponent multiplier p in {1,2,4,8}.
+template <int R, class V, class Base>
+__device__ __forceinline__ void powers(V* w, Base&& base) {
+  w[0] = mk<V>(1, 0);
+  if (R > 1) w[1] = base(1);
+  if (R > 2) w[2] = base(2);
+  if (R > 4) w[4] = base(4);
+  if (R > 8) w[8] = base(8);
+#pragma unroll
+  for (int r = 3; r < R; ++r) {
+    if (r == 4 || r == 8) continue;
+    const int hb = (r >= 8) ? 8 : (r >= 4 ? 4 : 2);   // highest power of two <= r
+    w[r] = cmul(w[hb], w[r - hb]);
+  }
+}
+
 // Stage twiddles: input r of a butterfly with k = j mod Ns gets
 // e^{S 2 pi i r k / (Ns R)} = pyr[Ns R + r k].
 template <int R, int Ns, int S, class V>
 __device__ __forceinline__ void apply_stage_tw(V* v, int k, const V* __restrict__ pyr) {
   if (Ns == 1) return;
+  V w[R];
+  powers<R>(w, [&](int p) { return signed_tw<S>(pyr[Ns * R + p * k]); });
 #pragma unroll
-  for (int r = 1; r < R; ++r) v[r] = cmul(v[r], signed_tw<S>(pyr[Ns * R + r * k]));
+  for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
 }
 
 // ------------------------------------------------------------------ layouts
@@ -301,12 +321,38 @@ __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
   const V* __restrict__ thi = PassPtr<V>::thi(a);
   const V* __restrict__ tlo = PassPtr<V>::tlo(a);
   V* __restrict__ outv = PassPtr<V>::work(a) + (int64_t)bv * a.g.N;
-  final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int c, int n2, V val, int) {
-    const int f1 = f1_0 + c;
-    const int64_t e = (int64_t)f1 * n2;
-    const V w = cmul(thi[e >> s_lo], tlo[e & mask]);
-    outv[(int64_t)n2 * N1 + f1] = cmul(val, signed_tw<S>(w));
-  });
+  {
+    // outputs n2 = j + m Ns of column f1 get w^{f1 n2} = w^{f1 j} (w^{f1 Ns})^m
+    constexpr int Ns = L / RL;
+    constexpr int NB = Lay::NF * L / RL;
+    constexpr int PER = (NB + NT - 1) / NT;
+    auto twe = [&](int64_t e) { return signed_tw<S>(cmul(thi[e >> s_lo], tlo[e & mask])); };
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int b = tid + i * NT;
+      if (b < NB) {
+        int c, j;
+        Lay::template split<RL>(b, c, j);
+        V v[RL];
+#pragma unroll
+        for (int r = 0; r < RL; ++r) v[r] = lds[Lay::addr(c, j + r * Ns)];
+        apply_stage_tw<RL, Ns, S>(v, j, pyr);
+        Dft<RL, S>::run(v);
+        const int f1 = f1_0 + c;
+        const V base = twe((int64_t)f1 * j);
+        const V step = twe((int64_t)f1 * Ns);
+        V sp[RL];
+        powers<RL>(sp, [&](int p) {
+          V s = step;
+          for (int q = 1; q < p; q <<= 1) s = cmul(s, s);
+          return s;
+        });
+#pragma unroll
+        for (int m = 0; m < RL; ++m)
+          outv[(int64_t)(j + m * Ns) * N1 + f1] = cmul(v[m], cmul(base, sp[m]));
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------------ pass 2
@@ -382,38 +428,33 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
   } else if constexpr (OUT == OUT_THRESH) {
     const float thr2 = a.thr2;
     const int lane = __lane_id();
-    unsigned long long best = 0ull;   // packed (p bits << 32 | ~n)
+    // running maximum in registers (ties to the lowest sample); crossings are
+    // rare, so each crossing lane appends with its own atomics
+    float bp = -1.f;
+    int bn = 0x7fffffff;
     final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int f, int n1, V val, int) {
-      const int n2 = row0 + f;
-      const int n = n2 + N2 * n1;
+      const int n = (row0 + f) + N2 * n1;
       const float p = val.x * val.x + val.y * val.y;
-      const unsigned long long key =
-          ((unsigned long long)__float_as_uint(p) << 32) | (unsigned long long)(0xffffffffu - (uint32_t)n);
-      best = key > best ? key : best;
-      const bool hit = p >= thr2;
-      const unsigned long long mask = __ballot(hit);
-      if (mask) {
-        const int cnt = __popcll(mask);
-        const int leader = __ffsll((long long)mask) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) {
-          base = atomicAdd(a.trig_count, (unsigned long long)cnt);
-          atomicAdd(&a.tmpl_count[v], cnt);
-        }
-        base = __shfl(base, leader);
-        if (hit) {
-          const unsigned long long idx = base + __popcll(mask & ((1ull << lane) - 1ull));
-          if ((int64_t)idx < a.trig_cap) {
-            TrigRec t;
-            t.tmpl = v;
-            t.sample = n;
-            t.re = val.x;
-            t.im = val.y;
-            a.trig[idx] = t;
-          }
+      if (p > bp || (p == bp && n < bn)) {
+        bp = p;
+        bn = n;
+      }
+      if (p >= thr2) {
+        const unsigned long long idx = atomicAdd(a.trig_count, 1ull);
+        atomicAdd(&a.tmpl_count[v], 1);
+        if ((int64_t)idx < a.trig_cap) {
+          TrigRec t;
+          t.tmpl = v;
+          t.sample = n;
+          t.re = val.x;
+          t.im = val.y;
+          a.trig[idx] = t;
         }
       }
     });
+    unsigned long long best =
+        bp < 0.f ? 0ull
+                 : ((unsigned long long)__float_as_uint(bp) << 32) | (unsigned long long)(0xffffffffu - (uint32_t)bn);
     // wave-reduce the running maximum, one atomic per wave
     for (int off = 32; off > 0; off >>= 1) {
       const unsigned long long o = __shfl_xor(best, off);

@@ -49,25 +49,16 @@ __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[
           const float s = a.row_inv ? a.row_inv[j] : 1.f;
           a.rho_out[(int64_t)j * a.N + n] = make_float2(re * s, im * s);
         }
-        const bool hit = (j < a.T) && (p >= a.thr2_row[j]);
-        const unsigned long long mask = __ballot(hit);
-        if (mask) {
-          const int cnt = __popcll(mask);
-          const int leader = __ffsll((long long)mask) - 1;
-          unsigned long long base = 0;
-          if (lane == leader) base = atomicAdd(a.trig_count, (unsigned long long)cnt);
-          base = __shfl(base, leader);
-          if (hit) {
-            atomicAdd(&a.tmpl_count[j], 1);
-            const unsigned long long idx = base + __popcll(mask & ((1ull << lane) - 1ull));
-            if ((int64_t)idx < a.trig_cap) {
-              TrigRec t;
-              t.tmpl = a.tmpl_base + j;
-              t.sample = n;
-              t.re = re;
-              t.im = im;
-              a.trig[idx] = t;
-            }
+        if (j < a.T && p >= a.thr2_row[j]) {   // rare: per-lane append
+          atomicAdd(&a.tmpl_count[j], 1);
+          const unsigned long long idx = atomicAdd(a.trig_count, 1ull);
+          if ((int64_t)idx < a.trig_cap) {
+            TrigRec t;
+            t.tmpl = a.tmpl_base + j;
+            t.sample = n;
+            t.re = re;
+            t.im = im;
+            a.trig[idx] = t;
           }
         }
       }
@@ -114,18 +105,40 @@ __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
 #pragma unroll
     for (int cb = 0; cb < WT_COLB; ++cb) acc[rb][cb] = (f32x16){};
 
-#pragma unroll 4
-  for (int k = 0; k < K; ++k) {
-    float av[WT_ROWB], bv[WT_COLB];
+  // operands of the next PF k-steps stay in flight while the MFMAs of this one run
+  constexpr int PF = 4;
+  float ra[PF][WT_ROWB], rbv[PF][WT_COLB];
 #pragma unroll
-    for (int rb = 0; rb < WT_ROWB; ++rb) av[rb] = ap[rb][(int64_t)k * 64];
+  for (int p = 0; p < PF; ++p) {
+    const int kk = p < K ? p : K - 1;
 #pragma unroll
-    for (int cb = 0; cb < WT_COLB; ++cb) bv[cb] = bp[(int64_t)(2 * k) * N + cb * 32];
+    for (int rb = 0; rb < WT_ROWB; ++rb) ra[p][rb] = ap[rb][(int64_t)kk * 64];
 #pragma unroll
-    for (int rb = 0; rb < WT_ROWB; ++rb)
+    for (int cb = 0; cb < WT_COLB; ++cb) rbv[p][cb] = bp[(int64_t)(2 * kk) * N + cb * 32];
+  }
+  for (int k0 = 0; k0 < K; k0 += PF) {
 #pragma unroll
-      for (int cb = 0; cb < WT_COLB; ++cb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
+    for (int p = 0; p < PF; ++p) {
+      const int k = k0 + p;
+      if (k < K) {
+        float av[WT_ROWB], bv[WT_COLB];
+#pragma unroll
+        for (int rb = 0; rb < WT_ROWB; ++rb) av[rb] = ra[p][rb];
+#pragma unroll
+        for (int cb = 0; cb < WT_COLB; ++cb) bv[cb] = rbv[p][cb];
+        if (k + PF < K) {
+#pragma unroll
+          for (int rb = 0; rb < WT_ROWB; ++rb) ra[p][rb] = ap[rb][(int64_t)(k + PF) * 64];
+#pragma unroll
+          for (int cb = 0; cb < WT_COLB; ++cb) rbv[p][cb] = bp[(int64_t)(2 * (k + PF)) * N + cb * 32];
+        }
+#pragma unroll
+        for (int rb = 0; rb < WT_ROWB; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < WT_COLB; ++cb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
+      }
+    }
   }
   epilogue(a, acc, rb0, q0);
 }

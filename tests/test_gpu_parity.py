@@ -243,3 +243,36 @@ def test_rb_16bit_matches_quantised_product(ctx, rb_case, dtype):
     trig, _, st = rbmf.rb_filter(ctx, basis, bank, case.strain, 5.0, 6.0)
     compare_triggers(trig, case.rho, 6.0)
     basis.close()
+
+
+def test_subbank_bases_partition(ctx, rb_case):
+    """Bases of three template ranges (sub-banks, Sec. III.B): the final
+    triggers equal the oracle's; per-range reconstruction matches the oracle's
+    with each range's own basis; bad partitions are rejected."""
+    case, bank = rb_case
+    bounds = [0, 97, 211, case.T]
+    bases = rbmf.subbank_bases(ctx, bank, bounds, rank=[10, 0, 23], tol=1e-3, dtype="f32")
+    assert [b.K for b in bases][0] == 10 and bases[2].K == 23
+    trig, _, st = rbmf.rb_filter(ctx, bases, bank, case.strain, 5.0, 6.0)
+    compare_triggers(trig, case.rho, 6.0)
+    k_lo, _ = om.band_limits(case.N, case.fs, case.f_low)
+    d = ob.whitened_data(case.s64, case.psd, case.fs, case.f_low)
+    b = bases[1]
+    V, c, _ = b.export()
+    assert c.shape == (bounds[2] - bounds[1], b.K)
+    rho = rbmf.debug_rho(ctx, bank, case.strain, b)
+    ref = ob.rb_snr(ob.basis_outputs(d, V, case.N, k_lo), c)
+    assert (np.abs(rho - ref) / np.maximum(np.abs(ref), 1.0)).max() <= 1e-4
+    S = np.zeros(3, dtype=rbmf.TRIGGER_NP)
+    S["tmpl"] = [bounds[1], bounds[1] + 5, bounds[2] - 1]
+    S["sample"] = [0, 100, case.N - 1]
+    r = rbmf.rho_at(ctx, b, case.strain, S)
+    np.testing.assert_allclose(r, rho[S["tmpl"] - bounds[1], S["sample"]], rtol=1e-5, atol=1e-5)
+    bad = S.copy()
+    bad["tmpl"][0] = 0          # outside the basis's range
+    with pytest.raises(rbmf.RbError):
+        rbmf.rho_at(ctx, b, case.strain, bad)
+    with pytest.raises(rbmf.RbError):          # gap in the partition
+        rbmf.rb_filter(ctx, [bases[0], bases[2]], bank, case.strain, 5.0, 6.0)
+    for x in bases:
+        x.close()
