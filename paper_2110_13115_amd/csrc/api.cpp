@@ -8,6 +8,8 @@
 #include <atomic>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <map>
@@ -142,11 +144,12 @@ struct rb_ctx_s {
   int live = 0;
   std::map<int64_t, std::unique_ptr<TwTables>> tw;
   // scratch
-  DevBuf work, work64, dspec, strain, z, z32, recs1, adjA, adjAhat, adjB, adjT, adjS, adjRho, adjG, adjC, adjGC,
+  DevBuf work, work64, dspec, strain, z, z32, recs1, thr_inf, adjA, adjAhat, adjB, adjT, adjS, adjRho, adjG, adjC, adjGC,
       adjOrd, adjSeg, trig1, trig2, recs, tmp, final_out, cnt1, cnt2, off1, off2, fill1, fill2,
       list1, list2, tmax, summary, counters, thr_row, peaks, flag, rho_tmp, zws;
   hipEvent_t ev[8] = {};
   std::vector<hipEvent_t> evs;
+  std::map<int64_t, int> fft_n2;   // autotuned four-step split per N (log2 N2)
   // batch search: per-item summaries and outputs, captured graph
   DevBuf bsum, bout;
   hipStream_t gstream = nullptr;
@@ -188,6 +191,7 @@ struct rb_basis_s {
   DevBuf row_scale_dev;        // Tp floats
   DevBuf thr_row;              // Tp floats: squared first-stage threshold per template
   float thr_cached = -1.f;
+  int gemm_variant = -1;       // autotuned reconstruction kernel variant (-1: not yet)
 };
 
 // ====================================================================== shared steps
@@ -280,6 +284,81 @@ PassArgs base_args(rb_bank bank, const FftGeom& g, const FftTables& tw) {
   a.zscale = 1.f;
   return a;
 }
+
+// ---------------------------------------------------------------- autotuner
+// The four-step split N = N1 N2 of the FFT passes is chosen per N by timing
+// the candidate splits (balanced, and one step either way) on a batch of
+// correlation + inverse transforms of the bank's own templates, once per
+// context.  RBMF_FFT_SPLIT=<log2 N2> forces a split, RBMF_AUTOTUNE=0 keeps
+// the balanced one.
+rb_status geom_for(rb_ctx ctx, rb_bank bank, FftGeom* out) {
+  const int64_t N = bank->grid.N;
+  auto it = ctx->fft_n2.find(N);
+  if (it != ctx->fft_n2.end()) {
+    *out = make_geom(N, it->second);
+    return RB_OK;
+  }
+  const FftGeom g0 = make_geom(N);
+  int choice = g0.log2N / 2;
+  const char* force = std::getenv("RBMF_FFT_SPLIT");
+  const char* at = std::getenv("RBMF_AUTOTUNE");
+  if (force) {
+    const FftGeom gf = make_geom(N, std::atoi(force));
+    RB_CHECK(geom_supported(gf), RB_ERR_ARG, "RBMF_FFT_SPLIT gives an unsupported split");
+    choice = std::atoi(force);
+  } else if (!(at && std::strcmp(at, "0") == 0)) {
+    std::vector<int> cand;
+    for (int c : {g0.log2N / 2, g0.log2N - g0.log2N / 2, g0.log2N / 2 - 1})
+      if (geom_supported(make_geom(N, c)) && std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+    if (cand.size() > 1) {
+      const int B = std::min<int64_t>(batch_vectors(N, bank->T), 32);
+      RB_TRY(ctx->work.ensure((size_t)B * N * 8));
+      RB_TRY(ctx->dspec.ensure((size_t)bank->nbs * 8));
+      RB_TRY(ctx->z32.ensure((size_t)2 * B * N * 4));
+      RB_TRY(fill32(ctx, ctx->dspec.p, 0u, bank->nbs * 2));
+      hipEvent_t e0, e1;
+      RB_HIP(hipEventCreate(&e0));
+      RB_HIP(hipEventCreate(&e1));
+      float best = 1e30f;
+      for (int c : cand) {
+        const FftGeom g = make_geom(N, c);
+        FftTables tw;
+        RB_TRY(get_tables(ctx, g, tw));
+        PassArgs a = base_args(bank, g, tw);
+        a.sign = +1;
+        a.nvec = B;
+        a.d = ctx->dspec.as<float2>();
+        a.src = bank->w.as<float2>();
+        a.work = ctx->work.as<float2>();
+        a.zout = ctx->z32.as<float>();
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 4; ++rep) {
+          RB_HIP(hipEventRecord(e0, ctx->stream));
+          RB_HIP(launch_pass1(a, IN_CORR, ctx->stream));
+          RB_HIP(launch_pass2(a, OUT_Z32, ctx->stream));
+          RB_HIP(hipEventRecord(e1, ctx->stream));
+          RB_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          RB_HIP(hipEventElapsedTime(&ms, e0, e1));
+          if (rep > 0) ms_min = std::min(ms_min, ms);   // first run warms up
+        }
+        if (ms_min < best) {
+          best = ms_min;
+          choice = c;
+        }
+        if (std::getenv("RBMF_VERBOSE"))
+          std::fprintf(stderr, "[rbmf] N=%lld split N1=%d N2=%d: %.4f ms / %d vectors\n", (long long)N, g.N1, g.N2,
+                       ms_min, B);
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+  }
+  ctx->fft_n2[N] = choice;
+  *out = make_geom(N, choice);
+  return RB_OK;
+}
+
 
 // strain -> device pointer (copied into ctx scratch if it is a host array)
 rb_status strain_device(rb_ctx ctx, const float* strain, int64_t N, const float** out) {
@@ -932,6 +1011,50 @@ rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq
   ga.tmpl_count = ctx->cnt1.as<int32_t>() + basis->t0;
   ga.rho_out = rho_out;
   ga.row_inv = basis->row_inv.as<float>();
+  if (basis->gemm_variant < 0) {
+    // autotune on this basis's first call: time every variant on the real Z
+    // with infinite thresholds (no trigger is appended), keep the fastest
+    const char* force = std::getenv("RBMF_GEMM_VARIANT");
+    const char* at = std::getenv("RBMF_AUTOTUNE");
+    int choice = 0;
+    if (force) {
+      choice = std::max(0, std::min(recon_variants(ga.dtype) - 1, std::atoi(force)));
+    } else if (!(at && std::strcmp(at, "0") == 0)) {
+      RB_TRY(ctx->thr_inf.ensure((size_t)basis->Tp * 4));
+      RB_TRY(fill32(ctx, ctx->thr_inf.p, 0x7f800000u, basis->Tp));
+      GemmArgs gt = ga;
+      gt.thr2_row = ctx->thr_inf.as<float>();
+      gt.rho_out = nullptr;
+      hipEvent_t e0, e1;
+      RB_HIP(hipEventCreate(&e0));
+      RB_HIP(hipEventCreate(&e1));
+      float best = 1e30f;
+      for (int v = 0; v < recon_variants(ga.dtype); ++v) {
+        gt.variant = v;
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          RB_HIP(hipEventRecord(e0, ctx->stream));
+          RB_HIP(launch_recon_gemm(gt, ctx->stream));
+          RB_HIP(hipEventRecord(e1, ctx->stream));
+          RB_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          RB_HIP(hipEventElapsedTime(&ms, e0, e1));
+          if (rep > 0) ms_min = std::min(ms_min, ms);
+        }
+        if (std::getenv("RBMF_VERBOSE"))
+          std::fprintf(stderr, "[rbmf] GEMM dtype %d K=%d T=%d variant %d: %.4f ms\n", ga.dtype, ga.K, ga.T, v,
+                       ms_min);
+        if (ms_min < best) {
+          best = ms_min;
+          choice = v;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+    basis->gemm_variant = choice;
+  }
+  ga.variant = basis->gemm_variant;
   RB_HIP(launch_recon_gemm(ga, ctx->stream));
   return RB_OK;
 }
@@ -989,7 +1112,8 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
   RB_CHECK(opts->reserved == 0, RB_ERR_ARG, "reserved must be 0");
   RB_CHECK(cap >= 0, RB_ERR_ARG, "cap must be >= 0");
   const int T = bank->T;
-  const FftGeom g = make_geom(bank->grid.N);
+  FftGeom g;
+  RB_TRY(geom_for(ctx, bank, &g));
   FftTables tw;
   RB_TRY(get_tables(ctx, g, tw));
   const float* s;
@@ -1097,7 +1221,8 @@ extern "C" rb_status mf_full(rb_ctx ctx, rb_bank bank, const float* strain, doub
   RB_CHECK(std::isfinite(thr) && thr > 0, RB_ERR_ARG, "thr must be > 0");
   RB_CHECK(cap >= 0, RB_ERR_ARG, "cap must be >= 0");
   const int T = bank->T;
-  const FftGeom g = make_geom(bank->grid.N);
+  FftGeom g;
+  RB_TRY(geom_for(ctx, bank, &g));
   FftTables tw;
   RB_TRY(get_tables(ctx, g, tw));
   const float* s;
@@ -1171,7 +1296,8 @@ extern "C" rb_status rb_debug_rho(rb_ctx ctx, rb_basis basis, rb_bank bank, cons
   RB_CHECK(bank->ctx == ctx && (basis == nullptr || basis->bank == bank), RB_ERR_ARG, "handle mismatch");
   const int T = bank->T;
   const int rows = basis ? basis->T : T;
-  const FftGeom g = make_geom(bank->grid.N);
+  FftGeom g;
+  RB_TRY(geom_for(ctx, bank, &g));
   RB_CHECK((double)rows * g.N <= 4e9, RB_ERR_ARG, "rows * N too large for a dump");
   FftTables tw;
   RB_TRY(get_tables(ctx, g, tw));
@@ -1217,7 +1343,8 @@ extern "C" rb_status rb_debug_basis_outputs(rb_ctx ctx, rb_basis basis, const fl
   RB_TRY(validate_ctx(ctx));
   RB_CHECK(basis != nullptr && beta != nullptr, RB_ERR_ARG, "NULL argument");
   rb_bank bank = basis->bank;
-  const FftGeom g = make_geom(bank->grid.N);
+  FftGeom g;
+  RB_TRY(geom_for(ctx, bank, &g));
   const int K = basis->K;
   FftTables tw;
   RB_TRY(get_tables(ctx, g, tw));
@@ -1328,7 +1455,8 @@ extern "C" rb_status rb_rho_at(rb_ctx ctx, rb_basis basis, const float* strain, 
   RB_CHECK(n >= 0, RB_ERR_ARG, "n must be >= 0");
   if (n == 0) return RB_OK;
   RB_CHECK(S != nullptr && rho != nullptr, RB_ERR_ARG, "NULL argument");
-  const FftGeom g = make_geom(basis->bank->grid.N);
+  FftGeom g;
+  RB_TRY(geom_for(ctx, basis->bank, &g));
   std::vector<int32_t> tm, sp;
   const float2* Cd;
   RB_TRY(adjoint_forward(ctx, basis, strain, S, n, C, g, tm, sp, &Cd));
@@ -1346,7 +1474,8 @@ extern "C" rb_status rb_backward(rb_ctx ctx, rb_basis basis, const float* strain
   RB_CHECK(n == 0 || S != nullptr, RB_ERR_ARG, "S is NULL");
   rb_bank bank = basis->bank;
   const int T = basis->T, K = basis->K;     // rows of C / grad_C: the basis's templates
-  const FftGeom g = make_geom(bank->grid.N);
+  FftGeom g;
+  RB_TRY(geom_for(ctx, bank, &g));
   const int64_t N = g.N;
   hipStream_t st = ctx->stream;
   std::vector<int32_t> tm, sp;
@@ -1452,7 +1581,8 @@ rb_status enqueue_item(rb_ctx ctx, const rb_batch_item& it, const rb_filter_opts
                        rb_trigger* out, int64_t cap_item) {
   rb_bank bank = it.bank;
   const int T = bank->T;
-  const FftGeom g = make_geom(bank->grid.N);
+  FftGeom g;
+  RB_TRY(geom_for(ctx, bank, &g));
   FftTables tw;
   RB_TRY(get_tables(ctx, g, tw));
   const float* s = it.strain;

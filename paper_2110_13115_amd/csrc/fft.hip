@@ -534,16 +534,21 @@ hipError_t disp2(const PassArgs& a, hipStream_t st) {
 
 }  // namespace
 
-FftGeom make_geom(int64_t N) {
+FftGeom make_geom(int64_t N, int n2log) {
   FftGeom g;
   g.N = N;
   int m = 0;
   while ((int64_t(1) << m) < N) ++m;
   g.log2N = m;
-  g.N2 = 1 << (m / 2);
-  g.N1 = 1 << (m - m / 2);
+  if (n2log < 0) n2log = m / 2;
+  g.N2 = 1 << n2log;
+  g.N1 = 1 << (m - n2log);
   g.s_lo = (m + 1) / 2;
   return g;
+}
+
+bool geom_supported(const FftGeom& g) {
+  return g.N2 >= 64 && g.N2 <= 1024 && g.N1 >= 64 && g.N1 <= 2048 && g.N1 * (int64_t)g.N2 == g.N;
 }
 
 hipError_t launch_pass1(const PassArgs& a, InKind in, hipStream_t st) {

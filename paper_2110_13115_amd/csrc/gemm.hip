@@ -30,13 +30,14 @@ constexpr int TILE_T = WAVES * WT_ROWB * 16;   // templates per workgroup (128)
 constexpr int TILE_N = WT_COLB * 32;           // samples per workgroup (64)
 constexpr size_t kLdsMax = 160 * 1024;         // gfx950 LDS per workgroup
 
-__device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[WT_ROWB][WT_COLB],
-                                         int rb0, int64_t q0) {
+template <int CB>
+__device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[WT_ROWB][CB], int rb0,
+                                         int64_t q0) {
   const int lane = __lane_id();
 #pragma unroll
   for (int rb = 0; rb < WT_ROWB; ++rb) {
 #pragma unroll
-    for (int cb = 0; cb < WT_COLB; ++cb) {
+    for (int cb = 0; cb < CB; ++cb) {
       const int64_t q = q0 + cb * 32 + (lane & 31);
       const int n = (int)(q / a.N1) + a.N2 * (int)(q % a.N1);
 #pragma unroll
@@ -70,6 +71,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[
 // template tiles sharing one sample tile run on the same XCD (workgroups are
 // dispatched round-robin over the 8 XCDs): Z is then fetched into each L2 once.
 __device__ __forceinline__ bool xcd_tile(int ntt, int64_t nwg, int& tt, int64_t& st) {
+  // (nwg = template tiles x sample tiles)
   const int64_t per = (nwg + 7) / 8;
   const int64_t bid = blockIdx.x;
   const int64_t L = (bid % 8) * per + bid / 8;
@@ -79,16 +81,19 @@ __device__ __forceinline__ bool xcd_tile(int ntt, int64_t nwg, int& tt, int64_t&
   return true;
 }
 
+// CB: 32-sample MFMA column blocks per wave (tile of 32 templates x 32 CB samples).
+template <int CB>
 __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
+  constexpr int TN = CB * 32;
   const int ntt = a.Tp / TILE_T;
-  const int64_t nwg = (int64_t)ntt * (a.N / TILE_N);
+  const int64_t nwg = (int64_t)ntt * (a.N / TN);
   int tt;
   int64_t st;
   if (!xcd_tile(ntt, nwg, tt, st)) return;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int rb0 = tt * (TILE_T / 16) + wave * WT_ROWB;     // first 16-template row block
-  const int64_t q0 = st * TILE_N;
+  const int64_t q0 = st * TN;
   const float* __restrict__ cpk = static_cast<const float*>(a.cpk);
   const float* __restrict__ z = static_cast<const float*>(a.z);
   const int K = a.K;
@@ -99,48 +104,48 @@ __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
   for (int rb = 0; rb < WT_ROWB; ++rb) ap[rb] = cpk + ((int64_t)(rb0 + rb) * K) * 64 + lane;
   const float* bp = z + (int64_t)(lane >> 5) * N + q0 + (lane & 31);
 
-  f32x16 acc[WT_ROWB][WT_COLB];
+  f32x16 acc[WT_ROWB][CB];
 #pragma unroll
   for (int rb = 0; rb < WT_ROWB; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < WT_COLB; ++cb) acc[rb][cb] = (f32x16){};
+    for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = (f32x16){};
 
   // operands of the next PF k-steps stay in flight while the MFMAs of this one run
   constexpr int PF = 4;
-  float ra[PF][WT_ROWB], rbv[PF][WT_COLB];
+  float ra[PF][WT_ROWB], rbv[PF][CB];
 #pragma unroll
   for (int p = 0; p < PF; ++p) {
     const int kk = p < K ? p : K - 1;
 #pragma unroll
     for (int rb = 0; rb < WT_ROWB; ++rb) ra[p][rb] = ap[rb][(int64_t)kk * 64];
 #pragma unroll
-    for (int cb = 0; cb < WT_COLB; ++cb) rbv[p][cb] = bp[(int64_t)(2 * kk) * N + cb * 32];
+    for (int cb = 0; cb < CB; ++cb) rbv[p][cb] = bp[(int64_t)(2 * kk) * N + cb * 32];
   }
   for (int k0 = 0; k0 < K; k0 += PF) {
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
       const int k = k0 + p;
       if (k < K) {
-        float av[WT_ROWB], bv[WT_COLB];
+        float av[WT_ROWB], bv[CB];
 #pragma unroll
         for (int rb = 0; rb < WT_ROWB; ++rb) av[rb] = ra[p][rb];
 #pragma unroll
-        for (int cb = 0; cb < WT_COLB; ++cb) bv[cb] = rbv[p][cb];
+        for (int cb = 0; cb < CB; ++cb) bv[cb] = rbv[p][cb];
         if (k + PF < K) {
 #pragma unroll
           for (int rb = 0; rb < WT_ROWB; ++rb) ra[p][rb] = ap[rb][(int64_t)(k + PF) * 64];
 #pragma unroll
-          for (int cb = 0; cb < WT_COLB; ++cb) rbv[p][cb] = bp[(int64_t)(2 * (k + PF)) * N + cb * 32];
+          for (int cb = 0; cb < CB; ++cb) rbv[p][cb] = bp[(int64_t)(2 * (k + PF)) * N + cb * 32];
         }
 #pragma unroll
         for (int rb = 0; rb < WT_ROWB; ++rb)
 #pragma unroll
-          for (int cb = 0; cb < WT_COLB; ++cb)
+          for (int cb = 0; cb < CB; ++cb)
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
       }
     }
   }
-  epilogue(a, acc, rb0, q0);
+  epilogue<CB>(a, acc, rb0, q0);
 }
 
 // 16-bit operands: one instruction reduces over 16 realified entries = 8
@@ -194,7 +199,7 @@ __global__ __launch_bounds__(256) void k_recon_16(GemmArgs a) {
               __builtin_bit_cast(f16x8, av[rb]), __builtin_bit_cast(f16x8, bv[cb]), acc[rb][cb], 0, 0, 0);
       }
   }
-  epilogue(a, acc, rb0, q0);
+  epilogue<WT_COLB>(a, acc, rb0, q0);
 }
 
 // 16-bit operands, Z tile staged in LDS.  One workgroup owns 64 samples and
@@ -249,7 +254,7 @@ __global__ __launch_bounds__(256) void k_recon_16_lds(GemmArgs a) {
                 __builtin_bit_cast(f16x8, av[rb]), __builtin_bit_cast(f16x8, bv[cb]), acc[rb][cb], 0, 0, 0);
         }
     }
-    epilogue(a, acc, rb0, q0);
+    epilogue<WT_COLB>(a, acc, rb0, q0);
   }
 }
 
@@ -311,16 +316,23 @@ __global__ void k_pack_16(const float2* C, int T, int Tp, int K, int Kp, int dty
 
 }  // namespace
 
+int recon_variants(int dtype) { return 2; }
+
 hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
-  if (a.Tp % TILE_T != 0 || a.N % TILE_N != 0) return hipErrorInvalidValue;
-  const int64_t nwg = (int64_t)(a.Tp / TILE_T) * (a.N / TILE_N);
-  const int64_t launch = ((nwg + 7) / 8) * 8;
-  if (a.dtype == 0) {
-    hipLaunchKernelGGL(k_recon_f32, dim3((unsigned)launch), dim3(256), 0, st, a);
+  if (a.Tp % TILE_T != 0 || a.N % 128 != 0) return hipErrorInvalidValue;
+  if (a.dtype == 0) {   // variant 0: 64-sample tiles, 1: 128-sample tiles
+    const int TN = a.variant == 1 ? 128 : 64;
+    const int64_t nwg = (int64_t)(a.Tp / TILE_T) * (a.N / TN);
+    const int64_t launch = ((nwg + 7) / 8) * 8;
+    if (a.variant == 1)
+      hipLaunchKernelGGL(k_recon_f32<4>, dim3((unsigned)launch), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_recon_f32<2>, dim3((unsigned)launch), dim3(256), 0, st, a);
     return hipGetLastError();
   }
+  // 16-bit: variant 0 stages the Z tile in LDS (when it fits), 1 loads fragments directly
   const size_t lds = (size_t)TILE_N * (2 * a.Kp + 8) * 2;
-  if (lds <= kLdsMax) {
+  if (a.variant == 0 && lds <= kLdsMax) {
     static bool attr_set = false;
     if (!attr_set) {
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_recon_16_lds<1>),
@@ -338,6 +350,8 @@ hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
       hipLaunchKernelGGL(k_recon_16_lds<2>, dim3(grid), dim3(256), lds, st, a);
     return hipGetLastError();
   }
+  const int64_t nwg = (int64_t)(a.Tp / TILE_T) * (a.N / TILE_N);
+  const int64_t launch = ((nwg + 7) / 8) * 8;
   if (a.dtype == 1)
     hipLaunchKernelGGL(k_recon_16<1>, dim3((unsigned)launch), dim3(256), 0, st, a);
   else

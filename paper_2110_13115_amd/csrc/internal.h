@@ -43,7 +43,9 @@ struct FftTables64 {
   const double2* thi;
 };
 
-FftGeom make_geom(int64_t N);
+// n2log < 0: the balanced split N2 = 2^floor(log2 N / 2).
+FftGeom make_geom(int64_t N, int n2log = -1);
+bool geom_supported(const FftGeom& g);
 
 // Pass-1 input variants.
 enum InKind { IN_CORR = 0, IN_REAL = 1, IN_DENSE = 2 };
@@ -122,7 +124,9 @@ struct GemmArgs {
   int32_t* tmpl_count;       // per local template (already offset by tmpl_base)
   float2* rho_out;           // debug: natural order T x N, or NULL
   const float* row_inv;      // per-template 1/scale applied to rho_out (16-bit), or NULL
+  int variant;               // kernel variant (autotuned): see launch_recon_gemm
 };
+int recon_variants(int dtype);
 hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t stream);
 // Packs C (T x K complex, FP32 interleaved, device) into the kernel's layout.
 hipError_t launch_pack_c(const float2* C, int T, int Tp, int K, int Kp, int dtype,

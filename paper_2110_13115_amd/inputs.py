@@ -375,6 +375,59 @@ WORKLOADS = {
 }
 
 
+@dataclass
+class BatchWorkload:
+    """Segments of uneven length, each searched with every sub-bank of a bank
+    built on that segment's grid."""
+    name: str
+    cfg: int
+    nseg: int
+    durations: Tuple[int, ...]     # seconds, drawn i.i.d. per segment (seed purpose 4)
+    fs: float
+    f_low: float
+    T: int
+    mmin: float
+    mmax: float
+    order: int
+    subbanks: int
+    ranks: Tuple[int, ...]
+    thr1: float = 5.0
+    thr2: float = 6.0
+    inj_snr: Tuple[float, float] = (6.0, 12.0)
+
+    def segment_lengths(self) -> List[int]:
+        rng = rng_for(self.cfg, PURPOSE_LEN)
+        return [int(d * self.fs) for d in rng.choice(self.durations, size=self.nseg)]
+
+    def grids(self) -> List[int]:
+        return sorted(set(self.segment_lengths()))
+
+    def bank_for(self, N: int) -> Bank:
+        """The same (tau0-ordered) masses on the grid of N samples."""
+        return random_bank(self.cfg, self.T, N, self.fs, self.f_low, self.mmin, self.mmax, self.order,
+                           sort_tau0=True)
+
+    def bounds(self) -> List[int]:
+        return [int(round(i * self.T / self.subbanks)) for i in range(self.subbanks + 1)]
+
+    def strain(self, i: int, N: int, bank: Bank, sigma_of) -> np.ndarray:
+        rng = np.random.default_rng([13115, self.cfg, PURPOSE_INJ, i])
+        inj = [Injection(int(rng.integers(0, bank.T)), float(rng.uniform(*self.inj_snr)), int(rng.integers(0, N)),
+                         float(rng.uniform(0, 2 * np.pi)))]
+        w = Workload(self.name, self.cfg * 1000 + i, N, self.fs, self.f_low, bank.T, self.mmin, self.mmax,
+                     self.order)
+        s, _ = make_strain(w, bank, sigma_of, inj, dtype=np.float32)
+        return s
+
+
+BATCH_WORKLOADS = {
+    # 64 segments with durations uniform in {64, 128, 256, 512} s, 10000 3.5PN templates with
+    # m1, m2 in [1, 50], split along tau0 into 4 sub-banks of 2500 with ranks 64/96/128/192
+    "batch_64seg": BatchWorkload("batch_64seg", 4, 64, (64, 128, 256, 512), 2048.0, 20.0, 10000,
+                                 1.0, 50.0, 7, 4, (64, 96, 128, 192)),
+}
+
+
 def make_strain(wl: Workload, bank: Bank, sigma_of, injections: Optional[List[Injection]] = None,
                 noise: bool = True, dtype=np.float32) -> Tuple[np.ndarray, List[Injection]]:
     """Coloured noise plus injections for workload `wl`.
