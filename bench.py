@@ -115,15 +115,17 @@ def run_batch(args, wname):
         items.append((torch.from_numpy(s).cuda(), bank, bases))
     prep_s = time.time() - t0
     cap_item = 1 << 17
-    eager, st_e = rbmf.rb_filter_batch(ctx, items, bw.thr1, bw.thr2, use_graph=False, cap_item=cap_item)
-    graph, st_g = rbmf.rb_filter_batch(ctx, items, bw.thr1, bw.thr2, use_graph=True, cap_item=cap_item)
-    same = all(a.tobytes() == b.tobytes() for a, b in zip(eager, graph))
+    sp = rbmf.RB_STAGE2_SPARSE
 
     def replay():
-        return rbmf.rb_filter_batch(ctx, items, bw.thr1, bw.thr2, use_graph=True, cap_item=cap_item)
+        return rbmf.rb_filter_batch(ctx, items, bw.thr1, bw.thr2, use_graph=True, cap_item=cap_item, stage2=sp)
 
     def eager_run():
-        return rbmf.rb_filter_batch(ctx, items, bw.thr1, bw.thr2, use_graph=False, cap_item=cap_item)
+        return rbmf.rb_filter_batch(ctx, items, bw.thr1, bw.thr2, use_graph=False, cap_item=cap_item, stage2=sp)
+    eager, _ = eager_run()
+    graph, _ = replay()
+    same = all(a.tobytes() == b.tobytes() for a, b in zip(eager, graph))
+    log(f"batch prepared in {prep_s:.1f} s; graph == eager: {same}")
     t_g, (res, st) = time_calls(replay, args.steps, args.warmup, torch)
     t_e, _ = time_calls(eager_run, max(1, args.steps // 2), 0, torch)
     tsec = sum(bw.T * n / bw.fs for n in lens)
@@ -134,7 +136,7 @@ def run_batch(args, wname):
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": bw.name, "segments": bw.nseg, "durations_s": list(bw.durations),
                    "segment_samples": lens, "templates": bw.T, "subbanks": bw.subbanks, "ranks": list(bw.ranks),
-                   "thr1": bw.thr1, "thr2": bw.thr2},
+                   "thr1": bw.thr1, "thr2": bw.thr2, "stage2": "sparse exact"},
         "eager_ms_per_step": t_e * 1e3, "graph_equals_eager": bool(same),
         "final_triggers": int(sum(len(x) for x in res)), "stage1_crossings": int(st.n_stage1),
         "refiltered": int(st.n_refiltered), "prep_s": prep_s,
@@ -198,11 +200,12 @@ def main():
     def mf_step():
         return rbmf.mf_full(ctx, bank, sd, wl.thr2, out=out)
 
-    # --- headline: rb_filter, FP32 (the workload's precision)
+    # --- headline: rb_filter, FP32 (the workload's precision), exact second stage evaluated at the
+    # first-stage crossings
     gemm_ms, s1, nref = [], [], []
 
     def rb_timed():
-        n, _, st = rbmf.rb_filter(ctx, bases, bank, sd, wl.thr1, wl.thr2, out=out)
+        n, _, st = rbmf.rb_filter(ctx, bases, bank, sd, wl.thr1, wl.thr2, stage2=rbmf.RB_STAGE2_SPARSE, out=out)
         gemm_ms.append(st.ms[2])
         s1.append(st.n_stage1)
         nref.append(st.n_refiltered)
@@ -211,7 +214,7 @@ def main():
     t_rb, (n_rb, st_rb) = time_calls(rb_timed, args.steps, args.warmup, torch)
     gemm_ms = gemm_ms[args.warmup:]
     rb_trig = out[:n_rb].cpu().numpy().view(rbmf.TRIGGER_NP).reshape(-1).copy()
-    log(f"rb_filter f32: {t_rb * 1e3:.2f} ms/step, final {n_rb}, stage-1 {s1[-1]}, refiltered "
+    log(f"rb_filter f32 (sparse stage 2): {t_rb * 1e3:.2f} ms/step, final {n_rb}, stage-1 {s1[-1]}, refiltered "
         f"{nref[-1]}, stage ms {[round(x, 3) for x in st_rb.ms[:7]]}")
 
     if args.headline_only:
@@ -226,20 +229,17 @@ def main():
     max_rel = float(np.max(np.abs(rb_trig["snr"] - mf_trig["snr"]) / mf_trig["snr"])) if same and n_rb else None
 
     extra = {}
-    # sparse exact second stage (same final triggers, stage 2 evaluated only at crossings)
-    gsp = []
-
-    def rb_sparse():
-        n, _, st = rbmf.rb_filter(ctx, bases, bank, sd, wl.thr1, wl.thr2, stage2=rbmf.RB_STAGE2_SPARSE, out=out)
-        gsp.append(st.ms[4])
+    # the second stage as a full matched filter of every crossing template (same final triggers)
+    def rb_full2():
+        n, _, st = rbmf.rb_filter(ctx, bases, bank, sd, wl.thr1, wl.thr2, stage2=rbmf.RB_STAGE2_FULL, out=out)
         return n, st
-    t_sp, (n_sp, st_sp) = time_calls(rb_sparse, args.steps, args.warmup, torch)
-    tr_sp = out[:n_sp].cpu().numpy().view(rbmf.TRIGGER_NP).reshape(-1)
-    ok_sp = n_sp == n_mf and np.array_equal(tr_sp[["tmpl", "sample"]], mf_trig[["tmpl", "sample"]])
-    extra["rb_f32_sparse_stage2"] = {"value": seg / t_sp, "ms_per_step": t_sp * 1e3,
-                                     "final_triggers_equal_mf": bool(ok_sp),
-                                     "stage_ms": [round(x, 4) for x in st_sp.ms[:7]]}
-    log(f"rb_filter f32 sparse stage 2: {t_sp * 1e3:.2f} ms/step")
+    t_f2, (n_f2, st_f2) = time_calls(rb_full2, args.steps, args.warmup, torch)
+    tr_f2 = out[:n_f2].cpu().numpy().view(rbmf.TRIGGER_NP).reshape(-1)
+    ok_f2 = n_f2 == n_mf and np.array_equal(tr_f2[["tmpl", "sample"]], mf_trig[["tmpl", "sample"]])
+    extra["rb_f32_full_stage2"] = {"value": seg / t_f2, "ms_per_step": t_f2 * 1e3,
+                                   "final_triggers_equal_mf": bool(ok_f2),
+                                   "stage_ms": [round(x, 4) for x in st_f2.ms[:7]]}
+    log(f"rb_filter f32 full stage 2: {t_f2 * 1e3:.2f} ms/step")
     if not args.skip_16bit:
         for dt in ("bf16", "f16"):
             b16 = rbmf.subbank_bases(ctx, bank, wl.bounds(), rank=wl.sub_ranks(), tol=wl.tol, dtype=dt)
@@ -290,7 +290,7 @@ def main():
         "config": {"workload": wl.name, "N": wl.N, "fs": wl.fs, "f_low": wl.f_low, "templates": wl.T,
                    "seconds": wl.seconds, "subbanks": wl.subbanks, "ranks": ranks,
                    "min_energy": min(b.energy for b in bases), "thr1": wl.thr1,
-                   "thr2": wl.thr2, "injections": len(inj), "stage2": "full"},
+                   "thr2": wl.thr2, "injections": len(inj), "stage2": "sparse exact"},
         "mf_full": {"value": seg / t_mf, "ms_per_step": t_mf * 1e3, "triggers": int(n_mf)},
         "rb_over_mf": t_mf / t_rb,
         "final_triggers_equal_mf": bool(same),

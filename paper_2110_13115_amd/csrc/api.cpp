@@ -1097,6 +1097,40 @@ rb_status check_partition(rb_ctx ctx, const rb_basis* bases, int32_t nb, rb_bank
   return RB_OK;
 }
 
+// Arguments of the sparse exact second stage over the stage-1 records grouped
+// by template (list1 / off1 / cnt1 / recs1).  d_count and n1_dev are the
+// device-side list length and stage-1 total of a captured search (NULL when
+// the host knows them).
+SparseArgs sparse_args(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTables& tw, double thr2,
+                       const int32_t* d_count, const int64_t* n1_dev, int64_t n1_cap) {
+  SparseArgs sa;
+  std::memset(&sa, 0, sizeof(sa));
+  sa.N = g.N;
+  sa.s_lo = g.s_lo;
+  sa.tlo = tw.tlo;
+  sa.thi = tw.thi;
+  sa.list = ctx->list1.as<int32_t>();
+  sa.d_count = d_count;
+  sa.n1_dev = n1_dev;
+  sa.n1_cap = n1_cap;
+  sa.offsets = ctx->off1.as<int32_t>();
+  sa.counts = ctx->cnt1.as<int32_t>();
+  sa.recs = ctx->recs1.as<TrigRec>();
+  sa.d = ctx->dspec.as<float2>();
+  sa.tmpl = bank->w.as<float2>();
+  sa.kb = bank->kb;
+  sa.nbs = bank->nbs;
+  sa.sup_lo = bank->sup_lo.as<int32_t>();
+  sa.sup_hi = bank->sup_hi.as<int32_t>();
+  sa.thr2 = (float)(thr2 * thr2);
+  sa.out = ctx->trig2.as<TrigRec>();
+  sa.out_cap = trig_capacity(ctx->trig2);
+  sa.out_count = ctx->counters.as<unsigned long long>() + 1;
+  sa.tmpl_count = ctx->cnt2.as<int32_t>();
+  sa.tmpl_max = ctx->tmax.as<unsigned long long>();
+  return sa;
+}
+
 }  // namespace
 
 extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases, rb_bank bank,
@@ -1159,28 +1193,7 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
     RB_TRY(fill32(ctx, ctx->cnt2.p, 0u, T));
     RB_TRY(fill32(ctx, ctx->tmax.p, 0u, 2 * (int64_t)T));
     if (sparse) {
-      SparseArgs sa;
-      std::memset(&sa, 0, sizeof(sa));
-      sa.N = g.N;
-      sa.s_lo = g.s_lo;
-      sa.tlo = tw.tlo;
-      sa.thi = tw.thi;
-      sa.list = ctx->list1.as<int32_t>();
-      sa.offsets = ctx->off1.as<int32_t>();
-      sa.counts = ctx->cnt1.as<int32_t>();
-      sa.recs = ctx->recs1.as<TrigRec>();
-      sa.d = ctx->dspec.as<float2>();
-      sa.tmpl = bank->w.as<float2>();
-      sa.kb = bank->kb;
-      sa.nbs = bank->nbs;
-      sa.sup_lo = bank->sup_lo.as<int32_t>();
-      sa.sup_hi = bank->sup_hi.as<int32_t>();
-      sa.thr2 = (float)(opts->thr2 * opts->thr2);
-      sa.out = ctx->trig2.as<TrigRec>();
-      sa.out_cap = trig_capacity(ctx->trig2);
-      sa.out_count = ctx->counters.as<unsigned long long>() + 1;
-      sa.tmpl_count = ctx->cnt2.as<int32_t>();
-      sa.tmpl_max = ctx->tmax.as<unsigned long long>();
+      const SparseArgs sa = sparse_args(ctx, bank, g, tw, opts->thr2, nullptr, nullptr, 0);
       RB_HIP(launch_sparse_exact(sa, (int)sum1[1], ctx->stream));
     } else {
       RB_TRY(step_mf(ctx, bank, g, tw, ctx->list1.as<int32_t>(), sum1[1], (float)(opts->thr2 * opts->thr2)));
@@ -1601,8 +1614,16 @@ rb_status enqueue_item(rb_ctx ctx, const rb_batch_item& it, const rb_filter_opts
   RB_TRY(fill32(ctx, ctx->cnt2.p, 0u, T));
   RB_TRY(fill32(ctx, ctx->tmax.p, 0u, 2 * (int64_t)T));
   // the low word of sm[1] (little-endian int64, < 2^31) is the stage-1 template count
-  RB_TRY(step_mf(ctx, bank, g, tw, ctx->list1.as<int32_t>(), T, (float)(opts->thr2 * opts->thr2),
-                 reinterpret_cast<const int32_t*>(sm + 1)));
+  const int32_t* nsel = reinterpret_cast<const int32_t*>(sm + 1);
+  if (opts->stage2 == RB_STAGE2_SPARSE) {
+    // group the stage-1 records by template (skipped, like the stage itself, when they overflowed)
+    const int64_t cap1 = trig_capacity(ctx->trig1);
+    RB_HIP(launch_scatter_triggers(ctx->trig1.as<TrigRec>(), cap1, sm, ctx->off1.as<int32_t>(),
+                                   ctx->fill1.as<int32_t>(), ctx->recs1.as<TrigRec>(), ctx->stream));
+    RB_HIP(launch_sparse_exact(sparse_args(ctx, bank, g, tw, opts->thr2, nsel, sm, cap1), T, ctx->stream));
+  } else {
+    RB_TRY(step_mf(ctx, bank, g, tw, ctx->list1.as<int32_t>(), T, (float)(opts->thr2 * opts->thr2), nsel));
+  }
   RB_HIP(launch_scan_counts(ctx->cnt2.as<int32_t>(), T, ctx->off2.as<int32_t>(), ctx->fill2.as<int32_t>(),
                             ctx->list2.as<int32_t>(), sm + 4, ctx->stream));
   const int64_t cap2 = trig_capacity(ctx->trig2);
@@ -1636,7 +1657,8 @@ std::string batch_key(int32_t n, const rb_batch_item* items, const rb_filter_opt
     for (int32_t m = 0; m < items[i].nbases; ++m) add(&items[i].bases[m], sizeof(void*));
   }
   const void* bufs[] = {ctx->work.p, ctx->work64.p, ctx->dspec.p, ctx->z.p, ctx->trig1.p, ctx->trig2.p,
-                        ctx->recs.p, ctx->tmp.p, ctx->bsum.p, ctx->bout.p, ctx->cnt1.p, ctx->cnt2.p};
+                        ctx->recs.p, ctx->tmp.p, ctx->bsum.p, ctx->bout.p, ctx->cnt1.p, ctx->cnt2.p,
+                        ctx->recs1.p};
   add(bufs, sizeof(bufs));
   return k;
 }
@@ -1651,8 +1673,8 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
   RB_CHECK(cap_item >= 0 && (out != nullptr || cap_item == 0), RB_ERR_ARG, "bad output buffer");
   RB_CHECK(std::isfinite(opts->thr1) && opts->thr1 > 0, RB_ERR_ARG, "thr1 must be > 0");
   RB_CHECK(std::isfinite(opts->thr2) && opts->thr2 >= opts->thr1, RB_ERR_ARG, "thr2 must be >= thr1");
-  RB_CHECK(opts->stage2 == RB_STAGE2_FULL && opts->reserved == 0, RB_ERR_ARG,
-           "batch search supports the full second stage only");
+  RB_CHECK(opts->stage2 == RB_STAGE2_FULL || opts->stage2 == RB_STAGE2_SPARSE, RB_ERR_ARG, "bad stage2 mode");
+  RB_CHECK(opts->reserved == 0, RB_ERR_ARG, "reserved must be 0");
   int Tmax = 0;
   for (int32_t i = 0; i < nitems; ++i) {
     const rb_batch_item& it = items[i];
@@ -1668,6 +1690,7 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
   const size_t cap2 = (size_t)trig_capacity(ctx->trig2);
   RB_TRY(ctx->recs.ensure(cap2 * sizeof(TrigRec)));
   RB_TRY(ctx->tmp.ensure(cap2 * sizeof(TrigRec)));
+  RB_TRY(ctx->recs1.ensure((size_t)trig_capacity(ctx->trig1) * sizeof(TrigRec)));
   std::vector<int64_t> sm((size_t)nitems * 8);
   const bool tm = stats != nullptr;
   for (int attempt = 0; attempt < 3; ++attempt) {
@@ -1721,7 +1744,9 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
       const int64_t* q = &sm[8 * (size_t)i];
       RB_CHECK(q[3] == 0, RB_ERR_NUMERIC, "item " + std::to_string(i) + ": strain contains non-finite values");
       if (q[0] > trig_capacity(ctx->trig1)) {
-        RB_TRY(ctx->trig1.ensure((size_t)(q[0] + q[0] / 4) * sizeof(TrigRec)));
+        const size_t c = (size_t)(q[0] + q[0] / 4);
+        RB_TRY(ctx->trig1.ensure(c * sizeof(TrigRec)));
+        RB_TRY(ctx->recs1.ensure(c * sizeof(TrigRec)));
         grow = true;
       }
       if (q[4] > trig_capacity(ctx->trig2)) {

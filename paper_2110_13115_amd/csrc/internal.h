@@ -156,6 +156,8 @@ struct SparseArgs {
   const float2* thi;
   const int32_t* list;        // selected templates
   const int32_t* d_count;     // optional device count of `list`
+  const int64_t* n1_dev;      // optional device stage-1 total: nothing runs when it exceeds n1_cap
+  int64_t n1_cap;             //   (the grouped records were not written)
   const int32_t* offsets;     // stage-1 records grouped by template: offsets / counts
   const int32_t* counts;
   const TrigRec* recs;

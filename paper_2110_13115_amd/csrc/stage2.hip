@@ -31,6 +31,7 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
   __shared__ float2 thi[1024];
   __shared__ float2 red[SP_M][SP_T / 64];
   if (a.d_count != nullptr && (int)blockIdx.x >= *a.d_count) return;
+  if (a.n1_dev != nullptr && *a.n1_dev > a.n1_cap) return;
   const int j = a.list[blockIdx.x];
   const int nlo = 1 << a.s_lo, nhi = (int)(a.N >> a.s_lo);
   for (int i = threadIdx.x; i < nlo; i += SP_T) tlo[i] = a.tlo[i];

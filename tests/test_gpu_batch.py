@@ -87,6 +87,25 @@ def test_graph_replays_with_new_data(batch):
         log("replay", rep, "ok", [len(x) for x in g])
 
 
+def test_batch_sparse_stage2(batch):
+    """Sparse exact second stage inside the batch (eager and graph) equals the
+    per-item sparse rb_filter and the full second stage."""
+    ctx, setups, items, strains = batch
+    sp = rbmf.RB_STAGE2_SPARSE
+    full, _ = rbmf.rb_filter_batch(ctx, items, 5.0, 6.0, use_graph=False)
+    eager, _ = rbmf.rb_filter_batch(ctx, items, 5.0, 6.0, use_graph=False, stage2=sp)
+    for rep in range(2):
+        graph, _ = rbmf.rb_filter_batch(ctx, items, 5.0, 6.0, use_graph=True, stage2=sp)
+        for i, (sd, bank, bases) in enumerate(items):
+            assert graph[i].tobytes() == eager[i].tobytes(), (rep, i)
+    for i, (sd, bank, bases) in enumerate(items):
+        one, _, _ = rbmf.rb_filter(ctx, bases, bank, sd, 5.0, 6.0, stage2=sp)
+        assert one.tobytes() == eager[i].tobytes(), i
+        assert np.array_equal(eager[i][["tmpl", "sample"]], full[i][["tmpl", "sample"]]), i
+        np.testing.assert_allclose(eager[i]["snr"], full[i]["snr"], rtol=1e-4)
+    log("sparse batch ok", [len(x) for x in eager])
+
+
 def test_batch_capacity(batch):
     ctx, setups, items, strains = batch
     with pytest.raises(rbmf.RbError) as ei:
