@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"f32": 157.3, "bf16": 2500.0, "f16": 2500.0}      # dense MFMA TFLOP/s, MI355X
+# split-BF16 (hi + lo) products issue three BF16 MFMAs per FP32-equivalent product
+PEAK["bf16x3"] = PEAK["bf16"] / 3
 HBM_PEAK_GBS = 8000.0
 
 
@@ -241,7 +243,7 @@ def main():
                                    "stage_ms": [round(x, 4) for x in st_f2.ms[:7]]}
     log(f"rb_filter f32 full stage 2: {t_f2 * 1e3:.2f} ms/step")
     if not args.skip_16bit:
-        for dt in ("bf16", "f16"):
+        for dt in ("bf16x3", "bf16", "f16"):
             b16 = rbmf.subbank_bases(ctx, bank, wl.bounds(), rank=wl.sub_ranks(), tol=wl.tol, dtype=dt)
             g16 = []
 

@@ -66,8 +66,12 @@ typedef enum {
 } rb_status;
 
 /* Storage type of the reconstruction operands C and Z (accumulation is FP32
- * in every case; basis construction, sigma and PSD products are FP64). */
-typedef enum { RB_F32 = 0, RB_BF16 = 1, RB_F16 = 2 } rb_dtype;
+ * in every case; basis construction, sigma and PSD products are FP64).
+ * RB_BF16X3 keeps FP32 accuracy on the BF16 matrix cores: every FP32 value x
+ * of C and Z is stored as hi = bf16(x) and lo = bf16(x - hi), and the product
+ * sums the three leading partial products Ch Zh + Ch Zl + Cl Zh (the dropped
+ * Cl Zl and the rounding of lo are ~2^-16 relative to each term). */
+typedef enum { RB_F32 = 0, RB_BF16 = 1, RB_F16 = 2, RB_BF16X3 = 3 } rb_dtype;
 
 /* Second-stage variant of rb_filter. */
 typedef enum {

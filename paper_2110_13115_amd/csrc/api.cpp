@@ -402,10 +402,13 @@ rb_status step_basis_outputs(rb_ctx ctx, rb_basis basis, const FftGeom& g, const
   const rb_dtype dt = force_f32 ? RB_F32 : basis->dtype;
   DevBuf& zb = force_f32 ? ctx->z32 : ctx->z;
   const size_t esz = dt == RB_F32 ? 4 : 2;
-  RB_TRY(zb.ensure((size_t)2 * Kp * g.N * esz));
+  const int planes = dt == RB_BF16X3 ? 2 : 1;           // BF16X3: hi plane, then lo plane
+  const size_t plane_bytes = (size_t)2 * Kp * g.N * esz;
+  RB_TRY(zb.ensure(plane_bytes * planes));
   if (Kp > K) {   // zero the padded rows so that 0 * pad never produces NaN
     const size_t off = (size_t)2 * K * g.N * esz, bytes = (size_t)2 * (Kp - K) * g.N * esz;
-    RB_TRY(fill32(ctx, static_cast<char*>(zb.p) + off, 0u, (int64_t)(bytes / 4)));
+    for (int p = 0; p < planes; ++p)
+      RB_TRY(fill32(ctx, static_cast<char*>(zb.p) + p * plane_bytes + off, 0u, (int64_t)(bytes / 4)));
   }
   const int B = batch_vectors(g.N, K);
   RB_TRY(ctx->work.ensure((size_t)B * g.N * 8));
@@ -416,6 +419,7 @@ rb_status step_basis_outputs(rb_ctx ctx, rb_basis basis, const FftGeom& g, const
   a.work = ctx->work.as<float2>();
   a.zout = zb.as<float>();
   a.zdtype = (int)dt;
+  a.zplane = (int64_t)2 * Kp * g.N;
   for (int v0 = 0; v0 < K; v0 += B) {
     a.vec_base = v0;
     a.nvec = std::min(B, K - v0);
@@ -780,7 +784,8 @@ extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, 
   RB_CHECK(t0 >= 0 && t0 < t1 && t1 <= bank->T, RB_ERR_ARG, "template range must satisfy 0 <= t0 < t1 <= T");
   RB_CHECK(rank >= 0, RB_ERR_ARG, "rank must be >= 0");
   RB_CHECK(rank > 0 || (tol > 0 && tol < 1), RB_ERR_ARG, "tol must be in (0, 1) when rank == 0");
-  RB_CHECK(dtype == RB_F32 || dtype == RB_BF16 || dtype == RB_F16, RB_ERR_ARG, "bad dtype");
+  RB_CHECK(dtype == RB_F32 || dtype == RB_BF16 || dtype == RB_F16 || dtype == RB_BF16X3, RB_ERR_ARG,
+           "bad dtype");
   *out = nullptr;
   const int64_t T = t1 - t0;
   const int64_t nb = bank->k_hi - bank->k_lo + 1, off = bank->k_lo - bank->kb, nbs = bank->nbs;
@@ -931,7 +936,8 @@ extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, 
   RB_HIP(hipMemcpyAsync(bs->row_inv.p, rinv.data(), (size_t)bs->Tp * 4, hipMemcpyHostToDevice, s));
   RB_HIP(hipMemcpyAsync(bs->row_scale_dev.p, bs->row_scale.data(), (size_t)bs->Tp * 4, hipMemcpyHostToDevice, s));
   const size_t cpk_bytes = (dtype == RB_F32) ? (size_t)(bs->Tp / 16) * K * 64 * 4
-                                             : (size_t)(bs->Tp / 16) * (bs->Kp / 8) * 64 * 8 * 2;
+                                             : (size_t)(bs->Tp / 16) * (bs->Kp / 8) * 64 * 8 * 2 *
+                                                   (dtype == RB_BF16X3 ? 2 : 1);
   RB_TRY(bs->cpk.ensure(cpk_bytes));
   RB_HIP(launch_pack_c(bs->C32.as<float2>(), (int)T, bs->Tp, K, bs->Kp, (int)dtype,
                        dtype == RB_F16 ? bs->row_scale_dev.as<float>() : nullptr, bs->cpk.p, s));
@@ -1371,7 +1377,8 @@ extern "C" rb_status rb_debug_basis_outputs(rb_ctx ctx, rb_basis basis, const fl
     RB_TRY(ctx->rho_tmp.ensure((size_t)K * g.N * 8));
     dst = ctx->rho_tmp.as<float2>();
   }
-  RB_HIP(launch_z_to_natural(ctx->z.p, (int)basis->dtype, 1.f, g.N, K, g.N1, g.N2, dst, ctx->stream));
+  RB_HIP(launch_z_to_natural(ctx->z.p, (int)basis->dtype, (int64_t)2 * basis->Kp * g.N, 1.f, g.N, K, g.N1, g.N2,
+                             dst, ctx->stream));
   if (!dev) RB_HIP(hipMemcpyAsync(beta, dst, (size_t)K * g.N * 8, hipMemcpyDeviceToHost, ctx->stream));
   RB_HIP(hipStreamSynchronize(ctx->stream));
   return RB_OK;

@@ -418,13 +418,27 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
     uint16_t* __restrict__ zr = reinterpret_cast<uint16_t*>(a.zout) + (int64_t)(2 * v) * N;
     uint16_t* __restrict__ zi = zr + N;
     const float sc = a.zscale;
-    const bool bf = (a.zdtype == 1);
-    final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int f, int n1, V val, int) {
-      const int64_t q = (int64_t)(row0 + f) * L + n1;
-      const float xr = val.x * sc, xi = val.y * sc;
-      zr[q] = bf ? f32_to_bf16_rne(xr) : f32_to_f16_rne(xr);
-      zi[q] = bf ? f32_to_bf16_rne(xi) : f32_to_f16_rne(xi);
-    });
+    if (a.zdtype == 3) {   // hi = bf16(x), lo = bf16(x - hi) in a second plane
+      uint16_t* __restrict__ lr = zr + a.zplane;
+      uint16_t* __restrict__ li = zi + a.zplane;
+      final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int f, int n1, V val, int) {
+        const int64_t q = (int64_t)(row0 + f) * L + n1;
+        const float xr = val.x * sc, xi = val.y * sc;
+        const uint16_t hr = f32_to_bf16_rne(xr), hi = f32_to_bf16_rne(xi);
+        zr[q] = hr;
+        zi[q] = hi;
+        lr[q] = f32_to_bf16_rne(xr - __uint_as_float((uint32_t)hr << 16));
+        li[q] = f32_to_bf16_rne(xi - __uint_as_float((uint32_t)hi << 16));
+      });
+    } else {
+      const bool bf = (a.zdtype == 1);
+      final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int f, int n1, V val, int) {
+        const int64_t q = (int64_t)(row0 + f) * L + n1;
+        const float xr = val.x * sc, xi = val.y * sc;
+        zr[q] = bf ? f32_to_bf16_rne(xr) : f32_to_f16_rne(xr);
+        zi[q] = bf ? f32_to_bf16_rne(xi) : f32_to_f16_rne(xi);
+      });
+    }
   } else if constexpr (OUT == OUT_THRESH) {
     const float thr2 = a.thr2;
     const int lane = __lane_id();

@@ -67,6 +67,30 @@ __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[
   }
 }
 
+// One 16-bit MFMA step; DT 1 = bf16, 2 = f16.
+template <int DT>
+__device__ __forceinline__ f32x16 mfma16(u16x8 a, u16x8 b, f32x16 c) {
+  if constexpr (DT == 2)
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                  0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
+// Accumulates one k-step: DT 1 / 2 one product; DT 3 (bf16 hi + lo split of
+// both operands) the three leading partial products, smallest first.
+template <int DT>
+__device__ __forceinline__ f32x16 kstep(u16x8 ah, u16x8 al, u16x8 bh, u16x8 bl, f32x16 c) {
+  if constexpr (DT == 3) {
+    c = mfma16<1>(al, bh, c);
+    c = mfma16<1>(ah, bl, c);
+    return mfma16<1>(ah, bh, c);
+  } else {
+    return mfma16<DT>(ah, bh, c);
+  }
+}
+
 // Maps a linear workgroup id to (template tile, sample tile) so that the
 // template tiles sharing one sample tile run on the same XCD (workgroups are
 // dispatched round-robin over the 8 XCDs): Z is then fetched into each L2 once.
@@ -82,9 +106,13 @@ __device__ __forceinline__ bool xcd_tile(int ntt, int64_t nwg, int& tt, int64_t&
 }
 
 // CB: 32-sample MFMA column blocks per wave (tile of 32 templates x 32 CB samples).
+// Operands of G k-steps are loaded into one of two register buffers while the
+// MFMAs of the other run (the steady state has no branch, so the loads of the
+// next group stay in flight); the last K mod 2G steps run one at a time.
 template <int CB>
 __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
   constexpr int TN = CB * 32;
+  constexpr int G = 4;
   const int ntt = a.Tp / TILE_T;
   const int64_t nwg = (int64_t)ntt * (a.N / TN);
   int tt;
@@ -94,15 +122,11 @@ __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
   const int lane = threadIdx.x & 63;
   const int rb0 = tt * (TILE_T / 16) + wave * WT_ROWB;     // first 16-template row block
   const int64_t q0 = st * TN;
-  const float* __restrict__ cpk = static_cast<const float*>(a.cpk);
-  const float* __restrict__ z = static_cast<const float*>(a.z);
   const int K = a.K;
   const int64_t N = a.N;
-  // lane's operand addresses
-  const float* ap[WT_ROWB];
-#pragma unroll
-  for (int rb = 0; rb < WT_ROWB; ++rb) ap[rb] = cpk + ((int64_t)(rb0 + rb) * K) * 64 + lane;
-  const float* bp = z + (int64_t)(lane >> 5) * N + q0 + (lane & 31);
+  const int64_t astr = (int64_t)K * 64;                    // floats per packed row block
+  const float* __restrict__ ap = static_cast<const float*>(a.cpk) + (int64_t)rb0 * astr + lane;
+  const float* __restrict__ bp = static_cast<const float*>(a.z) + (int64_t)(lane >> 5) * N + q0 + (lane & 31);
 
   f32x16 acc[WT_ROWB][CB];
 #pragma unroll
@@ -110,40 +134,64 @@ __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = (f32x16){};
 
-  // operands of the next PF k-steps stay in flight while the MFMAs of this one run
-  constexpr int PF = 4;
-  float ra[PF][WT_ROWB], rbv[PF][CB];
+  // A: one pointer per row block, k-steps at immediate offsets; B: one pointer
+  // per k-step of a group (rows 2k are 2N floats apart); all advance by a group.
+  const float* pa[WT_ROWB];
 #pragma unroll
-  for (int p = 0; p < PF; ++p) {
-    const int kk = p < K ? p : K - 1;
+  for (int rb = 0; rb < WT_ROWB; ++rb) pa[rb] = ap + rb * astr;
+  const float* pb[G];
 #pragma unroll
-    for (int rb = 0; rb < WT_ROWB; ++rb) ra[p][rb] = ap[rb][(int64_t)kk * 64];
+  for (int g = 0; g < G; ++g) pb[g] = bp + (int64_t)(2 * g) * N;
+  const int64_t bstep = (int64_t)(2 * G) * N;
+  float fa[2][G][WT_ROWB], fb[2][G][CB];
+  auto load = [&](int s) {   // loads the group at the pointers, then advances them
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) rbv[p][cb] = bp[(int64_t)(2 * kk) * N + cb * 32];
-  }
-  for (int k0 = 0; k0 < K; k0 += PF) {
+    for (int g = 0; g < G; ++g) {
 #pragma unroll
-    for (int p = 0; p < PF; ++p) {
-      const int k = k0 + p;
-      if (k < K) {
-        float av[WT_ROWB], bv[CB];
+      for (int rb = 0; rb < WT_ROWB; ++rb) fa[s][g][rb] = pa[rb][g * 64];
 #pragma unroll
-        for (int rb = 0; rb < WT_ROWB; ++rb) av[rb] = ra[p][rb];
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) bv[cb] = rbv[p][cb];
-        if (k + PF < K) {
-#pragma unroll
-          for (int rb = 0; rb < WT_ROWB; ++rb) ra[p][rb] = ap[rb][(int64_t)(k + PF) * 64];
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) rbv[p][cb] = bp[(int64_t)(2 * (k + PF)) * N + cb * 32];
-        }
-#pragma unroll
-        for (int rb = 0; rb < WT_ROWB; ++rb)
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb)
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
-      }
+      for (int cb = 0; cb < CB; ++cb) fb[s][g][cb] = pb[g][cb * 32];
     }
+#pragma unroll
+    for (int rb = 0; rb < WT_ROWB; ++rb) pa[rb] += G * 64;
+#pragma unroll
+    for (int g = 0; g < G; ++g) pb[g] += bstep;
+  };
+  auto mma = [&](int s) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int rb = 0; rb < WT_ROWB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[s][g][rb], fb[s][g][cb], acc[rb][cb], 0, 0, 0);
+  };
+  const int Kmain = (K / (2 * G)) * (2 * G);
+  if (Kmain > 0) {
+    load(0);
+    for (int k0 = 0; k0 < Kmain; k0 += 2 * G) {
+      // the barriers keep each group's loads ahead of the other group's MFMAs
+      load(1);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (k0 + 2 * G < Kmain) load(0);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  for (int k = Kmain; k < K; ++k) {
+    float av[WT_ROWB], bv[CB];
+#pragma unroll
+    for (int rb = 0; rb < WT_ROWB; ++rb) av[rb] = ap[rb * astr + (int64_t)k * 64];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) bv[cb] = bp[(int64_t)(2 * k) * N + cb * 32];
+#pragma unroll
+    for (int rb = 0; rb < WT_ROWB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
   }
   epilogue<CB>(a, acc, rb0, q0);
 }
@@ -155,6 +203,7 @@ __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
 // (row 2k = Re, 2k+1 = Im) and gathered into the interleaved order here.
 template <int DT>
 __global__ __launch_bounds__(256) void k_recon_16(GemmArgs a) {
+  constexpr int NP = DT == 3 ? 2 : 1;   // operand planes (hi, lo)
   const int ntt = a.Tp / TILE_T;
   const int64_t nwg = (int64_t)ntt * (a.N / TILE_N);
   int tt;
@@ -168,6 +217,8 @@ __global__ __launch_bounds__(256) void k_recon_16(GemmArgs a) {
   const uint16_t* __restrict__ z = static_cast<const uint16_t*>(a.z);
   const int KB = a.Kp / 8;        // k-steps of 8 complex values (16 reduction rows)
   const int64_t N = a.N;
+  const int64_t cplane = (int64_t)(a.Tp / 16) * KB * 64;   // u16x8 per C plane
+  const int64_t zplane = (int64_t)2 * a.Kp * N;            // u16 per Z plane
   f32x16 acc[WT_ROWB][WT_COLB];
 #pragma unroll
   for (int rb = 0; rb < WT_ROWB; ++rb)
@@ -175,29 +226,26 @@ __global__ __launch_bounds__(256) void k_recon_16(GemmArgs a) {
     for (int cb = 0; cb < WT_COLB; ++cb) acc[rb][cb] = (f32x16){};
 #pragma unroll 2
   for (int kb = 0; kb < KB; ++kb) {
-    u16x8 av[WT_ROWB], bv[WT_COLB];
+    u16x8 av[NP][WT_ROWB], bv[NP][WT_COLB];
 #pragma unroll
-    for (int rb = 0; rb < WT_ROWB; ++rb) av[rb] = cpk[((int64_t)(rb0 + rb) * KB + kb) * 64 + lane];
+    for (int p = 0; p < NP; ++p) {
 #pragma unroll
-    for (int cb = 0; cb < WT_COLB; ++cb) {
-      const int64_t col = q0 + cb * 32 + (lane & 31);
-      const int64_t row = 16 * kb + 8 * (lane >> 5);   // planar rows 2k+t of complex k = 8kb + 4h + ..
-      u16x8 b;
+      for (int rb = 0; rb < WT_ROWB; ++rb) av[p][rb] = cpk[p * cplane + ((int64_t)(rb0 + rb) * KB + kb) * 64 + lane];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) b[e] = z[(row + e) * N + col];
-      bv[cb] = b;
+      for (int cb = 0; cb < WT_COLB; ++cb) {
+        const int64_t col = q0 + cb * 32 + (lane & 31);
+        const int64_t row = 16 * kb + 8 * (lane >> 5);   // planar rows 2k+t of complex k = 8kb + 4h + ..
+        u16x8 b;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) b[e] = z[p * zplane + (row + e) * N + col];
+        bv[p][cb] = b;
+      }
     }
 #pragma unroll
     for (int rb = 0; rb < WT_ROWB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < WT_COLB; ++cb) {
-        if (DT == 1)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              __builtin_bit_cast(bf16x8, av[rb]), __builtin_bit_cast(bf16x8, bv[cb]), acc[rb][cb], 0, 0, 0);
-        else
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-              __builtin_bit_cast(f16x8, av[rb]), __builtin_bit_cast(f16x8, bv[cb]), acc[rb][cb], 0, 0, 0);
-      }
+      for (int cb = 0; cb < WT_COLB; ++cb)
+        acc[rb][cb] = kstep<DT>(av[0][rb], av[NP - 1][rb], bv[0][cb], bv[NP - 1][cb], acc[rb][cb]);
   }
   epilogue<WT_COLB>(a, acc, rb0, q0);
 }
@@ -210,61 +258,100 @@ __global__ __launch_bounds__(256) void k_recon_16(GemmArgs a) {
 // come from L2.
 template <int DT>
 __global__ __launch_bounds__(256) void k_recon_16_lds(GemmArgs a) {
+  constexpr int NP = DT == 3 ? 2 : 1;   // operand planes (hi, lo)
   extern __shared__ uint16_t zs[];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t q0 = (int64_t)blockIdx.x * TILE_N;
   const int Kp = a.Kp, KB = Kp / 8, R2 = 2 * Kp;
-  const int RS = R2 + 8;            // LDS row stride (u16) of one sample
+  const int RS = NP * R2 + 8;       // LDS row stride (u16) of one sample: planes side by side
   const int64_t N = a.N;
+  const int64_t zplane = (int64_t)R2 * N;
   const uint16_t* __restrict__ z = static_cast<const uint16_t*>(a.z);
-  for (int idx = threadIdx.x; idx < R2 * (TILE_N / 8); idx += 256) {
-    const int r = idx / (TILE_N / 8), c8 = (idx % (TILE_N / 8)) * 8;
-    const u16x8 v = *reinterpret_cast<const u16x8*>(z + (int64_t)r * N + q0 + c8);
+  for (int idx = threadIdx.x; idx < NP * R2 * (TILE_N / 8); idx += 256) {
+    const int pr = idx / (TILE_N / 8), c8 = (idx % (TILE_N / 8)) * 8;   // pr = plane * R2 + row
+    const int p = pr / R2, r = pr % R2;
+    const u16x8 v = *reinterpret_cast<const u16x8*>(z + p * zplane + (int64_t)r * N + q0 + c8);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) zs[(c8 + e) * RS + r] = v[e];
+    for (int e = 0; e < 8; ++e) zs[(c8 + e) * RS + pr] = v[e];
   }
   __syncthreads();
   const u16x8* __restrict__ cpk = static_cast<const u16x8*>(a.cpk);
   const int ntt = a.Tp / TILE_T;
+  const int64_t cplane = (int64_t)ntt * (TILE_T / 16) * KB * 64;
+  // A fragments of G k-steps prefetched into one of two register buffers while
+  // the other group's MFMAs run; B fragments come from LDS just before use.
+  constexpr int G = NP == 2 ? 2 : 4;
+  const int Kmain = (KB / (2 * G)) * (2 * G);
+  const uint16_t* zl = zs + (lane & 31) * RS + 8 * (lane >> 5);
   for (int tt = 0; tt < ntt; ++tt) {
     const int rb0 = tt * (TILE_T / 16) + wave * WT_ROWB;
+    const u16x8* __restrict__ ap = cpk + (int64_t)rb0 * KB * 64 + lane;
     f32x16 acc[WT_ROWB][WT_COLB];
 #pragma unroll
     for (int rb = 0; rb < WT_ROWB; ++rb)
 #pragma unroll
       for (int cb = 0; cb < WT_COLB; ++cb) acc[rb][cb] = (f32x16){};
-#pragma unroll 2
-    for (int kb = 0; kb < KB; ++kb) {
-      u16x8 av[WT_ROWB], bv[WT_COLB];
+    u16x8 fa[2][G][NP][WT_ROWB];
+    auto load = [&](int s, int kb0) {
 #pragma unroll
-      for (int rb = 0; rb < WT_ROWB; ++rb) av[rb] = cpk[((int64_t)(rb0 + rb) * KB + kb) * 64 + lane];
+      for (int g = 0; g < G; ++g)
 #pragma unroll
-      for (int cb = 0; cb < WT_COLB; ++cb)
-        bv[cb] = *reinterpret_cast<const u16x8*>(zs + (cb * 32 + (lane & 31)) * RS + 16 * kb + 8 * (lane >> 5));
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+          for (int rb = 0; rb < WT_ROWB; ++rb)
+            fa[s][g][p][rb] = ap[p * cplane + ((int64_t)rb * KB + kb0 + g) * 64];
+    };
+    auto step = [&](const u16x8 (&av)[NP][WT_ROWB], int kb) {
+      u16x8 bv[NP][WT_COLB];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int cb = 0; cb < WT_COLB; ++cb)
+          bv[p][cb] = *reinterpret_cast<const u16x8*>(zl + cb * 32 * RS + p * R2 + 16 * kb);
 #pragma unroll
       for (int rb = 0; rb < WT_ROWB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < WT_COLB; ++cb) {
-          if (DT == 1)
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, av[rb]), __builtin_bit_cast(bf16x8, bv[cb]), acc[rb][cb], 0, 0, 0);
-          else
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                __builtin_bit_cast(f16x8, av[rb]), __builtin_bit_cast(f16x8, bv[cb]), acc[rb][cb], 0, 0, 0);
-        }
+        for (int cb = 0; cb < WT_COLB; ++cb)
+          acc[rb][cb] = kstep<DT>(av[0][rb], av[NP - 1][rb], bv[0][cb], bv[NP - 1][cb], acc[rb][cb]);
+    };
+    if (Kmain > 0) {
+      load(0, 0);
+      for (int kb0 = 0; kb0 < Kmain; kb0 += 2 * G) {
+        // the barriers keep each group's A loads ahead of the other group's MFMAs
+        load(1, kb0 + G);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int g = 0; g < G; ++g) step(fa[0][g], kb0 + g);
+        __builtin_amdgcn_sched_barrier(0);
+        if (kb0 + 2 * G < Kmain) load(0, kb0 + 2 * G);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int g = 0; g < G; ++g) step(fa[1][g], kb0 + G + g);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    for (int kb = Kmain; kb < KB; ++kb) {
+      u16x8 av[NP][WT_ROWB];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int rb = 0; rb < WT_ROWB; ++rb) av[p][rb] = ap[p * cplane + ((int64_t)rb * KB + kb) * 64];
+      step(av, kb);
     }
     epilogue<WT_COLB>(a, acc, rb0, q0);
   }
 }
 
 // ------------------------------------------------------------------ packing
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 __device__ __forceinline__ uint16_t to16(float x, int dtype) {
-  if (dtype == 1) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-  }
+  if (dtype == 1 || dtype == 3) return bf16_rne(x);
   _Float16 h = (_Float16)x;
   return __builtin_bit_cast(uint16_t, h);
 }
@@ -310,7 +397,10 @@ __global__ void k_pack_16(const float2* C, int T, int Tp, int K, int Kp, int dty
     const int rb = (int)(rkb / KB);
     const int red = 8 * (l >> 5) + e;          // reduction index within the 16-step
     const int k = kb * 8 + (red >> 1);
-    out[i] = to16(a_entry(C, T, K, rb, l & 31, k, red & 1, row_scale), dtype);
+    const float x = a_entry(C, T, K, rb, l & 31, k, red & 1, row_scale);
+    const uint16_t h = to16(x, dtype);
+    out[i] = h;
+    if (dtype == 3) out[total + i] = bf16_rne(x - __uint_as_float((uint32_t)h << 16));   // lo plane
   }
 }
 
@@ -331,31 +421,37 @@ hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
     return hipGetLastError();
   }
   // 16-bit: variant 0 stages the Z tile in LDS (when it fits), 1 loads fragments directly
-  const size_t lds = (size_t)TILE_N * (2 * a.Kp + 8) * 2;
+  const int np = a.dtype == 3 ? 2 : 1;
+  const size_t lds = (size_t)TILE_N * (np * 2 * a.Kp + 8) * 2;
   if (a.variant == 0 && lds <= kLdsMax) {
     static bool attr_set = false;
     if (!attr_set) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_recon_16_lds<1>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
-      if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_recon_16_lds<2>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
-      if (e != hipSuccess) return e;
+      const void* fns[] = {reinterpret_cast<const void*>(&k_recon_16_lds<1>),
+                           reinterpret_cast<const void*>(&k_recon_16_lds<2>),
+                           reinterpret_cast<const void*>(&k_recon_16_lds<3>)};
+      for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+        if (e != hipSuccess) return e;
+      }
       attr_set = true;
     }
     const unsigned grid = (unsigned)(a.N / TILE_N);
     if (a.dtype == 1)
       hipLaunchKernelGGL(k_recon_16_lds<1>, dim3(grid), dim3(256), lds, st, a);
-    else
+    else if (a.dtype == 2)
       hipLaunchKernelGGL(k_recon_16_lds<2>, dim3(grid), dim3(256), lds, st, a);
+    else
+      hipLaunchKernelGGL(k_recon_16_lds<3>, dim3(grid), dim3(256), lds, st, a);
     return hipGetLastError();
   }
   const int64_t nwg = (int64_t)(a.Tp / TILE_T) * (a.N / TILE_N);
   const int64_t launch = ((nwg + 7) / 8) * 8;
   if (a.dtype == 1)
     hipLaunchKernelGGL(k_recon_16<1>, dim3((unsigned)launch), dim3(256), 0, st, a);
-  else
+  else if (a.dtype == 2)
     hipLaunchKernelGGL(k_recon_16<2>, dim3((unsigned)launch), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_recon_16<3>, dim3((unsigned)launch), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

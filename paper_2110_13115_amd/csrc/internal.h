@@ -52,7 +52,7 @@ enum InKind { IN_CORR = 0, IN_REAL = 1, IN_DENSE = 2 };
 // Pass-2 output variants.
 enum OutKind {
   OUT_Z32 = 0,       // planar FP32 Z: row 2v = Re, row 2v+1 = Im, row stride N
-  OUT_Z16 = 1,       // planar 16-bit Z (bf16 or f16), same layout, values * zscale
+  OUT_Z16 = 1,       // planar 16-bit Z (bf16, f16, or bf16 hi + lo planes), same layout, values * zscale
   OUT_THRESH = 2,    // |x|^2 >= thr2: append trigger, per-vector count and max
   OUT_NATURAL = 3,   // complex64 natural order out[v][n]
   OUT_SPECTRUM = 4,  // forward transform of the strain: d[k - kb] = wd[k] X[k], band only
@@ -90,8 +90,9 @@ struct PassArgs {
   float2* work;
   // pass-2 outputs
   float* zout;               // OUT_Z32 / OUT_Z16 (as raw bytes for 16-bit)
-  int zdtype;                // 0 f32, 1 bf16, 2 f16
+  int zdtype;                // 0 f32, 1 bf16, 2 f16, 3 bf16 hi plane + bf16 lo plane
   float zscale;
+  int64_t zplane;            // dtype 3: offset (16-bit elements) of the lo plane
   float thr2;                // OUT_THRESH: squared threshold
   TrigRec* trig;             // OUT_THRESH
   int64_t trig_cap;
@@ -199,8 +200,8 @@ hipError_t launch_row_norms(const float2* w, int64_t rows, int64_t len, int64_t 
 
 // ---------------------------------------------------------------- misc
 hipError_t launch_check_finite(const float* x, int64_t n, int64_t* flag, hipStream_t s);
-hipError_t launch_z_to_natural(const void* z, int dtype, float inv_scale, int64_t N, int K, int N1,
-                               int N2, float2* out, hipStream_t s);
+hipError_t launch_z_to_natural(const void* z, int dtype, int64_t plane, float inv_scale, int64_t N, int K,
+                               int N1, int N2, float2* out, hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint
 hipError_t launch_rho_at(const float* z, int64_t N, int K, int N1, int N2, const float2* C,

@@ -245,6 +245,39 @@ def test_rb_16bit_matches_quantised_product(ctx, rb_case, dtype):
     basis.close()
 
 
+def test_rb_bf16x3_fp32_accuracy(ctx, rb_case):
+    """Split-BF16 reconstruction (hi + lo of C and Z, three MFMA products):
+    equals the emulated split product to FP32 rounding and stays within the
+    FP32 path's 1e-4 of the FP64 reduced-basis SNR."""
+    case, bank = rb_case
+    basis = rbmf.Basis(ctx, bank, rank=0, tol=1e-3, dtype="bf16x3")
+    V, c, lam = basis.export()
+    Zs = rbmf.debug_basis_outputs(ctx, basis, case.strain)            # hi + lo (exact in FP32)
+    Zh = _quant(Zs.real, "bf16") + 1j * _quant(Zs.imag, "bf16")
+    Zl = Zs.astype(np.complex128) - Zh
+    Cc = np.conj(c).astype(np.complex64)
+
+    def split(x):
+        h = _quant(x, "bf16")
+        return h, _quant(np.asarray(x, np.float64) - h, "bf16")
+    hr, lr = split(Cc.real)
+    hi_, li = split(Cc.imag)
+    Ch, Cl = hr + 1j * hi_, lr + 1j * li
+    ref = Ch @ Zh + Ch @ Zl + Cl @ Zh
+    rho = rbmf.debug_rho(ctx, bank, case.strain, basis)
+    e_kernel = (np.abs(rho - ref) / np.maximum(np.abs(ref), 1.0)).max()
+    k_lo, _ = om.band_limits(case.N, case.fs, case.f_low)
+    d = ob.whitened_data(case.s64, case.psd, case.fs, case.f_low)
+    exact = ob.rb_snr(ob.basis_outputs(d, V, case.N, k_lo), c)
+    e64 = (np.abs(rho - exact) / np.maximum(np.abs(exact), 1.0))
+    log(f"  bf16x3 kernel err {e_kernel:.2e}  vs FP64 max {e64.max():.2e} rms {np.sqrt(np.mean(e64**2)):.2e}")
+    assert e_kernel <= 1e-5
+    assert e64.max() <= 1e-4
+    trig, _, st = rbmf.rb_filter(ctx, basis, bank, case.strain, 5.0, 6.0, stage2=rbmf.RB_STAGE2_SPARSE)
+    compare_triggers(trig, case.rho, 6.0)
+    basis.close()
+
+
 def test_subbank_bases_partition(ctx, rb_case):
     """Bases of three template ranges (sub-banks, Sec. III.B): the final
     triggers equal the oracle's; per-range reconstruction matches the oracle's
