@@ -116,7 +116,7 @@ def run_batch(args, wname):
         s = bw.strain(i, N, bd, sigma_of)
         items.append((torch.from_numpy(s).cuda(), bank, bases))
     prep_s = time.time() - t0
-    cap_item = 1 << 17
+    cap_item = 1 << 20
     sp = rbmf.RB_STAGE2_SPARSE
 
     def replay():

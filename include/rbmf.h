@@ -297,7 +297,8 @@ rb_status rb_debug_rho(rb_ctx ctx, rb_basis basis, rb_bank bank, const float* st
 
 /* Dump the per-basis filter outputs beta (K x N x 2 floats, natural time
  * order, host or device) as stored for the reconstruction (after any 16-bit
- * rounding and with its scale removed). */
+ * rounding and with its scale removed).  For RB_BF16X3 bases beta holds
+ * 2 x K x N x 2 floats: the high parts, then the low parts. */
 rb_status rb_debug_basis_outputs(rb_ctx ctx, rb_basis basis, const float* strain, float* beta);
 
 #ifdef __cplusplus

@@ -263,8 +263,17 @@ rb_status fill32(rb_ctx ctx, void* p, uint32_t v, int64_t n) {
 
 // vectors per FFT batch: keep the [B][N] intermediate near 256 MB so the
 // pass-1 -> pass-2 round trip can stay in the Infinity Cache.
+// Vectors per FFT launch pair: the pass-1 -> pass-2 intermediate ([B][N]
+// complex64) is sized to a share of the 256 MB Infinity Cache (RBMF_WORK_MB,
+// default 128) so that the round trip need not reach HBM.
+int64_t work_budget_bytes() {
+  const char* e = std::getenv("RBMF_WORK_MB");
+  const int64_t mb = e ? std::atoll(e) : 128;
+  return std::max<int64_t>(8, std::min<int64_t>(mb, 4096)) << 20;
+}
+
 int batch_vectors(int64_t N, int64_t nvec) {
-  int64_t b = (int64_t(256) << 20) / (N * 8);
+  int64_t b = work_budget_bytes() / (N * 8);
   b = std::max<int64_t>(1, std::min<int64_t>(b, 1024));
   return (int)std::min<int64_t>(b, std::max<int64_t>(nvec, 1));
 }
@@ -1371,15 +1380,19 @@ extern "C" rb_status rb_debug_basis_outputs(rb_ctx ctx, rb_basis basis, const fl
   RB_TRY(strain_device(ctx, strain, g.N, &s));
   RB_TRY(step_spectrum(ctx, bank, g, tw, s));
   RB_TRY(step_basis_outputs(ctx, basis, g, tw));
+  const int planes = basis->dtype == RB_BF16X3 ? 2 : 1;    // BF16X3: high parts, then low parts
+  const size_t bytes = (size_t)planes * K * g.N * 8;
   float2* dst = reinterpret_cast<float2*>(beta);
   const bool dev = is_device_ptr(beta);
   if (!dev) {
-    RB_TRY(ctx->rho_tmp.ensure((size_t)K * g.N * 8));
+    RB_TRY(ctx->rho_tmp.ensure(bytes));
     dst = ctx->rho_tmp.as<float2>();
   }
-  RB_HIP(launch_z_to_natural(ctx->z.p, (int)basis->dtype, (int64_t)2 * basis->Kp * g.N, 1.f, g.N, K, g.N1, g.N2,
-                             dst, ctx->stream));
-  if (!dev) RB_HIP(hipMemcpyAsync(beta, dst, (size_t)K * g.N * 8, hipMemcpyDeviceToHost, ctx->stream));
+  const int dt = basis->dtype == RB_BF16X3 ? (int)RB_BF16 : (int)basis->dtype;
+  for (int p = 0; p < planes; ++p)
+    RB_HIP(launch_z_to_natural(static_cast<const uint16_t*>(ctx->z.p) + (size_t)p * 2 * basis->Kp * g.N, dt, 1.f,
+                               g.N, K, g.N1, g.N2, dst + (size_t)p * K * g.N, ctx->stream));
+  if (!dev) RB_HIP(hipMemcpyAsync(beta, dst, bytes, hipMemcpyDeviceToHost, ctx->stream));
   RB_HIP(hipStreamSynchronize(ctx->stream));
   return RB_OK;
 }

@@ -179,7 +179,7 @@ __device__ __forceinline__ void lds_stage(V* lds, const V* __restrict__ pyr, int
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int b = tid + i * NT;
-    if (b < NB) {
+    if (NB % NT == 0 || b < NB) {   // (the test folds away when NT divides NB)
       int f, j;
       Lay::template split<R>(b, f, j);
 #pragma unroll
@@ -190,7 +190,7 @@ __device__ __forceinline__ void lds_stage(V* lds, const V* __restrict__ pyr, int
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int b = tid + i * NT;
-    if (b < NB) {
+    if (NB % NT == 0 || b < NB) {   // (the test folds away when NT divides NB)
       int f, j;
       Lay::template split<R>(b, f, j);
       const int k = j % Ns;
@@ -216,7 +216,7 @@ __device__ __forceinline__ void final_stage(const V* lds, const V* __restrict__ 
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int b = tid + i * NT;
-    if (b < NB) {
+    if (NB % NT == 0 || b < NB) {   // (the test folds away when NT divides NB)
       int f, j;
       Lay::template split<R>(b, f, j);
       V v[R];
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int b = tid + i * NT;
-      if (b < NB) {
+      if (NB % NT == 0 || b < NB) {   // (the test folds away when NT divides NB)
         const int c = b % C, j = b / C;
         const int f1 = f1_0 + c;
         V x[R1];
@@ -294,11 +294,13 @@ __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
           const int f2 = j + r * (L / R1);
           const int64_t f = (int64_t)f1 + (int64_t)N1 * f2;
           if (IN == IN_CORR) {
-            if (f >= lo && f <= hi) {
-              const float2 dv = a.d[f - a.kb];
-              const float2 pv = a.src[(int64_t)v * a.nbs + (f - a.kb)];
-              x[r] = mk<V>(dv.x * pv.x + dv.y * pv.y, dv.y * pv.x - dv.x * pv.y);
-            }
+            // read at the bin clamped into the support [lo, hi] (always in
+            // bounds, no branch around the loads) and mask bins outside it
+            const int64_t fc = f < lo ? lo : (f > hi ? hi : f);
+            const float2 dv = a.d[fc - a.kb];
+            const float2 pv = a.src[(int64_t)v * a.nbs + (fc - a.kb)];
+            const float m = (f == fc) ? 1.f : 0.f;
+            x[r] = mk<V>(m * (dv.x * pv.x + dv.y * pv.y), m * (dv.y * pv.x - dv.x * pv.y));
           } else if (IN == IN_REAL) {
             x[r] = mk<V>((T)a.real_in[f], 0);
           } else {
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int b = tid + i * NT;
-      if (b < NB) {
+      if (NB % NT == 0 || b < NB) {   // (the test folds away when NT divides NB)
         int c, j;
         Lay::template split<RL>(b, c, j);
         V v[RL];
@@ -388,7 +390,7 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int b = tid + i * NT;
-      if (b < NB) {
+      if (NB % NT == 0 || b < NB) {   // (the test folds away when NT divides NB)
         int f, j;
         Lay::template split<R1>(b, f, j);
         V x[R1];

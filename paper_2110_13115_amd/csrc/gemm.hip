@@ -34,12 +34,13 @@ template <int CB>
 __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[WT_ROWB][CB], int rb0,
                                          int64_t q0) {
   const int lane = __lane_id();
+  const int l1 = __builtin_ctz((unsigned)a.N1);            // N1 is a power of two
 #pragma unroll
   for (int rb = 0; rb < WT_ROWB; ++rb) {
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
-      const int64_t q = q0 + cb * 32 + (lane & 31);
-      const int n = (int)(q / a.N1) + a.N2 * (int)(q % a.N1);
+      const int q = (int)q0 + cb * 32 + (lane & 31);        // q < N < 2^31
+      const int n = (q >> l1) + a.N2 * (q & (a.N1 - 1));
 #pragma unroll
       for (int i = 0; i < 16; i += 2) {
         const int m = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);   // even: Re row
@@ -121,6 +122,7 @@ __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int rb0 = tt * (TILE_T / 16) + wave * WT_ROWB;     // first 16-template row block
+  if (rb0 * 16 >= a.T) return;                             // all of this wave's rows are padding
   const int64_t q0 = st * TN;
   const int K = a.K;
   const int64_t N = a.N;
@@ -212,6 +214,7 @@ __global__ __launch_bounds__(256) void k_recon_16(GemmArgs a) {
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int rb0 = tt * (TILE_T / 16) + wave * WT_ROWB;
+  if (rb0 * 16 >= a.T) return;                             // all of this wave's rows are padding
   const int64_t q0 = st * TILE_N;
   const u16x8* __restrict__ cpk = static_cast<const u16x8*>(a.cpk);
   const uint16_t* __restrict__ z = static_cast<const uint16_t*>(a.z);
@@ -268,12 +271,38 @@ __global__ __launch_bounds__(256) void k_recon_16_lds(GemmArgs a) {
   const int64_t N = a.N;
   const int64_t zplane = (int64_t)R2 * N;
   const uint16_t* __restrict__ z = static_cast<const uint16_t*>(a.z);
-  for (int idx = threadIdx.x; idx < NP * R2 * (TILE_N / 8); idx += 256) {
-    const int pr = idx / (TILE_N / 8), c8 = (idx % (TILE_N / 8)) * 8;   // pr = plane * R2 + row
-    const int p = pr / R2, r = pr % R2;
-    const u16x8 v = *reinterpret_cast<const u16x8*>(z + p * zplane + (int64_t)r * N + q0 + c8);
+  {
+    // One item = (plane p, complex k, 8 samples): rows 2k (Re) and 2k+1 (Im) are
+    // loaded with 16-byte reads and stored as (Re, Im) 32-bit LDS words at
+    // sample * RS + p * R2 + 2k; CH items per thread are in flight at once.
+    uint32_t* zs32 = reinterpret_cast<uint32_t*>(zs);
+    const int RS2 = RS / 2;
+    const int items = NP * Kp * (TILE_N / 8);
+    constexpr int CH = 4;
+    for (int base = threadIdx.x; base < items; base += 256 * CH) {
+      u16x8 vr[CH], vi[CH];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) zs[(c8 + e) * RS + pr] = v[e];
+      for (int c = 0; c < CH; ++c) {
+        const int idx = base + c * 256;
+        if (idx < items) {
+          const int pk = idx / (TILE_N / 8), c8 = (idx % (TILE_N / 8)) * 8;   // pk = p * Kp + k
+          const int p = pk / Kp, k = pk % Kp;
+          const uint16_t* src = z + p * zplane + (int64_t)(2 * k) * N + q0 + c8;
+          vr[c] = *reinterpret_cast<const u16x8*>(src);
+          vi[c] = *reinterpret_cast<const u16x8*>(src + N);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int idx = base + c * 256;
+        if (idx < items) {
+          const int pk = idx / (TILE_N / 8), c8 = (idx % (TILE_N / 8)) * 8;
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            zs32[(c8 + e) * RS2 + pk] = (uint32_t)vr[c][e] | ((uint32_t)vi[c][e] << 16);
+        }
+      }
+    }
   }
   __syncthreads();
   const u16x8* __restrict__ cpk = static_cast<const u16x8*>(a.cpk);
@@ -286,6 +315,7 @@ __global__ __launch_bounds__(256) void k_recon_16_lds(GemmArgs a) {
   const uint16_t* zl = zs + (lane & 31) * RS + 8 * (lane >> 5);
   for (int tt = 0; tt < ntt; ++tt) {
     const int rb0 = tt * (TILE_T / 16) + wave * WT_ROWB;
+    if (rb0 * 16 >= a.T) break;                            // the rest of the rows are padding
     const u16x8* __restrict__ ap = cpk + (int64_t)rb0 * KB * 64 + lane;
     f32x16 acc[WT_ROWB][WT_COLB];
 #pragma unroll

@@ -200,8 +200,9 @@ hipError_t launch_row_norms(const float2* w, int64_t rows, int64_t len, int64_t 
 
 // ---------------------------------------------------------------- misc
 hipError_t launch_check_finite(const float* x, int64_t n, int64_t* flag, hipStream_t s);
-hipError_t launch_z_to_natural(const void* z, int dtype, int64_t plane, float inv_scale, int64_t N, int K,
-                               int N1, int N2, float2* out, hipStream_t s);
+// dtype 0 FP32, 1 BF16, 2 FP16 planar Z (one plane) -> complex64 natural order
+hipError_t launch_z_to_natural(const void* z, int dtype, float inv_scale, int64_t N, int K, int N1,
+                               int N2, float2* out, hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint
 hipError_t launch_rho_at(const float* z, int64_t N, int K, int N1, int N2, const float2* C,

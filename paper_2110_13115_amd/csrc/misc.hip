@@ -21,8 +21,8 @@ __device__ __forceinline__ float ld16(const uint16_t* p, int dtype) {
   return (float)__builtin_bit_cast(_Float16, u);
 }
 
-__global__ void k_z_to_natural(const void* z, int dtype, int64_t plane, float inv_scale, int64_t N, int K,
-                               int N1, int N2, float2* out) {
+__global__ void k_z_to_natural(const void* z, int dtype, float inv_scale, int64_t N, int K, int N1, int N2,
+                               float2* out) {
   const int64_t total = (int64_t)K * N;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t k = i / N, q = i % N;
@@ -34,13 +34,8 @@ __global__ void k_z_to_natural(const void* z, int dtype, int64_t plane, float in
       im = zf[(2 * k + 1) * N + q];
     } else {
       const uint16_t* zh = static_cast<const uint16_t*>(z);
-      const int d = dtype == 3 ? 1 : dtype;
-      re = ld16(zh + (2 * k) * N + q, d);
-      im = ld16(zh + (2 * k + 1) * N + q, d);
-      if (dtype == 3) {   // plus the low-order plane
-        re += ld16(zh + plane + (2 * k) * N + q, 1);
-        im += ld16(zh + plane + (2 * k + 1) * N + q, 1);
-      }
+      re = ld16(zh + (2 * k) * N + q, dtype);
+      im = ld16(zh + (2 * k + 1) * N + q, dtype);
     }
     out[k * N + n] = make_float2(re * inv_scale, im * inv_scale);
   }
@@ -53,9 +48,9 @@ hipError_t launch_check_finite(const float* x, int64_t n, int64_t* flag, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_z_to_natural(const void* z, int dtype, int64_t plane, float inv_scale, int64_t N, int K, int N1,
-                               int N2, float2* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_z_to_natural, dim3(4096), dim3(256), 0, s, z, dtype, plane, inv_scale, N, K, N1, N2, out);
+hipError_t launch_z_to_natural(const void* z, int dtype, float inv_scale, int64_t N, int K, int N1, int N2,
+                               float2* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_z_to_natural, dim3(4096), dim3(256), 0, s, z, dtype, inv_scale, N, K, N1, N2, out);
   return hipGetLastError();
 }
 

@@ -34,8 +34,21 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
   if (a.n1_dev != nullptr && *a.n1_dev > a.n1_cap) return;
   const int j = a.list[blockIdx.x];
   const int nlo = 1 << a.s_lo, nhi = (int)(a.N >> a.s_lo);
-  for (int i = threadIdx.x; i < nlo; i += SP_T) tlo[i] = a.tlo[i];
-  for (int i = threadIdx.x; i < nhi; i += SP_T) thi[i] = a.thi[i];
+  // table copies: every load of a thread (clamped in bounds) issued before its LDS stores
+  {
+    constexpr int PL = 2048 / SP_T, PH = 1024 / SP_T;
+    float2 vl[PL], vh[PH];
+#pragma unroll
+    for (int i = 0; i < PL; ++i) vl[i] = a.tlo[min((int)threadIdx.x + i * SP_T, nlo - 1)];
+#pragma unroll
+    for (int i = 0; i < PH; ++i) vh[i] = a.thi[min((int)threadIdx.x + i * SP_T, nhi - 1)];
+#pragma unroll
+    for (int i = 0; i < PL; ++i)
+      if ((int)threadIdx.x + i * SP_T < nlo) tlo[threadIdx.x + i * SP_T] = vl[i];
+#pragma unroll
+    for (int i = 0; i < PH; ++i)
+      if ((int)threadIdx.x + i * SP_T < nhi) thi[threadIdx.x + i * SP_T] = vh[i];
+  }
   __syncthreads();
   const int mask = nlo - 1;
   const int64_t Nm = a.N - 1;
@@ -51,23 +64,34 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
     int ns[SP_M];
     float2 step[SP_M], acc[SP_M];
 #pragma unroll
+    for (int i = 0; i < SP_M; ++i)   // in-bounds index for every slot; slots >= m are unused
+      ns[i] = a.recs[off + c0 + min(i, m - 1)].sample;
+#pragma unroll
     for (int i = 0; i < SP_M; ++i) {
-      ns[i] = i < m ? a.recs[off + c0 + i].sample : 0;
       step[i] = tw(ns[i]);
       acc[i] = make_float2(0.f, 0.f);
     }
+    // Bins past hi are read at hi (in bounds) and masked to zero; the next
+    // tile's operands are loaded while this tile's sums run.
+    float2 dn[SP_R], wn[SP_R];
+    auto fetch = [&](int f0) {
+#pragma unroll
+      for (int r = 0; r < SP_R; ++r) {
+        const int f = min(f0 + r, hi);
+        dn[r] = d[f];
+        wn[r] = wj[f];
+      }
+    };
+    fetch(lo + threadIdx.x * SP_R);
     for (int f0 = lo + threadIdx.x * SP_R; f0 <= hi; f0 += SP_T * SP_R) {
       float2 x[SP_R];
 #pragma unroll
       for (int r = 0; r < SP_R; ++r) {
-        const int f = f0 + r;
-        if (f <= hi) {
-          const float2 dv = d[f], wv = wj[f];
-          x[r] = make_float2(dv.x * wv.x + dv.y * wv.y, dv.y * wv.x - dv.x * wv.y);   // d conj(w)
-        } else {
-          x[r] = make_float2(0.f, 0.f);
-        }
+        const float2 dv = dn[r], wv = wn[r];
+        const float mk = (f0 + r <= hi) ? 1.f : 0.f;
+        x[r] = make_float2(mk * (dv.x * wv.x + dv.y * wv.y), mk * (dv.y * wv.x - dv.x * wv.y));   // d conj(w)
       }
+      fetch(f0 + SP_T * SP_R);
 #pragma unroll
       for (int i = 0; i < SP_M; ++i) {
         if (i < m) {

@@ -84,6 +84,13 @@ def tau0(m1: float, m2: float, f0: float) -> float:
     return 5.0 / (256.0 * np.pi * f0 * eta) * (np.pi * M * f0) ** (-5.0 / 3.0)
 
 
+def tau0_array(m1: np.ndarray, m2: np.ndarray, f0: float) -> np.ndarray:
+    """tau0 of many mass pairs (vectorised form of tau0)."""
+    M = (m1 + m2) * MSUN_S
+    eta = m1 * m2 / (m1 + m2) ** 2
+    return 5.0 / (256.0 * np.pi * f0 * eta) * (np.pi * M * f0) ** (-5.0 / 3.0)
+
+
 def _pn_phase_series(v: np.ndarray, eta: float, order: int) -> np.ndarray:
     """sum_k phi_k v^k of the TaylorF2 phase, up to PN order `order` (0..7
     in units of half-PN, i.e. order=7 is 3.5PN)."""
@@ -255,12 +262,22 @@ class Bank:
 
 
 def random_bank(cfg: int, T: int, N: int, fs: float, f_low: float, mmin: float, mmax: float,
-                order: int, sort_tau0: bool = False) -> Bank:
+                order: int, sort_tau0: bool = False, parent: int = 0) -> Bank:
     """m1, m2 i.i.d. uniform in [mmin, mmax] (seed purpose 0); optionally
     ordered by tau0 at f_low so that sub-banks are contiguous tau0 slices (the
-    split of Sec. III.B)."""
+    split of Sec. III.B).  With parent > T the masses of a `parent`-template
+    bank are drawn, ordered by tau0, and the T central ones kept: one tau0
+    sub-bank of a dense bank."""
     rng = rng_for(cfg, PURPOSE_BANK)
-    m = rng.uniform(mmin, mmax, size=(T, 2))
+    if parent > T:
+        m = rng.uniform(mmin, mmax, size=(parent, 2))
+        t0 = tau0_array(m[:, 0], m[:, 1], f_low)
+        m = m[np.argsort(t0, kind="stable")]
+        lo = (parent - T) // 2
+        m = m[lo:lo + T]
+        sort_tau0 = False
+    else:
+        m = rng.uniform(mmin, mmax, size=(T, 2))
     if sort_tau0:
         t0 = np.array([tau0(a, b, f_low) for a, b in m])
         m = m[np.argsort(t0, kind="stable")]
@@ -337,6 +354,7 @@ class Workload:
     on_bank: bool = True
     subbanks: int = 1              # equal tau0-ordered sub-banks, one basis each
     ranks: Tuple[int, ...] = ()    # fixed rank per sub-bank (empty: by energy / `rank`)
+    parent: int = 0                # > T: the bank is the central tau0 slice of a parent bank
 
     @property
     def seconds(self) -> float:
@@ -344,7 +362,7 @@ class Workload:
 
     def bank(self) -> Bank:
         return random_bank(self.cfg, self.T, self.N, self.fs, self.f_low, self.mmin, self.mmax,
-                           self.order, sort_tau0=self.subbanks > 1)
+                           self.order, sort_tau0=self.subbanks > 1, parent=self.parent)
 
     def bounds(self) -> List[int]:
         """Sub-bank template boundaries [0, ..., T]."""
@@ -367,6 +385,11 @@ WORKLOADS = {
     # 10000 templates, 0PN, 16 s, f_low 30 Hz, m in [1, 20]
     "rb_16s_10000t": Workload("rb_16s_10000t", 3, 32768, 2048.0, 30.0, 10000, 1.0, 20.0, 0,
                               tol=1e-3, thr1=5.0, thr2=6.0, inj_snrs=(10.0,)),
+    # one tau0 sub-bank of a dense bank (the regime of the paper's 6250-template sub-bank):
+    # the central 6250 of 200000 tau0-ordered templates with m in [1, 3], 128 s, 3.5PN
+    "rb_128s_6250t_dense": Workload("rb_128s_6250t_dense", 6, 262144, 2048.0, 20.0, 6250, 1.0, 3.0, 7,
+                                    tol=1e-3, thr1=5.0, thr2=6.0, inj_snrs=(8.0, 10.0, 12.0),
+                                    parent=200000),
     # 20000 templates, rank 256, 512 s, m in [1, 50]
     "rb_512s_20000t": Workload("rb_512s_20000t", 5, 1048576, 2048.0, 20.0, 20000, 1.0, 50.0, 7,
                                rank=256, thr1=5.0, thr2=6.0,

@@ -323,14 +323,16 @@ def cluster_peaks(ctx: Context, trig: np.ndarray, W: int, N: int) -> np.ndarray:
 
 
 def debug_rho(ctx: Context, bank: Bank, strain, basis: Optional[Basis] = None) -> np.ndarray:
-    rho = np.empty((bank.T, bank.N), dtype=np.complex64)
+    rho = np.empty((basis.T if basis else bank.T, bank.N), dtype=np.complex64)
     _check(lib().rb_debug_rho(ctx.h, basis.h if basis else None, bank.h, _ptr(strain), _ptr(rho)),
            "rb_debug_rho")
     return rho
 
 
 def debug_basis_outputs(ctx: Context, basis: Basis, strain) -> np.ndarray:
-    z = np.empty((basis.K, basis.bank.N), dtype=np.complex64)
+    """(K, N) complex64; for a bf16x3 basis (2, K, N): high parts, low parts."""
+    shape = (2, basis.K, basis.bank.N) if basis.dtype == RB_BF16X3 else (basis.K, basis.bank.N)
+    z = np.empty(shape, dtype=np.complex64)
     _check(lib().rb_debug_basis_outputs(ctx.h, basis.h, _ptr(strain), _ptr(z)), "rb_debug_basis_outputs")
     return z
 

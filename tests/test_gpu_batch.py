@@ -89,7 +89,9 @@ def test_graph_replays_with_new_data(batch):
 
 def test_batch_sparse_stage2(batch):
     """Sparse exact second stage inside the batch (eager and graph) equals the
-    per-item sparse rb_filter and the full second stage."""
+    per-item sparse rb_filter; its triggers are the full second stage's at the
+    first-stage crossings (the low fixed ranks here leave reconstruction errors
+    above thr2 - thr1, so the full stage may find more), with the same SNRs."""
     ctx, setups, items, strains = batch
     sp = rbmf.RB_STAGE2_SPARSE
     full, _ = rbmf.rb_filter_batch(ctx, items, 5.0, 6.0, use_graph=False)
@@ -98,12 +100,18 @@ def test_batch_sparse_stage2(batch):
         graph, _ = rbmf.rb_filter_batch(ctx, items, 5.0, 6.0, use_graph=True, stage2=sp)
         for i, (sd, bank, bases) in enumerate(items):
             assert graph[i].tobytes() == eager[i].tobytes(), (rep, i)
+    missed = []
     for i, (sd, bank, bases) in enumerate(items):
         one, _, _ = rbmf.rb_filter(ctx, bases, bank, sd, 5.0, 6.0, stage2=sp)
         assert one.tobytes() == eager[i].tobytes(), i
-        assert np.array_equal(eager[i][["tmpl", "sample"]], full[i][["tmpl", "sample"]]), i
-        np.testing.assert_allclose(eager[i]["snr"], full[i]["snr"], rtol=1e-4)
-    log("sparse batch ok", [len(x) for x in eager])
+        key_f = {(int(t), int(n)): k for k, (t, n) in enumerate(zip(full[i]["tmpl"], full[i]["sample"]))}
+        idx = np.array([key_f.get((int(t), int(n)), -1) for t, n in zip(eager[i]["tmpl"], eager[i]["sample"])],
+                       dtype=np.int64)
+        # sparse triggers are full triggers, except within 1e-4 of the threshold (FFT vs direct sums)
+        assert (eager[i]["snr"][idx < 0] < 6.0 * (1 + 1e-4)).all(), i
+        np.testing.assert_allclose(eager[i]["snr"][idx >= 0], full[i]["snr"][idx[idx >= 0]], rtol=1e-4)
+        missed.append(len(full[i]) - len(eager[i]))
+    log("sparse batch ok", [len(x) for x in eager], "full-stage extras", missed)
 
 
 def test_batch_capacity(batch):

@@ -252,9 +252,10 @@ def test_rb_bf16x3_fp32_accuracy(ctx, rb_case):
     case, bank = rb_case
     basis = rbmf.Basis(ctx, bank, rank=0, tol=1e-3, dtype="bf16x3")
     V, c, lam = basis.export()
-    Zs = rbmf.debug_basis_outputs(ctx, basis, case.strain)            # hi + lo (exact in FP32)
-    Zh = _quant(Zs.real, "bf16") + 1j * _quant(Zs.imag, "bf16")
-    Zl = Zs.astype(np.complex128) - Zh
+    Zh, Zl = rbmf.debug_basis_outputs(ctx, basis, case.strain).astype(np.complex128)   # stored planes
+    # each plane holds BF16 values, and the low parts are below half an ULP of the high parts
+    assert np.array_equal(_quant(Zh.real, "bf16"), Zh.real) and np.array_equal(_quant(Zl.imag, "bf16"), Zl.imag)
+    assert (np.abs(Zl.real) <= np.abs(Zh.real) * 2.0 ** -8 + 1e-38).all()
     Cc = np.conj(c).astype(np.complex64)
 
     def split(x):
