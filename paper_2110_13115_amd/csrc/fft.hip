@@ -130,12 +130,21 @@ __device__ __forceinline__ void powers(V* w, Base&& base) {
 }
 
 // Stage twiddles: input r of a butterfly with k = j mod Ns gets
-// e^{S 2 pi i r k / (Ns R)} = pyr[Ns R + r k].
+// e^{S 2 pi i r k / (Ns R)} = pyr[Ns R + r k].  The table entries for
+// r = 1, 2, 4, 8 (the bases of `powers`) are gathered first (stage_tw_load),
+// ahead of the LDS traffic and barriers, and applied later (stage_tw_apply).
+template <int R> struct NBase { static constexpr int value = R > 8 ? 4 : (R > 4 ? 3 : (R > 2 ? 2 : 1)); };
 template <int R, int Ns, int S, class V>
-__device__ __forceinline__ void apply_stage_tw(V* v, int k, const V* __restrict__ pyr) {
+__device__ __forceinline__ void stage_tw_load(V (&b)[NBase<R>::value], int k, const V* __restrict__ pyr) {
+  if (Ns == 1) return;
+#pragma unroll
+  for (int q = 0; q < NBase<R>::value; ++q) b[q] = signed_tw<S>(pyr[Ns * R + (1 << q) * k]);
+}
+template <int R, int Ns, class V>
+__device__ __forceinline__ void stage_tw_apply(V* v, const V (&b)[NBase<R>::value]) {
   if (Ns == 1) return;
   V w[R];
-  powers<R>(w, [&](int p) { return signed_tw<S>(pyr[Ns * R + p * k]); });
+  powers<R>(w, [&](int p) { return b[p == 1 ? 0 : (p == 2 ? 1 : (p == 4 ? 2 : 3))]; });
 #pragma unroll
   for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
 }
@@ -176,12 +185,14 @@ __device__ __forceinline__ void lds_stage(V* lds, const V* __restrict__ pyr, int
   constexpr int NB = Lay::NF * L / R;
   constexpr int PER = (NB + NT - 1) / NT;
   V v[PER][R];
+  V tb[PER][NBase<R>::value];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int b = tid + i * NT;
     if (NB % NT == 0 || b < NB) {   // (the test folds away when NT divides NB)
       int f, j;
       Lay::template split<R>(b, f, j);
+      stage_tw_load<R, Ns, S>(tb[i], j % Ns, pyr);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = lds[Lay::addr(f, j + r * (L / R))];
     }
@@ -194,7 +205,7 @@ __device__ __forceinline__ void lds_stage(V* lds, const V* __restrict__ pyr, int
       int f, j;
       Lay::template split<R>(b, f, j);
       const int k = j % Ns;
-      apply_stage_tw<R, Ns, S>(v[i], k, pyr);
+      stage_tw_apply<R, Ns>(v[i], tb[i]);
       Dft<R, S>::run(v[i]);
       const int idxD = (j / Ns) * Ns * R + k;
 #pragma unroll
@@ -213,6 +224,16 @@ __device__ __forceinline__ void final_stage(const V* lds, const V* __restrict__ 
   constexpr int Ns = L / R;
   constexpr int NB = Lay::NF * L / R;
   constexpr int PER = (NB + NT - 1) / NT;
+  V tb[PER][NBase<R>::value];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int b = tid + i * NT;
+    if (NB % NT == 0 || b < NB) {
+      int f, j;
+      Lay::template split<R>(b, f, j);
+      stage_tw_load<R, Ns, S>(tb[i], j, pyr);
+    }
+  }
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int b = tid + i * NT;
@@ -222,7 +243,7 @@ __device__ __forceinline__ void final_stage(const V* lds, const V* __restrict__ 
       V v[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) v[r] = lds[Lay::addr(f, j + r * (L / R))];
-      apply_stage_tw<R, Ns, S>(v, j, pyr);
+      stage_tw_apply<R, Ns>(v, tb[i]);
       Dft<R, S>::run(v);
 #pragma unroll
       for (int m = 0; m < R; ++m) store(f, j + m * Ns, v[m], m);
@@ -328,21 +349,40 @@ __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
     constexpr int Ns = L / RL;
     constexpr int NB = Lay::NF * L / RL;
     constexpr int PER = (NB + NT - 1) / NT;
-    auto twe = [&](int64_t e) { return signed_tw<S>(cmul(thi[e >> s_lo], tlo[e & mask])); };
+    // table gathers of PC butterflies are issued together, then the butterflies run
+    constexpr int PC = PER < 4 ? PER : 4;
+    static_assert(PER % PC == 0, "butterflies per thread");
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int b = tid + i * NT;
+    for (int i0 = 0; i0 < PER; i0 += PC) {
+      V tb[PC][NBase<RL>::value], bh[PC], bl[PC], sh[PC], sl[PC];
+#pragma unroll
+      for (int u = 0; u < PC; ++u) {
+        const int b = tid + (i0 + u) * NT;
+        if (NB % NT == 0 || b < NB) {
+          int c, j;
+          Lay::template split<RL>(b, c, j);
+          stage_tw_load<RL, Ns, S>(tb[u], j, pyr);
+          const int64_t e1 = (int64_t)(f1_0 + c) * j, e2 = (int64_t)(f1_0 + c) * Ns;
+          bh[u] = thi[e1 >> s_lo];
+          bl[u] = tlo[e1 & mask];
+          sh[u] = thi[e2 >> s_lo];
+          sl[u] = tlo[e2 & mask];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PC; ++u) {
+      const int b = tid + (i0 + u) * NT;
       if (NB % NT == 0 || b < NB) {   // (the test folds away when NT divides NB)
         int c, j;
         Lay::template split<RL>(b, c, j);
         V v[RL];
 #pragma unroll
         for (int r = 0; r < RL; ++r) v[r] = lds[Lay::addr(c, j + r * Ns)];
-        apply_stage_tw<RL, Ns, S>(v, j, pyr);
+        stage_tw_apply<RL, Ns>(v, tb[u]);
         Dft<RL, S>::run(v);
         const int f1 = f1_0 + c;
-        const V base = twe((int64_t)f1 * j);
-        const V step = twe((int64_t)f1 * Ns);
+        const V base = signed_tw<S>(cmul(bh[u], bl[u]));
+        const V step = signed_tw<S>(cmul(sh[u], sl[u]));
         V sp[RL];
         powers<RL>(sp, [&](int p) {
           V s = step;
@@ -352,6 +392,7 @@ __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
 #pragma unroll
         for (int m = 0; m < RL; ++m)
           outv[(int64_t)(j + m * Ns) * N1 + f1] = cmul(v[m], cmul(base, sp[m]));
+      }
       }
     }
   }
