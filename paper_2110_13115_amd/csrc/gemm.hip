@@ -30,13 +30,13 @@ constexpr int TILE_T = WAVES * WT_ROWB * 16;   // templates per workgroup (128)
 constexpr int TILE_N = WT_COLB * 32;           // samples per workgroup (64)
 constexpr size_t kLdsMax = 160 * 1024;         // gfx950 LDS per workgroup
 
-template <int CB>
-__device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[WT_ROWB][CB], int rb0,
+template <int RB, int CB>
+__device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[RB][CB], int rb0,
                                          int64_t q0) {
   const int lane = __lane_id();
   const int l1 = __builtin_ctz((unsigned)a.N1);            // N1 is a power of two
 #pragma unroll
-  for (int rb = 0; rb < WT_ROWB; ++rb) {
+  for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
       const int q = (int)q0 + cb * 32 + (lane & 31);        // q < N < 2^31
@@ -106,22 +106,23 @@ __device__ __forceinline__ bool xcd_tile(int ntt, int64_t nwg, int& tt, int64_t&
   return true;
 }
 
-// CB: 32-sample MFMA column blocks per wave (tile of 32 templates x 32 CB samples).
+// RB x CB: 16-template row blocks x 32-sample column blocks per wave.
 // Operands of G k-steps are loaded into one of two register buffers while the
 // MFMAs of the other run (the steady state has no branch, so the loads of the
 // next group stay in flight); the last K mod 2G steps run one at a time.
-template <int CB>
+template <int RB, int CB>
 __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
+  constexpr int TT = WAVES * RB * 16;   // templates per workgroup
   constexpr int TN = CB * 32;
   constexpr int G = 4;
-  const int ntt = a.Tp / TILE_T;
+  const int ntt = a.Tp / TT;
   const int64_t nwg = (int64_t)ntt * (a.N / TN);
   int tt;
   int64_t st;
   if (!xcd_tile(ntt, nwg, tt, st)) return;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int rb0 = tt * (TILE_T / 16) + wave * WT_ROWB;     // first 16-template row block
+  const int rb0 = tt * (TT / 16) + wave * RB;     // first 16-template row block
   if (rb0 * 16 >= a.T) return;                             // all of this wave's rows are padding
   const int64_t q0 = st * TN;
   const int K = a.K;
@@ -130,32 +131,32 @@ __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
   const float* __restrict__ ap = static_cast<const float*>(a.cpk) + (int64_t)rb0 * astr + lane;
   const float* __restrict__ bp = static_cast<const float*>(a.z) + (int64_t)(lane >> 5) * N + q0 + (lane & 31);
 
-  f32x16 acc[WT_ROWB][CB];
+  f32x16 acc[RB][CB];
 #pragma unroll
-  for (int rb = 0; rb < WT_ROWB; ++rb)
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = (f32x16){};
 
   // A: one pointer per row block, k-steps at immediate offsets; B: one pointer
   // per k-step of a group (rows 2k are 2N floats apart); all advance by a group.
-  const float* pa[WT_ROWB];
+  const float* pa[RB];
 #pragma unroll
-  for (int rb = 0; rb < WT_ROWB; ++rb) pa[rb] = ap + rb * astr;
+  for (int rb = 0; rb < RB; ++rb) pa[rb] = ap + rb * astr;
   const float* pb[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) pb[g] = bp + (int64_t)(2 * g) * N;
   const int64_t bstep = (int64_t)(2 * G) * N;
-  float fa[2][G][WT_ROWB], fb[2][G][CB];
+  float fa[2][G][RB], fb[2][G][CB];
   auto load = [&](int s) {   // loads the group at the pointers, then advances them
 #pragma unroll
     for (int g = 0; g < G; ++g) {
 #pragma unroll
-      for (int rb = 0; rb < WT_ROWB; ++rb) fa[s][g][rb] = pa[rb][g * 64];
+      for (int rb = 0; rb < RB; ++rb) fa[s][g][rb] = pa[rb][g * 64];
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) fb[s][g][cb] = pb[g][cb * 32];
     }
 #pragma unroll
-    for (int rb = 0; rb < WT_ROWB; ++rb) pa[rb] += G * 64;
+    for (int rb = 0; rb < RB; ++rb) pa[rb] += G * 64;
 #pragma unroll
     for (int g = 0; g < G; ++g) pb[g] += bstep;
   };
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-      for (int rb = 0; rb < WT_ROWB; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[s][g][rb], fb[s][g][cb], acc[rb][cb], 0, 0, 0);
@@ -184,18 +185,18 @@ __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
     }
   }
   for (int k = Kmain; k < K; ++k) {
-    float av[WT_ROWB], bv[CB];
+    float av[RB], bv[CB];
 #pragma unroll
-    for (int rb = 0; rb < WT_ROWB; ++rb) av[rb] = ap[rb * astr + (int64_t)k * 64];
+    for (int rb = 0; rb < RB; ++rb) av[rb] = ap[rb * astr + (int64_t)k * 64];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) bv[cb] = bp[(int64_t)(2 * k) * N + cb * 32];
 #pragma unroll
-    for (int rb = 0; rb < WT_ROWB; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
   }
-  epilogue<CB>(a, acc, rb0, q0);
+  epilogue<RB, CB>(a, acc, rb0, q0);
 }
 
 // 16-bit operands: one instruction reduces over 16 realified entries = 8
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(256) void k_recon_16(GemmArgs a) {
       for (int cb = 0; cb < WT_COLB; ++cb)
         acc[rb][cb] = kstep<DT>(av[0][rb], av[NP - 1][rb], bv[0][cb], bv[NP - 1][cb], acc[rb][cb]);
   }
-  epilogue<WT_COLB>(a, acc, rb0, q0);
+  epilogue<WT_ROWB, WT_COLB>(a, acc, rb0, q0);
 }
 
 // 16-bit operands, Z tile staged in LDS.  One workgroup owns 64 samples and
@@ -369,7 +370,7 @@ __global__ __launch_bounds__(256) void k_recon_16_lds(GemmArgs a) {
         for (int rb = 0; rb < WT_ROWB; ++rb) av[p][rb] = ap[p * cplane + ((int64_t)rb * KB + kb) * 64];
       step(av, kb);
     }
-    epilogue<WT_COLB>(a, acc, rb0, q0);
+    epilogue<WT_ROWB, WT_COLB>(a, acc, rb0, q0);
   }
 }
 
@@ -436,18 +437,21 @@ __global__ void k_pack_16(const float2* C, int T, int Tp, int K, int Kp, int dty
 
 }  // namespace
 
-int recon_variants(int dtype) { return 2; }
+int recon_variants(int dtype) { return dtype == 0 ? 3 : 2; }
 
 hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
   if (a.Tp % TILE_T != 0 || a.N % 128 != 0) return hipErrorInvalidValue;
-  if (a.dtype == 0) {   // variant 0: 64-sample tiles, 1: 128-sample tiles
-    const int TN = a.variant == 1 ? 128 : 64;
-    const int64_t nwg = (int64_t)(a.Tp / TILE_T) * (a.N / TN);
+  if (a.dtype == 0) {   // per-wave tiles: variant 0 = 2 x 2, 1 = 2 x 4, 2 = 1 x 4 (row x column blocks)
+    const int rbw = a.variant == 2 ? 1 : 2;
+    const int TN = a.variant == 0 ? 64 : 128;
+    const int64_t nwg = (int64_t)(a.Tp / (WAVES * rbw * 16)) * (a.N / TN);
     const int64_t launch = ((nwg + 7) / 8) * 8;
-    if (a.variant == 1)
-      hipLaunchKernelGGL(k_recon_f32<4>, dim3((unsigned)launch), dim3(256), 0, st, a);
+    if (a.variant == 2)
+      hipLaunchKernelGGL((k_recon_f32<1, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
+    else if (a.variant == 1)
+      hipLaunchKernelGGL((k_recon_f32<2, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
     else
-      hipLaunchKernelGGL(k_recon_f32<2>, dim3((unsigned)launch), dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_recon_f32<2, 2>), dim3((unsigned)launch), dim3(256), 0, st, a);
     return hipGetLastError();
   }
   // 16-bit: variant 0 stages the Z tile in LDS (when it fits), 1 loads fragments directly
