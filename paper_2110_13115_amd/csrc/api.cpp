@@ -14,6 +14,7 @@
 #include <limits>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <random>
 #include <string>
 #include <thread>
@@ -150,6 +151,7 @@ struct rb_ctx_s {
   hipEvent_t ev[8] = {};
   std::vector<hipEvent_t> evs;
   std::map<int64_t, int> fft_n2;   // autotuned four-step split per N (log2 N2)
+  std::string arch;                // device architecture name (tuning cache key prefix)
   // batch search: per-item summaries and outputs, captured graph
   DevBuf bsum, bout;
   hipStream_t gstream = nullptr;
@@ -294,6 +296,75 @@ PassArgs base_args(rb_bank bank, const FftGeom& g, const FftTables& tw) {
   return a;
 }
 
+// Persistent tuning cache.  With RBMF_TUNE_FILE set, tuned choices (FFT split
+// per N, GEMM variant per dtype / K / T / N) are read from and written back to
+// that file, a flat JSON object {"<arch>/<kind>/<key>": <int>, ...}; without
+// it choices live for the process only.  A process-wide table shared by all
+// contexts.
+class TuneCache {
+ public:
+  bool get(const std::string& key, int* v) {
+    std::lock_guard<std::mutex> lk(mu_);
+    load();
+    auto it = map_.find(key);
+    if (it == map_.end()) return false;
+    *v = it->second;
+    return true;
+  }
+  void put(const std::string& key, int v) {
+    std::lock_guard<std::mutex> lk(mu_);
+    load();
+    map_[key] = v;
+    const char* f = std::getenv("RBMF_TUNE_FILE");
+    if (!f || !*f) return;
+    const std::string tmp = std::string(f) + ".tmp";
+    FILE* fp = std::fopen(tmp.c_str(), "w");
+    if (!fp) return;
+    std::fprintf(fp, "{\n");
+    size_t i = 0;
+    for (const auto& kv : map_)
+      std::fprintf(fp, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < map_.size() ? "," : "");
+    std::fprintf(fp, "}\n");
+    const bool ok = std::fclose(fp) == 0;
+    if (ok) (void)std::rename(tmp.c_str(), f);
+  }
+
+ private:
+  void load() {   // once; a missing or malformed file is an empty cache
+    if (loaded_) return;
+    loaded_ = true;
+    const char* f = std::getenv("RBMF_TUNE_FILE");
+    if (!f || !*f) return;
+    FILE* fp = std::fopen(f, "r");
+    if (!fp) return;
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof(buf), fp)) > 0) text.append(buf, n);
+    std::fclose(fp);
+    size_t p = 0;
+    while ((p = text.find('"', p)) != std::string::npos) {
+      const size_t q = text.find('"', p + 1);
+      if (q == std::string::npos) break;
+      const std::string key = text.substr(p + 1, q - p - 1);
+      const size_t c = text.find(':', q);
+      if (c == std::string::npos) break;
+      char* end = nullptr;
+      const long v = std::strtol(text.c_str() + c + 1, &end, 10);
+      if (end != text.c_str() + c + 1) map_[key] = (int)v;
+      p = end ? (size_t)(end - text.c_str()) : q + 1;
+    }
+  }
+  std::mutex mu_;
+  bool loaded_ = false;
+  std::map<std::string, int> map_;
+};
+
+TuneCache& tune_cache() {
+  static TuneCache c;
+  return c;
+}
+
 // ---------------------------------------------------------------- autotuner
 // The four-step split N = N1 N2 of the FFT passes is chosen per N by timing
 // the candidate splits (balanced, and one step either way) on a batch of
@@ -311,10 +382,14 @@ rb_status geom_for(rb_ctx ctx, rb_bank bank, FftGeom* out) {
   int choice = g0.log2N / 2;
   const char* force = std::getenv("RBMF_FFT_SPLIT");
   const char* at = std::getenv("RBMF_AUTOTUNE");
+  const std::string key = ctx->arch + "/fft/N=" + std::to_string(N);
+  int cached = -1;
   if (force) {
     const FftGeom gf = make_geom(N, std::atoi(force));
     RB_CHECK(geom_supported(gf), RB_ERR_ARG, "RBMF_FFT_SPLIT gives an unsupported split");
     choice = std::atoi(force);
+  } else if (tune_cache().get(key, &cached) && geom_supported(make_geom(N, cached))) {
+    choice = cached;
   } else if (!(at && std::strcmp(at, "0") == 0)) {
     std::vector<int> cand;
     for (int c : {g0.log2N / 2, g0.log2N - g0.log2N / 2, g0.log2N / 2 - 1})
@@ -361,6 +436,7 @@ rb_status geom_for(rb_ctx ctx, rb_bank bank, FftGeom* out) {
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
+      tune_cache().put(key, choice);
     }
   }
   ctx->fft_n2[N] = choice;
@@ -572,6 +648,7 @@ extern "C" rb_status rb_ctx_create(int device, void* hip_stream, rb_ctx* out) {
   auto c = new (std::nothrow) rb_ctx_s;
   RB_CHECK(c != nullptr, RB_ERR_OOM, "host allocation failed");
   c->device = device;
+  c->arch = prop.gcnArchName;
   c->stream = static_cast<hipStream_t>(hip_stream);
   for (auto& e : c->ev) {
     if (hipEventCreate(&e) != hipSuccess) {
@@ -1031,9 +1108,13 @@ rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq
     // with infinite thresholds (no trigger is appended), keep the fastest
     const char* force = std::getenv("RBMF_GEMM_VARIANT");
     const char* at = std::getenv("RBMF_AUTOTUNE");
-    int choice = 0;
+    const std::string key = ctx->arch + "/gemm/dt=" + std::to_string(ga.dtype) + "/K=" + std::to_string(ga.K) +
+                            "/T=" + std::to_string(ga.T) + "/N=" + std::to_string(ga.N);
+    int choice = 0, cached = -1;
     if (force) {
       choice = std::max(0, std::min(recon_variants(ga.dtype) - 1, std::atoi(force)));
+    } else if (tune_cache().get(key, &cached) && cached >= 0 && cached < recon_variants(ga.dtype)) {
+      choice = cached;
     } else if (!(at && std::strcmp(at, "0") == 0)) {
       RB_TRY(ctx->thr_inf.ensure((size_t)basis->Tp * 4));
       RB_TRY(fill32(ctx, ctx->thr_inf.p, 0x7f800000u, basis->Tp));
@@ -1066,6 +1147,7 @@ rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
+      tune_cache().put(key, choice);
     }
     basis->gemm_variant = choice;
   }

@@ -279,6 +279,23 @@ def test_rb_bf16x3_fp32_accuracy(ctx, rb_case):
     basis.close()
 
 
+def test_tune_cache_file(ctx, rb_case, tmp_path, monkeypatch):
+    """Tuned choices are written to RBMF_TUNE_FILE as a flat JSON object."""
+    import json
+    case, bank = rb_case
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("RBMF_TUNE_FILE", str(path))
+    basis = rbmf.Basis(ctx, bank, rank=7, dtype="f32")          # a (K, T) pair not tuned before
+    rbmf.rb_filter(ctx, basis, bank, case.strain, 5.0, 6.0)
+    basis.close()
+    table = json.loads(path.read_text())
+    key = f"/gemm/dt=0/K=7/T={case.T}/N={case.N}"
+    hits = [k for k in table if k.endswith(key)]
+    assert len(hits) == 1 and table[hits[0]] in (0, 1, 2)
+    assert all(isinstance(v, int) for v in table.values())
+    log("  tune cache", len(table), "entries")
+
+
 def test_subbank_bases_partition(ctx, rb_case):
     """Bases of three template ranges (sub-banks, Sec. III.B): the final
     triggers equal the oracle's; per-range reconstruction matches the oracle's
