@@ -266,11 +266,11 @@ rb_status fill32(rb_ctx ctx, void* p, uint32_t v, int64_t n) {
 // vectors per FFT batch: keep the [B][N] intermediate near 256 MB so the
 // pass-1 -> pass-2 round trip can stay in the Infinity Cache.
 // Vectors per FFT launch pair: the pass-1 -> pass-2 intermediate ([B][N]
-// complex64) is sized to a share of the 256 MB Infinity Cache (RBMF_WORK_MB,
-// default 128) so that the round trip need not reach HBM.
+// complex64) holds RBMF_WORK_MB megabytes (default 512).  Larger batches mean
+// fewer launch pairs and fewer partly filled last waves of workgroups.
 int64_t work_budget_bytes() {
   const char* e = std::getenv("RBMF_WORK_MB");
-  const int64_t mb = e ? std::atoll(e) : 128;
+  const int64_t mb = e ? std::atoll(e) : 512;
   return std::max<int64_t>(8, std::min<int64_t>(mb, 4096)) << 20;
 }
 

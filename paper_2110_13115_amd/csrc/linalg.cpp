@@ -24,13 +24,20 @@ bool tql_implicit(int n, std::vector<double>& d, std::vector<double>& e, std::ve
   if (n == 1) return true;
   e[n - 1] = 0.0;
   const double eps = std::numeric_limits<double>::epsilon();
+  // Deflation test against the largest |d| + |e| met so far (a norm of the
+  // tridiagonal), not only against the neighbouring diagonal: inside a
+  // cluster of eigenvalues at round-off level (rank-deficient Gram matrices)
+  // both neighbours are themselves round-off and a purely local test never
+  // succeeds.  Perturbations below eps times the norm are backward stable.
+  double tst = 0.0;
   for (int l = 0; l < n; ++l) {
     int iter = 0;
     int m;
+    tst = std::max(tst, std::fabs(d[l]) + std::fabs(e[l]));
     do {
       for (m = l; m < n - 1; ++m) {
         const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-        if (std::fabs(e[m]) <= eps * dd) break;
+        if (std::fabs(e[m]) <= eps * dd || std::fabs(e[m]) <= eps * tst) break;
       }
       if (m != l) {
         if (++iter > 100) return false;
