@@ -146,7 +146,9 @@ __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
 #pragma unroll
   for (int g = 0; g < G; ++g) pb[g] = bp + (int64_t)(2 * g) * N;
   const int64_t bstep = (int64_t)(2 * G) * N;
-  float fa[2][G][RB], fb[2][G][CB];
+  // three register buffers: group i lives in buffer i % 3 and is loaded two
+  // groups before its MFMAs run, so HBM latency hides behind two groups of work
+  float fa[3][G][RB], fb[3][G][CB];
   auto load = [&](int s) {   // loads the group at the pointers, then advances them
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -169,21 +171,31 @@ __global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
         for (int cb = 0; cb < CB; ++cb)
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[s][g][rb], fb[s][g][cb], acc[rb][cb], 0, 0, 0);
   };
-  const int Kmain = (K / (2 * G)) * (2 * G);
-  if (Kmain > 0) {
-    load(0);
-    for (int k0 = 0; k0 < Kmain; k0 += 2 * G) {
-      // the barriers keep each group's loads ahead of the other group's MFMAs
-      load(1);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(0);
-      __builtin_amdgcn_sched_barrier(0);
-      if (k0 + 2 * G < Kmain) load(0);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(1);
-      __builtin_amdgcn_sched_barrier(0);
-    }
+  const int ng = K / G;                 // full groups; the last K mod G k-steps run singly
+  const int Kmain = ng * G;
+  if (ng > 0) load(0);
+  if (ng > 1) load(1);
+  int gi = 0;
+  // the scheduling barriers keep each load batch ahead of the MFMAs that follow it
+  for (; gi + 3 <= ng; gi += 3) {
+    if (gi + 2 < ng) load(2);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(0);
+    __builtin_amdgcn_sched_barrier(0);
+    if (gi + 3 < ng) load(0);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (gi + 4 < ng) load(1);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(2);
+    __builtin_amdgcn_sched_barrier(0);
   }
+  if (gi < ng) {   // at most two groups remain, in buffers 0 and 1
+    mma(0);
+    ++gi;
+  }
+  if (gi < ng) mma(1);
   for (int k = Kmain; k < K; ++k) {
     float av[RB], bv[CB];
 #pragma unroll
