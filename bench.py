@@ -8,15 +8,17 @@ injections at SNR 5..12; the bank is split along tau0 into 10 sub-banks of
 first stage threshold 5.0, final threshold 6.0.
 
 A step is one rb_filter call (strain FFT, correlation + basis IFFTs, MFMA
-reconstruction with the fused first-stage threshold, full matched filter of
-the selected templates, sort and output).  The full per-template matched
-filter (mf_full) of the same segment is timed beside it as the comparator.
-Prints one JSON line.
+reconstruction with the fused first-stage threshold, exact second stage of
+the selected templates at their first-stage crossings, sort and output).  The
+full per-template matched filter (mf_full) of the same segment is timed beside
+it as the comparator, with the full second stage and the 16-bit / split-BF16
+reconstructions as further variants.  Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import re
 import os
 import sys
 import time
@@ -53,6 +55,25 @@ def make_inputs(wl, rbmf, ctx):
 
     strain, inj = gi.make_strain(wl, bank_def, sigma_of, dtype=np.float32)
     return bank_def, bank, psd, strain, inj
+
+
+def gemm_traffic():
+    """HBM bytes per launch of the FP32 reconstruction GEMM, as measured with
+    rocprofv3 FETCH_SIZE / WRITE_SIZE (copy-calibrated) and recorded in
+    profiles/; None when the kernel source has changed since."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    prof = os.path.join(here, "profiles", "recon_gemm_f32_traffic_rb_256s_2000t.md")
+    src = os.path.join(here, "paper_2110_13115_amd", "csrc", "gemm.hip")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch=([0-9.e+]+) launches=\d+ gemm_hip_sha1=([0-9a-f]+)", text)
+    if not m or m.group(2) != sha:
+        return None
+    return float(m.group(1))
 
 
 def time_calls(fn, steps, warmup, torch):
@@ -269,9 +290,11 @@ def main():
     flops = sum(8.0 * b.K * b.T * wl.N for b in bases)
     achieved = flops / (gm * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"], "unit": "TFLOP/s",
-            "frac": achieved / PEAK["f32"], "traffic": None,
+            "frac": achieved / PEAK["f32"], "traffic": gemm_traffic(),
             "kernel": "k_recon_f32 (rho = C Z, realified complex GEMM, FP32 MFMA 32x32x2)",
-            "per_step": f"sum over sub-banks of 8*K_m*T_m*N = {flops:.4g} flop", "avg_ms_per_step": gm}
+            "per_step": f"sum over sub-banks of 8*K_m*T_m*N = {flops:.4g} flop", "avg_ms_per_step": gm,
+            "traffic_unit": "HBM bytes per launch (mean of the sub-bank launches; "
+                            "profiles/recon_gemm_f32_traffic_rb_256s_2000t.md)"}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, bank_def, psd, strain)
