@@ -796,12 +796,13 @@ struct BasisWork {
 };
 
 // Orthonormalise the columns of Y (T x L, complex128, row-major ld = L) in
-// place of Q: twice "scale, Gram, eigen-decompose" (SVQB).  Returns the kept
-// column count in *Lout.
-rb_status svqb(rb_ctx ctx, BasisWork& bw, const double2* Y, int64_t T, int L, double2* Qout, int* Lout) {
+// place of Q: `passes` times "scale, Gram, eigen-decompose" (SVQB).  Returns
+// the kept column count in *Lout.
+rb_status svqb(rb_ctx ctx, BasisWork& bw, const double2* Y, int64_t T, int L, double2* Qout, int* Lout,
+               int passes = 2) {
   const double2* src = Y;
   int Lc = L;
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = 0; pass < passes; ++pass) {
     RB_TRY(bw.M.ensure((size_t)Lc * Lc * 16));
     ZOperand A{src, 0, 1, Lc, 1};
     ZOperand Bo{src, 0, Lc, 1, 0};
@@ -838,8 +839,8 @@ rb_status svqb(rb_ctx ctx, BasisWork& bw, const double2* Y, int64_t T, int L, do
     src = outp;
     Lc = keep;
   }
-  // result of pass 2 is in Y; copy to Qout
-  RB_HIP(hipMemcpyAsync(Qout, bw.Y.p, (size_t)T * Lc * 16, hipMemcpyDeviceToDevice, ctx->stream));
+  // after an even number of passes the result is in Y
+  if (src != Qout) RB_HIP(hipMemcpyAsync(Qout, src, (size_t)T * Lc * 16, hipMemcpyDeviceToDevice, ctx->stream));
   *Lout = Lc;
   return RB_OK;
 }
@@ -915,8 +916,8 @@ extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, 
         ZOperand Bop{bw.B.p, 0, Lc, 1, 0};
         RB_HIP(launch_zgemm(T, Lc, nb, Wop, Bop, bw.Y.as<double2>(), Lc, 0, bw.ws.as<double2>(),
                             (int64_t)(bw.ws.bytes / 16), s));
-        int Ln = 0;
-        RB_TRY(svqb(ctx, bw, bw.Y.as<double2>(), T, Lc, bw.Q.as<double2>(), &Ln));
+        int Ln = 0;   // one SVQB pass between products, two after the last
+        RB_TRY(svqb(ctx, bw, bw.Y.as<double2>(), T, Lc, bw.Q.as<double2>(), &Ln, it + 1 < q ? 1 : 2));
         Lc = Ln;
       }
     }
@@ -937,6 +938,12 @@ extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, 
     }
     int npos = 0;
     while (npos < Lc && theta[npos] > 1e-14 * theta[0]) ++npos;
+    if (std::getenv("RBMF_VERBOSE")) {
+      double cs = 0.0;
+      for (int k = 0; k < npos; ++k) cs += theta[k];
+      std::fprintf(stderr, "[rbmf] basis T=%lld: subspace %d, captured energy %.6f\n", (long long)T, Lc,
+                   cs / trace);
+    }
     if (rank > 0) {
       K = std::min(rank, npos);
       break;
@@ -1291,7 +1298,10 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
     RB_TRY(fill32(ctx, ctx->tmax.p, 0u, 2 * (int64_t)T));
     if (sparse) {
       const SparseArgs sa = sparse_args(ctx, bank, g, tw, opts->thr2, nullptr, nullptr, 0);
-      RB_HIP(launch_sparse_exact(sa, (int)sum1[1], ctx->stream));
+      // enough workgroups per template that the busiest one is not a straggler
+      const int64_t per = sparse_crossings_per_group();
+      const int groups = (int)std::min<int64_t>(64, std::max<int64_t>(1, (sum1[2] + per - 1) / per));
+      RB_HIP(launch_sparse_exact(sa, (int)sum1[1], groups, ctx->stream));
     } else {
       RB_TRY(step_mf(ctx, bank, g, tw, ctx->list1.as<int32_t>(), sum1[1], (float)(opts->thr2 * opts->thr2)));
     }
@@ -1722,7 +1732,8 @@ rb_status enqueue_item(rb_ctx ctx, const rb_batch_item& it, const rb_filter_opts
     const int64_t cap1 = trig_capacity(ctx->trig1);
     RB_HIP(launch_scatter_triggers(ctx->trig1.as<TrigRec>(), cap1, sm, ctx->off1.as<int32_t>(),
                                    ctx->fill1.as<int32_t>(), ctx->recs1.as<TrigRec>(), ctx->stream));
-    RB_HIP(launch_sparse_exact(sparse_args(ctx, bank, g, tw, opts->thr2, nsel, sm, cap1), T, ctx->stream));
+    // counts are on the device here: a fixed split of every template's crossings over 4 workgroups
+    RB_HIP(launch_sparse_exact(sparse_args(ctx, bank, g, tw, opts->thr2, nsel, sm, cap1), T, 4, ctx->stream));
   } else {
     RB_TRY(step_mf(ctx, bank, g, tw, ctx->list1.as<int32_t>(), T, (float)(opts->thr2 * opts->thr2), nsel));
   }

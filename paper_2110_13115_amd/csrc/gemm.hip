@@ -110,11 +110,10 @@ __device__ __forceinline__ bool xcd_tile(int ntt, int64_t nwg, int& tt, int64_t&
 // Operands of G k-steps are loaded into one of two register buffers while the
 // MFMAs of the other run (the steady state has no branch, so the loads of the
 // next group stay in flight); the last K mod 2G steps run one at a time.
-template <int RB, int CB>
-__global__ __launch_bounds__(256) void k_recon_f32(GemmArgs a) {
+template <int RB, int CB, int G>
+__global__ __launch_bounds__(256, 2) void k_recon_f32(GemmArgs a) {   // at least 2 waves per SIMD
   constexpr int TT = WAVES * RB * 16;   // templates per workgroup
-  constexpr int TN = CB * 32;
-  constexpr int G = 4;
+  constexpr int TN = CB * 32;           // G: k-steps per pipeline group
   const int ntt = a.Tp / TT;
   const int64_t nwg = (int64_t)ntt * (a.N / TN);
   int tt;
@@ -449,21 +448,24 @@ __global__ void k_pack_16(const float2* C, int T, int Tp, int K, int Kp, int dty
 
 }  // namespace
 
-int recon_variants(int dtype) { return dtype == 0 ? 3 : 2; }
+int recon_variants(int dtype) { return dtype == 0 ? 4 : 2; }
 
 hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
   if (a.Tp % TILE_T != 0 || a.N % 128 != 0) return hipErrorInvalidValue;
-  if (a.dtype == 0) {   // per-wave tiles: variant 0 = 2 x 2, 1 = 2 x 4, 2 = 1 x 4 (row x column blocks)
+  if (a.dtype == 0) {   // per-wave tiles (row x column blocks, k-steps per pipeline group):
+                        // variant 0 = 2 x 2 / 4, 1 = 2 x 4 / 4, 2 = 1 x 4 / 4, 3 = 2 x 4 / 2
     const int rbw = a.variant == 2 ? 1 : 2;
     const int TN = a.variant == 0 ? 64 : 128;
     const int64_t nwg = (int64_t)(a.Tp / (WAVES * rbw * 16)) * (a.N / TN);
     const int64_t launch = ((nwg + 7) / 8) * 8;
-    if (a.variant == 2)
-      hipLaunchKernelGGL((k_recon_f32<1, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
+    if (a.variant == 3)
+      hipLaunchKernelGGL((k_recon_f32<2, 4, 2>), dim3((unsigned)launch), dim3(256), 0, st, a);
+    else if (a.variant == 2)
+      hipLaunchKernelGGL((k_recon_f32<1, 4, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
     else if (a.variant == 1)
-      hipLaunchKernelGGL((k_recon_f32<2, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_recon_f32<2, 4, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
     else
-      hipLaunchKernelGGL((k_recon_f32<2, 2>), dim3((unsigned)launch), dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_recon_f32<2, 2, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
     return hipGetLastError();
   }
   // 16-bit: variant 0 stages the Z tile in LDS (when it fits), 1 loads fragments directly

@@ -174,7 +174,10 @@ struct SparseArgs {
   int32_t* tmpl_count;
   unsigned long long* tmpl_max;
 };
-hipError_t launch_sparse_exact(const SparseArgs& a, int grid, hipStream_t s);
+// grid: listed templates (upper bound with d_count); groups: workgroups that
+// share one template's crossings (each takes every groups-th group of 8).
+hipError_t launch_sparse_exact(const SparseArgs& a, int grid, int groups, hipStream_t s);
+int sparse_crossings_per_group();
 
 // ---------------------------------------------------------------- FP64 complex GEMM
 // C[m][n] (+)= sum_k opA(A)[m][k] * opB(B)[k][n], complex128 accumulation.

@@ -11,12 +11,31 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <thread>
 
 namespace rbmf {
 
 using cd = std::complex<double>;
 
 namespace {
+
+// Splits [0, n) into contiguous blocks run on up to 16 host threads (serially
+// when the work is small); f(lo, hi) must touch only its own block.
+template <class F>
+void par_blocks(int n, int min_block, F&& f) {
+  static const int hw = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+  const int nt = std::min(hw, n / std::max(1, min_block));
+  if (nt <= 1) {
+    f(0, n);
+    return;
+  }
+  const int step = (n + nt - 1) / nt;
+  std::vector<std::thread> th;
+  th.reserve(nt - 1);
+  for (int t = 1; t < nt; ++t) th.emplace_back([&, t] { f(t * step, std::min(n, (t + 1) * step)); });
+  f(0, std::min(n, step));
+  for (auto& x : th) x.join();
+}
 
 // Implicit QL on a real symmetric tridiagonal (d: diagonal, e[i] = T[i+1][i],
 // e[n-1] unused).  Z (n x n, column-major: Z[i + n*j]) accumulates rotations.
@@ -30,6 +49,8 @@ bool tql_implicit(int n, std::vector<double>& d, std::vector<double>& e, std::ve
   // both neighbours are themselves round-off and a purely local test never
   // succeeds.  Perturbations below eps times the norm are backward stable.
   double tst = 0.0;
+  std::vector<int> rot_i;
+  std::vector<double> rot_s, rot_c;
   for (int l = 0; l < n; ++l) {
     int iter = 0;
     int m;
@@ -47,6 +68,9 @@ bool tql_implicit(int n, std::vector<double>& d, std::vector<double>& e, std::ve
         double s = 1.0, c = 1.0, p = 0.0;
         int i;
         bool deflated = false;
+        rot_i.clear();
+        rot_s.clear();
+        rot_c.clear();
         for (i = m - 1; i >= l; --i) {
           double f = s * e[i];
           const double b = c * e[i];
@@ -65,14 +89,26 @@ bool tql_implicit(int n, std::vector<double>& d, std::vector<double>& e, std::ve
           p = s * r;
           d[i + 1] = g + p;
           g = c * r - b;
-          double* zi = &Z[(size_t)n * i];
-          double* zi1 = &Z[(size_t)n * (i + 1)];
-          for (int k = 0; k < n; ++k) {
-            f = zi1[k];
-            zi1[k] = s * zi[k] + c * f;
-            zi[k] = c * zi[k] - s * f;
-          }
+          rot_i.push_back(i);
+          rot_s.push_back(s);
+          rot_c.push_back(c);
         }
+        // the sweep's plane rotations, in order, applied to every row of Z
+        // (rows are independent, so blocks of rows run in parallel)
+        const int nr = (int)rot_i.size();
+        par_blocks(n, 64 * std::max(1, 4096 / std::max(1, nr)), [&](int k0, int k1) {
+          for (int t = 0; t < nr; ++t) {
+            const int ii = rot_i[t];
+            const double st = rot_s[t], ct = rot_c[t];
+            double* zi = &Z[(size_t)n * ii];
+            double* zi1 = &Z[(size_t)n * (ii + 1)];
+            for (int k = k0; k < k1; ++k) {
+              const double f = zi1[k];
+              zi1[k] = st * zi[k] + ct * f;
+              zi[k] = ct * zi[k] - st * f;
+            }
+          }
+        });
         if (deflated) continue;
         d[l] -= p;
         e[l] = g;
@@ -119,20 +155,24 @@ bool herm_eig_desc(int n, const std::vector<cd>& Ain, std::vector<double>& w, st
     const double vn = std::sqrt(vn2);
     for (int i = 0; i < m; ++i) v[i] /= vn;
     // p = A22 v ; Kv = v^H p ; w = p - Kv v ; A22 -= 2 (v w^H + w v^H)
-    for (int i = 0; i < m; ++i) {
-      cd s(0.0, 0.0);
-      const cd* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
-      for (int j = 0; j < m; ++j) s += row[j] * v[j];
-      p[i] = s;
-    }
+    par_blocks(m, 128, [&](int i0, int i1) {
+      for (int i = i0; i < i1; ++i) {
+        cd s(0.0, 0.0);
+        const cd* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
+        for (int j = 0; j < m; ++j) s += row[j] * v[j];
+        p[i] = s;
+      }
+    });
     cd Kv(0.0, 0.0);
     for (int i = 0; i < m; ++i) Kv += std::conj(v[i]) * p[i];
     const double kr = Kv.real();
     for (int i = 0; i < m; ++i) wv[i] = p[i] - kr * v[i];
-    for (int i = 0; i < m; ++i) {
-      cd* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
-      for (int j = 0; j < m; ++j) row[j] -= 2.0 * (v[i] * std::conj(wv[j]) + wv[i] * std::conj(v[j]));
-    }
+    par_blocks(m, 128, [&](int i0, int i1) {
+      for (int i = i0; i < i1; ++i) {
+        cd* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
+        for (int j = 0; j < m; ++j) row[j] -= 2.0 * (v[i] * std::conj(wv[j]) + wv[i] * std::conj(v[j]));
+      }
+    });
     sub[k] = alpha;
     for (int i = 0; i < m; ++i) {
       A[(size_t)(k + 1 + i) * n + k] = (i == 0) ? alpha : cd(0.0, 0.0);
@@ -164,16 +204,25 @@ bool herm_eig_desc(int n, const std::vector<cd>& Ain, std::vector<double>& w, st
     for (int i = 0; i < n; ++i) V[(size_t)i * n + jj] = delta[i] * Z[(size_t)n * j + i];
   }
   // back-transform: U = H_0 H_1 ... H_{n-3} Y
-  for (int k = (int)refl.size() - 1; k >= 0; --k) {
-    const std::vector<cd>& v = refl[k];
-    const int m = (int)v.size();
-    for (int col = 0; col < n; ++col) {
-      cd s(0.0, 0.0);
-      for (int i = 0; i < m; ++i) s += std::conj(v[i]) * V[(size_t)(k + 1 + i) * n + col];
-      s *= 2.0;
-      for (int i = 0; i < m; ++i) V[(size_t)(k + 1 + i) * n + col] -= v[i] * s;
+  // (blocks of columns in parallel; rows are walked contiguously)
+  par_blocks(n, 64, [&](int c0, int c1) {
+    std::vector<cd> sc(c1 - c0);
+    for (int k = (int)refl.size() - 1; k >= 0; --k) {
+      const std::vector<cd>& v = refl[k];
+      const int m = (int)v.size();
+      std::fill(sc.begin(), sc.end(), cd(0.0, 0.0));
+      for (int i = 0; i < m; ++i) {
+        const cd cv = std::conj(v[i]);
+        const cd* row = &V[(size_t)(k + 1 + i) * n];
+        for (int col = c0; col < c1; ++col) sc[col - c0] += cv * row[col];
+      }
+      for (int i = 0; i < m; ++i) {
+        const cd vi = 2.0 * v[i];
+        cd* row = &V[(size_t)(k + 1 + i) * n];
+        for (int col = c0; col < c1; ++col) row[col] -= vi * sc[col - c0];
+      }
     }
-  }
+  });
   return true;
 }
 

@@ -7,8 +7,10 @@
 // reconstruction error stays below thr2 - thr1, so the final trigger set equals
 // the template method's.
 //
-// One workgroup per selected template streams w_j once per group of up to
-// SP_M crossings.  A thread owns 8 consecutive bins of each 2048-bin tile:
+// Workgroup (x, y) takes template list[x] and its crossing groups y, y + G,
+// y + 2G, ... (G = gridDim.y, groups of up to SP_M crossings), streaming w_j
+// once per group; G > 1 spreads templates with many crossings (near a loud
+// signal) over several workgroups.  A thread owns 8 consecutive bins of each 2048-bin tile:
 // the twiddle of its first bin comes exactly from the two-level table
 // (e = f n mod N), the next seven by multiplication with e^{2 pi i n / N}
 // (error <= 8 ulp).
@@ -33,6 +35,8 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
   if (a.d_count != nullptr && (int)blockIdx.x >= *a.d_count) return;
   if (a.n1_dev != nullptr && *a.n1_dev > a.n1_cap) return;
   const int j = a.list[blockIdx.x];
+  const int cnt = a.counts[j];
+  if ((int)blockIdx.y * SP_M >= cnt) return;   // no group of this template for this workgroup
   const int nlo = 1 << a.s_lo, nhi = (int)(a.N >> a.s_lo);
   // table copies: every load of a thread (clamped in bounds) issued before its LDS stores
   {
@@ -54,12 +58,12 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
   const int64_t Nm = a.N - 1;
   auto tw = [&](int64_t e) { return cmulf(thi[(e & Nm) >> a.s_lo], tlo[e & mask]); };
   const int lo = a.sup_lo[j], hi = a.sup_hi[j];
-  const int off = a.offsets[j], cnt = a.counts[j];
+  const int off = a.offsets[j];
   const float2* __restrict__ wj = a.tmpl + (int64_t)j * a.nbs - a.kb;   // indexed by absolute bin
   const float2* __restrict__ d = a.d - a.kb;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned long long best = 0ull;
-  for (int c0 = 0; c0 < cnt; c0 += SP_M) {
+  for (int c0 = blockIdx.y * SP_M; c0 < cnt; c0 += gridDim.y * SP_M) {
     const int m = min(SP_M, cnt - c0);
     int ns[SP_M];
     float2 step[SP_M], acc[SP_M];
@@ -148,10 +152,13 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
 
 }  // namespace
 
-hipError_t launch_sparse_exact(const SparseArgs& a, int grid, hipStream_t s) {
+hipError_t launch_sparse_exact(const SparseArgs& a, int grid, int groups, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sparse_exact, dim3(grid), dim3(SP_T), 0, s, a);
+  groups = groups < 1 ? 1 : (groups > 64 ? 64 : groups);
+  hipLaunchKernelGGL(k_sparse_exact, dim3(grid, groups), dim3(SP_T), 0, s, a);
   return hipGetLastError();
 }
+
+int sparse_crossings_per_group() { return SP_M; }
 
 }  // namespace rbmf

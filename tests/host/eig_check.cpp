@@ -45,7 +45,10 @@ int main(int argc, char** argv) {
     }
   std::vector<double> w;
   std::vector<cd> V;
-  if (!rbmf::herm_eig_desc(n, A, w, V)) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const bool ok = rbmf::herm_eig_desc(n, A, w, V);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (!ok) {
     std::printf("n=%d: no convergence\n", n);
     return 1;
   }
@@ -65,6 +68,7 @@ int main(int argc, char** argv) {
       std::printf("n=%d: not descending at %d\n", n, i);
       return 1;
     }
-  std::printf("n=%d rank=%d min=1e%g: max eigenvalue error %.2e, leading residual %.2e\n", n, rk, lo, ev, res);
+  std::printf("n=%d rank=%d min=1e%g: max eigenvalue error %.2e, leading residual %.2e (%.2f s)\n", n, rk, lo, ev,
+              res, secs);
   return (ev <= 1e-12 && res <= 1e-12) ? 0 : 1;
 }

@@ -17,7 +17,7 @@ def eig_check(tmp_path_factory):
     if shutil.which("g++") is None:
         pytest.skip("g++ not available")
     exe = str(tmp_path_factory.mktemp("eig") / "eig_check")
-    subprocess.run(["g++", "-O2", "-std=c++17", "-I", SRC, os.path.join(HERE, "host", "eig_check.cpp"),
+    subprocess.run(["g++", "-O2", "-std=c++17", "-pthread", "-I", SRC, os.path.join(HERE, "host", "eig_check.cpp"),
                     os.path.join(SRC, "linalg.cpp"), "-o", exe], check=True)
     return exe
 
