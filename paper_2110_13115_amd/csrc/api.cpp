@@ -951,8 +951,11 @@ extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, 
     double cum = 0.0;
     K = 0;
     while (K < npos && cum < (1.0 - tol) * trace) cum += theta[K++];
-    if (cum >= (1.0 - tol) * trace && (K + over <= Lc || Lc >= T)) break;
-    if (Lc >= T || L >= T) break;   // cannot grow further
+    // enough: the tolerance is met with `over` spare Ritz vectors, or the
+    // subspace already spans every direction above the round-off floor
+    // (the orthonormalisation dropped columns: the bank's numerical rank is Lc)
+    if (cum >= (1.0 - tol) * trace && (K + over <= Lc || Lc >= T || Lc < L)) break;
+    if (Lc >= T || L >= T || Lc < L) break;   // cannot grow further (or nothing left to find)
     L = (int)std::min<int64_t>(T, 2 * (int64_t)L);
   }
   RB_CHECK(K >= 1, RB_ERR_NUMERIC, "basis has rank zero");

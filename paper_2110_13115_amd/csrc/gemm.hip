@@ -265,19 +265,20 @@ __global__ __launch_bounds__(256) void k_recon_16(GemmArgs a) {
   epilogue<WT_ROWB, WT_COLB>(a, acc, rb0, q0);
 }
 
-// 16-bit operands, Z tile staged in LDS.  One workgroup owns 64 samples and
+// 16-bit operands, Z tile staged in LDS.  One workgroup owns 32 CB samples and
 // loops over every 128-template tile of the (sub-)bank: the planar Z tile
 // (2Kp rows x 64 samples) is read from HBM once with 16-byte loads and stored
 // transposed (sample-major, reduction index contiguous, rows padded by 16 B)
 // so each lane's B fragment is a single 16-byte LDS read; the packed C tiles
 // come from L2.
-template <int DT>
-__global__ __launch_bounds__(256) void k_recon_16_lds(GemmArgs a) {
+template <int DT, int CB>
+__global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
+  constexpr int TNS = CB * 32;          // samples per workgroup
   constexpr int NP = DT == 3 ? 2 : 1;   // operand planes (hi, lo)
   extern __shared__ uint16_t zs[];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int64_t q0 = (int64_t)blockIdx.x * TILE_N;
+  const int64_t q0 = (int64_t)blockIdx.x * TNS;
   const int Kp = a.Kp, KB = Kp / 8, R2 = 2 * Kp;
   const int RS = NP * R2 + 8;       // LDS row stride (u16) of one sample: planes side by side
   const int64_t N = a.N;
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(256) void k_recon_16_lds(GemmArgs a) {
     // sample * RS + p * R2 + 2k; CH items per thread are in flight at once.
     uint32_t* zs32 = reinterpret_cast<uint32_t*>(zs);
     const int RS2 = RS / 2;
-    const int items = NP * Kp * (TILE_N / 8);
+    const int items = NP * Kp * (TNS / 8);
     constexpr int CH = 4;
     for (int base = threadIdx.x; base < items; base += 256 * CH) {
       u16x8 vr[CH], vi[CH];
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(256) void k_recon_16_lds(GemmArgs a) {
       for (int c = 0; c < CH; ++c) {
         const int idx = base + c * 256;
         if (idx < items) {
-          const int pk = idx / (TILE_N / 8), c8 = (idx % (TILE_N / 8)) * 8;   // pk = p * Kp + k
+          const int pk = idx / (TNS / 8), c8 = (idx % (TNS / 8)) * 8;   // pk = p * Kp + k
           const int p = pk / Kp, k = pk % Kp;
           const uint16_t* src = z + p * zplane + (int64_t)(2 * k) * N + q0 + c8;
           vr[c] = *reinterpret_cast<const u16x8*>(src);
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(256) void k_recon_16_lds(GemmArgs a) {
       for (int c = 0; c < CH; ++c) {
         const int idx = base + c * 256;
         if (idx < items) {
-          const int pk = idx / (TILE_N / 8), c8 = (idx % (TILE_N / 8)) * 8;
+          const int pk = idx / (TNS / 8), c8 = (idx % (TNS / 8)) * 8;
 #pragma unroll
           for (int e = 0; e < 8; ++e)
             zs32[(c8 + e) * RS2 + pk] = (uint32_t)vr[c][e] | ((uint32_t)vi[c][e] << 16);
@@ -329,11 +330,11 @@ __global__ __launch_bounds__(256) void k_recon_16_lds(GemmArgs a) {
     const int rb0 = tt * (TILE_T / 16) + wave * WT_ROWB;
     if (rb0 * 16 >= a.T) break;                            // the rest of the rows are padding
     const u16x8* __restrict__ ap = cpk + (int64_t)rb0 * KB * 64 + lane;
-    f32x16 acc[WT_ROWB][WT_COLB];
+    f32x16 acc[WT_ROWB][CB];
 #pragma unroll
     for (int rb = 0; rb < WT_ROWB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < WT_COLB; ++cb) acc[rb][cb] = (f32x16){};
+      for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = (f32x16){};
     u16x8 fa[2][G][NP][WT_ROWB];
     auto load = [&](int s, int kb0) {
 #pragma unroll
@@ -345,16 +346,16 @@ __global__ __launch_bounds__(256) void k_recon_16_lds(GemmArgs a) {
             fa[s][g][p][rb] = ap[p * cplane + ((int64_t)rb * KB + kb0 + g) * 64];
     };
     auto step = [&](const u16x8 (&av)[NP][WT_ROWB], int kb) {
-      u16x8 bv[NP][WT_COLB];
+      u16x8 bv[NP][CB];
 #pragma unroll
       for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int cb = 0; cb < WT_COLB; ++cb)
+        for (int cb = 0; cb < CB; ++cb)
           bv[p][cb] = *reinterpret_cast<const u16x8*>(zl + cb * 32 * RS + p * R2 + 16 * kb);
 #pragma unroll
       for (int rb = 0; rb < WT_ROWB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < WT_COLB; ++cb)
+        for (int cb = 0; cb < CB; ++cb)
           acc[rb][cb] = kstep<DT>(av[0][rb], av[NP - 1][rb], bv[0][cb], bv[NP - 1][cb], acc[rb][cb]);
     };
     if (Kmain > 0) {
@@ -381,7 +382,7 @@ __global__ __launch_bounds__(256) void k_recon_16_lds(GemmArgs a) {
         for (int rb = 0; rb < WT_ROWB; ++rb) av[p][rb] = ap[p * cplane + ((int64_t)rb * KB + kb) * 64];
       step(av, kb);
     }
-    epilogue<WT_ROWB, WT_COLB>(a, acc, rb0, q0);
+    epilogue<WT_ROWB, CB>(a, acc, rb0, q0);
   }
 }
 
@@ -448,7 +449,7 @@ __global__ void k_pack_16(const float2* C, int T, int Tp, int K, int Kp, int dty
 
 }  // namespace
 
-int recon_variants(int dtype) { return dtype == 0 ? 4 : 2; }
+int recon_variants(int dtype) { return dtype == 0 ? 4 : 3; }
 
 hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
   if (a.Tp % TILE_T != 0 || a.N % 128 != 0) return hipErrorInvalidValue;
@@ -468,28 +469,39 @@ hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
       hipLaunchKernelGGL((k_recon_f32<2, 2, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
     return hipGetLastError();
   }
-  // 16-bit: variant 0 stages the Z tile in LDS (when it fits), 1 loads fragments directly
+  // 16-bit: variant 0 / 2 stage a 64 / 128-sample Z tile in LDS (when it fits),
+  // variant 1 loads fragments directly
   const int np = a.dtype == 3 ? 2 : 1;
-  const size_t lds = (size_t)TILE_N * (np * 2 * a.Kp + 8) * 2;
-  if (a.variant == 0 && lds <= kLdsMax) {
+  const int tns = (a.variant == 2 && a.dtype != 3) ? 128 : 64;   // (the split-BF16 operands do not fit 128)
+  const size_t lds = (size_t)tns * (np * 2 * a.Kp + 8) * 2;
+  if (a.variant != 1 && lds <= kLdsMax) {
     static bool attr_set = false;
     if (!attr_set) {
-      const void* fns[] = {reinterpret_cast<const void*>(&k_recon_16_lds<1>),
-                           reinterpret_cast<const void*>(&k_recon_16_lds<2>),
-                           reinterpret_cast<const void*>(&k_recon_16_lds<3>)};
+      const void* fns[] = {reinterpret_cast<const void*>(&k_recon_16_lds<1, 2>),
+                           reinterpret_cast<const void*>(&k_recon_16_lds<2, 2>),
+                           reinterpret_cast<const void*>(&k_recon_16_lds<3, 2>),
+                           reinterpret_cast<const void*>(&k_recon_16_lds<1, 4>),
+                           reinterpret_cast<const void*>(&k_recon_16_lds<2, 4>)};
       for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
         if (e != hipSuccess) return e;
       }
       attr_set = true;
     }
-    const unsigned grid = (unsigned)(a.N / TILE_N);
-    if (a.dtype == 1)
-      hipLaunchKernelGGL(k_recon_16_lds<1>, dim3(grid), dim3(256), lds, st, a);
-    else if (a.dtype == 2)
-      hipLaunchKernelGGL(k_recon_16_lds<2>, dim3(grid), dim3(256), lds, st, a);
-    else
-      hipLaunchKernelGGL(k_recon_16_lds<3>, dim3(grid), dim3(256), lds, st, a);
+    const unsigned grid = (unsigned)(a.N / tns);
+    if (tns == 128) {
+      if (a.dtype == 1)
+        hipLaunchKernelGGL((k_recon_16_lds<1, 4>), dim3(grid), dim3(256), lds, st, a);
+      else
+        hipLaunchKernelGGL((k_recon_16_lds<2, 4>), dim3(grid), dim3(256), lds, st, a);
+    } else {
+      if (a.dtype == 1)
+        hipLaunchKernelGGL((k_recon_16_lds<1, 2>), dim3(grid), dim3(256), lds, st, a);
+      else if (a.dtype == 2)
+        hipLaunchKernelGGL((k_recon_16_lds<2, 2>), dim3(grid), dim3(256), lds, st, a);
+      else
+        hipLaunchKernelGGL((k_recon_16_lds<3, 2>), dim3(grid), dim3(256), lds, st, a);
+    }
     return hipGetLastError();
   }
   const int64_t nwg = (int64_t)(a.Tp / TILE_T) * (a.N / TILE_N);

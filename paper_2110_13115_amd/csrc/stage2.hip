@@ -28,6 +28,104 @@ __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// One group of M (a power of two, >= m) crossings of template j: slots m..M-1
+// repeat the last crossing and are discarded, so the sums are straight-line
+// code across the M crossings.
+template <int M>
+__device__ __forceinline__ void sparse_group(const SparseArgs& a, const float2* tlo, const float2* thi,
+                                             float2 (*red)[SP_T / 64], int j, int c0, int m, int lo, int hi,
+                                             const float2* __restrict__ d, const float2* __restrict__ wj,
+                                             unsigned long long& best) {
+  const int mask = (1 << a.s_lo) - 1;
+  const int N = (int)a.N;                       // N <= 2^30
+  auto tw = [&](int e) { return cmulf(thi[e >> a.s_lo], tlo[e & mask]); };   // e in [0, N)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int off = a.offsets[j];
+  int ns[M], e[M], inc[M];
+  float2 step[M], acc[M];
+  const int f00 = lo + threadIdx.x * SP_R;
+#pragma unroll
+  for (int i = 0; i < M; ++i) ns[i] = a.recs[off + c0 + min(i, m - 1)].sample;
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    step[i] = tw(ns[i]);
+    acc[i] = make_float2(0.f, 0.f);
+    e[i] = (int)(((int64_t)f00 * ns[i]) % N);                   // exponent of this thread's first bin
+    inc[i] = (int)(((int64_t)(SP_T * SP_R) * ns[i]) % N);       // advance per tile
+  }
+  // Bins past hi are read at hi (in bounds) and masked to zero; the next
+  // tile's operands are loaded while this tile's sums run.
+  float2 dn[SP_R], wn[SP_R];
+  auto fetch = [&](int f0) {
+#pragma unroll
+    for (int r = 0; r < SP_R; ++r) {
+      const int f = min(f0 + r, hi);
+      dn[r] = d[f];
+      wn[r] = wj[f];
+    }
+  };
+  fetch(f00);
+  for (int f0 = f00; f0 <= hi; f0 += SP_T * SP_R) {
+    float2 x[SP_R];
+#pragma unroll
+    for (int r = 0; r < SP_R; ++r) {
+      const float2 dv = dn[r], wv = wn[r];
+      const float mk = (f0 + r <= hi) ? 1.f : 0.f;
+      x[r] = make_float2(mk * (dv.x * wv.x + dv.y * wv.y), mk * (dv.y * wv.x - dv.x * wv.y));   // d conj(w)
+    }
+    fetch(f0 + SP_T * SP_R);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      float2 w = tw(e[i]);
+#pragma unroll
+      for (int r = 0; r < SP_R; ++r) {
+        acc[i].x += x[r].x * w.x - x[r].y * w.y;
+        acc[i].y += x[r].x * w.y + x[r].y * w.x;
+        w = cmulf(w, step[i]);
+      }
+      e[i] += inc[i];
+      if (e[i] >= N) e[i] -= N;
+    }
+  }
+  // workgroup reduction of the accumulators
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    float re = acc[i].x, im = acc[i].y;
+    for (int o = 32; o > 0; o >>= 1) {
+      re += __shfl_xor(re, o);
+      im += __shfl_xor(im, o);
+    }
+    if (lane == 0) red[i][wave] = make_float2(re, im);
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < m) {
+    const int i = threadIdx.x;
+    float re = 0.f, im = 0.f;
+    for (int w = 0; w < SP_T / 64; ++w) {
+      re += red[i][w].x;
+      im += red[i][w].y;
+    }
+    const float p = re * re + im * im;
+    const int n = a.recs[off + c0 + i].sample;
+    const unsigned long long key =
+        ((unsigned long long)__float_as_uint(p) << 32) | (unsigned long long)(0xffffffffu - (uint32_t)n);
+    best = key > best ? key : best;
+    if (p >= a.thr2) {
+      const unsigned long long idx = atomicAdd(a.out_count, 1ull);
+      atomicAdd(&a.tmpl_count[j], 1);
+      if ((int64_t)idx < a.out_cap) {
+        TrigRec t;
+        t.tmpl = j;
+        t.sample = n;
+        t.re = re;
+        t.im = im;
+        a.out[idx] = t;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
   __shared__ float2 tlo[2048];
   __shared__ float2 thi[1024];
@@ -54,98 +152,20 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
       if ((int)threadIdx.x + i * SP_T < nhi) thi[threadIdx.x + i * SP_T] = vh[i];
   }
   __syncthreads();
-  const int mask = nlo - 1;
-  const int64_t Nm = a.N - 1;
-  auto tw = [&](int64_t e) { return cmulf(thi[(e & Nm) >> a.s_lo], tlo[e & mask]); };
   const int lo = a.sup_lo[j], hi = a.sup_hi[j];
-  const int off = a.offsets[j];
   const float2* __restrict__ wj = a.tmpl + (int64_t)j * a.nbs - a.kb;   // indexed by absolute bin
   const float2* __restrict__ d = a.d - a.kb;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned long long best = 0ull;
   for (int c0 = blockIdx.y * SP_M; c0 < cnt; c0 += gridDim.y * SP_M) {
-    const int m = min(SP_M, cnt - c0);
-    int ns[SP_M];
-    float2 step[SP_M], acc[SP_M];
-#pragma unroll
-    for (int i = 0; i < SP_M; ++i)   // in-bounds index for every slot; slots >= m are unused
-      ns[i] = a.recs[off + c0 + min(i, m - 1)].sample;
-#pragma unroll
-    for (int i = 0; i < SP_M; ++i) {
-      step[i] = tw(ns[i]);
-      acc[i] = make_float2(0.f, 0.f);
-    }
-    // Bins past hi are read at hi (in bounds) and masked to zero; the next
-    // tile's operands are loaded while this tile's sums run.
-    float2 dn[SP_R], wn[SP_R];
-    auto fetch = [&](int f0) {
-#pragma unroll
-      for (int r = 0; r < SP_R; ++r) {
-        const int f = min(f0 + r, hi);
-        dn[r] = d[f];
-        wn[r] = wj[f];
-      }
-    };
-    fetch(lo + threadIdx.x * SP_R);
-    for (int f0 = lo + threadIdx.x * SP_R; f0 <= hi; f0 += SP_T * SP_R) {
-      float2 x[SP_R];
-#pragma unroll
-      for (int r = 0; r < SP_R; ++r) {
-        const float2 dv = dn[r], wv = wn[r];
-        const float mk = (f0 + r <= hi) ? 1.f : 0.f;
-        x[r] = make_float2(mk * (dv.x * wv.x + dv.y * wv.y), mk * (dv.y * wv.x - dv.x * wv.y));   // d conj(w)
-      }
-      fetch(f0 + SP_T * SP_R);
-#pragma unroll
-      for (int i = 0; i < SP_M; ++i) {
-        if (i < m) {
-          float2 w = tw((int64_t)f0 * ns[i]);
-#pragma unroll
-          for (int r = 0; r < SP_R; ++r) {
-            acc[i].x += x[r].x * w.x - x[r].y * w.y;
-            acc[i].y += x[r].x * w.y + x[r].y * w.x;
-            w = cmulf(w, step[i]);
-          }
-        }
-      }
-    }
-    // workgroup reduction of the m accumulators
-#pragma unroll
-    for (int i = 0; i < SP_M; ++i) {
-      float re = acc[i].x, im = acc[i].y;
-      for (int o = 32; o > 0; o >>= 1) {
-        re += __shfl_xor(re, o);
-        im += __shfl_xor(im, o);
-      }
-      if (lane == 0) red[i][wave] = make_float2(re, im);
-    }
-    __syncthreads();
-    if (threadIdx.x < SP_M && (int)threadIdx.x < m) {
-      const int i = threadIdx.x;
-      float re = 0.f, im = 0.f;
-      for (int w = 0; w < SP_T / 64; ++w) {
-        re += red[i][w].x;
-        im += red[i][w].y;
-      }
-      const float p = re * re + im * im;
-      const int n = ns[i];
-      const unsigned long long key =
-          ((unsigned long long)__float_as_uint(p) << 32) | (unsigned long long)(0xffffffffu - (uint32_t)n);
-      best = key > best ? key : best;
-      if (p >= a.thr2) {
-        const unsigned long long idx = atomicAdd(a.out_count, 1ull);
-        atomicAdd(&a.tmpl_count[j], 1);
-        if ((int64_t)idx < a.out_cap) {
-          TrigRec t;
-          t.tmpl = j;
-          t.sample = n;
-          t.re = re;
-          t.im = im;
-          a.out[idx] = t;
-        }
-      }
-    }
-    __syncthreads();
+    const int m = min(SP_M, cnt - c0);            // uniform over the workgroup
+    if (m <= 1)
+      sparse_group<1>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best);
+    else if (m <= 2)
+      sparse_group<2>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best);
+    else if (m <= 4)
+      sparse_group<4>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best);
+    else
+      sparse_group<8>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best);
   }
   if (threadIdx.x < SP_M && best != 0ull) atomicMax(&a.tmpl_max[j], best);
 }
