@@ -263,6 +263,18 @@ def main():
                                    "final_triggers_equal_mf": bool(ok_f2),
                                    "stage_ms": [round(x, 4) for x in st_f2.ms[:7]]}
     log(f"rb_filter f32 full stage 2: {t_f2 * 1e3:.2f} ms/step")
+
+    # per-template choice: full matched filter for templates with many crossings, direct sums otherwise
+    def rb_auto():
+        n, _, st = rbmf.rb_filter(ctx, bases, bank, sd, wl.thr1, wl.thr2, stage2=rbmf.RB_STAGE2_AUTO, out=out)
+        return n, st
+    t_au, (n_au, st_au) = time_calls(rb_auto, args.steps, args.warmup, torch)
+    tr_au = out[:n_au].cpu().numpy().view(rbmf.TRIGGER_NP).reshape(-1)
+    ok_au = n_au == n_mf and np.array_equal(tr_au[["tmpl", "sample"]], mf_trig[["tmpl", "sample"]])
+    extra["rb_f32_auto_stage2"] = {"value": seg / t_au, "ms_per_step": t_au * 1e3,
+                                   "final_triggers_equal_mf": bool(ok_au),
+                                   "stage_ms": [round(x, 4) for x in st_au.ms[:7]]}
+    log(f"rb_filter f32 auto stage 2: {t_au * 1e3:.2f} ms/step")
     if not args.skip_16bit:
         for dt in ("bf16x3", "bf16", "f16"):
             b16 = rbmf.subbank_bases(ctx, bank, wl.bounds(), rank=wl.sub_ranks(), tol=wl.tol, dtype=dt)

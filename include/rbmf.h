@@ -77,8 +77,12 @@ typedef enum { RB_F32 = 0, RB_BF16 = 1, RB_F16 = 2, RB_BF16X3 = 3 } rb_dtype;
 typedef enum {
   RB_STAGE2_FULL = 0,      /* full matched filter (all N samples) of every
                               template with a first-stage crossing            */
-  RB_STAGE2_SPARSE = 1     /* exact SNR evaluated only at the first-stage
+  RB_STAGE2_SPARSE = 1,    /* exact SNR evaluated only at the first-stage
                               crossing samples (direct frequency sums)        */
+  RB_STAGE2_AUTO = 2       /* per template: FULL when it has at least
+                              RBMF_STAGE2_SPLIT (default 32) first-stage
+                              crossings, SPARSE otherwise (rb_filter only;
+                              rb_filter_batch returns RB_ERR_UNSUPPORTED)     */
 } rb_stage2_mode;
 
 typedef struct rb_ctx_s*   rb_ctx;

@@ -147,7 +147,7 @@ struct rb_ctx_s {
   // scratch
   DevBuf work, work64, dspec, strain, z, z32, recs1, thr_inf, adjA, adjAhat, adjB, adjT, adjS, adjRho, adjG, adjC, adjGC,
       adjOrd, adjSeg, trig1, trig2, recs, tmp, final_out, cnt1, cnt2, off1, off2, fill1, fill2,
-      list1, list2, tmax, summary, counters, thr_row, peaks, flag, rho_tmp, zws;
+      list1, list2, tmax, summary, counters, thr_row, peaks, flag, rho_tmp, zws, listH, listL, nsplit;
   hipEvent_t ev[8] = {};
   std::vector<hipEvent_t> evs;
   std::map<int64_t, int> fft_n2;   // autotuned four-step split per N (log2 N2)
@@ -272,6 +272,15 @@ int64_t work_budget_bytes() {
   const char* e = std::getenv("RBMF_WORK_MB");
   const int64_t mb = e ? std::atoll(e) : 512;
   return std::max<int64_t>(8, std::min<int64_t>(mb, 4096)) << 20;
+}
+
+// RB_STAGE2_AUTO: crossings from which a template takes the full matched
+// filter (RBMF_STAGE2_SPLIT, default 32: four groups of direct sums cost about
+// as much as the two FFT passes of one template).
+int stage2_split() {
+  const char* e = std::getenv("RBMF_STAGE2_SPLIT");
+  const int v = e ? std::atoi(e) : 32;
+  return v < 1 ? 1 : v;
 }
 
 int batch_vectors(int64_t N, int64_t nvec) {
@@ -1249,7 +1258,8 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
   RB_TRY(check_partition(ctx, bases, nbases, bank));
   RB_CHECK(std::isfinite(opts->thr1) && opts->thr1 > 0, RB_ERR_ARG, "thr1 must be > 0");
   RB_CHECK(std::isfinite(opts->thr2) && opts->thr2 >= opts->thr1, RB_ERR_ARG, "thr2 must be >= thr1");
-  RB_CHECK(opts->stage2 == RB_STAGE2_FULL || opts->stage2 == RB_STAGE2_SPARSE, RB_ERR_ARG, "bad stage2 mode");
+  RB_CHECK(opts->stage2 == RB_STAGE2_FULL || opts->stage2 == RB_STAGE2_SPARSE || opts->stage2 == RB_STAGE2_AUTO,
+           RB_ERR_ARG, "bad stage2 mode");
   RB_CHECK(opts->reserved == 0, RB_ERR_ARG, "reserved must be 0");
   RB_CHECK(cap >= 0, RB_ERR_ARG, "cap must be >= 0");
   const int T = bank->T;
@@ -1289,25 +1299,45 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
   RB_HIP(hipStreamSynchronize(ctx->stream));
   RB_CHECK(flag == 0, RB_ERR_NUMERIC, "strain contains non-finite values");
   int64_t sum2[3];
-  const bool sparse = opts->stage2 == RB_STAGE2_SPARSE;
+  const bool autom = opts->stage2 == RB_STAGE2_AUTO;
+  const bool sparse = opts->stage2 == RB_STAGE2_SPARSE || autom;
   if (sparse) {   // stage-1 records grouped by template (off1 / fill1 from the scan)
     RB_TRY(ctx->recs1.ensure(std::max<size_t>(16, (size_t)sum1[0] * sizeof(TrigRec))));
     RB_HIP(launch_scatter_triggers(ctx->trig1.as<TrigRec>(), sum1[0], nullptr, ctx->off1.as<int32_t>(),
                                    ctx->fill1.as<int32_t>(), ctx->recs1.as<TrigRec>(), ctx->stream));
   }
+  // AUTO: templates with many crossings take the full matched filter (two FFT
+  // passes), the rest the direct sums; nsplit = {heavy, light} list lengths
+  int32_t nsplit[2] = {0, (int32_t)sum1[1]};
+  const int split = stage2_split();
+  if (autom) {
+    RB_TRY(ctx->listH.ensure((size_t)T * 4));
+    RB_TRY(ctx->listL.ensure((size_t)T * 4));
+    RB_TRY(ctx->nsplit.ensure(16));
+    RB_TRY(fill32(ctx, ctx->nsplit.p, 0u, 2));
+    RB_HIP(launch_split_list(ctx->list1.as<int32_t>(), sum1[1], ctx->cnt1.as<int32_t>(), split,
+                             ctx->listH.as<int32_t>(), ctx->listL.as<int32_t>(), ctx->nsplit.as<int32_t>(),
+                             ctx->stream));
+    RB_HIP(hipMemcpyAsync(nsplit, ctx->nsplit.p, 8, hipMemcpyDeviceToHost, ctx->stream));
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+  }
   for (;;) {
     RB_TRY(fill32(ctx, ctx->counters.p, 0u, 4));
     RB_TRY(fill32(ctx, ctx->cnt2.p, 0u, T));
     RB_TRY(fill32(ctx, ctx->tmax.p, 0u, 2 * (int64_t)T));
-    if (sparse) {
-      const SparseArgs sa = sparse_args(ctx, bank, g, tw, opts->thr2, nullptr, nullptr, 0);
+    if (sparse && nsplit[1] > 0) {
+      SparseArgs sa = sparse_args(ctx, bank, g, tw, opts->thr2, nullptr, nullptr, 0);
+      if (autom) sa.list = ctx->listL.as<int32_t>();
       // enough workgroups per template that the busiest one is not a straggler
       const int64_t per = sparse_crossings_per_group();
-      const int groups = (int)std::min<int64_t>(64, std::max<int64_t>(1, (sum1[2] + per - 1) / per));
-      RB_HIP(launch_sparse_exact(sa, (int)sum1[1], groups, ctx->stream));
-    } else {
-      RB_TRY(step_mf(ctx, bank, g, tw, ctx->list1.as<int32_t>(), sum1[1], (float)(opts->thr2 * opts->thr2)));
+      const int64_t mx = autom ? std::min<int64_t>(sum1[2], split - 1) : sum1[2];
+      const int groups = (int)std::min<int64_t>(64, std::max<int64_t>(1, (mx + per - 1) / per));
+      RB_HIP(launch_sparse_exact(sa, nsplit[1], groups, ctx->stream));
     }
+    if (!sparse)
+      RB_TRY(step_mf(ctx, bank, g, tw, ctx->list1.as<int32_t>(), sum1[1], (float)(opts->thr2 * opts->thr2)));
+    else if (nsplit[0] > 0)
+      RB_TRY(step_mf(ctx, bank, g, tw, ctx->listH.as<int32_t>(), nsplit[0], (float)(opts->thr2 * opts->thr2)));
     if (tm) RB_TRY(event(ctx, e_s2));
     RB_TRY(scan_and_read(ctx, T, ctx->cnt2, ctx->off2, ctx->fill2, ctx->list2, sum2));
     if (sum2[0] <= trig_capacity(ctx->trig2)) break;
@@ -1789,6 +1819,7 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
   RB_CHECK(cap_item >= 0 && (out != nullptr || cap_item == 0), RB_ERR_ARG, "bad output buffer");
   RB_CHECK(std::isfinite(opts->thr1) && opts->thr1 > 0, RB_ERR_ARG, "thr1 must be > 0");
   RB_CHECK(std::isfinite(opts->thr2) && opts->thr2 >= opts->thr1, RB_ERR_ARG, "thr2 must be >= thr1");
+  RB_CHECK(opts->stage2 != RB_STAGE2_AUTO, RB_ERR_UNSUPPORTED, "the batch search takes FULL or SPARSE");
   RB_CHECK(opts->stage2 == RB_STAGE2_FULL || opts->stage2 == RB_STAGE2_SPARSE, RB_ERR_ARG, "bad stage2 mode");
   RB_CHECK(opts->reserved == 0, RB_ERR_ARG, "reserved must be 0");
   int Tmax = 0;

@@ -135,6 +135,9 @@ hipError_t launch_pack_c(const float2* C, int T, int Tp, int K, int Kp, int dtyp
 
 // ---------------------------------------------------------------- triggers
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+// list -> heavy (counts >= thresh) / light lists; n_out[2] (zeroed) receives their lengths
+hipError_t launch_split_list(const int32_t* list, int64_t n, const int32_t* counts, int thresh, int32_t* heavy,
+                             int32_t* light, int32_t* n_out, hipStream_t s);
 // summary (device, 3 x int64): total, number of listed templates, max count
 hipError_t launch_scan_counts(const int32_t* counts, int T, int32_t* offsets, int32_t* fill,
                               int32_t* list, int64_t* summary, hipStream_t s);

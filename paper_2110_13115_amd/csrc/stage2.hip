@@ -24,8 +24,14 @@ constexpr int SP_T = 256;      // threads
 constexpr int SP_R = 8;        // consecutive bins per thread and tile
 constexpr int SP_M = 8;        // crossings per pass
 
+// Every product and sum of this file is written as an explicit fmaf / mul
+// with contraction off, so that each crossing's SNR has the same bits in
+// every instantiation of sparse_group (the grouping of crossings depends on
+// the order in which the first stage appended them).
+#pragma clang fp contract(off)
+
 __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 
 // One group of M (a power of two, >= m) crossings of template j: slots m..M-1
@@ -71,7 +77,7 @@ __device__ __forceinline__ void sparse_group(const SparseArgs& a, const float2* 
     for (int r = 0; r < SP_R; ++r) {
       const float2 dv = dn[r], wv = wn[r];
       const float mk = (f0 + r <= hi) ? 1.f : 0.f;
-      x[r] = make_float2(mk * (dv.x * wv.x + dv.y * wv.y), mk * (dv.y * wv.x - dv.x * wv.y));   // d conj(w)
+      x[r] = make_float2(mk * fmaf(dv.x, wv.x, dv.y * wv.y), mk * fmaf(dv.y, wv.x, -(dv.x * wv.y)));   // d conj(w)
     }
     fetch(f0 + SP_T * SP_R);
 #pragma unroll
@@ -79,8 +85,8 @@ __device__ __forceinline__ void sparse_group(const SparseArgs& a, const float2* 
       float2 w = tw(e[i]);
 #pragma unroll
       for (int r = 0; r < SP_R; ++r) {
-        acc[i].x += x[r].x * w.x - x[r].y * w.y;
-        acc[i].y += x[r].x * w.y + x[r].y * w.x;
+        acc[i].x = fmaf(-x[r].y, w.y, fmaf(x[r].x, w.x, acc[i].x));
+        acc[i].y = fmaf(x[r].y, w.x, fmaf(x[r].x, w.y, acc[i].y));
         w = cmulf(w, step[i]);
       }
       e[i] += inc[i];
@@ -105,7 +111,7 @@ __device__ __forceinline__ void sparse_group(const SparseArgs& a, const float2* 
       re += red[i][w].x;
       im += red[i][w].y;
     }
-    const float p = re * re + im * im;
+    const float p = fmaf(re, re, im * im);
     const int n = a.recs[off + c0 + i].sample;
     const unsigned long long key =
         ((unsigned long long)__float_as_uint(p) << 32) | (unsigned long long)(0xffffffffu - (uint32_t)n);

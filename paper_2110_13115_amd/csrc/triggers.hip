@@ -250,6 +250,20 @@ __global__ void k_cluster(const rb_trigger* t, int64_t n, int W, int64_t N, uint
   }
 }
 
+// Splits a template list by first-stage crossing count: counts >= thresh to
+// `heavy`, the rest to `light`; n_out[0] / n_out[1] (zeroed by the caller)
+// receive the two lengths.  The order inside each list is arbitrary.
+__global__ void k_split_list(const int32_t* list, int64_t n, const int32_t* counts, int thresh, int32_t* heavy,
+                             int32_t* light, int32_t* n_out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int j = list[i];
+    if (counts[j] >= thresh)
+      heavy[atomicAdd(&n_out[0], 1)] = j;
+    else
+      light[atomicAdd(&n_out[1], 1)] = j;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
@@ -257,6 +271,14 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   int64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)g), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_list(const int32_t* list, int64_t n, const int32_t* counts, int thresh, int32_t* heavy,
+                             int32_t* light, int32_t* n_out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t g = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
+  hipLaunchKernelGGL(k_split_list, dim3((unsigned)g), dim3(256), 0, s, list, n, counts, thresh, heavy, light, n_out);
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librbmf.so")
 RB_OK, RB_ERR_ARG, RB_ERR_OOM, RB_ERR_DEVICE, RB_ERR_CAPACITY, RB_ERR_NUMERIC, RB_ERR_UNSUPPORTED, \
     RB_ERR_CALLBACK = range(8)
 RB_F32, RB_BF16, RB_F16, RB_BF16X3 = 0, 1, 2, 3
-RB_STAGE2_FULL, RB_STAGE2_SPARSE = 0, 1
+RB_STAGE2_FULL, RB_STAGE2_SPARSE, RB_STAGE2_AUTO = 0, 1, 2
 DTYPES = {"f32": RB_F32, "bf16": RB_BF16, "f16": RB_F16, "bf16x3": RB_BF16X3}
 
 FUNCTIONS = ["rb_ctx_create", "rb_ctx_destroy", "rb_last_error", "rb_bank_create", "rb_bank_free",

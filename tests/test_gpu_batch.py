@@ -114,6 +114,13 @@ def test_batch_sparse_stage2(batch):
     log("sparse batch ok", [len(x) for x in eager], "full-stage extras", missed)
 
 
+def test_batch_rejects_auto_stage2(batch):
+    ctx, setups, items, strains = batch
+    with pytest.raises(rbmf.RbError) as ei:
+        rbmf.rb_filter_batch(ctx, items, 5.0, 6.0, use_graph=False, stage2=rbmf.RB_STAGE2_AUTO)
+    assert ei.value.status == rbmf.RB_ERR_UNSUPPORTED
+
+
 def test_batch_capacity(batch):
     ctx, setups, items, strains = batch
     with pytest.raises(rbmf.RbError) as ei:

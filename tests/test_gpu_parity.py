@@ -206,6 +206,23 @@ def test_rb_filter_final_triggers(ctx, rb_case):
     basis.close()
 
 
+def test_rb_filter_stage2_auto(ctx, rb_case, monkeypatch):
+    """AUTO second stage: templates with many first-stage crossings take the
+    full matched filter, the rest the direct sums; with the split forced low
+    (2 crossings) both paths run, and the final triggers still equal the
+    oracle's and the full second stage's."""
+    case, bank = rb_case
+    basis = rbmf.Basis(ctx, bank, rank=0, tol=1e-3, dtype="f32")
+    full, _, st_f = rbmf.rb_filter(ctx, basis, bank, case.strain, 5.0, 6.0, stage2=rbmf.RB_STAGE2_FULL)
+    for split in ("2", "1000000"):
+        monkeypatch.setenv("RBMF_STAGE2_SPLIT", split)
+        auto, _, st_a = rbmf.rb_filter(ctx, basis, bank, case.strain, 5.0, 6.0, stage2=rbmf.RB_STAGE2_AUTO)
+        compare_triggers(auto, case.rho, 6.0)
+        assert st_a.n_refiltered == st_f.n_refiltered
+        log(f"  auto split {split}: {len(auto)} final (full {len(full)})")
+    basis.close()
+
+
 def _quant(x, dtype):
     """Round-to-nearest-even to bf16 / f16 (numpy emulation)."""
     x = np.asarray(x, np.float32)
