@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--skip-16bit", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline rb_filter call (for profiler runs)")
+    ap.add_argument("--mf-only", action="store_true",
+                    help="time only the mf_full comparator (for profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device-to-device copy of MIB MiB and exit (scales HBM byte "
                          "counters)")
@@ -222,6 +224,12 @@ def main():
 
     def mf_step():
         return rbmf.mf_full(ctx, bank, sd, wl.thr2, out=out)
+
+    if args.mf_only:
+        t_mf, (n_mf, _, st_mf) = time_calls(mf_step, args.steps, args.warmup, torch)
+        print(json.dumps({"mf_full_ms_per_step": t_mf * 1e3, "triggers": int(n_mf),
+                          "stage_ms": [round(x, 4) for x in st_mf.ms[:7]]}), flush=True)
+        return
 
     # --- headline: rb_filter, FP32 (the workload's precision), exact second stage evaluated at the
     # first-stage crossings

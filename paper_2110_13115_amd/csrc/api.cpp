@@ -152,6 +152,7 @@ struct rb_ctx_s {
   std::vector<hipEvent_t> evs;
   std::map<int64_t, int> fft_n2;   // autotuned four-step split per N (log2 N2)
   std::string arch;                // device architecture name (tuning cache key prefix)
+  bool want_peaks = false;         // the current call returns per-template peaks (tmax is needed)
   // batch search: per-item summaries and outputs, captured graph
   DevBuf bsum, bout;
   hipStream_t gstream = nullptr;
@@ -565,7 +566,7 @@ rb_status step_mf(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTables& t
   a.trig_cap = trig_capacity(ctx->trig2);
   a.trig_count = ctx->counters.as<unsigned long long>() + 1;
   a.tmpl_count = ctx->cnt2.as<int32_t>();
-  a.tmpl_max = ctx->tmax.as<unsigned long long>();
+  a.tmpl_max = ctx->want_peaks ? ctx->tmax.as<unsigned long long>() : nullptr;
   for (int64_t i0 = 0; i0 < nlist; i0 += B) {
     a.vec_base = (int)i0;
     a.nvec = (int)std::min<int64_t>(B, nlist - i0);
@@ -1243,7 +1244,7 @@ SparseArgs sparse_args(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTabl
   sa.out_cap = trig_capacity(ctx->trig2);
   sa.out_count = ctx->counters.as<unsigned long long>() + 1;
   sa.tmpl_count = ctx->cnt2.as<int32_t>();
-  sa.tmpl_max = ctx->tmax.as<unsigned long long>();
+  sa.tmpl_max = ctx->want_peaks ? ctx->tmax.as<unsigned long long>() : nullptr;
   return sa;
 }
 
@@ -1263,6 +1264,7 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
   RB_CHECK(opts->reserved == 0, RB_ERR_ARG, "reserved must be 0");
   RB_CHECK(cap >= 0, RB_ERR_ARG, "cap must be >= 0");
   const int T = bank->T;
+  ctx->want_peaks = peaks != nullptr;
   FftGeom g;
   RB_TRY(geom_for(ctx, bank, &g));
   FftTables tw;
@@ -1374,6 +1376,7 @@ extern "C" rb_status mf_full(rb_ctx ctx, rb_bank bank, const float* strain, doub
   RB_CHECK(std::isfinite(thr) && thr > 0, RB_ERR_ARG, "thr must be > 0");
   RB_CHECK(cap >= 0, RB_ERR_ARG, "cap must be >= 0");
   const int T = bank->T;
+  ctx->want_peaks = peaks != nullptr;
   FftGeom g;
   RB_TRY(geom_for(ctx, bank, &g));
   FftTables tw;
@@ -1832,6 +1835,7 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
     Tmax = std::max(Tmax, it.bank->T);
   }
   RB_TRY(ensure_trigger_scratch(ctx, Tmax));
+  ctx->want_peaks = false;   // the batch returns triggers only
   RB_TRY(ctx->bsum.ensure((size_t)nitems * 8 * 8));
   RB_TRY(ctx->bout.ensure(std::max<size_t>(16, (size_t)nitems * cap_item * sizeof(rb_trigger))));
   const size_t cap2 = (size_t)trig_capacity(ctx->trig2);

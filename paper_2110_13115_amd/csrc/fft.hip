@@ -487,12 +487,14 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
     const int lane = __lane_id();
     // running maximum in registers (ties to the lowest sample); crossings are
     // rare, so each crossing lane appends with its own atomics
+    // (tracked only when the caller asked for per-template peaks: tmpl_max != NULL)
+    const bool track = a.tmpl_max != nullptr;
     float bp = -1.f;
     int bn = 0x7fffffff;
     final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int f, int n1, V val, int) {
       const int n = (row0 + f) + N2 * n1;
       const float p = val.x * val.x + val.y * val.y;
-      if (p > bp || (p == bp && n < bn)) {
+      if (track && (p > bp || (p == bp && n < bn))) {
         bp = p;
         bn = n;
       }
@@ -509,15 +511,17 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
         }
       }
     });
-    unsigned long long best =
-        bp < 0.f ? 0ull
-                 : ((unsigned long long)__float_as_uint(bp) << 32) | (unsigned long long)(0xffffffffu - (uint32_t)bn);
-    // wave-reduce the running maximum, one atomic per wave
-    for (int off = 32; off > 0; off >>= 1) {
-      const unsigned long long o = __shfl_xor(best, off);
-      best = o > best ? o : best;
+    if (track) {
+      unsigned long long best =
+          bp < 0.f ? 0ull
+                   : ((unsigned long long)__float_as_uint(bp) << 32) | (unsigned long long)(0xffffffffu - (uint32_t)bn);
+      // wave-reduce the running maximum, one atomic per wave
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(best, off);
+        best = o > best ? o : best;
+      }
+      if (lane == 0 && best != 0ull) atomicMax(&a.tmpl_max[v], best);
     }
-    if (lane == 0 && best != 0ull) atomicMax(&a.tmpl_max[v], best);
   } else if constexpr (OUT == OUT_NATURAL) {
     float2* __restrict__ o = a.cout + (int64_t)v * N;
     final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int f, int n1, V val, int) {

@@ -173,7 +173,7 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
     else
       sparse_group<8>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best);
   }
-  if (threadIdx.x < SP_M && best != 0ull) atomicMax(&a.tmpl_max[j], best);
+  if (a.tmpl_max != nullptr && threadIdx.x < SP_M && best != 0ull) atomicMax(&a.tmpl_max[j], best);
 }
 
 }  // namespace
