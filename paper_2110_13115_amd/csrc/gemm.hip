@@ -110,20 +110,11 @@ __device__ __forceinline__ bool xcd_tile(int ntt, int64_t nwg, int& tt, int64_t&
 // Operands of G k-steps are loaded into one of two register buffers while the
 // MFMAs of the other run (the steady state has no branch, so the loads of the
 // next group stay in flight); the last K mod 2G steps run one at a time.
+// Main loop and epilogue of one wave's RB x CB tile (templates from row
+// block rb0, samples from q0).
 template <int RB, int CB, int G>
-__global__ __launch_bounds__(256, 2) void k_recon_f32(GemmArgs a) {   // at least 2 waves per SIMD
-  constexpr int TT = WAVES * RB * 16;   // templates per workgroup
-  constexpr int TN = CB * 32;           // G: k-steps per pipeline group
-  const int ntt = a.Tp / TT;
-  const int64_t nwg = (int64_t)ntt * (a.N / TN);
-  int tt;
-  int64_t st;
-  if (!xcd_tile(ntt, nwg, tt, st)) return;
-  const int wave = threadIdx.x >> 6;
+__device__ __forceinline__ void recon_f32_tile(const GemmArgs& a, int rb0, int64_t q0) {
   const int lane = threadIdx.x & 63;
-  const int rb0 = tt * (TT / 16) + wave * RB;     // first 16-template row block
-  if (rb0 * 16 >= a.T) return;                             // all of this wave's rows are padding
-  const int64_t q0 = st * TN;
   const int K = a.K;
   const int64_t N = a.N;
   const int64_t astr = (int64_t)K * 64;                    // floats per packed row block
@@ -208,6 +199,26 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(GemmArgs a) {   // at leas
         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
   }
   epilogue<RB, CB>(a, acc, rb0, q0);
+}
+
+template <int RB, int CB, int G>
+__global__ __launch_bounds__(256, 2) void k_recon_f32(GemmArgs a) {   // at least 2 waves per SIMD
+  constexpr int TT = WAVES * RB * 16;   // templates per workgroup
+  constexpr int TN = CB * 32;           // G: k-steps per pipeline group
+  const int ntt = a.Tp / TT;
+  const int64_t nwg = (int64_t)ntt * (a.N / TN);
+  int tt;
+  int64_t st;
+  if (!xcd_tile(ntt, nwg, tt, st)) return;
+  const int wave = threadIdx.x >> 6;
+  const int rb0 = tt * (TT / 16) + wave * RB;     // first 16-template row block
+  if (rb0 * 16 >= a.T) return;                             // all of this wave's rows are padding
+  const int64_t q0 = st * TN;
+  // a wave whose second row block is all padding runs the one-block tile
+  if (RB == 2 && (rb0 + 1) * 16 >= a.T)
+    recon_f32_tile<1, CB, G>(a, rb0, q0);
+  else
+    recon_f32_tile<RB, CB, G>(a, rb0, q0);
 }
 
 // 16-bit operands: one instruction reduces over 16 realified entries = 8
