@@ -12,6 +12,10 @@ mf      the template method: strain FFT, sigma, complex SNR series, triggers,
 basis   PCA/SVD basis of the whitened unit-norm bank, rank rule, coefficients,
         reduced-basis SNR (Sec. II.A, Eqs. Eq-PCA/Eq-SVD, basis_SNR,
         Beta_eqn, SNR_loss; Sec. III.B).
+hier    the binned (hierarchical) first stage: bin means of the basis
+        outputs, triggering bins, fine reconstruction of their samples, the
+        second-stage variants, the template-method fold of Eq. avg_fft2 and
+        the target SNR of Eq. target_snr_criteria (Sec. III.C-D, III.F).
 grad    loss sum g |rho|^2 over a frozen trigger set and its gradients with
         respect to the coefficients and the strain (torch CPU float64
         autograd through an independent plain forward).
