@@ -79,10 +79,14 @@ typedef enum {
                               template with a first-stage crossing            */
   RB_STAGE2_SPARSE = 1,    /* exact SNR evaluated only at the first-stage
                               crossing samples (direct frequency sums)        */
-  RB_STAGE2_AUTO = 2       /* per template: FULL when it has at least
+  RB_STAGE2_AUTO = 2,      /* per template: FULL when it has at least
                               RBMF_STAGE2_SPLIT (default 32) first-stage
                               crossings, SPARSE otherwise (rb_filter only;
                               rb_filter_batch returns RB_ERR_UNSUPPORTED)     */
+  RB_STAGE2_RECON = 3      /* the paper's own second stage (Sec. III.C): no
+                              exact filter; the final triggers are the
+                              candidates whose reconstructed |rho_RB| reaches
+                              thr2, with that SNR (rb_filter only)            */
 } rb_stage2_mode;
 
 typedef struct rb_ctx_s*   rb_ctx;
@@ -111,21 +115,31 @@ typedef struct {
 } rb_peak;
 
 typedef struct {
-  int64_t n_stage1;        /* first-stage crossings (rb_filter)              */
+  int64_t n_stage1;        /* candidates: first-stage crossings of |rho_RB|
+                              (rb_filter; with bins, those of the fine
+                              reconstruction)                                */
   int32_t n_refiltered;    /* templates passed to the second stage           */
   int32_t rank;            /* basis rank used                                */
   float   ms[8];           /* device time per stage, ms: [0] strain FFT,
-                              [1] correlation + basis IFFTs, [2] reconstruction
-                              GEMM + first-stage threshold, [3] selection,
-                              [4] second stage / full MF, [5] sort + output,
-                              [6] total, [7] reserved                        */
+                              [1] correlation + basis IFFTs (+ bin means),
+                              [2] reconstruction GEMM + first-stage threshold,
+                              [3] selection, [4] second stage / full MF,
+                              [5] sort + output, [6] total, [7] of [2], the
+                              fine reconstruction of triggering bins         */
+  int64_t n_bins;          /* triggering (template, bin) pairs (bin_w >= 2)  */
 } rb_stats;
 
 typedef struct {
-  double  thr1;            /* first-stage threshold on |rho_RB| (> 0)        */
-  double  thr2;            /* final threshold on the exact |rho| (>= thr1)   */
+  double  thr1;            /* candidate threshold on |rho_RB| (> 0)          */
+  double  thr2;            /* final threshold (>= thr1): on the exact |rho|,
+                              or on |rho_RB| with RB_STAGE2_RECON            */
   int32_t stage2;          /* rb_stage2_mode                                 */
-  int32_t reserved;        /* must be 0                                      */
+  int32_t bin_w;           /* 0 or 1: rho_RB at every sample (first stage =
+                              candidates); 2..64, a power of two with
+                              N / bin_w >= 256: the binned first stage of
+                              Sec. III.C (see rb_filter)                     */
+  double  thr_bin;         /* bin_w >= 2: threshold rho_I on the averaged
+                              |rho_avg| (> 0); ignored otherwise             */
 } rb_filter_opts;
 
 /* Bank source.  Fills out[(t1-t0) * (k1-k0) * 2] with the complex128 values
@@ -212,17 +226,29 @@ rb_status rb_basis_export(rb_basis basis, double* V, double* c, double* lambda);
 /* Hierarchical reduced-basis search of one segment (Sec. III.C):
  *   1. s~ of the strain (forward FFT), whitened on the band;
  *   2. beta_k = IFFT(d conj(v_k)) for every basis vector of every sub-bank;
- *   3. rho_RB = C beta (MFMA GEMM), first-stage crossings |rho_RB| >= thr1;
- *   4. second stage (opts->stage2): the exact |rho| of the selected templates,
- *      final triggers |rho| >= thr2.
+ *   3. bin_w <= 1: rho_RB = C beta (MFMA GEMM) at every sample, candidates
+ *      |rho_RB| >= thr1.
+ *      bin_w = w >= 2 (the binned first stage): the bin means
+ *      beta_avg_k[i] = (1/w) sum_{r<w} beta_k[i w + r] (Eq. for beta^avg),
+ *      rho_avg = C beta_avg (MFMA GEMM on N/w samples), triggering bins
+ *      |rho_avg| >= thr_bin; then rho_RB at every sample of every
+ *      triggering (template, bin) (FP32), candidates |rho_RB| >= thr1;
+ *   4. second stage (opts->stage2) on the candidates: the exact |rho|
+ *      (FULL, SPARSE, AUTO) or the reconstruction itself (RECON); final
+ *      triggers reach thr2.
+ *   With bin_w >= 2 the candidate set only holds samples of triggering bins:
+ *   averaging lowers |rho| (the complex SNR rotates within a bin), so thr_bin
+ *   must sit well below thr1 to keep a given recovery (Sec. IV.B).
  *   bases   nbases (>= 1) bases of this bank whose template ranges partition
  *           [0, T) (one basis of the whole bank, or one per sub-bank).
  *   strain  host or device, N floats.
  *   out     host or device, cap entries; triggers sorted by (tmpl, sample).
  *   n_out   host; number of final triggers.  If it exceeds cap the call
  *           returns RB_ERR_CAPACITY with the required count in *n_out.
- *   peaks   host or device, T entries, or NULL.
- *   stats   host or NULL. */
+ *   peaks   host or device, T entries, or NULL (with RECON: the maximum
+ *           |rho_RB| over the template's candidates).
+ *   stats   host or NULL.
+ * RB_ERR_ARG for a bad threshold, mode, bin_w or thr_bin. */
 rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases, rb_bank bank,
                     const float* strain, const rb_filter_opts* opts, rb_trigger* out, int64_t cap,
                     int64_t* n_out, rb_peak* peaks, rb_stats* stats);
@@ -238,8 +264,9 @@ typedef struct {
 
 /* Batched hierarchical search (Sec. III.B sub-banks x segments of any length;
  * one item per (segment, bank)).  Each item runs the same steps as rb_filter
- * (full second stage only) with device-side counts, so the whole batch is a
- * sequence of kernel launches with no host synchronisation inside.
+ * (FULL or SPARSE second stage, bin_w 0 or 1; RB_ERR_UNSUPPORTED otherwise)
+ * with device-side counts, so the whole batch is a sequence of kernel
+ * launches with no host synchronisation inside.
  *   use_graph  1: the batch is captured once into a hipGraph (keyed by the
  *              item pointers, thresholds and capacities) and replayed on later
  *              calls with the same key: refill the strain buffers and call
@@ -298,6 +325,12 @@ rb_status rb_cluster_peaks(rb_ctx ctx, const rb_trigger* trig, int64_t n, int32_
  * method for all T templates; otherwise the first-stage reconstruction
  * rho_RB = C beta for the basis's t1 - t0 templates. */
 rb_status rb_debug_rho(rb_ctx ctx, rb_basis basis, rb_bank bank, const float* strain, float* rho);
+
+/* Dump the averaged series of the binned first stage (small T*N only):
+ * rho_avg = C beta_avg for the basis's t1 - t0 templates as rb_filter
+ * computes it with bin_w = w (Sec. III.C), rows x (N/w) x 2 floats (host or
+ * device), bins in natural order, storage scales removed. */
+rb_status rb_debug_rho_binned(rb_ctx ctx, rb_basis basis, const float* strain, int32_t w, float* rho);
 
 /* Dump the per-basis filter outputs beta (K x N x 2 floats, natural time
  * order, host or device) as stored for the reconstruction (after any 16-bit

@@ -147,7 +147,8 @@ struct rb_ctx_s {
   // scratch
   DevBuf work, work64, dspec, strain, z, z32, recs1, thr_inf, adjA, adjAhat, adjB, adjT, adjS, adjRho, adjG, adjC, adjGC,
       adjOrd, adjSeg, trig1, trig2, recs, tmp, final_out, cnt1, cnt2, off1, off2, fill1, fill2,
-      list1, list2, tmax, summary, counters, thr_row, peaks, flag, rho_tmp, zws, listH, listL, nsplit;
+      list1, list2, tmax, summary, counters, thr_row, peaks, flag, rho_tmp, zws, listH, listL, nsplit,
+      zfine, zpart, trigB, cntB, snap, tinv;
   hipEvent_t ev[8] = {};
   std::vector<hipEvent_t> evs;
   std::map<int64_t, int> fft_n2;   // autotuned four-step split per N (log2 N2)
@@ -194,7 +195,7 @@ struct rb_basis_s {
   DevBuf row_scale_dev;        // Tp floats
   DevBuf thr_row;              // Tp floats: squared first-stage threshold per template
   float thr_cached = -1.f;
-  int gemm_variant = -1;       // autotuned reconstruction kernel variant (-1: not yet)
+  std::map<int64_t, int> gemm_variant;   // autotuned reconstruction kernel variant per column count
 };
 
 // ====================================================================== shared steps
@@ -524,6 +525,91 @@ rb_status step_basis_outputs(rb_ctx ctx, rb_basis basis, const FftGeom& g, const
   return RB_OK;
 }
 
+int64_t trig_capacity(const DevBuf& b) { return (int64_t)(b.bytes / sizeof(TrigRec)); }
+
+// Binned first stage (Sec. III.C): FP32 Z of every basis vector in the
+// OUT_ZBIN layout (ctx->zfine, read by the fine reconstruction) and the bin
+// means beta_avg in the reconstruction dtype (ctx->z, planar [2Kp][N/w], the
+// GEMM's operand), from partial sums written by the same pass-2 launch.
+rb_status step_basis_outputs_binned(rb_ctx ctx, rb_basis basis, const FftGeom& g, const FftTables& tw, int w) {
+  rb_bank bank = basis->bank;
+  const int K = basis->K, Kp = basis->Kp;
+  const rb_dtype dt = basis->dtype;
+  const int64_t Nb = g.N / w;
+  const int G = std::min(pass2_rows(g.N1), w);
+  const size_t esz = dt == RB_F32 ? 4 : 2;
+  const int planes = dt == RB_BF16X3 ? 2 : 1;
+  const size_t plane_bytes = (size_t)2 * Kp * Nb * esz;
+  RB_TRY(ctx->z.ensure(plane_bytes * planes));
+  if (Kp > K) {
+    const size_t off = (size_t)2 * K * Nb * esz, bytes = (size_t)2 * (Kp - K) * Nb * esz;
+    for (int p = 0; p < planes; ++p)
+      RB_TRY(fill32(ctx, static_cast<char*>(ctx->z.p) + p * plane_bytes + off, 0u, (int64_t)(bytes / 4)));
+  }
+  RB_TRY(ctx->zfine.ensure((size_t)2 * K * g.N * 4));
+  RB_TRY(ctx->zpart.ensure((size_t)K * (g.N / G) * 8));
+  const int B = batch_vectors(g.N, K);
+  RB_TRY(ctx->work.ensure((size_t)B * g.N * 8));
+  PassArgs a = base_args(bank, g, tw);
+  a.sign = +1;
+  a.d = ctx->dspec.as<float2>();
+  a.src = basis->P.as<float2>();
+  a.work = ctx->work.as<float2>();
+  a.zout = ctx->zfine.as<float>();
+  a.zpart = ctx->zpart.as<float2>();
+  a.bin_g = G;
+  for (int v0 = 0; v0 < K; v0 += B) {
+    a.vec_base = v0;
+    a.nvec = std::min(B, K - v0);
+    RB_HIP(launch_pass1(a, IN_CORR, ctx->stream));
+    RB_HIP(launch_pass2(a, OUT_ZBIN, ctx->stream));
+  }
+  BinReduceArgs r;
+  std::memset(&r, 0, sizeof(r));
+  r.part = ctx->zpart.as<float2>();
+  r.N = g.N;
+  r.N1 = g.N1;
+  r.N2 = g.N2;
+  r.G = G;
+  r.w = w;
+  r.vec_base = 0;
+  r.nvec = K;
+  r.zavg = ctx->z.p;
+  r.dtype = (int)dt;
+  r.zscale = 1.f;
+  r.zplane = (int64_t)2 * Kp * Nb;
+  RB_HIP(launch_bin_reduce(r, ctx->stream));
+  return RB_OK;
+}
+
+// rho_RB at every sample of the triggering bins appended by basis `basis`
+// since the snapshot `snap` of the bin counter; candidates into trig1 / cnt1.
+rb_status step_fine(rb_ctx ctx, rb_basis basis, const FftGeom& g, int w, float thr1sq,
+                    const unsigned long long* snap) {
+  FineArgs f;
+  std::memset(&f, 0, sizeof(f));
+  f.z = ctx->zfine.as<float>();
+  f.N = g.N;
+  f.N1 = g.N1;
+  f.N2 = g.N2;
+  f.F = pass2_rows(g.N1);
+  f.K = basis->K;
+  f.w = w;
+  f.C = basis->C32.as<float2>();
+  f.t0 = basis->t0;
+  f.bins = ctx->trigB.as<TrigRec>();
+  f.begin = snap;
+  f.end = ctx->counters.as<unsigned long long>() + 2;
+  f.bins_cap = trig_capacity(ctx->trigB);
+  f.thr_sq = thr1sq;
+  f.out = ctx->trig1.as<TrigRec>();
+  f.out_cap = trig_capacity(ctx->trig1);
+  f.out_count = ctx->counters.as<unsigned long long>();
+  f.tmpl_count = ctx->cnt1.as<int32_t>();
+  RB_HIP(launch_fine_recon(f, 1024, ctx->stream));
+  return RB_OK;
+}
+
 rb_status ensure_trigger_scratch(rb_ctx ctx, int T) {
   RB_TRY(ctx->cnt1.ensure((size_t)T * 4));
   RB_TRY(ctx->cnt2.ensure((size_t)T * 4));
@@ -536,13 +622,13 @@ rb_status ensure_trigger_scratch(rb_ctx ctx, int T) {
   RB_TRY(ctx->tmax.ensure((size_t)T * 8));
   RB_TRY(ctx->summary.ensure(8 * 8));
   RB_TRY(ctx->counters.ensure(4 * 8));
+  RB_TRY(ctx->cntB.ensure((size_t)T * 4));
   RB_TRY(ctx->flag.ensure(8));
   if (ctx->trig1.bytes == 0) RB_TRY(ctx->trig1.ensure((size_t)1 << 22 << 4));
   if (ctx->trig2.bytes == 0) RB_TRY(ctx->trig2.ensure((size_t)1 << 20 << 4));
+  if (ctx->trigB.bytes == 0) RB_TRY(ctx->trigB.ensure((size_t)1 << 20 << 4));
   return RB_OK;
 }
-
-int64_t trig_capacity(const DevBuf& b) { return (int64_t)(b.bytes / sizeof(TrigRec)); }
 
 // Full matched filter of a template list (or all templates) with the
 // threshold epilogue; counts in cnt2, records in trig2, maxima in tmax.
@@ -1090,7 +1176,10 @@ extern "C" rb_status rb_basis_export(rb_basis basis, double* V, double* c, doubl
 // ====================================================================== search
 namespace {
 
-rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq, float2* rho_out) {
+// rho = C Z on the basis outputs (w = 1: every sample, crossings into trig1 /
+// cnt1) or on their bin means (w >= 2: N/w columns, triggering bins into
+// trigB / cntB with the bin index as the sample).
+rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq, float2* rho_out, int w = 1) {
   const float want = rho_out ? std::numeric_limits<float>::infinity() : thr1sq;
   if (!(basis->thr_cached == want)) {
     RB_TRY(basis->thr_row.ensure((size_t)basis->Tp * 4));
@@ -1105,7 +1194,7 @@ rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq
   }
   GemmArgs ga;
   std::memset(&ga, 0, sizeof(ga));
-  ga.N = g.N;
+  ga.N = g.N / w;
   ga.T = basis->T;
   ga.Tp = basis->Tp;
   ga.K = basis->K;
@@ -1115,15 +1204,16 @@ rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq
   ga.z = ctx->z.p;
   ga.thr2_row = basis->thr_row.as<float>();
   ga.N1 = g.N1;
-  ga.N2 = g.N2;
-  ga.trig = ctx->trig1.as<TrigRec>();
-  ga.trig_cap = trig_capacity(ctx->trig1);
-  ga.trig_count = ctx->counters.as<unsigned long long>();
+  ga.N2 = g.N2 / w;
+  DevBuf& tb = w > 1 ? ctx->trigB : ctx->trig1;
+  ga.trig = tb.as<TrigRec>();
+  ga.trig_cap = trig_capacity(tb);
+  ga.trig_count = ctx->counters.as<unsigned long long>() + (w > 1 ? 2 : 0);
   ga.tmpl_base = basis->t0;
-  ga.tmpl_count = ctx->cnt1.as<int32_t>() + basis->t0;
+  ga.tmpl_count = (w > 1 ? ctx->cntB : ctx->cnt1).as<int32_t>() + basis->t0;
   ga.rho_out = rho_out;
   ga.row_inv = basis->row_inv.as<float>();
-  if (basis->gemm_variant < 0) {
+  if (basis->gemm_variant.find(ga.N) == basis->gemm_variant.end()) {
     // autotune on this basis's first call: time every variant on the real Z
     // with infinite thresholds (no trigger is appended), keep the fastest
     const char* force = std::getenv("RBMF_GEMM_VARIANT");
@@ -1169,9 +1259,9 @@ rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq
       (void)hipEventDestroy(e1);
       tune_cache().put(key, choice);
     }
-    basis->gemm_variant = choice;
+    basis->gemm_variant[ga.N] = choice;
   }
-  ga.variant = basis->gemm_variant;
+  ga.variant = basis->gemm_variant[ga.N];
   RB_HIP(launch_recon_gemm(ga, ctx->stream));
   return RB_OK;
 }
@@ -1259,9 +1349,13 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
   RB_TRY(check_partition(ctx, bases, nbases, bank));
   RB_CHECK(std::isfinite(opts->thr1) && opts->thr1 > 0, RB_ERR_ARG, "thr1 must be > 0");
   RB_CHECK(std::isfinite(opts->thr2) && opts->thr2 >= opts->thr1, RB_ERR_ARG, "thr2 must be >= thr1");
-  RB_CHECK(opts->stage2 == RB_STAGE2_FULL || opts->stage2 == RB_STAGE2_SPARSE || opts->stage2 == RB_STAGE2_AUTO,
+  RB_CHECK(opts->stage2 == RB_STAGE2_FULL || opts->stage2 == RB_STAGE2_SPARSE || opts->stage2 == RB_STAGE2_AUTO ||
+               opts->stage2 == RB_STAGE2_RECON,
            RB_ERR_ARG, "bad stage2 mode");
-  RB_CHECK(opts->reserved == 0, RB_ERR_ARG, "reserved must be 0");
+  const int w = opts->bin_w >= 2 ? opts->bin_w : 1;
+  RB_CHECK(opts->bin_w >= 0 && opts->bin_w <= 64 && (w & (w - 1)) == 0 && bank->grid.N / w >= 256, RB_ERR_ARG,
+           "bin_w must be 0, 1 or a power of two <= 64 with N / bin_w >= 256");
+  RB_CHECK(w == 1 || (std::isfinite(opts->thr_bin) && opts->thr_bin > 0), RB_ERR_ARG, "thr_bin must be > 0");
   RB_CHECK(cap >= 0, RB_ERR_ARG, "cap must be >= 0");
   const int T = bank->T;
   ctx->want_peaks = peaks != nullptr;
@@ -1273,7 +1367,8 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
   RB_TRY(strain_device(ctx, strain, g.N, &s));
   RB_TRY(ensure_trigger_scratch(ctx, T));
   const bool tm = stats != nullptr;
-  // events: 0 start, 1 spectrum, 2+2m Z of basis m, 3+2m GEMM of basis m, then scan, stage 2, end
+  // events: 0 start, 1 spectrum, 2+2m Z of basis m, 3+2m GEMM (+ fine) of basis m, then scan,
+  // stage 2, end; with bins, e_end + 1 + m between the GEMM and the fine step of basis m
   const size_t e_scan = 2 + 2 * (size_t)nbases, e_s2 = e_scan + 1, e_end = e_s2 + 1;
   if (tm) RB_TRY(event(ctx, 0));
   RB_TRY(fill32(ctx, ctx->flag.p, 0u, 2));
@@ -1281,17 +1376,40 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
   RB_TRY(step_spectrum(ctx, bank, g, tw, s));
   if (tm) RB_TRY(event(ctx, 1));
   int64_t sum1[3];
+  int64_t nbins = 0;
   const float thr1sq = (float)(opts->thr1 * opts->thr1);
+  if (w > 1) RB_TRY(ctx->snap.ensure((size_t)nbases * 8));
   for (;;) {
     RB_TRY(fill32(ctx, ctx->counters.p, 0u, 2));
     RB_TRY(fill32(ctx, ctx->cnt1.p, 0u, T));
+    if (w > 1) {
+      RB_TRY(fill32(ctx, ctx->counters.as<unsigned long long>() + 2, 0u, 2));
+      RB_TRY(fill32(ctx, ctx->cntB.p, 0u, T));
+    }
     for (int32_t m = 0; m < nbases; ++m) {
-      RB_TRY(step_basis_outputs(ctx, bases[m], g, tw));
-      if (tm) RB_TRY(event(ctx, 2 + 2 * (size_t)m));
-      RB_TRY(stage1_gemm(ctx, bases[m], g, thr1sq, nullptr));
+      if (w == 1) {
+        RB_TRY(step_basis_outputs(ctx, bases[m], g, tw));
+        if (tm) RB_TRY(event(ctx, 2 + 2 * (size_t)m));
+        RB_TRY(stage1_gemm(ctx, bases[m], g, thr1sq, nullptr));
+      } else {
+        RB_TRY(step_basis_outputs_binned(ctx, bases[m], g, tw, w));
+        if (tm) RB_TRY(event(ctx, 2 + 2 * (size_t)m));
+        unsigned long long* snap = ctx->snap.as<unsigned long long>() + m;
+        RB_HIP(launch_copy_u64(ctx->counters.as<unsigned long long>() + 2, snap, ctx->stream));
+        RB_TRY(stage1_gemm(ctx, bases[m], g, (float)(opts->thr_bin * opts->thr_bin), nullptr, w));
+        if (tm) RB_TRY(event(ctx, e_end + 1 + (size_t)m));
+        RB_TRY(step_fine(ctx, bases[m], g, w, thr1sq, snap));
+      }
       if (tm) RB_TRY(event(ctx, 3 + 2 * (size_t)m));
     }
+    if (w > 1)
+      RB_HIP(hipMemcpyAsync(&nbins, ctx->counters.as<unsigned long long>() + 2, 8, hipMemcpyDeviceToHost,
+                            ctx->stream));
     RB_TRY(scan_and_read(ctx, T, ctx->cnt1, ctx->off1, ctx->fill1, ctx->list1, sum1));
+    if (nbins > trig_capacity(ctx->trigB)) {
+      RB_TRY(ctx->trigB.ensure((size_t)(nbins + nbins / 4) * sizeof(TrigRec)));
+      continue;
+    }
     if (sum1[0] <= trig_capacity(ctx->trig1)) break;
     RB_TRY(ctx->trig1.ensure((size_t)(sum1[0] + sum1[0] / 4) * sizeof(TrigRec)));
   }
@@ -1301,8 +1419,23 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
   RB_HIP(hipStreamSynchronize(ctx->stream));
   RB_CHECK(flag == 0, RB_ERR_NUMERIC, "strain contains non-finite values");
   int64_t sum2[3];
+  const bool recon = opts->stage2 == RB_STAGE2_RECON;
   const bool autom = opts->stage2 == RB_STAGE2_AUTO;
   const bool sparse = opts->stage2 == RB_STAGE2_SPARSE || autom;
+  // RECON without bins reads the GEMM's records, which carry the 16-bit row
+  // scales: gather every basis's inverse scales by global template
+  const float* inv_scale = nullptr;
+  if (recon && w == 1) {
+    bool scaled = false;
+    for (int32_t m = 0; m < nbases; ++m) scaled |= bases[m]->dtype != RB_F32;
+    if (scaled) {
+      RB_TRY(ctx->tinv.ensure((size_t)T * 4));
+      for (int32_t m = 0; m < nbases; ++m)
+        RB_HIP(hipMemcpyAsync(ctx->tinv.as<float>() + bases[m]->t0, bases[m]->row_inv.p, (size_t)bases[m]->T * 4,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+      inv_scale = ctx->tinv.as<float>();
+    }
+  }
   if (sparse) {   // stage-1 records grouped by template (off1 / fill1 from the scan)
     RB_TRY(ctx->recs1.ensure(std::max<size_t>(16, (size_t)sum1[0] * sizeof(TrigRec))));
     RB_HIP(launch_scatter_triggers(ctx->trig1.as<TrigRec>(), sum1[0], nullptr, ctx->off1.as<int32_t>(),
@@ -1324,9 +1457,16 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
     RB_HIP(hipStreamSynchronize(ctx->stream));
   }
   for (;;) {
-    RB_TRY(fill32(ctx, ctx->counters.p, 0u, 4));
+    RB_TRY(fill32(ctx, ctx->counters.as<unsigned long long>() + 1, 0u, 2));
     RB_TRY(fill32(ctx, ctx->cnt2.p, 0u, T));
     RB_TRY(fill32(ctx, ctx->tmax.p, 0u, 2 * (int64_t)T));
+    if (recon)
+      RB_HIP(launch_select_final(ctx->trig1.as<TrigRec>(), ctx->counters.as<unsigned long long>(),
+                                 trig_capacity(ctx->trig1), inv_scale, (float)(opts->thr2 * opts->thr2),
+                                 ctx->trig2.as<TrigRec>(), trig_capacity(ctx->trig2),
+                                 ctx->counters.as<unsigned long long>() + 1, ctx->cnt2.as<int32_t>(),
+                                 ctx->want_peaks ? ctx->tmax.as<unsigned long long>() : nullptr, sum1[0],
+                                 ctx->stream));
     if (sparse && nsplit[1] > 0) {
       SparseArgs sa = sparse_args(ctx, bank, g, tw, opts->thr2, nullptr, nullptr, 0);
       if (autom) sa.list = ctx->listL.as<int32_t>();
@@ -1336,9 +1476,9 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
       const int groups = (int)std::min<int64_t>(64, std::max<int64_t>(1, (mx + per - 1) / per));
       RB_HIP(launch_sparse_exact(sa, nsplit[1], groups, ctx->stream));
     }
-    if (!sparse)
+    if (!sparse && !recon)
       RB_TRY(step_mf(ctx, bank, g, tw, ctx->list1.as<int32_t>(), sum1[1], (float)(opts->thr2 * opts->thr2)));
-    else if (nsplit[0] > 0)
+    else if (sparse && nsplit[0] > 0)
       RB_TRY(step_mf(ctx, bank, g, tw, ctx->listH.as<int32_t>(), nsplit[0], (float)(opts->thr2 * opts->thr2)));
     if (tm) RB_TRY(event(ctx, e_s2));
     RB_TRY(scan_and_read(ctx, T, ctx->cnt2, ctx->off2, ctx->fill2, ctx->list2, sum2));
@@ -1352,6 +1492,7 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
     std::memset(stats, 0, sizeof(*stats));
     stats->n_stage1 = sum1[0];
     stats->n_refiltered = (int32_t)sum1[1];
+    stats->n_bins = nbins;
     int kmax = 0;
     for (int32_t m = 0; m < nbases; ++m) kmax = std::max(kmax, (int)bases[m]->K);
     stats->rank = kmax;
@@ -1360,6 +1501,8 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
       stats->ms[1] += elapsed(ctx, m == 0 ? 1 : 3 + 2 * (size_t)(m - 1), 2 + 2 * (size_t)m);
       stats->ms[2] += elapsed(ctx, 2 + 2 * (size_t)m, 3 + 2 * (size_t)m);
     }
+    if (w > 1)
+      for (int32_t m = 0; m < nbases; ++m) stats->ms[7] += elapsed(ctx, e_end + 1 + (size_t)m, 3 + 2 * (size_t)m);
     stats->ms[3] = elapsed(ctx, 3 + 2 * (size_t)(nbases - 1), e_scan);
     stats->ms[4] = elapsed(ctx, e_scan, e_s2);
     stats->ms[5] = elapsed(ctx, e_s2, e_end);
@@ -1491,6 +1634,38 @@ extern "C" rb_status rb_debug_rho(rb_ctx ctx, rb_basis basis, rb_bank bank, cons
     RB_TRY(stage1_gemm(ctx, basis, g, 0.f, dst));   // rows [t0, t0 + T) of the basis
   }
   if (!dev) RB_HIP(hipMemcpyAsync(rho, dst, (size_t)rows * g.N * 8, hipMemcpyDeviceToHost, ctx->stream));
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  return RB_OK;
+}
+
+extern "C" rb_status rb_debug_rho_binned(rb_ctx ctx, rb_basis basis, const float* strain, int32_t w, float* rho) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(basis != nullptr && rho != nullptr, RB_ERR_ARG, "NULL argument");
+  rb_bank bank = basis->bank;
+  RB_CHECK(w >= 2 && w <= 64 && (w & (w - 1)) == 0 && bank->grid.N / w >= 256, RB_ERR_ARG,
+           "w must be a power of two in [2, 64] with N / w >= 256");
+  const int rows = basis->T;
+  FftGeom g;
+  RB_TRY(geom_for(ctx, bank, &g));
+  const int64_t Nb = g.N / w;
+  RB_CHECK((double)rows * Nb <= 4e9, RB_ERR_ARG, "rows * N / w too large for a dump");
+  FftTables tw;
+  RB_TRY(get_tables(ctx, g, tw));
+  const float* s;
+  RB_TRY(strain_device(ctx, strain, g.N, &s));
+  RB_TRY(ensure_trigger_scratch(ctx, bank->T));
+  float2* dst = reinterpret_cast<float2*>(rho);
+  const bool dev = is_device_ptr(rho);
+  if (!dev) {
+    RB_TRY(ctx->rho_tmp.ensure((size_t)rows * Nb * 8));
+    dst = ctx->rho_tmp.as<float2>();
+  }
+  RB_TRY(step_spectrum(ctx, bank, g, tw, s));
+  RB_TRY(step_basis_outputs_binned(ctx, basis, g, tw, w));
+  RB_TRY(fill32(ctx, ctx->counters.as<unsigned long long>() + 2, 0u, 2));
+  RB_TRY(fill32(ctx, ctx->cntB.p, 0u, bank->T));
+  RB_TRY(stage1_gemm(ctx, basis, g, 0.f, dst, w));
+  if (!dev) RB_HIP(hipMemcpyAsync(rho, dst, (size_t)rows * Nb * 8, hipMemcpyDeviceToHost, ctx->stream));
   RB_HIP(hipStreamSynchronize(ctx->stream));
   return RB_OK;
 }
@@ -1822,9 +1997,11 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
   RB_CHECK(cap_item >= 0 && (out != nullptr || cap_item == 0), RB_ERR_ARG, "bad output buffer");
   RB_CHECK(std::isfinite(opts->thr1) && opts->thr1 > 0, RB_ERR_ARG, "thr1 must be > 0");
   RB_CHECK(std::isfinite(opts->thr2) && opts->thr2 >= opts->thr1, RB_ERR_ARG, "thr2 must be >= thr1");
-  RB_CHECK(opts->stage2 != RB_STAGE2_AUTO, RB_ERR_UNSUPPORTED, "the batch search takes FULL or SPARSE");
+  RB_CHECK(opts->stage2 != RB_STAGE2_AUTO && opts->stage2 != RB_STAGE2_RECON, RB_ERR_UNSUPPORTED,
+           "the batch search takes FULL or SPARSE");
+  RB_CHECK(opts->bin_w <= 1, RB_ERR_UNSUPPORTED, "the batch search takes bin_w 0 or 1");
   RB_CHECK(opts->stage2 == RB_STAGE2_FULL || opts->stage2 == RB_STAGE2_SPARSE, RB_ERR_ARG, "bad stage2 mode");
-  RB_CHECK(opts->reserved == 0, RB_ERR_ARG, "reserved must be 0");
+  RB_CHECK(opts->bin_w >= 0, RB_ERR_ARG, "bin_w must be >= 0");
   int Tmax = 0;
   for (int32_t i = 0; i < nitems; ++i) {
     const rb_batch_item& it = items[i];

@@ -217,7 +217,8 @@ __device__ __forceinline__ void lds_stage(V* lds, const V* __restrict__ pyr, int
 
 // Reads the R inputs of the final stage's butterflies and applies the stage
 // twiddles and DFT; the caller stores.  Output m of butterfly j is position
-// j + m * (L / R).
+// j + m * (L / R); the last argument of store is the output's index among the
+// calling thread's outputs (i * R + m, a compile-time constant once unrolled).
 template <class Lay, int L, int R, int S, class V, class Store>
 __device__ __forceinline__ void final_stage(const V* lds, const V* __restrict__ pyr, int tid,
                                             Store&& store) {
@@ -246,7 +247,7 @@ __device__ __forceinline__ void final_stage(const V* lds, const V* __restrict__ 
       stage_tw_apply<R, Ns>(v, tb[i]);
       Dft<R, S>::run(v);
 #pragma unroll
-      for (int m = 0; m < R; ++m) store(f, j + m * Ns, v[m], m);
+      for (int m = 0; m < R; ++m) store(f, j + m * Ns, v[m], i * R + m);
     }
   }
 }
@@ -528,6 +529,51 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
       const int64_t n = (int64_t)(row0 + f) + (int64_t)N2 * n1;
       o[n] = make_float2(val.x, val.y);
     });
+  } else if constexpr (OUT == OUT_ZBIN) {
+    // Binned first stage.  The block holds F consecutive rows (samples
+    // row0 .. row0 + F - 1 of every n1 slice); after the final stage the
+    // outputs go back to LDS and leave as
+    //  (a) FP32 Z with each slice's F samples adjacent: q = row0 L + n1 F + f,
+    //      so that the fine reconstruction of a bin reads whole runs;
+    //  (b) sums over G = min(F, w) consecutive samples, [N2 / G][L] complex64,
+    //      summed in a fixed order (f ascending).
+    constexpr int F = Lay::NF;
+    constexpr int NBF = F * L / RL;
+    constexpr int PERF = (NBF + NT - 1) / NT;
+    V keep[PERF * RL];
+    final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int, int, V val, int idx) { keep[idx] = val; });
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PERF; ++i) {
+      const int b = tid + i * NT;
+      if (NBF % NT == 0 || b < NBF) {
+        int f, j;
+        Lay::template split<RL>(b, f, j);
+#pragma unroll
+        for (int m = 0; m < RL; ++m) lds[Lay::addr(f, j + m * (L / RL))] = keep[i * RL + m];
+      }
+    }
+    __syncthreads();
+    float* __restrict__ zr = a.zout + (int64_t)(2 * v) * N + (int64_t)row0 * L;
+    float* __restrict__ zi = zr + N;
+    for (int e = tid; e < F * L; e += NT) {
+      const V x = lds[Lay::addr(e % F, e / F)];
+      zr[e] = x.x;
+      zi[e] = x.y;
+    }
+    const int G = a.bin_g;            // power of two dividing F
+    const int ng = F / G;
+    float2* __restrict__ part = a.zpart + (int64_t)v * (N / G) + (int64_t)(row0 / G) * L;
+    for (int o = tid; o < ng * L; o += NT) {
+      const int n1 = o % L, gi = o / L;
+      float sr = 0.f, si = 0.f;
+      for (int f = 0; f < G; ++f) {
+        const V x = lds[Lay::addr(gi * G + f, n1)];
+        sr += x.x;
+        si += x.y;
+      }
+      part[(int64_t)gi * L + n1] = make_float2(sr, si);
+    }
   } else if constexpr (OUT == OUT_TRANSPOSED) {
     float2* __restrict__ o = a.cout + (int64_t)v * N;
     final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int f, int n1, V val, int) {
@@ -627,6 +673,7 @@ hipError_t launch_pass2(const PassArgs& a, OutKind out, hipStream_t st) {
     case OUT_THRESH: return disp2<float2, OUT_THRESH, 1>(a, st);
     case OUT_NATURAL:
       return a.sign > 0 ? disp2<float2, OUT_NATURAL, 1>(a, st) : disp2<float2, OUT_NATURAL, -1>(a, st);
+    case OUT_ZBIN: return disp2<float2, OUT_ZBIN, 1>(a, st);
     case OUT_TRANSPOSED:
       return a.sign > 0 ? disp2<float2, OUT_TRANSPOSED, 1>(a, st) : disp2<float2, OUT_TRANSPOSED, -1>(a, st);
     case OUT_SPECTRUM: return disp2<double2, OUT_SPECTRUM, -1>(a, st);

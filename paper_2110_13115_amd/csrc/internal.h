@@ -56,7 +56,11 @@ enum OutKind {
   OUT_THRESH = 2,    // |x|^2 >= thr2: append trigger, per-vector count and max
   OUT_NATURAL = 3,   // complex64 natural order out[v][n]
   OUT_SPECTRUM = 4,  // forward transform of the strain: d[k - kb] = wd[k] X[k], band only
-  OUT_TRANSPOSED = 5 // complex64 in the pass order out[v][q] (adjoint)
+  OUT_TRANSPOSED = 5, // complex64 in the pass order out[v][q] (adjoint)
+  OUT_ZBIN = 6       // binned first stage: planar FP32 Z with each pass-2 block's F rows
+                     // adjacent per n1 (q = row0 N1 + n1 F + f, F = 4096 / N1 rows per
+                     // block, at least 1), plus sums over bin_g consecutive samples in zpart
+                     // ([N2 / bin_g][N1] complex64 per vector)
 };
 
 struct TrigRec {     // device trigger record before sorting
@@ -99,6 +103,8 @@ struct PassArgs {
   unsigned long long* trig_count;
   int32_t* tmpl_count;       // per template crossing counts
   unsigned long long* tmpl_max;  // per template packed (|x|^2 bits << 32 | ~n)
+  float2* zpart;             // OUT_ZBIN: partial bin sums, N / bin_g per vector
+  int bin_g;                 // OUT_ZBIN: samples per partial sum, min(F, w)
   float2* cout;              // OUT_NATURAL / OUT_SPECTRUM / OUT_TRANSPOSED
   int32_t k_lo;              // OUT_SPECTRUM band
   int32_t k_hi;
@@ -181,6 +187,49 @@ struct SparseArgs {
 // share one template's crossings (each takes every groups-th group of 8).
 hipError_t launch_sparse_exact(const SparseArgs& a, int grid, int groups, hipStream_t s);
 int sparse_crossings_per_group();
+
+// ---------------------------------------------------------------- binned first stage
+// Rows of one pass-2 workgroup (consecutive samples of an n1 slice).
+inline int pass2_rows(int N1) { return N1 >= 4096 ? 1 : 4096 / N1; }
+
+struct BinReduceArgs {
+  const float2* part;        // OUT_ZBIN partial sums, [vec][N2/G][N1]
+  int64_t N;
+  int N1, N2;
+  int G, w;                  // samples per partial sum, per bin (powers of two, G | w)
+  int vec_base, nvec;
+  void* zavg;                // planar bin means [2Kp][N/w] in `dtype` (as the GEMM's Z)
+  int dtype;                 // 0 f32, 1 bf16, 2 f16, 3 bf16 hi + lo planes
+  float zscale;              // 16-bit: value scale
+  int64_t zplane;            // dtype 3: offset (16-bit elements) of the lo plane
+};
+hipError_t launch_bin_reduce(const BinReduceArgs& a, hipStream_t s);
+hipError_t launch_copy_u64(const unsigned long long* src, unsigned long long* dst, hipStream_t s);
+
+struct FineArgs {
+  const float* z;            // OUT_ZBIN FP32 Z, planes 2k / 2k+1 of stride N
+  int64_t N;
+  int N1, N2, F;             // FFT split; F = pass2_rows(N1)
+  int K, w;
+  const float2* C;           // local T x K complex64, C = conj(c), unscaled
+  int t0;                    // global index of local template 0
+  const TrigRec* bins;       // triggering (template, bin) records: sample = bin index
+  const unsigned long long* begin;   // device: first record of this basis
+  const unsigned long long* end;     // device: records appended so far
+  int64_t bins_cap;
+  float thr_sq;              // candidate threshold, squared
+  TrigRec* out;
+  int64_t out_cap;
+  unsigned long long* out_count;
+  int32_t* tmpl_count;       // per global template
+};
+// grid: workgroups of four waves, each wave taking every (4 grid)-th record
+hipError_t launch_fine_recon(const FineArgs& a, int grid, hipStream_t s);
+// n_bound: an upper bound of the record count used to size the launch
+hipError_t launch_select_final(const TrigRec* in, const unsigned long long* n_in, int64_t cap_in,
+                               const float* inv_scale, float thr2_sq, TrigRec* out, int64_t out_cap,
+                               unsigned long long* out_count, int32_t* tmpl_count,
+                               unsigned long long* tmpl_max, int64_t n_bound, hipStream_t s);
 
 // ---------------------------------------------------------------- FP64 complex GEMM
 // C[m][n] (+)= sum_k opA(A)[m][k] * opB(B)[k][n], complex128 accumulation.

@@ -19,14 +19,14 @@ LIB_PATH = os.path.join(_HERE, "librbmf.so")
 RB_OK, RB_ERR_ARG, RB_ERR_OOM, RB_ERR_DEVICE, RB_ERR_CAPACITY, RB_ERR_NUMERIC, RB_ERR_UNSUPPORTED, \
     RB_ERR_CALLBACK = range(8)
 RB_F32, RB_BF16, RB_F16, RB_BF16X3 = 0, 1, 2, 3
-RB_STAGE2_FULL, RB_STAGE2_SPARSE, RB_STAGE2_AUTO = 0, 1, 2
+RB_STAGE2_FULL, RB_STAGE2_SPARSE, RB_STAGE2_AUTO, RB_STAGE2_RECON = 0, 1, 2, 3
 DTYPES = {"f32": RB_F32, "bf16": RB_BF16, "f16": RB_F16, "bf16x3": RB_BF16X3}
 
 FUNCTIONS = ["rb_ctx_create", "rb_ctx_destroy", "rb_last_error", "rb_bank_create", "rb_bank_free",
              "rb_bank_info", "rb_build_basis", "rb_build_basis_range", "rb_basis_info",
              "rb_basis_free", "rb_basis_export", "rb_filter",
              "rb_filter_batch", "mf_full", "rb_rho_at", "rb_backward", "rb_cluster_peaks", "rb_debug_rho",
-             "rb_debug_basis_outputs"]
+             "rb_debug_rho_binned", "rb_debug_basis_outputs"]
 
 
 class Grid(C.Structure):
@@ -43,12 +43,12 @@ class Peak(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("n_stage1", C.c_int64), ("n_refiltered", C.c_int32), ("rank", C.c_int32),
-                ("ms", C.c_float * 8)]
+                ("ms", C.c_float * 8), ("n_bins", C.c_int64)]
 
 
 class FilterOpts(C.Structure):
     _fields_ = [("thr1", C.c_double), ("thr2", C.c_double), ("stage2", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("bin_w", C.c_int32), ("thr_bin", C.c_double)]
 
 
 TRIGGER_NP = np.dtype([("tmpl", np.int32), ("sample", np.int32), ("snr", np.float32),
@@ -98,6 +98,7 @@ def lib():
         L.rb_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, C.POINTER(dbl)]
         L.rb_cluster_peaks.argtypes = [vp, vp, i64, i32, i64, vp]
         L.rb_debug_rho.argtypes = [vp, vp, vp, vp, vp]
+        L.rb_debug_rho_binned.argtypes = [vp, vp, vp, i32, vp]
         L.rb_debug_basis_outputs.argtypes = [vp, vp, vp, vp]
         for f in FUNCTIONS:
             if f != "rb_last_error":
@@ -246,14 +247,15 @@ def subbank_bases(ctx: Context, bank: Bank, bounds, rank=0, tol: float = 1e-3, d
 
 def rb_filter(ctx: Context, bases, bank: Bank, strain, thr1: float, thr2: float,
               stage2: int = RB_STAGE2_FULL, cap: int = 1 << 20, peaks: bool = False,
-              out=None):
-    """bases: one Basis or a list partitioning the bank.  Returns (triggers as a
-    TRIGGER_NP array, or their count when `out` is a device buffer; peaks or
-    None; Stats)."""
+              out=None, bin_w: int = 0, thr_bin: float = 0.0):
+    """bases: one Basis or a list partitioning the bank.  bin_w >= 2 selects the
+    binned first stage with threshold thr_bin on the averaged SNR.  Returns
+    (triggers as a TRIGGER_NP array, or their count when `out` is a device
+    buffer; peaks or None; Stats)."""
     if isinstance(bases, Basis):
         bases = [bases]
     arr = (C.c_void_p * len(bases))(*[b.h.value for b in bases])
-    o = FilterOpts(thr1, thr2, stage2, 0)
+    o = FilterOpts(thr1, thr2, stage2, int(bin_w), float(thr_bin))
     dev = out is not None and not isinstance(out, np.ndarray)
     buf = out if out is not None else _triggers_out(cap, False)
     cap = buf.shape[0]
@@ -329,6 +331,13 @@ def debug_rho(ctx: Context, bank: Bank, strain, basis: Optional[Basis] = None) -
     return rho
 
 
+def debug_rho_binned(ctx: Context, basis: Basis, strain, w: int) -> np.ndarray:
+    """Averaged first-stage series rho_avg (basis.T, N / w) complex64."""
+    rho = np.empty((basis.T, basis.bank.N // w), dtype=np.complex64)
+    _check(lib().rb_debug_rho_binned(ctx.h, basis.h, _ptr(strain), int(w), _ptr(rho)), "rb_debug_rho_binned")
+    return rho
+
+
 def debug_basis_outputs(ctx: Context, basis: Basis, strain) -> np.ndarray:
     """(K, N) complex64; for a bf16x3 basis (2, K, N): high parts, low parts."""
     shape = (2, basis.K, basis.bank.N) if basis.dtype == RB_BF16X3 else (basis.K, basis.bank.N)
@@ -356,7 +365,7 @@ def rb_filter_batch(ctx: Context, items, thr1: float, thr2: float, use_graph: bo
         bp = (C.c_void_p * len(bases))(*[b.h.value for b in bases])
         keep.append(bp)
         arr[i] = BatchItem(_ptr(s), bank.h.value, C.cast(bp, C.POINTER(C.c_void_p)), len(bases))
-    o = FilterOpts(thr1, thr2, stage2, 0)
+    o = FilterOpts(thr1, thr2, stage2, 0, 0.0)
     dev = out is not None and not isinstance(out, np.ndarray)
     buf = out if out is not None else np.empty(max(1, n * cap_item), dtype=TRIGGER_NP)
     counts = (C.c_int64 * n)()

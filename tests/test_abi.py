@@ -62,9 +62,25 @@ def test_error_paths_without_gpu():
     assert L.mf_full(None, None, None, 5.0, None, 0, C.byref(n), None, None) == rbmf.RB_ERR_ARG
 
 
-def test_struct_layouts_match_header():
-    assert C.sizeof(rbmf.Trigger) == 16 and rbmf.TRIGGER_NP.itemsize == 16
-    assert C.sizeof(rbmf.Peak) == 8 and rbmf.PEAK_NP.itemsize == 8
-    assert C.sizeof(rbmf.Grid) == 24
-    assert C.sizeof(rbmf.FilterOpts) == 24
-    assert C.sizeof(rbmf.Stats) == 8 + 4 + 4 + 32
+def test_struct_layouts_match_header(tmp_path):
+    """Every field offset and struct size of the ctypes binding equals what a
+    C compiler makes of include/rbmf.h."""
+    structs = {"rb_trigger": rbmf.Trigger, "rb_peak": rbmf.Peak, "rb_grid": rbmf.Grid,
+               "rb_filter_opts": rbmf.FilterOpts, "rb_stats": rbmf.Stats, "rb_batch_item": rbmf.BatchItem}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rbmf.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                          check=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[f"{cname} size"]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname} {f}"]) == getattr(py, f).offset, (cname, f)
+    assert rbmf.TRIGGER_NP.itemsize == C.sizeof(rbmf.Trigger) and rbmf.PEAK_NP.itemsize == C.sizeof(rbmf.Peak)
