@@ -38,7 +38,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def make_inputs(wl, rbmf, ctx):
+def make_inputs(wl, rbmf, ctx, with_sigma=False):
     from paper_2110_13115_amd import inputs as gi
     t0 = time.time()
     bank_def = wl.bank()
@@ -54,6 +54,8 @@ def make_inputs(wl, rbmf, ctx):
         return s
 
     strain, inj = gi.make_strain(wl, bank_def, sigma_of, dtype=np.float32)
+    if with_sigma:
+        return bank_def, bank, psd, strain, inj, sigma_of
     return bank_def, bank, psd, strain, inj
 
 
@@ -104,6 +106,79 @@ def cpu_baseline(wl, bank_def, psd, strain, budget_s=15.0):
     return {"value": n * wl.seconds / dt, "unit": "template-s/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} of {wl.T} templates of the same segment, full SNR series + threshold, "
                       f"{dt:.1f} s, numpy pocketfft (1 thread)"}
+
+
+def binned_runs(ctx, wl, bank_def, bank, bases_by_dt, sd, out, mf_trig, t_mf, sigma_of, args, torch):
+    """The binned first stage (Sec. III.C) at bin width wl.bin_w: rho_I chosen
+    by the target-SNR rule (Eq. target_snr_criteria, ratio 0.99, final
+    threshold thr2) on an independent noise segment of the same bank, then the
+    RECON and SPARSE second stages timed on the benchmark segment, with the
+    share of the template method's final triggers they keep."""
+    from paper_2110_13115_amd import inputs as gi
+    from paper_2110_13115_amd import rbmf, tuning
+    seg = wl.T * wl.seconds
+    strain_t, _ = gi.make_strain(wl, bank_def, sigma_of, dtype=np.float32, realisation=1)
+    st_dev = torch.from_numpy(strain_t).cuda()
+    thr_bin, table = tuning.tune_bin_threshold(ctx, bases_by_dt["f32"], bank, st_dev, wl.bin_w, wl.thr1, wl.thr2,
+                                               wl.thr_bin_grid)
+    log(f"binned w={wl.bin_w}: rho_I = {thr_bin} from the tuning segment "
+        f"{[(r['thr_bin'], r['target_snr']) for r in table]}")
+    mf_pairs = set(zip(mf_trig["tmpl"].tolist(), mf_trig["sample"].tolist()))
+    res = {"w": wl.bin_w, "thr_bin": thr_bin, "tuning_segment": table}
+    for dt, bs in bases_by_dt.items():
+        for mode, name in ((rbmf.RB_STAGE2_RECON, "recon"), (rbmf.RB_STAGE2_SPARSE, "sparse")):
+            def call():
+                n, _, st = rbmf.rb_filter(ctx, bs, bank, sd, wl.thr1, wl.thr2, stage2=mode, bin_w=wl.bin_w,
+                                          thr_bin=thr_bin, out=out)
+                return n, st
+            t, (n, st) = time_calls(call, args.steps, args.warmup, torch)
+            tr = out[:n].cpu().numpy().view(rbmf.TRIGGER_NP).reshape(-1)
+            kept = sum(1 for a, b in zip(tr["tmpl"].tolist(), tr["sample"].tolist()) if (a, b) in mf_pairs)
+            res[f"{dt}_{name}"] = {"value": seg / t, "ms_per_step": t * 1e3, "rb_over_mf": t_mf / t,
+                                   "kept_of_mf": kept / max(1, len(mf_pairs)), "final": int(n),
+                                   "bins": int(st.n_bins), "candidates": int(st.n_stage1),
+                                   "stage_ms": [round(x, 4) for x in st.ms]}
+            log(f"binned {dt} {name}: {t * 1e3:.2f} ms/step (mf {t_mf * 1e3:.2f}), kept {kept}/{len(mf_pairs)} "
+                f"of the template method's triggers, bins {st.n_bins}, stage ms {[round(x, 3) for x in st.ms]}")
+    return res
+
+
+def paper_regime(args, torch):
+    """The paper's regime: one dense tau0 sub-bank (6250 templates of a
+    200 000-template bank, K ~ 40 at 0.999 energy), 128 s: the template method,
+    the unbinned search and the binned search on the same GPU."""
+    from paper_2110_13115_amd import inputs as gi
+    from paper_2110_13115_amd import rbmf
+    wl = gi.WORKLOADS["rb_128s_6250t_dense"]
+    ctx = rbmf.Context(0)
+    bank_def, bank, psd, strain, inj, sigma_of = make_inputs(wl, rbmf, ctx, with_sigma=True)
+    seg = wl.T * wl.seconds
+    bases = {dt: rbmf.subbank_bases(ctx, bank, wl.bounds(), rank=wl.sub_ranks(), tol=wl.tol, dtype=dt)
+             for dt in ("f32", "bf16")}
+    sd = torch.from_numpy(strain).cuda()
+    out = torch.empty((1 << 21, 4), dtype=torch.int32, device="cuda")
+    t_mf, (n_mf, _, _) = time_calls(lambda: rbmf.mf_full(ctx, bank, sd, wl.thr2, out=out), args.steps,
+                                    args.warmup, torch)
+    mf_trig = out[:n_mf].cpu().numpy().view(rbmf.TRIGGER_NP).reshape(-1).copy()
+    log(f"dense sub-bank: mf_full {t_mf * 1e3:.2f} ms/step, {n_mf} triggers, K = {[b.K for b in bases['f32']]}")
+    t_rb, (n_rb, _, st_rb) = time_calls(
+        lambda: rbmf.rb_filter(ctx, bases["f32"], bank, sd, wl.thr1, wl.thr2, stage2=rbmf.RB_STAGE2_SPARSE,
+                               out=out), args.steps, args.warmup, torch)
+    tr = out[:n_rb].cpu().numpy().view(rbmf.TRIGGER_NP).reshape(-1)
+    same = n_rb == n_mf and np.array_equal(tr[["tmpl", "sample"]], mf_trig[["tmpl", "sample"]])
+    res = {"workload": wl.name, "N": wl.N, "templates": wl.T, "ranks": [b.K for b in bases["f32"]],
+           "mf_full": {"value": seg / t_mf, "ms_per_step": t_mf * 1e3, "triggers": int(n_mf)},
+           "rb_f32_sparse_unbinned": {"value": seg / t_rb, "ms_per_step": t_rb * 1e3,
+                                      "final_triggers_equal_mf": bool(same),
+                                      "stage_ms": [round(x, 4) for x in st_rb.ms[:7]]}}
+    log(f"dense sub-bank: rb_filter f32 unbinned {t_rb * 1e3:.2f} ms/step")
+    res["binned"] = binned_runs(ctx, wl, bank_def, bank, bases, sd, out, mf_trig, t_mf, sigma_of, args, torch)
+    for bs in bases.values():
+        for b in bs:
+            b.close()
+    bank.close()
+    ctx.close()
+    return res
 
 
 def run_batch(args, wname):
@@ -179,6 +254,8 @@ def main():
                     help="time only the headline rb_filter call (for profiler runs)")
     ap.add_argument("--mf-only", action="store_true",
                     help="time only the mf_full comparator (for profiler runs)")
+    ap.add_argument("--no-binned", action="store_true", help="skip the binned first stage runs")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense sub-bank (paper regime) runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device-to-device copy of MIB MiB and exit (scales HBM byte "
                          "counters)")
@@ -209,7 +286,7 @@ def main():
     wl = gi.WORKLOADS[args.workload]
     torch.cuda.init()
     ctx = rbmf.Context(0)
-    bank_def, bank, psd, strain, inj = make_inputs(wl, rbmf, ctx)
+    bank_def, bank, psd, strain, inj, sigma_of = make_inputs(wl, rbmf, ctx, with_sigma=True)
     t0 = time.time()
     bases = rbmf.subbank_bases(ctx, bank, wl.bounds(), rank=wl.sub_ranks(), tol=wl.tol, dtype="f32")
     prep_basis_s = time.time() - t0
@@ -305,6 +382,15 @@ def main():
             log(f"rb_filter {dt}: {t16 * 1e3:.2f} ms/step, gemm {gm:.3f} ms")
             for b in b16:
                 b.close()
+
+    if not args.no_binned:
+        b16 = rbmf.subbank_bases(ctx, bank, wl.bounds(), rank=wl.sub_ranks(), tol=wl.tol, dtype="bf16")
+        extra["binned"] = binned_runs(ctx, wl, bank_def, bank, {"f32": bases, "bf16": b16}, sd, out, mf_trig,
+                                      t_mf, sigma_of, args, torch)
+        for b in b16:
+            b.close()
+    if not args.no_dense:
+        extra["paper_regime"] = paper_regime(args, torch)
 
     gm = float(np.mean(gemm_ms))
     flops = sum(8.0 * b.K * b.T * wl.N for b in bases)

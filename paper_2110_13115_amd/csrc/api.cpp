@@ -456,6 +456,23 @@ rb_status geom_for(rb_ctx ctx, rb_bank bank, FftGeom* out) {
 }
 
 
+// Split for the binned first stage: the pass-2 workgroup rows F should cover
+// a whole bin (F >= w) so that the pass writes the bin means itself; take the
+// tuned split when it does, else the supported split nearest to it that does,
+// else the one with the most rows.  A split forced with RBMF_FFT_SPLIT is kept.
+FftGeom binned_geom(const FftGeom& g, int w) {
+  if (pass2_rows(g.N1) >= w || std::getenv("RBMF_FFT_SPLIT")) return g;
+  for (int n1 = 4096 / w; n1 >= 64; n1 >>= 1) {
+    const FftGeom c = make_geom(g.N, g.log2N - __builtin_ctz((unsigned)n1));
+    if (geom_supported(c)) return c;
+  }
+  for (int n2log = g.log2N; n2log >= 0; --n2log) {
+    const FftGeom c = make_geom(g.N, n2log);
+    if (geom_supported(c)) return c;   // largest N2, smallest N1: most rows
+  }
+  return g;
+}
+
 // strain -> device pointer (copied into ctx scratch if it is a host array)
 rb_status strain_device(rb_ctx ctx, const float* strain, int64_t N, const float** out) {
   RB_CHECK(strain != nullptr, RB_ERR_ARG, "strain is NULL");
@@ -546,8 +563,8 @@ rb_status step_basis_outputs_binned(rb_ctx ctx, rb_basis basis, const FftGeom& g
     for (int p = 0; p < planes; ++p)
       RB_TRY(fill32(ctx, static_cast<char*>(ctx->z.p) + p * plane_bytes + off, 0u, (int64_t)(bytes / 4)));
   }
-  RB_TRY(ctx->zfine.ensure((size_t)2 * K * g.N * 4));
-  RB_TRY(ctx->zpart.ensure((size_t)K * (g.N / G) * 8));
+  RB_TRY(ctx->zfine.ensure((size_t)K * g.N * 8));
+  if (G < w) RB_TRY(ctx->zpart.ensure((size_t)K * (g.N / G) * 8));
   const int B = batch_vectors(g.N, K);
   RB_TRY(ctx->work.ensure((size_t)B * g.N * 8));
   PassArgs a = base_args(bank, g, tw);
@@ -555,15 +572,20 @@ rb_status step_basis_outputs_binned(rb_ctx ctx, rb_basis basis, const FftGeom& g
   a.d = ctx->dspec.as<float2>();
   a.src = basis->P.as<float2>();
   a.work = ctx->work.as<float2>();
-  a.zout = ctx->zfine.as<float>();
-  a.zpart = ctx->zpart.as<float2>();
+  a.zfine = ctx->zfine.as<float2>();
+  a.zout = ctx->z.as<float>();
+  a.zdtype = (int)dt;
+  a.zplane = (int64_t)2 * Kp * Nb;
+  a.zpart = G < w ? ctx->zpart.as<float2>() : nullptr;
   a.bin_g = G;
+  a.bin_w = w;
   for (int v0 = 0; v0 < K; v0 += B) {
     a.vec_base = v0;
     a.nvec = std::min(B, K - v0);
     RB_HIP(launch_pass1(a, IN_CORR, ctx->stream));
     RB_HIP(launch_pass2(a, OUT_ZBIN, ctx->stream));
   }
+  if (G == w) return RB_OK;   // the pass wrote the bin means itself
   BinReduceArgs r;
   std::memset(&r, 0, sizeof(r));
   r.part = ctx->zpart.as<float2>();
@@ -588,7 +610,7 @@ rb_status step_fine(rb_ctx ctx, rb_basis basis, const FftGeom& g, int w, float t
                     const unsigned long long* snap) {
   FineArgs f;
   std::memset(&f, 0, sizeof(f));
-  f.z = ctx->zfine.as<float>();
+  f.z = ctx->zfine.as<float2>();
   f.N = g.N;
   f.N1 = g.N1;
   f.N2 = g.N2;
@@ -1378,6 +1400,7 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
   int64_t sum1[3];
   int64_t nbins = 0;
   const float thr1sq = (float)(opts->thr1 * opts->thr1);
+  const FftGeom gb = w > 1 ? binned_geom(g, w) : g;   // the twiddle tables depend on N only
   if (w > 1) RB_TRY(ctx->snap.ensure((size_t)nbases * 8));
   for (;;) {
     RB_TRY(fill32(ctx, ctx->counters.p, 0u, 2));
@@ -1392,13 +1415,13 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
         if (tm) RB_TRY(event(ctx, 2 + 2 * (size_t)m));
         RB_TRY(stage1_gemm(ctx, bases[m], g, thr1sq, nullptr));
       } else {
-        RB_TRY(step_basis_outputs_binned(ctx, bases[m], g, tw, w));
+        RB_TRY(step_basis_outputs_binned(ctx, bases[m], gb, tw, w));
         if (tm) RB_TRY(event(ctx, 2 + 2 * (size_t)m));
         unsigned long long* snap = ctx->snap.as<unsigned long long>() + m;
         RB_HIP(launch_copy_u64(ctx->counters.as<unsigned long long>() + 2, snap, ctx->stream));
-        RB_TRY(stage1_gemm(ctx, bases[m], g, (float)(opts->thr_bin * opts->thr_bin), nullptr, w));
+        RB_TRY(stage1_gemm(ctx, bases[m], gb, (float)(opts->thr_bin * opts->thr_bin), nullptr, w));
         if (tm) RB_TRY(event(ctx, e_end + 1 + (size_t)m));
-        RB_TRY(step_fine(ctx, bases[m], g, w, thr1sq, snap));
+        RB_TRY(step_fine(ctx, bases[m], gb, w, thr1sq, snap));
       }
       if (tm) RB_TRY(event(ctx, 3 + 2 * (size_t)m));
     }
@@ -1661,10 +1684,11 @@ extern "C" rb_status rb_debug_rho_binned(rb_ctx ctx, rb_basis basis, const float
     dst = ctx->rho_tmp.as<float2>();
   }
   RB_TRY(step_spectrum(ctx, bank, g, tw, s));
-  RB_TRY(step_basis_outputs_binned(ctx, basis, g, tw, w));
+  const FftGeom gb = binned_geom(g, w);
+  RB_TRY(step_basis_outputs_binned(ctx, basis, gb, tw, w));
   RB_TRY(fill32(ctx, ctx->counters.as<unsigned long long>() + 2, 0u, 2));
   RB_TRY(fill32(ctx, ctx->cntB.p, 0u, bank->T));
-  RB_TRY(stage1_gemm(ctx, basis, g, 0.f, dst, w));
+  RB_TRY(stage1_gemm(ctx, basis, gb, 0.f, dst, w));
   if (!dev) RB_HIP(hipMemcpyAsync(rho, dst, (size_t)rows * Nb * 8, hipMemcpyDeviceToHost, ctx->stream));
   RB_HIP(hipStreamSynchronize(ctx->stream));
   return RB_OK;

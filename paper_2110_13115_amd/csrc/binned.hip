@@ -97,11 +97,10 @@ __global__ __launch_bounds__(256) void k_fine_recon(FineArgs a) {
     const float2* c = a.C + (int64_t)j * a.K;
     float re = 0.f, im = 0.f;
     for (int k = s; k < a.K; k += slices) {
-      const float zr = a.z[(2 * (int64_t)k) * a.N + q];
-      const float zi = a.z[(2 * (int64_t)k + 1) * a.N + q];
+      const float2 zk = a.z[(int64_t)k * a.N + q];
       const float2 ck = c[k];
-      re += ck.x * zr - ck.y * zi;
-      im += ck.x * zi + ck.y * zr;
+      re += ck.x * zk.x - ck.y * zk.y;
+      im += ck.x * zk.y + ck.y * zk.x;
     }
     for (int off = w; off < 64; off <<= 1) {
       re += __shfl_xor(re, off);

@@ -531,18 +531,24 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
     });
   } else if constexpr (OUT == OUT_ZBIN) {
     // Binned first stage.  The block holds F consecutive rows (samples
-    // row0 .. row0 + F - 1 of every n1 slice); after the final stage the
-    // outputs go back to LDS and leave as
-    //  (a) FP32 Z with each slice's F samples adjacent: q = row0 L + n1 F + f,
-    //      so that the fine reconstruction of a bin reads whole runs;
-    //  (b) sums over G = min(F, w) consecutive samples, [N2 / G][L] complex64,
-    //      summed in a fixed order (f ascending).
+    // row0 .. row0 + F - 1 of every n1 slice).  After the final stage the
+    // outputs go back to LDS as X[e], e = n1 F + f (one pad slot every 32
+    // elements keeps both the row-wise stores and the e-wise loads free of
+    // bank conflicts) and leave as
+    //  (a) complex64 Z with each slice's F samples adjacent,
+    //      q = row0 L + n1 F + f, so that the fine reconstruction of a bin
+    //      reads whole runs;
+    //  (b) sums over G = min(F, w) consecutive samples in a fixed order
+    //      (f ascending): the bin means themselves when G = w (planar, in the
+    //      reconstruction dtype, [N2 / w][L] per plane), else partial sums
+    //      ([N2 / G][L] complex64) that k_bin_reduce completes.
     constexpr int F = Lay::NF;
     constexpr int NBF = F * L / RL;
     constexpr int PERF = (NBF + NT - 1) / NT;
     V keep[PERF * RL];
     final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int, int, V val, int idx) { keep[idx] = val; });
     __syncthreads();
+    auto xa = [](int e) { return e + (e >> 5); };
 #pragma unroll
     for (int i = 0; i < PERF; ++i) {
       const int b = tid + i * NT;
@@ -550,29 +556,61 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
         int f, j;
         Lay::template split<RL>(b, f, j);
 #pragma unroll
-        for (int m = 0; m < RL; ++m) lds[Lay::addr(f, j + m * (L / RL))] = keep[i * RL + m];
+        for (int m = 0; m < RL; ++m) lds[xa((j + m * (L / RL)) * F + f)] = keep[i * RL + m];
       }
     }
     __syncthreads();
-    float* __restrict__ zr = a.zout + (int64_t)(2 * v) * N + (int64_t)row0 * L;
-    float* __restrict__ zi = zr + N;
-    for (int e = tid; e < F * L; e += NT) {
-      const V x = lds[Lay::addr(e % F, e / F)];
-      zr[e] = x.x;
-      zi[e] = x.y;
-    }
+    float2* __restrict__ zf = a.zfine + (int64_t)v * N + (int64_t)row0 * L;
+    for (int e = tid; e < F * L; e += NT) zf[e] = lds[xa(e)];
     const int G = a.bin_g;            // power of two dividing F
     const int ng = F / G;
-    float2* __restrict__ part = a.zpart + (int64_t)v * (N / G) + (int64_t)(row0 / G) * L;
-    for (int o = tid; o < ng * L; o += NT) {
-      const int n1 = o % L, gi = o / L;
-      float sr = 0.f, si = 0.f;
-      for (int f = 0; f < G; ++f) {
-        const V x = lds[Lay::addr(gi * G + f, n1)];
-        sr += x.x;
-        si += x.y;
+    const int64_t r0 = row0 / G;
+    if (G == a.bin_w) {
+      const int64_t Nb = N / G;
+      const float sc = a.zscale / (float)G;   // G is a power of two: exact
+      for (int o = tid; o < ng * L; o += NT) {
+        const int n1 = o % L, gi = o / L;
+        float sr = 0.f, si = 0.f;
+        for (int f = 0; f < G; ++f) {
+          const V x = lds[xa(n1 * F + gi * G + f)];
+          sr += x.x;
+          si += x.y;
+        }
+        const int64_t ob = (r0 + gi) * L + n1;
+        const float xr = sr * sc, xi = si * sc;
+        if (a.zdtype == 0) {
+          a.zout[(int64_t)(2 * v) * Nb + ob] = xr;
+          a.zout[(int64_t)(2 * v + 1) * Nb + ob] = xi;
+        } else {
+          uint16_t* zr = reinterpret_cast<uint16_t*>(a.zout) + (int64_t)(2 * v) * Nb + ob;
+          uint16_t* zi = zr + Nb;
+          if (a.zdtype == 3) {
+            const uint16_t hr = f32_to_bf16_rne(xr), hi = f32_to_bf16_rne(xi);
+            zr[0] = hr;
+            zi[0] = hi;
+            zr[a.zplane] = f32_to_bf16_rne(xr - __uint_as_float((uint32_t)hr << 16));
+            zi[a.zplane] = f32_to_bf16_rne(xi - __uint_as_float((uint32_t)hi << 16));
+          } else if (a.zdtype == 1) {
+            zr[0] = f32_to_bf16_rne(xr);
+            zi[0] = f32_to_bf16_rne(xi);
+          } else {
+            zr[0] = f32_to_f16_rne(xr);
+            zi[0] = f32_to_f16_rne(xi);
+          }
+        }
       }
-      part[(int64_t)gi * L + n1] = make_float2(sr, si);
+    } else {
+      float2* __restrict__ part = a.zpart + (int64_t)v * (N / G) + r0 * L;
+      for (int o = tid; o < ng * L; o += NT) {
+        const int n1 = o % L, gi = o / L;
+        float sr = 0.f, si = 0.f;
+        for (int f = 0; f < G; ++f) {
+          const V x = lds[xa(n1 * F + gi * G + f)];
+          sr += x.x;
+          si += x.y;
+        }
+        part[(int64_t)gi * L + n1] = make_float2(sr, si);
+      }
     }
   } else if constexpr (OUT == OUT_TRANSPOSED) {
     float2* __restrict__ o = a.cout + (int64_t)v * N;

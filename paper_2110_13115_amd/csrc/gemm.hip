@@ -51,16 +51,34 @@ __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[
           const float s = a.row_inv ? a.row_inv[j] : 1.f;
           a.rho_out[(int64_t)j * a.N + n] = make_float2(re * s, im * s);
         }
-        if (j < a.T && p >= a.thr2_row[j]) {   // rare: per-lane append
-          atomicAdd(&a.tmpl_count[j], 1);
-          const unsigned long long idx = atomicAdd(a.trig_count, 1ull);
-          if ((int64_t)idx < a.trig_cap) {
-            TrigRec t;
-            t.tmpl = a.tmpl_base + j;
-            t.sample = n;
-            t.re = re;
-            t.im = im;
-            a.trig[idx] = t;
+        // Crossings are appended per wave: one counter atomic for the wave
+        // and one per template row (lanes 0-31 and 32-63 each hold one row
+        // of this 16-element step), slots by the prefix count of the ballot.
+        const bool hit = j < a.T && p >= a.thr2_row[j];
+        const unsigned long long mask = __ballot(hit);
+        if (mask != 0ull) {
+          const int leader = __ffsll((long long)mask) - 1;
+          unsigned base_lo = 0, base_hi = 0;
+          if (lane == leader) {
+            const unsigned long long b = atomicAdd(a.trig_count, (unsigned long long)__popcll(mask));
+            base_lo = (unsigned)b;
+            base_hi = (unsigned)(b >> 32);
+          }
+          base_lo = (unsigned)__builtin_amdgcn_readlane((int)base_lo, leader);
+          base_hi = (unsigned)__builtin_amdgcn_readlane((int)base_hi, leader);
+          const unsigned half = (unsigned)(mask >> (lane & 32));
+          if ((lane & 31) == 0 && half != 0u) atomicAdd(&a.tmpl_count[j], __popc(half));
+          if (hit) {
+            const unsigned long long idx = (((unsigned long long)base_hi << 32) | base_lo) +
+                                           (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
+            if ((int64_t)idx < a.trig_cap) {
+              TrigRec t;
+              t.tmpl = a.tmpl_base + j;
+              t.sample = n;
+              t.re = re;
+              t.im = im;
+              a.trig[idx] = t;
+            }
           }
         }
       }

@@ -57,10 +57,12 @@ enum OutKind {
   OUT_NATURAL = 3,   // complex64 natural order out[v][n]
   OUT_SPECTRUM = 4,  // forward transform of the strain: d[k - kb] = wd[k] X[k], band only
   OUT_TRANSPOSED = 5, // complex64 in the pass order out[v][q] (adjoint)
-  OUT_ZBIN = 6       // binned first stage: planar FP32 Z with each pass-2 block's F rows
-                     // adjacent per n1 (q = row0 N1 + n1 F + f, F = 4096 / N1 rows per
-                     // block, at least 1), plus sums over bin_g consecutive samples in zpart
-                     // ([N2 / bin_g][N1] complex64 per vector)
+  OUT_ZBIN = 6       // binned first stage: complex64 Z in zfine with each pass-2 block's F
+                     // rows adjacent per n1 (q = row0 N1 + n1 F + f, F = pass2_rows(N1)),
+                     // plus sums over bin_g = min(F, bin_w) consecutive samples: the bin
+                     // means in zout (planar, zdtype, plane stride N / bin_w) when
+                     // bin_g == bin_w, else partial sums in zpart ([N2 / bin_g][N1]
+                     // complex64 per vector)
 };
 
 struct TrigRec {     // device trigger record before sorting
@@ -103,8 +105,10 @@ struct PassArgs {
   unsigned long long* trig_count;
   int32_t* tmpl_count;       // per template crossing counts
   unsigned long long* tmpl_max;  // per template packed (|x|^2 bits << 32 | ~n)
+  float2* zfine;             // OUT_ZBIN: complex64 Z, N per vector
   float2* zpart;             // OUT_ZBIN: partial bin sums, N / bin_g per vector
-  int bin_g;                 // OUT_ZBIN: samples per partial sum, min(F, w)
+  int bin_g;                 // OUT_ZBIN: samples per partial sum, min(F, bin_w)
+  int bin_w;                 // OUT_ZBIN: samples per bin
   float2* cout;              // OUT_NATURAL / OUT_SPECTRUM / OUT_TRANSPOSED
   int32_t k_lo;              // OUT_SPECTRUM band
   int32_t k_hi;
@@ -207,7 +211,7 @@ hipError_t launch_bin_reduce(const BinReduceArgs& a, hipStream_t s);
 hipError_t launch_copy_u64(const unsigned long long* src, unsigned long long* dst, hipStream_t s);
 
 struct FineArgs {
-  const float* z;            // OUT_ZBIN FP32 Z, planes 2k / 2k+1 of stride N
+  const float2* z;           // OUT_ZBIN complex64 Z, row k of stride N
   int64_t N;
   int N1, N2, F;             // FFT split; F = pass2_rows(N1)
   int K, w;

@@ -43,8 +43,9 @@ EULER_GAMMA = 0.5772156649015329
 PURPOSE_BANK, PURPOSE_NOISE, PURPOSE_INJ, PURPOSE_FD, PURPOSE_LEN = 0, 1, 2, 3, 4
 
 
-def rng_for(cfg: int, purpose: int) -> np.random.Generator:
-    return np.random.default_rng([13115, int(cfg), int(purpose)])
+def rng_for(cfg: int, purpose: int, realisation: int = 0) -> np.random.Generator:
+    key = [13115, int(cfg), int(purpose)] + ([int(realisation)] if realisation else [])
+    return np.random.default_rng(key)
 
 
 # --------------------------------------------------------------------------
@@ -320,8 +321,9 @@ class Injection:
 
 
 def draw_injections(cfg: int, count: int, snrs: Sequence[float], T: int, N: int,
-                    on_bank: bool = True, mrange: Tuple[float, float] = (1.0, 3.0)) -> List[Injection]:
-    rng = rng_for(cfg, PURPOSE_INJ)
+                    on_bank: bool = True, mrange: Tuple[float, float] = (1.0, 3.0),
+                    realisation: int = 0) -> List[Injection]:
+    rng = rng_for(cfg, PURPOSE_INJ, realisation)
     out = []
     for i in range(count):
         tmpl = int(rng.integers(0, T)) if on_bank else -1
@@ -355,6 +357,8 @@ class Workload:
     subbanks: int = 1              # equal tau0-ordered sub-banks, one basis each
     ranks: Tuple[int, ...] = ()    # fixed rank per sub-bank (empty: by energy / `rank`)
     parent: int = 0                # > T: the bank is the central tau0 slice of a parent bank
+    bin_w: int = 4                 # binned first stage: samples per bin
+    thr_bin_grid: Tuple[float, ...] = (3.0, 3.25, 3.5, 3.75, 4.0)   # rho_I values tried
 
     @property
     def seconds(self) -> float:
@@ -452,20 +456,22 @@ BATCH_WORKLOADS = {
 
 
 def make_strain(wl: Workload, bank: Bank, sigma_of, injections: Optional[List[Injection]] = None,
-                noise: bool = True, dtype=np.float32) -> Tuple[np.ndarray, List[Injection]]:
+                noise: bool = True, dtype=np.float32, realisation: int = 0) -> Tuple[np.ndarray, List[Injection]]:
     """Coloured noise plus injections for workload `wl`.
 
     `sigma_of(h)` must return the optimal-SNR normalisation of a waveform h on
     the full rfft grid; the caller supplies it (the oracle in tests, the
     library's own FP64 sigma in the benchmark), so that this module stays free
-    of the search's arithmetic."""
+    of the search's arithmetic.  realisation > 0 draws an independent noise
+    segment and injection set for the same bank (seeds [13115, cfg,
+    purpose, realisation])."""
     N, fs = wl.N, wl.fs
     psd = psd_on_grid(N, fs)
-    st = coloured_noise_tilde(psd, N, fs, rng_for(wl.cfg, PURPOSE_NOISE)) if noise else \
+    st = coloured_noise_tilde(psd, N, fs, rng_for(wl.cfg, PURPOSE_NOISE, realisation)) if noise else \
         np.zeros(N // 2 + 1, dtype=np.complex128)
     if injections is None:
         injections = draw_injections(wl.cfg, len(wl.inj_snrs), wl.inj_snrs, bank.T, N, wl.on_bank,
-                                     (bank.m1.min(), bank.m1.max()) if bank.T else (1.0, 3.0))
+                                     (bank.m1.min(), bank.m1.max()) if bank.T else (1.0, 3.0), realisation)
     f = np.arange(N // 2 + 1, dtype=np.float64) * (fs / N)
     for inj in injections:
         if inj.template >= 0:
