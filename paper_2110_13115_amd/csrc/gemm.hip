@@ -35,50 +35,72 @@ __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[
                                          int64_t q0) {
   const int lane = __lane_id();
   const int l1 = __builtin_ctz((unsigned)a.N1);            // N1 is a power of two
+  if (a.rho_out != nullptr) {   // debug dump (thresholds are infinite then: nothing is appended)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const int q = (int)q0 + cb * 32 + (lane & 31);      // q < N < 2^31
+        const int n = (q >> l1) + a.N2 * (q & (a.N1 - 1));
+#pragma unroll
+        for (int i = 0; i < 16; i += 2) {
+          const int m = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);   // even: Re row
+          const int j = (rb0 + rb) * 16 + (m >> 1);
+          if (j < a.T) {
+            const float s = a.row_inv ? a.row_inv[j] : 1.f;
+            a.rho_out[(int64_t)j * a.N + n] = make_float2(acc[rb][cb][i] * s, acc[rb][cb][i + 1] * s);
+          }
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      const int q = (int)q0 + cb * 32 + (lane & 31);        // q < N < 2^31
-      const int n = (q >> l1) + a.N2 * (q & (a.N1 - 1));
+    for (int i = 0; i < 16; i += 2) {
+      // one template row per half-wave at this step; its threshold (padded
+      // rows have C = 0, so |rho|^2 = 0 never reaches a positive threshold)
+      const int m = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+      const int j = (rb0 + rb) * 16 + (m >> 1);
+      const float thr = a.thr2_row[j];
+      float pmax = 0.f;
 #pragma unroll
-      for (int i = 0; i < 16; i += 2) {
-        const int m = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);   // even: Re row
-        const int j = (rb0 + rb) * 16 + (m >> 1);
+      for (int cb = 0; cb < CB; ++cb) {
         const float re = acc[rb][cb][i], im = acc[rb][cb][i + 1];
-        const float p = re * re + im * im;
-        if (a.rho_out != nullptr && j < a.T) {
-          const float s = a.row_inv ? a.row_inv[j] : 1.f;
-          a.rho_out[(int64_t)j * a.N + n] = make_float2(re * s, im * s);
-        }
+        pmax = fmaxf(pmax, re * re + im * im);
+      }
+      if (__ballot(pmax >= thr) == 0ull) continue;   // the common case: no crossing in the step
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const float re = acc[rb][cb][i], im = acc[rb][cb][i + 1];
         // Crossings are appended per wave: one counter atomic for the wave
         // and one per template row (lanes 0-31 and 32-63 each hold one row
-        // of this 16-element step), slots by the prefix count of the ballot.
-        const bool hit = j < a.T && p >= a.thr2_row[j];
+        // of this step), slots by the prefix count of the ballot.
+        const bool hit = j < a.T && re * re + im * im >= thr;
         const unsigned long long mask = __ballot(hit);
-        if (mask != 0ull) {
-          const int leader = __ffsll((long long)mask) - 1;
-          unsigned base_lo = 0, base_hi = 0;
-          if (lane == leader) {
-            const unsigned long long b = atomicAdd(a.trig_count, (unsigned long long)__popcll(mask));
-            base_lo = (unsigned)b;
-            base_hi = (unsigned)(b >> 32);
-          }
-          base_lo = (unsigned)__builtin_amdgcn_readlane((int)base_lo, leader);
-          base_hi = (unsigned)__builtin_amdgcn_readlane((int)base_hi, leader);
-          const unsigned half = (unsigned)(mask >> (lane & 32));
-          if ((lane & 31) == 0 && half != 0u) atomicAdd(&a.tmpl_count[j], __popc(half));
-          if (hit) {
-            const unsigned long long idx = (((unsigned long long)base_hi << 32) | base_lo) +
-                                           (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
-            if ((int64_t)idx < a.trig_cap) {
-              TrigRec t;
-              t.tmpl = a.tmpl_base + j;
-              t.sample = n;
-              t.re = re;
-              t.im = im;
-              a.trig[idx] = t;
-            }
+        if (mask == 0ull) continue;
+        const int leader = __ffsll((long long)mask) - 1;
+        unsigned base_lo = 0, base_hi = 0;
+        if (lane == leader) {
+          const unsigned long long b = atomicAdd(a.trig_count, (unsigned long long)__popcll(mask));
+          base_lo = (unsigned)b;
+          base_hi = (unsigned)(b >> 32);
+        }
+        base_lo = (unsigned)__builtin_amdgcn_readlane((int)base_lo, leader);
+        base_hi = (unsigned)__builtin_amdgcn_readlane((int)base_hi, leader);
+        const unsigned half = (unsigned)(mask >> (lane & 32));
+        if ((lane & 31) == 0 && half != 0u) atomicAdd(&a.tmpl_count[j], __popc(half));
+        if (hit) {
+          const unsigned long long idx = (((unsigned long long)base_hi << 32) | base_lo) +
+                                         (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
+          if ((int64_t)idx < a.trig_cap) {
+            const int q = (int)q0 + cb * 32 + (lane & 31);
+            TrigRec t;
+            t.tmpl = a.tmpl_base + j;
+            t.sample = (q >> l1) + a.N2 * (q & (a.N1 - 1));
+            t.re = re;
+            t.im = im;
+            a.trig[idx] = t;
           }
         }
       }
