@@ -563,7 +563,9 @@ rb_status step_basis_outputs_binned(rb_ctx ctx, rb_basis basis, const FftGeom& g
     for (int p = 0; p < planes; ++p)
       RB_TRY(fill32(ctx, static_cast<char*>(ctx->z.p) + p * plane_bytes + off, 0u, (int64_t)(bytes / 4)));
   }
-  RB_TRY(ctx->zfine.ensure((size_t)K * g.N * 8));
+  // the fine reconstruction reads Z in the basis's storage precision (FP32 for split BF16)
+  const int z16 = dt == RB_BF16 ? 1 : dt == RB_F16 ? 2 : 0;
+  RB_TRY(ctx->zfine.ensure((size_t)K * g.N * (z16 ? 4 : 8)));
   if (G < w) RB_TRY(ctx->zpart.ensure((size_t)K * (g.N / G) * 8));
   const int B = batch_vectors(g.N, K);
   RB_TRY(ctx->work.ensure((size_t)B * g.N * 8));
@@ -572,7 +574,8 @@ rb_status step_basis_outputs_binned(rb_ctx ctx, rb_basis basis, const FftGeom& g
   a.d = ctx->dspec.as<float2>();
   a.src = basis->P.as<float2>();
   a.work = ctx->work.as<float2>();
-  a.zfine = ctx->zfine.as<float2>();
+  a.zfine = ctx->zfine.p;
+  a.zfine16 = z16;
   a.zout = ctx->z.as<float>();
   a.zdtype = (int)dt;
   a.zplane = (int64_t)2 * Kp * Nb;
@@ -610,7 +613,8 @@ rb_status step_fine(rb_ctx ctx, rb_basis basis, const FftGeom& g, int w, float t
                     const unsigned long long* snap) {
   FineArgs f;
   std::memset(&f, 0, sizeof(f));
-  f.z = ctx->zfine.as<float2>();
+  f.z = ctx->zfine.p;
+  f.z16 = basis->dtype == RB_BF16 ? 1 : basis->dtype == RB_F16 ? 2 : 0;
   f.N = g.N;
   f.N1 = g.N1;
   f.N2 = g.N2;

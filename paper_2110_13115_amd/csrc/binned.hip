@@ -72,13 +72,34 @@ __global__ void k_copy_u64(const unsigned long long* src, unsigned long long* ds
   if (threadIdx.x == 0) *dst = *src;
 }
 
+template <int Z16>
+__device__ __forceinline__ float2 fine_z(const void* z, int64_t idx) {
+  if constexpr (Z16 == 0) {
+    return static_cast<const float2*>(z)[idx];
+  } else {
+    const uint32_t u = static_cast<const uint32_t*>(z)[idx];
+    if constexpr (Z16 == 1) return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
+    __half_raw lo, hi;
+    lo.x = (unsigned short)(u & 0xffffu);
+    hi.x = (unsigned short)(u >> 16);
+    return make_float2(__half2float(__half(lo)), __half2float(__half(hi)));
+  }
+}
+
+constexpr int FINE_WAVES = 4;     // waves per workgroup
+constexpr int FINE_STAGE = 128;   // candidate records staged per wave before one counter atomic
+
 // One wave per triggering (template, bin) record: rho_RB at the w samples of
-// the bin (Eq. Beta_eqn with C = conj(c), FP32), the w lanes of sample r each
-// summing every (64/w)-th basis vector, then a butterfly over the slices.
-// Samples with |rho_RB|^2 >= thr_sq are appended as candidates.
-__global__ __launch_bounds__(256) void k_fine_recon(FineArgs a) {
+// the bin (Eq. Beta_eqn with C = conj(c), FP32 accumulation), the w lanes of
+// sample r each summing every (64/w)-th basis vector, then a butterfly over
+// the slices.  Samples with |rho_RB|^2 >= thr_sq are candidates: one count
+// atomic per (template, bin), staged per wave in LDS and appended with one
+// counter atomic per FINE_STAGE records.
+template <int Z16>
+__global__ __launch_bounds__(FINE_WAVES * 64) void k_fine_recon(FineArgs a) {
+  __shared__ TrigRec stage[FINE_WAVES][FINE_STAGE];
   const int lane = threadIdx.x & 63;
-  const int wpb = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6;
   const int w = a.w;
   const int r = lane & (w - 1);
   const int slices = 64 / w;
@@ -86,8 +107,24 @@ __global__ __launch_bounds__(256) void k_fine_recon(FineArgs a) {
   const int64_t end = (int64_t)min(*a.end, (unsigned long long)a.bins_cap);
   const int64_t begin = (int64_t)*a.begin;
   const int l2 = __builtin_ctz((unsigned)a.N2);
-  for (int64_t i = begin + (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); i < end;
-       i += (int64_t)gridDim.x * wpb) {
+  int nst = 0;   // staged records of this wave (wave-uniform)
+  auto flush = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    unsigned lo = 0, hi = 0;
+    if (lane == 0) {
+      const unsigned long long b = atomicAdd(a.out_count, (unsigned long long)nst);
+      lo = (unsigned)b;
+      hi = (unsigned)(b >> 32);
+    }
+    const unsigned long long base = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)hi) << 32) |
+                                    (unsigned)__builtin_amdgcn_readfirstlane((int)lo);
+    for (int t = lane; t < nst; t += 64)
+      if ((int64_t)(base + t) < a.out_cap) a.out[base + t] = stage[wave][t];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    nst = 0;
+  };
+  for (int64_t i = begin + (int64_t)blockIdx.x * FINE_WAVES + wave; i < end;
+       i += (int64_t)gridDim.x * FINE_WAVES) {
     const TrigRec b = a.bins[i];
     const int j = b.tmpl - a.t0;
     const int64_t n = (int64_t)b.sample * w + r;
@@ -97,7 +134,7 @@ __global__ __launch_bounds__(256) void k_fine_recon(FineArgs a) {
     const float2* c = a.C + (int64_t)j * a.K;
     float re = 0.f, im = 0.f;
     for (int k = s; k < a.K; k += slices) {
-      const float2 zk = a.z[(int64_t)k * a.N + q];
+      const float2 zk = fine_z<Z16>(a.z, (int64_t)k * a.N + q);
       const float2 ck = c[k];
       re += ck.x * zk.x - ck.y * zk.y;
       im += ck.x * zk.y + ck.y * zk.x;
@@ -106,22 +143,23 @@ __global__ __launch_bounds__(256) void k_fine_recon(FineArgs a) {
       re += __shfl_xor(re, off);
       im += __shfl_xor(im, off);
     }
-    if (lane < w) {
-      const float p = re * re + im * im;
-      if (p >= a.thr_sq) {
-        atomicAdd(&a.tmpl_count[b.tmpl], 1);
-        const unsigned long long idx = atomicAdd(a.out_count, 1ull);
-        if ((int64_t)idx < a.out_cap) {
-          TrigRec t;
-          t.tmpl = b.tmpl;
-          t.sample = (int32_t)n;
-          t.re = re;
-          t.im = im;
-          a.out[idx] = t;
-        }
-      }
+    const bool hit = lane < w && re * re + im * im >= a.thr_sq;
+    const unsigned long long mask = __ballot(hit);
+    if (mask == 0ull) continue;
+    const int cnt = __popcll(mask);
+    if (lane == 0) atomicAdd(&a.tmpl_count[b.tmpl], cnt);
+    if (nst + cnt > FINE_STAGE) flush();
+    if (hit) {
+      TrigRec t;
+      t.tmpl = b.tmpl;
+      t.sample = (int32_t)n;
+      t.re = re;
+      t.im = im;
+      stage[wave][nst + __popcll(mask & ((1ull << lane) - 1ull))] = t;
     }
+    nst += cnt;
   }
+  if (nst > 0) flush();
 }
 
 // Second stage = the reconstruction: candidates whose |rho|^2 (values times
@@ -167,7 +205,11 @@ hipError_t launch_copy_u64(const unsigned long long* src, unsigned long long* ds
 }
 
 hipError_t launch_fine_recon(const FineArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_fine_recon, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, a);
+  const dim3 g(grid > 0 ? grid : 1), b(FINE_WAVES * 64);
+  if (a.w < 1 || a.w > 64 || (a.w & (a.w - 1)) != 0) return hipErrorInvalidValue;
+  if (a.z16 == 1) hipLaunchKernelGGL(k_fine_recon<1>, g, b, 0, s, a);
+  else if (a.z16 == 2) hipLaunchKernelGGL(k_fine_recon<2>, g, b, 0, s, a);
+  else hipLaunchKernelGGL(k_fine_recon<0>, g, b, 0, s, a);
   return hipGetLastError();
 }
 

@@ -560,8 +560,19 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
       }
     }
     __syncthreads();
-    float2* __restrict__ zf = a.zfine + (int64_t)v * N + (int64_t)row0 * L;
-    for (int e = tid; e < F * L; e += NT) zf[e] = lds[xa(e)];
+    if (a.zfine16 == 0) {
+      float2* __restrict__ zf = static_cast<float2*>(a.zfine) + (int64_t)v * N + (int64_t)row0 * L;
+      for (int e = tid; e < F * L; e += NT) zf[e] = lds[xa(e)];
+    } else {   // 16-bit (Re, Im) pairs: bf16 (1) or f16 (2)
+      uint32_t* __restrict__ zf = static_cast<uint32_t*>(a.zfine) + (int64_t)v * N + (int64_t)row0 * L;
+      const bool bf = a.zfine16 == 1;
+      for (int e = tid; e < F * L; e += NT) {
+        const V x = lds[xa(e)];
+        const uint32_t lo = bf ? f32_to_bf16_rne(x.x) : f32_to_f16_rne(x.x);
+        const uint32_t hi = bf ? f32_to_bf16_rne(x.y) : f32_to_f16_rne(x.y);
+        zf[e] = lo | (hi << 16);
+      }
+    }
     const int G = a.bin_g;            // power of two dividing F
     const int ng = F / G;
     const int64_t r0 = row0 / G;

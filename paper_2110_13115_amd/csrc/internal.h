@@ -57,7 +57,7 @@ enum OutKind {
   OUT_NATURAL = 3,   // complex64 natural order out[v][n]
   OUT_SPECTRUM = 4,  // forward transform of the strain: d[k - kb] = wd[k] X[k], band only
   OUT_TRANSPOSED = 5, // complex64 in the pass order out[v][q] (adjoint)
-  OUT_ZBIN = 6       // binned first stage: complex64 Z in zfine with each pass-2 block's F
+  OUT_ZBIN = 6       // binned first stage: Z in zfine (complex64 or 16-bit pairs) with each pass-2 block's F
                      // rows adjacent per n1 (q = row0 N1 + n1 F + f, F = pass2_rows(N1)),
                      // plus sums over bin_g = min(F, bin_w) consecutive samples: the bin
                      // means in zout (planar, zdtype, plane stride N / bin_w) when
@@ -105,7 +105,8 @@ struct PassArgs {
   unsigned long long* trig_count;
   int32_t* tmpl_count;       // per template crossing counts
   unsigned long long* tmpl_max;  // per template packed (|x|^2 bits << 32 | ~n)
-  float2* zfine;             // OUT_ZBIN: complex64 Z, N per vector
+  void* zfine;               // OUT_ZBIN: Z for the fine reconstruction, N per vector:
+  int zfine16;               //   complex64 (0) or 16-bit (Re, Im) pairs, bf16 (1) / f16 (2)
   float2* zpart;             // OUT_ZBIN: partial bin sums, N / bin_g per vector
   int bin_g;                 // OUT_ZBIN: samples per partial sum, min(F, bin_w)
   int bin_w;                 // OUT_ZBIN: samples per bin
@@ -211,7 +212,8 @@ hipError_t launch_bin_reduce(const BinReduceArgs& a, hipStream_t s);
 hipError_t launch_copy_u64(const unsigned long long* src, unsigned long long* dst, hipStream_t s);
 
 struct FineArgs {
-  const float2* z;           // OUT_ZBIN complex64 Z, row k of stride N
+  const void* z;             // OUT_ZBIN Z, row k of stride N: complex64, or 16-bit pairs
+  int z16;                   //   0 complex64, 1 bf16 pairs, 2 f16 pairs
   int64_t N;
   int N1, N2, F;             // FFT split; F = pass2_rows(N1)
   int K, w;

@@ -217,3 +217,40 @@ def test_binned_subbanks_partition(ctx, bcase):
     check_sets(got, definite, possible, a_rb)
     for b in subs:
         b.close()
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16", "bf16x3"])
+def test_binned_16bit_storage(ctx, bcase, dtype):
+    """Binned first stage on 16-bit storage: the averaged series within the
+    rounding of its operands, and the RECON finals (fine reconstruction from
+    Z in the basis's storage precision, FP32 accumulation) against the FP64
+    reconstruction with a band and tolerance of that precision."""
+    case, bank, basis, beta, c = bcase
+    tol = {"bf16": 3e-2, "f16": 4e-3, "bf16x3": 1e-4}[dtype]
+    b16 = rbmf.Basis(ctx, bank, rank=0, tol=1e-3, dtype=dtype)
+    assert b16.K == basis.K
+    w, thr_bin, thr1, thr2 = 8, 3.0, 4.5, 5.5
+    got_avg = rbmf.debug_rho_binned(ctx, b16, case.strain, w)
+    ref_avg = oh.averaged_snr(beta, c, w)
+    err = (np.abs(got_avg - ref_avg) / np.maximum(np.abs(ref_avg), 1.0)).max()
+    log(dtype, "rho_avg max err", err)
+    assert err <= tol
+    got, _, st = rbmf.rb_filter(ctx, b16, bank, case.strain, thr1, thr2, stage2=rbmf.RB_STAGE2_RECON,
+                                bin_w=w, thr_bin=thr_bin)
+    a_avg = np.abs(ref_avg)
+    a_rb = np.abs(ob.rb_snr(beta, c))
+    band = lambda x, t: np.abs(x / t - 1) <= tol
+    on = np.repeat(a_avg >= thr_bin, w, axis=1)
+    amb = np.repeat(band(a_avg, thr_bin), w, axis=1)
+    sure = on & ~amb & (a_rb >= thr1) & ~band(a_rb, thr1)
+    maybe = (on | amb) & (a_rb >= thr1 * (1 - tol)) & ~sure
+    definite = sure & (a_rb >= thr2) & ~band(a_rb, thr2)
+    possible = (sure | maybe) & (a_rb >= thr2 * (1 - tol))
+    G = np.zeros_like(definite)
+    G[got["tmpl"], got["sample"]] = True
+    log(dtype, "final", len(got), "oracle", int(definite.sum()))
+    assert definite.sum() > 10
+    assert not (definite & ~G).any() and not (G & ~possible).any()
+    rel = np.abs(got["snr"] - a_rb[got["tmpl"], got["sample"]]) / a_rb[got["tmpl"], got["sample"]]
+    assert rel.max() <= tol
+    b16.close()
