@@ -255,6 +255,9 @@ def main():
     ap.add_argument("--mf-only", action="store_true",
                     help="time only the mf_full comparator (for profiler runs)")
     ap.add_argument("--no-binned", action="store_true", help="skip the binned first stage runs")
+    ap.add_argument("--binned-only", action="store_true",
+                    help="time only the binned search (RECON, FP32 and BF16) at --thr-bin (for profiler runs)")
+    ap.add_argument("--thr-bin", type=float, default=4.0, help="rho_I of --binned-only")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense sub-bank (paper regime) runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device-to-device copy of MIB MiB and exit (scales HBM byte "
@@ -301,6 +304,21 @@ def main():
 
     def mf_step():
         return rbmf.mf_full(ctx, bank, sd, wl.thr2, out=out)
+
+    if args.binned_only:
+        res = {}
+        for dt in ("f32", "bf16"):
+            bs = bases if dt == "f32" else rbmf.subbank_bases(ctx, bank, wl.bounds(), rank=wl.sub_ranks(),
+                                                              tol=wl.tol, dtype=dt)
+            def call():
+                n, _, st = rbmf.rb_filter(ctx, bs, bank, sd, wl.thr1, wl.thr2, stage2=rbmf.RB_STAGE2_RECON,
+                                          bin_w=wl.bin_w, thr_bin=args.thr_bin, out=out)
+                return n, st
+            t, (n, st) = time_calls(call, args.steps, args.warmup, torch)
+            res[dt] = {"ms_per_step": t * 1e3, "final": int(n), "bins": int(st.n_bins),
+                       "stage_ms": [round(x, 4) for x in st.ms]}
+        print(json.dumps({"workload": wl.name, "w": wl.bin_w, "thr_bin": args.thr_bin, **res}), flush=True)
+        return
 
     if args.mf_only:
         t_mf, (n_mf, _, st_mf) = time_calls(mf_step, args.steps, args.warmup, torch)

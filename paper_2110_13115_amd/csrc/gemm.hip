@@ -30,6 +30,52 @@ constexpr int TILE_T = WAVES * WT_ROWB * 16;   // templates per workgroup (128)
 constexpr int TILE_N = WT_COLB * 32;           // samples per workgroup (64)
 constexpr size_t kLdsMax = 160 * 1024;         // gfx950 LDS per workgroup
 
+// Per-lane threshold epilogue: each output element tests its own |rho|^2 and
+// appends on its own.  Used by the FP32 kernels, whose epilogue is a small
+// part of a tile's time: measured, their main loops run faster with this
+// plain form than with the wave-aggregated one below.
+template <int RB, int CB>
+__device__ __forceinline__ void epilogue_lane(const GemmArgs& a, const f32x16 (&acc)[RB][CB], int rb0,
+                                              int64_t q0) {
+  const int lane = __lane_id();
+  const int l1 = __builtin_ctz((unsigned)a.N1);            // N1 is a power of two
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int q = (int)q0 + cb * 32 + (lane & 31);        // q < N < 2^31
+      const int n = (q >> l1) + a.N2 * (q & (a.N1 - 1));
+#pragma unroll
+      for (int i = 0; i < 16; i += 2) {
+        const int m = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);   // even: Re row
+        const int j = (rb0 + rb) * 16 + (m >> 1);
+        const float re = acc[rb][cb][i], im = acc[rb][cb][i + 1];
+        const float p = re * re + im * im;
+        if (a.rho_out != nullptr && j < a.T) {
+          const float s = a.row_inv ? a.row_inv[j] : 1.f;
+          a.rho_out[(int64_t)j * a.N + n] = make_float2(re * s, im * s);
+        }
+        if (j < a.T && p >= a.thr2_row[j]) {
+          atomicAdd(&a.tmpl_count[j], 1);
+          const unsigned long long idx = atomicAdd(a.trig_count, 1ull);
+          if ((int64_t)idx < a.trig_cap) {
+            TrigRec t;
+            t.tmpl = a.tmpl_base + j;
+            t.sample = n;
+            t.re = re;
+            t.im = im;
+            a.trig[idx] = t;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Wave-level threshold epilogue (16-bit kernels, whose short k-loops make the
+// epilogue a large part of a tile): one threshold load and one ballot per
+// template-row step after a maximum over the columns, and crossings appended
+// with one counter atomic per wave.
 template <int RB, int CB>
 __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[RB][CB], int rb0,
                                          int64_t q0) {
@@ -238,7 +284,7 @@ __device__ __forceinline__ void recon_f32_tile(const GemmArgs& a, int rb0, int64
       for (int cb = 0; cb < CB; ++cb)
         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
   }
-  epilogue<RB, CB>(a, acc, rb0, q0);
+  epilogue_lane<RB, CB>(a, acc, rb0, q0);
 }
 
 template <int RB, int CB, int G>
