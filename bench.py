@@ -258,6 +258,7 @@ def main():
     ap.add_argument("--binned-only", action="store_true",
                     help="time only the binned search (RECON, FP32 and BF16) at --thr-bin (for profiler runs)")
     ap.add_argument("--thr-bin", type=float, default=4.0, help="rho_I of --binned-only")
+    ap.add_argument("--dtypes", default="f32,bf16", help="storage types of --binned-only")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense sub-bank (paper regime) runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device-to-device copy of MIB MiB and exit (scales HBM byte "
@@ -307,7 +308,7 @@ def main():
 
     if args.binned_only:
         res = {}
-        for dt in ("f32", "bf16"):
+        for dt in args.dtypes.split(","):
             bs = bases if dt == "f32" else rbmf.subbank_bases(ctx, bank, wl.bounds(), rank=wl.sub_ranks(),
                                                               tol=wl.tol, dtype=dt)
             def call():

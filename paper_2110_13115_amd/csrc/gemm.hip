@@ -72,13 +72,40 @@ __device__ __forceinline__ void epilogue_lane(const GemmArgs& a, const f32x16 (&
   }
 }
 
+// Crossing records of one wave staged in LDS: a tile whose samples meet many
+// crossings (an injection seen by every template of the bank) would otherwise
+// wait on one returning counter atomic per step; staged, it takes one per
+// kStage records.
+constexpr int kStage = 64;
+constexpr size_t kStageBytes = (size_t)WAVES * kStage * sizeof(TrigRec);
+struct WaveStage {
+  TrigRec* buf;   // this wave's kStage LDS slots
+  int n;          // records staged (wave-uniform)
+};
+
+__device__ __forceinline__ void stage_flush(const GemmArgs& a, WaveStage& s, int lane) {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  unsigned lo = 0, hi = 0;
+  if (lane == 0) {
+    const unsigned long long b = atomicAdd(a.trig_count, (unsigned long long)s.n);
+    lo = (unsigned)b;
+    hi = (unsigned)(b >> 32);
+  }
+  const unsigned long long base = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)hi) << 32) |
+                                  (unsigned)__builtin_amdgcn_readfirstlane((int)lo);
+  for (int t = lane; t < s.n; t += 64)
+    if ((int64_t)(base + t) < a.trig_cap) a.trig[base + t] = s.buf[t];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  s.n = 0;
+}
+
 // Wave-level threshold epilogue (16-bit kernels, whose short k-loops make the
 // epilogue a large part of a tile): one threshold load and one ballot per
-// template-row step after a maximum over the columns, and crossings appended
-// with one counter atomic per wave.
+// template-row step after a maximum over the columns; crossings are staged
+// per wave (stage_flush appends them).
 template <int RB, int CB>
 __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[RB][CB], int rb0,
-                                         int64_t q0) {
+                                         int64_t q0, WaveStage& stg) {
   const int lane = __lane_id();
   const int l1 = __builtin_ctz((unsigned)a.N1);            // N1 is a power of two
   if (a.rho_out != nullptr) {   // debug dump (thresholds are infinite then: nothing is appended)
@@ -119,36 +146,26 @@ __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
         const float re = acc[rb][cb][i], im = acc[rb][cb][i + 1];
-        // Crossings are appended per wave: one counter atomic for the wave
-        // and one per template row (lanes 0-31 and 32-63 each hold one row
-        // of this step), slots by the prefix count of the ballot.
+        // one count atomic per template row (lanes 0-31 and 32-63 each hold
+        // one row of this step); the records go to the wave's stage at the
+        // prefix count of the ballot
         const bool hit = j < a.T && re * re + im * im >= thr;
         const unsigned long long mask = __ballot(hit);
         if (mask == 0ull) continue;
-        const int leader = __ffsll((long long)mask) - 1;
-        unsigned base_lo = 0, base_hi = 0;
-        if (lane == leader) {
-          const unsigned long long b = atomicAdd(a.trig_count, (unsigned long long)__popcll(mask));
-          base_lo = (unsigned)b;
-          base_hi = (unsigned)(b >> 32);
-        }
-        base_lo = (unsigned)__builtin_amdgcn_readlane((int)base_lo, leader);
-        base_hi = (unsigned)__builtin_amdgcn_readlane((int)base_hi, leader);
+        const int cnt = __popcll(mask);
         const unsigned half = (unsigned)(mask >> (lane & 32));
         if ((lane & 31) == 0 && half != 0u) atomicAdd(&a.tmpl_count[j], __popc(half));
+        if (stg.n + cnt > kStage) stage_flush(a, stg, lane);
         if (hit) {
-          const unsigned long long idx = (((unsigned long long)base_hi << 32) | base_lo) +
-                                         (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
-          if ((int64_t)idx < a.trig_cap) {
-            const int q = (int)q0 + cb * 32 + (lane & 31);
-            TrigRec t;
-            t.tmpl = a.tmpl_base + j;
-            t.sample = (q >> l1) + a.N2 * (q & (a.N1 - 1));
-            t.re = re;
-            t.im = im;
-            a.trig[idx] = t;
-          }
+          const int q = (int)q0 + cb * 32 + (lane & 31);
+          TrigRec t;
+          t.tmpl = a.tmpl_base + j;
+          t.sample = (q >> l1) + a.N2 * (q & (a.N1 - 1));
+          t.re = re;
+          t.im = im;
+          stg.buf[stg.n + __popcll(mask & ((1ull << lane) - 1ull))] = t;
         }
+        stg.n += cnt;
       }
     }
   }
@@ -359,7 +376,10 @@ __global__ __launch_bounds__(256) void k_recon_16(GemmArgs a) {
       for (int cb = 0; cb < WT_COLB; ++cb)
         acc[rb][cb] = kstep<DT>(av[0][rb], av[NP - 1][rb], bv[0][cb], bv[NP - 1][cb], acc[rb][cb]);
   }
-  epilogue<WT_ROWB, WT_COLB>(a, acc, rb0, q0);
+  __shared__ TrigRec stage_mem[WAVES][kStage];
+  WaveStage stg{stage_mem[wave], 0};
+  epilogue<WT_ROWB, WT_COLB>(a, acc, rb0, q0, stg);
+  if (stg.n > 0) stage_flush(a, stg, lane);
 }
 
 // 16-bit operands, Z tile staged in LDS.  One workgroup owns 32 CB samples and
@@ -373,8 +393,10 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
   constexpr int TNS = CB * 32;          // samples per workgroup
   constexpr int NP = DT == 3 ? 2 : 1;   // operand planes (hi, lo)
   extern __shared__ uint16_t zs[];
+  __shared__ TrigRec stage_mem[WAVES][kStage];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
+  WaveStage stg{stage_mem[wave], 0};
   const int64_t q0 = (int64_t)blockIdx.x * TNS;
   const int Kp = a.Kp, KB = Kp / 8, R2 = 2 * Kp;
   const int RS = NP * R2 + 8;       // LDS row stride (u16) of one sample: planes side by side
@@ -471,16 +493,26 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
         __builtin_amdgcn_sched_barrier(0);
       }
     }
-    for (int kb = Kmain; kb < KB; ++kb) {
-      u16x8 av[NP][WT_ROWB];
+    // the last KB - Kmain (< 2G) k-steps: all their A loads issue together
+    // (into the two group buffers) before the first of their MFMAs, so a
+    // short k-loop (small rank) waits for one load latency, not one per step
+    const int nt = KB - Kmain;
+    if (nt > 0) {
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
+      for (int g = 0; g < 2 * G; ++g)
+        if (g < nt)
 #pragma unroll
-        for (int rb = 0; rb < WT_ROWB; ++rb) av[p][rb] = ap[p * cplane + ((int64_t)rb * KB + kb) * 64];
-      step(av, kb);
+          for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int rb = 0; rb < WT_ROWB; ++rb)
+              fa[g / G][g % G][p][rb] = ap[p * cplane + ((int64_t)rb * KB + Kmain + g) * 64];
+#pragma unroll
+      for (int g = 0; g < 2 * G; ++g)
+        if (g < nt) step(fa[g / G][g % G], Kmain + g);
     }
-    epilogue<WT_ROWB, CB>(a, acc, rb0, q0);
+    epilogue<WT_ROWB, CB>(a, acc, rb0, q0, stg);
   }
+  if (stg.n > 0) stage_flush(a, stg, lane);
 }
 
 // ------------------------------------------------------------------ packing
@@ -570,8 +602,8 @@ hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
   // variant 1 loads fragments directly
   const int np = a.dtype == 3 ? 2 : 1;
   const int tns = (a.variant == 2 && a.dtype != 3) ? 128 : 64;   // (the split-BF16 operands do not fit 128)
-  const size_t lds = (size_t)tns * (np * 2 * a.Kp + 8) * 2;
-  if (a.variant != 1 && lds <= kLdsMax) {
+  const size_t lds = (size_t)tns * (np * 2 * a.Kp + 8) * 2;   // dynamic part (the staging is static)
+  if (a.variant != 1 && lds + kStageBytes <= kLdsMax) {
     static bool attr_set = false;
     if (!attr_set) {
       const void* fns[] = {reinterpret_cast<const void*>(&k_recon_16_lds<1, 2>),
@@ -580,7 +612,8 @@ hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
                            reinterpret_cast<const void*>(&k_recon_16_lds<1, 4>),
                            reinterpret_cast<const void*>(&k_recon_16_lds<2, 4>)};
       for (const void* f : fns) {
-        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+        const hipError_t e =
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsMax - kStageBytes));
         if (e != hipSuccess) return e;
       }
       attr_set = true;
