@@ -140,6 +140,13 @@ typedef struct {
                               Sec. III.C (see rb_filter)                     */
   double  thr_bin;         /* bin_w >= 2: threshold rho_I on the averaged
                               |rho_avg| (> 0); ignored otherwise             */
+  int32_t bin_source;      /* bin_w >= 2: 0 = the averaged series from the
+                              basis (C beta_avg, Sec. III.C); 1 = from the
+                              templates (Sec. III.D, Eq. avg_fft2: each
+                              template's band product folded onto N/bin_w
+                              bins and inverse transformed; the exact bin
+                              means; needs N / bin_w >= 4096)                */
+  int32_t reserved;        /* must be 0                                      */
 } rb_filter_opts;
 
 /* Bank source.  Fills out[(t1-t0) * (k1-k0) * 2] with the complex128 values
@@ -233,6 +240,9 @@ rb_status rb_basis_export(rb_basis basis, double* V, double* c, double* lambda);
  *      rho_avg = C beta_avg (MFMA GEMM on N/w samples), triggering bins
  *      |rho_avg| >= thr_bin; then rho_RB at every sample of every
  *      triggering (template, bin) (FP32), candidates |rho_RB| >= thr1;
+ *      with bin_source = 1 the averaged series comes from the templates
+ *      instead (the fast first stage of Sec. III.D) and the basis serves
+ *      the fine reconstruction only;
  *   4. second stage (opts->stage2) on the candidates: the exact |rho|
  *      (FULL, SPARSE, AUTO) or the reconstruction itself (RECON); final
  *      triggers reach thr2.

@@ -148,7 +148,9 @@ struct rb_ctx_s {
   DevBuf work, work64, dspec, strain, z, z32, recs1, thr_inf, adjA, adjAhat, adjB, adjT, adjS, adjRho, adjG, adjC, adjGC,
       adjOrd, adjSeg, trig1, trig2, recs, tmp, final_out, cnt1, cnt2, off1, off2, fill1, fill2,
       list1, list2, tmax, summary, counters, thr_row, peaks, flag, rho_tmp, zws, listH, listL, nsplit,
-      zfine, zpart, trigB, cntB, snap, tinv;
+      zfine, zpart, trigB, cntB, snap, tinv, gfold, offB, fillB, listB, recsB;
+  int64_t gfold_N = 0;             // grid and bin width of the table in gfold
+  int gfold_w = 0;
   hipEvent_t ev[8] = {};
   std::vector<hipEvent_t> evs;
   std::map<int64_t, int> fft_n2;   // autotuned four-step split per N (log2 N2)
@@ -610,7 +612,8 @@ rb_status step_basis_outputs_binned(rb_ctx ctx, rb_basis basis, const FftGeom& g
 // rho_RB at every sample of the triggering bins appended by basis `basis`
 // since the snapshot `snap` of the bin counter; candidates into trig1 / cnt1.
 rb_status step_fine(rb_ctx ctx, rb_basis basis, const FftGeom& g, int w, float thr1sq,
-                    const unsigned long long* snap) {
+                    const unsigned long long* snap, const TrigRec* bins = nullptr, int64_t begin_h = 0,
+                    int64_t end_h = 0) {
   FineArgs f;
   std::memset(&f, 0, sizeof(f));
   f.z = ctx->zfine.p;
@@ -623,9 +626,11 @@ rb_status step_fine(rb_ctx ctx, rb_basis basis, const FftGeom& g, int w, float t
   f.w = w;
   f.C = basis->C32.as<float2>();
   f.t0 = basis->t0;
-  f.bins = ctx->trigB.as<TrigRec>();
-  f.begin = snap;
-  f.end = ctx->counters.as<unsigned long long>() + 2;
+  f.bins = bins ? bins : ctx->trigB.as<TrigRec>();
+  f.begin = bins ? nullptr : snap;
+  f.end = bins ? nullptr : ctx->counters.as<unsigned long long>() + 2;
+  f.begin_h = begin_h;
+  f.end_h = end_h;
   f.bins_cap = trig_capacity(ctx->trigB);
   f.thr_sq = thr1sq;
   f.out = ctx->trig1.as<TrigRec>();
@@ -633,6 +638,62 @@ rb_status step_fine(rb_ctx ctx, rb_basis basis, const FftGeom& g, int w, float t
   f.out_count = ctx->counters.as<unsigned long long>();
   f.tmpl_count = ctx->cnt1.as<int32_t>();
   RB_HIP(launch_fine_recon(f, 1024, ctx->stream));
+  return RB_OK;
+}
+
+// Template-method first stage of the binned search (Sec. III.D, Eq. avg_fft2):
+// for every template, the band product with the whitened data folded onto
+// M = N / w bins with the geometric-sum weights G, an M-point inverse
+// transform (the bin means of its SNR series, exactly), and the threshold
+// |<rho>_b|^2 >= thr_sq into trigB / cntB (the bin index as the sample).
+rb_status step_fold(rb_ctx ctx, rb_bank bank, const FftGeom& gM, int w, float thr_sq) {
+  const int64_t N = bank->grid.N;
+  if (ctx->gfold_N != N || ctx->gfold_w != w) {   // G[F] for F < N/2, FP64 on the host
+    std::vector<float2> G((size_t)(N / 2));
+    for (int64_t F = 0; F < N / 2; ++F) {
+      if (F == 0) {
+        G[0] = make_float2((float)w, 0.f);
+        continue;
+      }
+      // (1 - z^w) / (1 - z), z = e^{2 pi i F / N}
+      const double a = 2.0 * M_PI * (double)F / (double)N;
+      const cd z(std::cos(a), std::sin(a)), zw(std::cos(a * w), std::sin(a * w));
+      const cd g = (1.0 - zw) / (1.0 - z);
+      G[(size_t)F] = make_float2((float)g.real(), (float)g.imag());
+    }
+    RB_TRY(ctx->gfold.ensure(G.size() * sizeof(float2)));
+    RB_HIP(hipMemcpyAsync(ctx->gfold.p, G.data(), G.size() * sizeof(float2), hipMemcpyHostToDevice, ctx->stream));
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->gfold_N = N;
+    ctx->gfold_w = w;
+  }
+  FftTables tw;
+  RB_TRY(get_tables(ctx, gM, tw));
+  const int T = bank->T;
+  const int B = batch_vectors(gM.N, T);
+  RB_TRY(ctx->work.ensure((size_t)B * gM.N * 8));
+  PassArgs a = base_args(bank, gM, tw);
+  a.sign = +1;
+  a.d = ctx->dspec.as<float2>();
+  a.src = bank->w.as<float2>();
+  a.sup_lo = bank->sup_lo.as<int32_t>();
+  a.sup_hi = bank->sup_hi.as<int32_t>();
+  a.gfold = ctx->gfold.as<float2>();
+  a.fold_half = w / 2;
+  a.fold_inv = 1.f / (float)w;
+  a.work = ctx->work.as<float2>();
+  a.thr2 = thr_sq;
+  a.trig = ctx->trigB.as<TrigRec>();
+  a.trig_cap = trig_capacity(ctx->trigB);
+  a.trig_count = ctx->counters.as<unsigned long long>() + 2;
+  a.tmpl_count = ctx->cntB.as<int32_t>();
+  a.tmpl_max = nullptr;
+  for (int64_t i0 = 0; i0 < T; i0 += B) {
+    a.vec_base = (int)i0;
+    a.nvec = (int)std::min<int64_t>(B, T - i0);
+    RB_HIP(launch_pass1(a, IN_FOLD, ctx->stream));
+    RB_HIP(launch_pass2(a, OUT_THRESH, ctx->stream));
+  }
   return RB_OK;
 }
 
@@ -1382,6 +1443,15 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
   RB_CHECK(opts->bin_w >= 0 && opts->bin_w <= 64 && (w & (w - 1)) == 0 && bank->grid.N / w >= 256, RB_ERR_ARG,
            "bin_w must be 0, 1 or a power of two <= 64 with N / bin_w >= 256");
   RB_CHECK(w == 1 || (std::isfinite(opts->thr_bin) && opts->thr_bin > 0), RB_ERR_ARG, "thr_bin must be > 0");
+  RB_CHECK(opts->bin_source == 0 || (opts->bin_source == 1 && w > 1), RB_ERR_ARG,
+           "bin_source must be 0, or 1 with bin_w >= 2");
+  RB_CHECK(opts->reserved == 0, RB_ERR_ARG, "reserved must be 0");
+  const bool fold = opts->bin_source == 1;
+  FftGeom gM{};
+  if (fold) {
+    gM = make_geom(bank->grid.N / w);
+    RB_CHECK(geom_supported(gM), RB_ERR_ARG, "bin_source 1 needs N / bin_w >= 4096");
+  }
   RB_CHECK(cap >= 0, RB_ERR_ARG, "cap must be >= 0");
   const int T = bank->T;
   ctx->want_peaks = peaks != nullptr;
@@ -1406,10 +1476,38 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
   const float thr1sq = (float)(opts->thr1 * opts->thr1);
   const FftGeom gb = w > 1 ? binned_geom(g, w) : g;   // the twiddle tables depend on N only
   if (w > 1) RB_TRY(ctx->snap.ensure((size_t)nbases * 8));
+  std::vector<int32_t> offB, cntB;   // template fold: bins grouped by template
+  if (fold) {
+    if (tm) RB_TRY(event(ctx, e_end + 1 + (size_t)nbases));
+    for (;;) {
+      RB_TRY(fill32(ctx, ctx->counters.as<unsigned long long>() + 2, 0u, 2));
+      RB_TRY(fill32(ctx, ctx->cntB.p, 0u, T));
+      RB_TRY(step_fold(ctx, bank, gM, w, (float)(opts->thr_bin * opts->thr_bin)));
+      RB_HIP(hipMemcpyAsync(&nbins, ctx->counters.as<unsigned long long>() + 2, 8, hipMemcpyDeviceToHost,
+                            ctx->stream));
+      RB_HIP(hipStreamSynchronize(ctx->stream));
+      if (nbins <= trig_capacity(ctx->trigB)) break;
+      RB_TRY(ctx->trigB.ensure((size_t)(nbins + nbins / 4) * sizeof(TrigRec)));
+    }
+    RB_TRY(ctx->offB.ensure((size_t)T * 4));
+    RB_TRY(ctx->fillB.ensure((size_t)T * 4));
+    RB_TRY(ctx->listB.ensure((size_t)T * 4));
+    RB_TRY(ctx->recsB.ensure(std::max<size_t>(16, (size_t)nbins * sizeof(TrigRec))));
+    int64_t sumB[3];
+    RB_TRY(scan_and_read(ctx, T, ctx->cntB, ctx->offB, ctx->fillB, ctx->listB, sumB));
+    RB_HIP(launch_scatter_triggers(ctx->trigB.as<TrigRec>(), nbins, nullptr, ctx->offB.as<int32_t>(),
+                                   ctx->fillB.as<int32_t>(), ctx->recsB.as<TrigRec>(), ctx->stream));
+    offB.resize(T);
+    cntB.resize(T);
+    RB_HIP(hipMemcpyAsync(offB.data(), ctx->offB.p, (size_t)T * 4, hipMemcpyDeviceToHost, ctx->stream));
+    RB_HIP(hipMemcpyAsync(cntB.data(), ctx->cntB.p, (size_t)T * 4, hipMemcpyDeviceToHost, ctx->stream));
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+    if (tm) RB_TRY(event(ctx, e_end + 2 + (size_t)nbases));
+  }
   for (;;) {
     RB_TRY(fill32(ctx, ctx->counters.p, 0u, 2));
     RB_TRY(fill32(ctx, ctx->cnt1.p, 0u, T));
-    if (w > 1) {
+    if (w > 1 && !fold) {
       RB_TRY(fill32(ctx, ctx->counters.as<unsigned long long>() + 2, 0u, 2));
       RB_TRY(fill32(ctx, ctx->cntB.p, 0u, T));
     }
@@ -1418,6 +1516,13 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
         RB_TRY(step_basis_outputs(ctx, bases[m], g, tw));
         if (tm) RB_TRY(event(ctx, 2 + 2 * (size_t)m));
         RB_TRY(stage1_gemm(ctx, bases[m], g, thr1sq, nullptr));
+      } else if (fold) {   // the basis serves the fine stage only
+        RB_TRY(step_basis_outputs_binned(ctx, bases[m], gb, tw, w));
+        if (tm) RB_TRY(event(ctx, 2 + 2 * (size_t)m));
+        if (tm) RB_TRY(event(ctx, e_end + 1 + (size_t)m));
+        const int t0 = bases[m]->t0, t1 = t0 + bases[m]->T;
+        RB_TRY(step_fine(ctx, bases[m], gb, w, thr1sq, nullptr, ctx->recsB.as<TrigRec>(), offB[t0],
+                         (int64_t)offB[t1 - 1] + cntB[t1 - 1]));
       } else {
         RB_TRY(step_basis_outputs_binned(ctx, bases[m], gb, tw, w));
         if (tm) RB_TRY(event(ctx, 2 + 2 * (size_t)m));
@@ -1429,7 +1534,7 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
       }
       if (tm) RB_TRY(event(ctx, 3 + 2 * (size_t)m));
     }
-    if (w > 1)
+    if (w > 1 && !fold)
       RB_HIP(hipMemcpyAsync(&nbins, ctx->counters.as<unsigned long long>() + 2, 8, hipMemcpyDeviceToHost,
                             ctx->stream));
     RB_TRY(scan_and_read(ctx, T, ctx->cnt1, ctx->off1, ctx->fill1, ctx->list1, sum1));
@@ -1530,6 +1635,11 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
     }
     if (w > 1)
       for (int32_t m = 0; m < nbases; ++m) stats->ms[7] += elapsed(ctx, e_end + 1 + (size_t)m, 3 + 2 * (size_t)m);
+    if (fold) {   // the template fold is a first stage of its own: counted in [2]
+      const float f = elapsed(ctx, e_end + 1 + (size_t)nbases, e_end + 2 + (size_t)nbases);
+      stats->ms[2] += f;
+      stats->ms[1] -= f;
+    }
     stats->ms[3] = elapsed(ctx, 3 + 2 * (size_t)(nbases - 1), e_scan);
     stats->ms[4] = elapsed(ctx, e_scan, e_s2);
     stats->ms[5] = elapsed(ctx, e_s2, e_end);
@@ -2030,6 +2140,7 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
   RB_CHECK(opts->bin_w <= 1, RB_ERR_UNSUPPORTED, "the batch search takes bin_w 0 or 1");
   RB_CHECK(opts->stage2 == RB_STAGE2_FULL || opts->stage2 == RB_STAGE2_SPARSE, RB_ERR_ARG, "bad stage2 mode");
   RB_CHECK(opts->bin_w >= 0, RB_ERR_ARG, "bin_w must be >= 0");
+  RB_CHECK(opts->bin_source == 0 && opts->reserved == 0, RB_ERR_ARG, "bin_source and reserved must be 0");
   int Tmax = 0;
   for (int32_t i = 0; i < nitems; ++i) {
     const rb_batch_item& it = items[i];

@@ -104,8 +104,8 @@ __global__ __launch_bounds__(FINE_WAVES * 64) void k_fine_recon(FineArgs a) {
   const int r = lane & (w - 1);
   const int slices = 64 / w;
   const int s = lane / w;
-  const int64_t end = (int64_t)min(*a.end, (unsigned long long)a.bins_cap);
-  const int64_t begin = (int64_t)*a.begin;
+  const int64_t end = a.end ? (int64_t)min(*a.end, (unsigned long long)a.bins_cap) : a.end_h;
+  const int64_t begin = a.begin ? (int64_t)*a.begin : a.begin_h;
   const int l2 = __builtin_ctz((unsigned)a.N2);
   int nst = 0;   // staged records of this wave (wave-uniform)
   auto flush = [&]() {

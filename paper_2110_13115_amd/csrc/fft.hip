@@ -17,7 +17,11 @@
 // Fused prologues (pass 1):  IN_CORR  X[f] = d[f] conj(src_v[f]) on the
 //   vector's support (Sec. III.C: filter the whitened data with every basis
 //   vector / template); negative frequencies are zero, so only the first half
-//   of every column is read.  IN_REAL: the real strain.  IN_DENSE: complex.
+//   of every column is read.  IN_FOLD: the same product folded onto
+//   M = N / w bins with the geometric-sum weights of Sec. III.D (Eq.
+//   avg_fft2), X~[f'] = (1/w) sum_l X[l M + f'] G[l M + f'], whose M-point
+//   inverse transform is the bin mean of the template's SNR series.
+//   IN_REAL: the real strain.  IN_DENSE: complex.
 // The batched passes run in FP32.  The one forward transform of the strain
 // runs in FP64: raw strain carries out-of-band (low-frequency) power many
 // orders of magnitude above the band, and FP32 rounding relative to the total
@@ -293,7 +297,7 @@ __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
   const V* __restrict__ pyr = PassPtr<V>::pyr(a);
 
   int lo = a.band_lo, hi = a.band_hi;
-  if (IN == IN_CORR && a.sup_lo != nullptr) {
+  if ((IN == IN_CORR || IN == IN_FOLD) && a.sup_lo != nullptr) {
     lo = a.sup_lo[v];
     hi = a.sup_hi[v];
   }
@@ -323,6 +327,21 @@ __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
             const float2 pv = a.src[(int64_t)v * a.nbs + (fc - a.kb)];
             const float m = (f == fc) ? 1.f : 0.f;
             x[r] = mk<V>(m * (dv.x * pv.x + dv.y * pv.y), m * (dv.y * pv.x - dv.x * pv.y));
+          } else if (IN == IN_FOLD) {
+            // f < M; the one-sided spectrum is zero from N/2 = (w/2) M on
+            float xr = 0.f, xi = 0.f;
+            for (int l = 0; l < a.fold_half; ++l) {
+              const int64_t F = f + (int64_t)l * a.g.N;
+              const int64_t fc = F < lo ? lo : (F > hi ? hi : F);
+              const float2 dv = a.d[fc - a.kb];
+              const float2 pv = a.src[(int64_t)v * a.nbs + (fc - a.kb)];
+              const float2 gv = a.gfold[F];
+              const float m = (F == fc) ? 1.f : 0.f;
+              const float cr = m * (dv.x * pv.x + dv.y * pv.y), ci = m * (dv.y * pv.x - dv.x * pv.y);
+              xr += cr * gv.x - ci * gv.y;
+              xi += cr * gv.y + ci * gv.x;
+            }
+            x[r] = mk<V>((T)(xr * a.fold_inv), (T)(xi * a.fold_inv));
           } else if (IN == IN_REAL) {
             x[r] = mk<V>((T)a.real_in[f], 0);
           } else {
@@ -710,6 +729,7 @@ bool geom_supported(const FftGeom& g) {
 hipError_t launch_pass1(const PassArgs& a, InKind in, hipStream_t st) {
   if (a.nvec <= 0) return hipSuccess;
   if (in == IN_CORR) return a.sign > 0 ? disp1<float2, IN_CORR, 1>(a, st) : disp1<float2, IN_CORR, -1>(a, st);
+  if (in == IN_FOLD) return a.sign > 0 ? disp1<float2, IN_FOLD, 1>(a, st) : hipErrorInvalidValue;
   if (in == IN_REAL) return disp1<double2, IN_REAL, -1>(a, st);     // strain spectrum: FP64
   return a.sign > 0 ? disp1<float2, IN_DENSE, 1>(a, st) : disp1<float2, IN_DENSE, -1>(a, st);
 }

@@ -48,7 +48,7 @@ FftGeom make_geom(int64_t N, int n2log = -1);
 bool geom_supported(const FftGeom& g);
 
 // Pass-1 input variants.
-enum InKind { IN_CORR = 0, IN_REAL = 1, IN_DENSE = 2 };
+enum InKind { IN_CORR = 0, IN_REAL = 1, IN_DENSE = 2, IN_FOLD = 3 };
 // Pass-2 output variants.
 enum OutKind {
   OUT_Z32 = 0,       // planar FP32 Z: row 2v = Re, row 2v+1 = Im, row stride N
@@ -92,6 +92,9 @@ struct PassArgs {
   const int32_t* sup_lo;     // IN_CORR: per-vector first non-zero bin (absolute)
   const int32_t* sup_hi;     // IN_CORR: per-vector last non-zero bin
   int32_t band_lo, band_hi;  // IN_CORR when sup_* are NULL
+  const float2* gfold;       // IN_FOLD: G[F] = sum_{r<w} e^{+2 pi i F r / (w g.N)}, F < (w/2) g.N
+  int fold_half;             // IN_FOLD: w / 2 (folded bins per output below N/2)
+  float fold_inv;            // IN_FOLD: 1 / w
   // intermediate [nvec][N] complex64
   float2* work;
   // pass-2 outputs
@@ -220,8 +223,9 @@ struct FineArgs {
   const float2* C;           // local T x K complex64, C = conj(c), unscaled
   int t0;                    // global index of local template 0
   const TrigRec* bins;       // triggering (template, bin) records: sample = bin index
-  const unsigned long long* begin;   // device: first record of this basis
-  const unsigned long long* end;     // device: records appended so far
+  const unsigned long long* begin;   // device: first record of this basis (NULL: begin_h)
+  const unsigned long long* end;     // device: records appended so far (NULL: end_h)
+  int64_t begin_h, end_h;            // host-known record range
   int64_t bins_cap;
   float thr_sq;              // candidate threshold, squared
   TrigRec* out;

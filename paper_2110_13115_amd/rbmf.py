@@ -48,7 +48,8 @@ class Stats(C.Structure):
 
 class FilterOpts(C.Structure):
     _fields_ = [("thr1", C.c_double), ("thr2", C.c_double), ("stage2", C.c_int32),
-                ("bin_w", C.c_int32), ("thr_bin", C.c_double)]
+                ("bin_w", C.c_int32), ("thr_bin", C.c_double), ("bin_source", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 TRIGGER_NP = np.dtype([("tmpl", np.int32), ("sample", np.int32), ("snr", np.float32),
@@ -247,15 +248,16 @@ def subbank_bases(ctx: Context, bank: Bank, bounds, rank=0, tol: float = 1e-3, d
 
 def rb_filter(ctx: Context, bases, bank: Bank, strain, thr1: float, thr2: float,
               stage2: int = RB_STAGE2_FULL, cap: int = 1 << 20, peaks: bool = False,
-              out=None, bin_w: int = 0, thr_bin: float = 0.0):
+              out=None, bin_w: int = 0, thr_bin: float = 0.0, bin_source: int = 0):
     """bases: one Basis or a list partitioning the bank.  bin_w >= 2 selects the
-    binned first stage with threshold thr_bin on the averaged SNR.  Returns
+    binned first stage with threshold thr_bin on the averaged SNR, taken from
+    the basis (bin_source 0) or from the templates (bin_source 1).  Returns
     (triggers as a TRIGGER_NP array, or their count when `out` is a device
     buffer; peaks or None; Stats)."""
     if isinstance(bases, Basis):
         bases = [bases]
     arr = (C.c_void_p * len(bases))(*[b.h.value for b in bases])
-    o = FilterOpts(thr1, thr2, stage2, int(bin_w), float(thr_bin))
+    o = FilterOpts(thr1, thr2, stage2, int(bin_w), float(thr_bin), int(bin_source), 0)
     dev = out is not None and not isinstance(out, np.ndarray)
     buf = out if out is not None else _triggers_out(cap, False)
     cap = buf.shape[0]
@@ -365,7 +367,7 @@ def rb_filter_batch(ctx: Context, items, thr1: float, thr2: float, use_graph: bo
         bp = (C.c_void_p * len(bases))(*[b.h.value for b in bases])
         keep.append(bp)
         arr[i] = BatchItem(_ptr(s), bank.h.value, C.cast(bp, C.POINTER(C.c_void_p)), len(bases))
-    o = FilterOpts(thr1, thr2, stage2, 0, 0.0)
+    o = FilterOpts(thr1, thr2, stage2, 0, 0.0, 0, 0)
     dev = out is not None and not isinstance(out, np.ndarray)
     buf = out if out is not None else np.empty(max(1, n * cap_item), dtype=TRIGGER_NP)
     counts = (C.c_int64 * n)()

@@ -254,3 +254,44 @@ def test_binned_16bit_storage(ctx, bcase, dtype):
     rel = np.abs(got["snr"] - a_rb[got["tmpl"], got["sample"]]) / a_rb[got["tmpl"], got["sample"]]
     assert rel.max() <= tol
     b16.close()
+
+
+@pytest.mark.parametrize("mode", ["recon", "sparse"])
+def test_template_fold_first_stage(ctx, bcase, mode):
+    """bin_source 1: the averaged series from the templates (Sec. III.D, the
+    fold of Eq. avg_fft2, exact bin means of the template method), the fine
+    stage from the basis.  Bins against the oracle's bin means of the FP64
+    template-method series; candidates and finals as in the basis case."""
+    case, bank, basis, beta, c = bcase
+    w, thr_bin, thr1, thr2 = 8, 3.0, 4.5, 5.5
+    st2 = rbmf.RB_STAGE2_RECON if mode == "recon" else rbmf.RB_STAGE2_SPARSE
+    got, _, st = rbmf.rb_filter(ctx, basis, bank, case.strain, thr1, thr2, stage2=st2, bin_w=w,
+                                thr_bin=thr_bin, bin_source=1)
+    a_avg = np.abs(oh.bin_means(case.rho, w))
+    a_rb = np.abs(ob.rb_snr(beta, c))
+    on = np.repeat(a_avg >= thr_bin, w, axis=1)
+    amb = np.repeat(_band(a_avg, thr_bin), w, axis=1)
+    sure = on & ~amb & (a_rb >= thr1) & ~_band(a_rb, thr1)
+    maybe = (on | amb) & (a_rb >= thr1 * (1 - BAND)) & ~sure
+    lo, hi = (a_avg >= thr_bin * (1 + BAND)).sum(), (a_avg >= thr_bin * (1 - BAND)).sum()
+    log("fold", mode, "bins", st.n_bins, "oracle", lo, hi, "final", len(got))
+    assert lo <= st.n_bins <= hi and lo > 50
+    assert sure.sum() <= st.n_stage1 <= (sure | maybe).sum()
+    ref = a_rb if mode == "recon" else np.abs(case.rho)
+    definite = sure & (ref >= thr2) & ~_band(ref, thr2)
+    possible = (sure | maybe) & (ref >= thr2 * (1 - BAND))
+    assert definite.sum() > 10
+    check_sets(got, definite, possible, ref)
+
+
+def test_template_fold_arguments(ctx, bcase):
+    case, bank, basis, beta, c = bcase
+    for kw in ({"bin_w": 16, "thr_bin": 2.0, "bin_source": 1},     # N / w = 2048 < 4096
+               {"bin_w": 0, "thr_bin": 2.0, "bin_source": 1},      # needs bins
+               {"bin_w": 8, "thr_bin": 2.0, "bin_source": 2}):
+        with pytest.raises(rbmf.RbError) as ei:
+            rbmf.rb_filter(ctx, basis, bank, case.strain, 4.5, 5.5, **kw)
+        assert ei.value.status == rbmf.RB_ERR_ARG, kw
+    got, _, st = rbmf.rb_filter(ctx, basis, bank, case.strain, 4.5, 5.5, stage2=rbmf.RB_STAGE2_RECON,
+                                bin_w=8, thr_bin=40.0, bin_source=1)
+    assert len(got) == 0 and st.n_bins == 0 and st.n_stage1 == 0
