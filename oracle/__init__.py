@@ -16,6 +16,8 @@ hier    the binned (hierarchical) first stage: bin means of the basis
         outputs, triggering bins, fine reconstruction of their samples, the
         second-stage variants, the template-method fold of Eq. avg_fft2 and
         the target SNR of Eq. target_snr_criteria (Sec. III.C-D, III.F).
+stream  overlap-save segmentation of a long strain (Sec. III.E): segment
+        starts, valid windows, stitched trigger lists.
 grad    loss sum g |rho|^2 over a frozen trigger set and its gradients with
         respect to the coefficients and the strain (torch CPU float64
         autograd through an independent plain forward).

@@ -164,3 +164,40 @@ def test_target_snr_definition():
     assert oh.target_snr(fin, flat, grid) == 5.1
     assert oh.target_snr(fin, flat, grid, ratio=0.8) == 4.5
     assert oh.target_snr(np.array([]), flat, np.array([4.0])) == float("inf")
+
+
+# ----------------------------------------------------------------- overlap-save segments
+from oracle import stream as osm   # noqa: E402
+
+
+@pytest.mark.parametrize("n,N", [(64, 64), (96, 64), (128, 64), (100, 64), (1000, 64), (65, 64)])
+def test_segment_windows_partition_the_stream(n, N):
+    seg = osm.segments(n, N)
+    cover = np.zeros(n, dtype=int)
+    for i, (s, lo, hi) in enumerate(seg):
+        assert 0 <= s <= n - N and lo < hi
+        assert s <= lo and hi <= s + N                       # a window lies inside its segment
+        if 0 < i < len(seg) - 2:
+            assert (lo, hi) == (s + N // 4, s + 3 * N // 4)  # the central half
+        elif 0 < i == len(seg) - 2:                          # may end where the last (moved back) starts its half
+            assert lo == s + N // 4 and hi <= s + 3 * N // 4
+        cover[lo:hi] += 1
+    assert np.all(cover == 1)
+    assert [s for s, _, _ in seg[:-1]] == [i * N // 2 for i in range(len(seg) - 1)]
+    assert seg[-1][0] == n - N
+
+
+def test_stream_triggers_report_every_sample_once():
+    n, N = 1000, 64
+    strain = np.arange(n, dtype=np.float64)
+
+    def everything(x):
+        t = np.zeros(x.shape[0], dtype=om.TRIGGER_DTYPE)
+        t["sample"] = np.arange(x.shape[0])
+        t["snr"] = x                                        # the stream sample itself
+        return t
+    t = osm.stream_triggers(strain, N, everything)
+    assert np.array_equal(t["sample"], np.arange(n))
+    assert np.array_equal(t["snr"], strain)                 # shifted to the right sample
+    with pytest.raises(ValueError):
+        osm.segments(10, 64)
