@@ -125,11 +125,15 @@ def binned_runs(ctx, wl, bank_def, bank, bases_by_dt, sd, out, mf_trig, t_mf, si
         f"{[(r['thr_bin'], r['target_snr']) for r in table]}")
     mf_pairs = set(zip(mf_trig["tmpl"].tolist(), mf_trig["sample"].tolist()))
     res = {"w": wl.bin_w, "thr_bin": thr_bin, "tuning_segment": table}
+    fold_ok = wl.N // wl.bin_w >= 4096
     for dt, bs in bases_by_dt.items():
-        for mode, name in ((rbmf.RB_STAGE2_RECON, "recon"), (rbmf.RB_STAGE2_SPARSE, "sparse")):
+        runs = [(rbmf.RB_STAGE2_RECON, "recon", 0), (rbmf.RB_STAGE2_SPARSE, "sparse", 0)]
+        if fold_ok:   # the averaged series from the templates (Sec. III.D), the basis for the fine stage
+            runs.append((rbmf.RB_STAGE2_RECON, "fold_recon", 1))
+        for mode, name, src in runs:
             def call():
                 n, _, st = rbmf.rb_filter(ctx, bs, bank, sd, wl.thr1, wl.thr2, stage2=mode, bin_w=wl.bin_w,
-                                          thr_bin=thr_bin, out=out)
+                                          thr_bin=thr_bin, bin_source=src, out=out)
                 return n, st
             t, (n, st) = time_calls(call, args.steps, args.warmup, torch)
             tr = out[:n].cpu().numpy().view(rbmf.TRIGGER_NP).reshape(-1)

@@ -263,6 +263,26 @@ rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases, rb_bank b
                     const float* strain, const rb_filter_opts* opts, rb_trigger* out, int64_t cap,
                     int64_t* n_out, rb_peak* peaks, rb_stats* stats);
 
+/* Overlap-save search of a long strain (Sec. III.E): segments of N samples
+ * (the bank's grid), each overlapping the previous one by N/2, searched with
+ * rb_filter.  Segment i starts at i N/2 (the last one at n - N) and reports
+ * the final triggers of its central half [start + N/4, start + 3N/4); the
+ * first segment's window starts at 0, the last one's ends at n, and where
+ * the last segment was moved back the previous window ends where its half
+ * begins, so every stream sample is reported by exactly one segment.
+ *   strain  host or device, n floats, N <= n < 2^31.  Segments are cut
+ *           without tapering: condition the stream first (no power far below
+ *           f_low), or the out-of-band power leaks into the band at every
+ *           segment edge.
+ *   out     host or device, cap entries; sample = index in the stream; in
+ *           segment order, sorted by (tmpl, sample) within a segment.
+ *   n_out   host; RB_ERR_CAPACITY (with the required count) if it exceeds cap.
+ *   stats   host or NULL: counts and device times summed over the segments.
+ * Other arguments and errors as rb_filter. */
+rb_status rb_filter_stream(rb_ctx ctx, const rb_basis* bases, int32_t nbases, rb_bank bank,
+                           const float* strain, int64_t n, const rb_filter_opts* opts, rb_trigger* out,
+                           int64_t cap, int64_t* n_out, rb_stats* stats);
+
 /* One work item of a batched search: a segment and the bank (on that
  * segment's grid) with the bases of its sub-banks. */
 typedef struct {

@@ -148,7 +148,7 @@ struct rb_ctx_s {
   DevBuf work, work64, dspec, strain, z, z32, recs1, thr_inf, adjA, adjAhat, adjB, adjT, adjS, adjRho, adjG, adjC, adjGC,
       adjOrd, adjSeg, trig1, trig2, recs, tmp, final_out, cnt1, cnt2, off1, off2, fill1, fill2,
       list1, list2, tmax, summary, counters, thr_row, peaks, flag, rho_tmp, zws, listH, listL, nsplit,
-      zfine, zpart, trigB, cntB, snap, tinv, gfold, offB, fillB, listB, recsB;
+      zfine, zpart, trigB, cntB, snap, tinv, gfold, offB, fillB, listB, recsB, sstrain, segout, wout, wcount;
   int64_t gfold_N = 0;             // grid and bin width of the table in gfold
   int gfold_w = 0;
   hipEvent_t ev[8] = {};
@@ -1646,6 +1646,76 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
     stats->ms[6] = elapsed(ctx, 0, e_end);
   }
   return st;
+}
+
+extern "C" rb_status rb_filter_stream(rb_ctx ctx, const rb_basis* bases, int32_t nbases, rb_bank bank,
+                                      const float* strain, int64_t n, const rb_filter_opts* opts, rb_trigger* out,
+                                      int64_t cap, int64_t* n_out, rb_stats* stats) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(bank != nullptr && opts != nullptr && n_out != nullptr && strain != nullptr, RB_ERR_ARG, "NULL argument");
+  RB_CHECK(bank->ctx == ctx, RB_ERR_ARG, "bank belongs to another context");
+  RB_CHECK(cap >= 0 && (out != nullptr || cap == 0), RB_ERR_ARG, "bad output buffer");
+  const int64_t N = bank->grid.N;
+  RB_CHECK(n >= N && n <= (int64_t)INT32_MAX, RB_ERR_ARG, "need N <= n < 2^31 samples");
+  const float* sdev = strain;
+  if (!is_device_ptr(strain)) {
+    RB_TRY(ctx->sstrain.ensure((size_t)n * sizeof(float)));
+    RB_HIP(hipMemcpyAsync(ctx->sstrain.p, strain, (size_t)n * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    sdev = ctx->sstrain.as<float>();
+  }
+  rb_trigger* odev = out;
+  if (out != nullptr && !is_device_ptr(out)) {
+    RB_TRY(ctx->wout.ensure(std::max<size_t>(16, (size_t)cap * sizeof(rb_trigger))));
+    odev = ctx->wout.as<rb_trigger>();
+  }
+  RB_TRY(ctx->wcount.ensure(8));
+  RB_TRY(fill32(ctx, ctx->wcount.p, 0u, 2));
+  if (ctx->segout.bytes == 0) RB_TRY(ctx->segout.ensure((size_t)1 << 16 << 4));
+  const int64_t hop = N / 2, count = (n - N + hop - 1) / hop + 1;
+  rb_stats acc;
+  std::memset(&acc, 0, sizeof(acc));
+  int64_t lo = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t s0 = std::min(i * hop, n - N);
+    const int64_t hi = i == count - 1 ? n : std::min((i + 1) * hop, n - N) + N / 4;
+    int64_t ni = 0;
+    rb_stats st;
+    for (;;) {   // the segment's own search; grow the scratch output if it is short
+      const int64_t segcap = (int64_t)(ctx->segout.bytes / sizeof(rb_trigger));
+      const rb_status r = rb_filter(ctx, bases, nbases, bank, sdev + s0, opts, ctx->segout.as<rb_trigger>(), segcap,
+                                    &ni, nullptr, stats ? &st : nullptr);
+      if (r == RB_ERR_CAPACITY) {
+        RB_TRY(ctx->segout.ensure((size_t)(ni + ni / 4) * sizeof(rb_trigger)));
+        continue;
+      }
+      if (r != RB_OK) return r;
+      break;
+    }
+    if (ni > 0)
+      RB_HIP(launch_window(ctx->segout.p, ni, s0, lo, hi, odev, cap, ctx->wcount.as<int64_t>(), ctx->stream));
+    if (stats) {
+      acc.n_stage1 += st.n_stage1;
+      acc.n_refiltered += st.n_refiltered;
+      acc.rank = std::max(acc.rank, st.rank);
+      acc.n_bins += st.n_bins;
+      for (int k = 0; k < 8; ++k) acc.ms[k] += st.ms[k];
+    }
+    lo = hi;
+  }
+  int64_t total = 0;
+  RB_HIP(hipMemcpyAsync(&total, ctx->wcount.p, 8, hipMemcpyDeviceToHost, ctx->stream));
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  *n_out = total;
+  if (stats) *stats = acc;
+  if (total > cap) {
+    set_error("trigger capacity " + std::to_string(cap) + " < required " + std::to_string(total));
+    return RB_ERR_CAPACITY;
+  }
+  if (odev != out && total > 0) {
+    RB_HIP(hipMemcpyAsync(out, odev, (size_t)total * sizeof(rb_trigger), hipMemcpyDeviceToHost, ctx->stream));
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  return RB_OK;
 }
 
 extern "C" rb_status mf_full(rb_ctx ctx, rb_bank bank, const float* strain, double thr, rb_trigger* out,

@@ -163,6 +163,10 @@ hipError_t launch_scatter_triggers(const TrigRec* in, int64_t n, const int64_t* 
 hipError_t launch_segment_sort(TrigRec* recs, TrigRec* tmp, const int32_t* offsets,
                                const int32_t* counts, const int32_t* list, int nlist, void* out,
                                const int64_t* summary_dev, int64_t out_cap, hipStream_t s);
+// keeps in[i] (rb_trigger, n of them) with sample + shift in [lo, hi), shifted, appended in order at
+// out[*n_out ...] (entries beyond cap are counted, not written); *n_out is advanced
+hipError_t launch_window(const void* in, int64_t n, int64_t shift, int64_t lo, int64_t hi, void* out, int64_t cap,
+                         int64_t* n_out, hipStream_t s);
 hipError_t launch_peaks_from_max(const unsigned long long* tmax, int T, void* out_peaks,
                                  hipStream_t s);
 hipError_t launch_cluster_peaks(const void* trig, int64_t n, int W, int64_t N, uint8_t* is_peak,

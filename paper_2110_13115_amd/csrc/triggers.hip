@@ -282,6 +282,39 @@ hipError_t launch_split_list(const int32_t* list, int64_t n, const int32_t* coun
   return hipGetLastError();
 }
 
+// Overlap-save stitching: keeps the triggers (sorted by template, sample) of
+// one segment whose stream sample (sample + shift) lies in [lo, hi), shifted,
+// appended in order after the *n_out already written (one workgroup, chunks
+// of SCAN_T with a block scan, so the order is preserved).
+__global__ __launch_bounds__(SCAN_T) void k_window(const rb_trigger* in, int64_t n, int64_t shift, int64_t lo,
+                                                   int64_t hi, rb_trigger* out, int64_t cap, int64_t* n_out) {
+  __shared__ int sh[64];
+  int64_t base = *n_out;
+  for (int64_t c0 = 0; c0 < n; c0 += SCAN_T) {
+    const int64_t i = c0 + threadIdx.x;
+    rb_trigger t;
+    int keep = 0;
+    if (i < n) {
+      t = in[i];
+      const int64_t g = (int64_t)t.sample + shift;
+      keep = (g >= lo && g < hi) ? 1 : 0;
+      t.sample = (int32_t)g;
+    }
+    int tot;
+    const int ex = block_excl_scan(keep, sh, tot);
+    if (keep && base + ex < cap) out[base + ex] = t;
+    base += tot;
+  }
+  if (threadIdx.x == 0) *n_out = base;
+}
+
+hipError_t launch_window(const void* in, int64_t n, int64_t shift, int64_t lo, int64_t hi, void* out, int64_t cap,
+                         int64_t* n_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_window, dim3(1), dim3(SCAN_T), 0, s, static_cast<const rb_trigger*>(in), n, shift, lo, hi,
+                     static_cast<rb_trigger*>(out), cap, n_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan_counts(const int32_t* counts, int T, int32_t* offsets, int32_t* fill,
                               int32_t* list, int64_t* summary, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(SCAN_T), 0, s, counts, T, offsets, fill, list, summary);

@@ -25,7 +25,7 @@ DTYPES = {"f32": RB_F32, "bf16": RB_BF16, "f16": RB_F16, "bf16x3": RB_BF16X3}
 FUNCTIONS = ["rb_ctx_create", "rb_ctx_destroy", "rb_last_error", "rb_bank_create", "rb_bank_free",
              "rb_bank_info", "rb_build_basis", "rb_build_basis_range", "rb_basis_info",
              "rb_basis_free", "rb_basis_export", "rb_filter",
-             "rb_filter_batch", "mf_full", "rb_rho_at", "rb_backward", "rb_cluster_peaks", "rb_debug_rho",
+             "rb_filter_stream", "rb_filter_batch", "mf_full", "rb_rho_at", "rb_backward", "rb_cluster_peaks", "rb_debug_rho",
              "rb_debug_rho_binned", "rb_debug_basis_outputs"]
 
 
@@ -93,6 +93,8 @@ def lib():
         L.rb_filter.argtypes = [vp, C.POINTER(vp), i32, vp, vp, C.POINTER(FilterOpts), vp, i64,
                                 C.POINTER(i64), vp, C.POINTER(Stats)]
         L.mf_full.argtypes = [vp, vp, vp, dbl, vp, i64, C.POINTER(i64), vp, C.POINTER(Stats)]
+        L.rb_filter_stream.argtypes = [vp, C.POINTER(vp), i32, vp, vp, i64, C.POINTER(FilterOpts), vp, i64,
+                                       C.POINTER(i64), C.POINTER(Stats)]
         L.rb_filter_batch.argtypes = [vp, i32, vp, C.POINTER(FilterOpts), i32, vp, i64, C.POINTER(i64),
                                       C.POINTER(Stats)]
         L.rb_rho_at.argtypes = [vp, vp, vp, vp, i64, vp, vp]
@@ -267,6 +269,23 @@ def rb_filter(ctx: Context, bases, bank: Bank, strain, thr1: float, thr2: float,
     _check(lib().rb_filter(ctx.h, arr, len(bases), bank.h, _ptr(strain), C.byref(o), _ptr(buf), cap,
                            C.byref(n), _ptr(pk), C.byref(st)), "rb_filter")
     return _as_np_triggers(buf, n.value) if not dev else n.value, pk, st
+
+
+def rb_filter_stream(ctx: Context, bases, bank: Bank, strain, thr1: float, thr2: float,
+                     stage2: int = RB_STAGE2_FULL, cap: int = 1 << 20, bin_w: int = 0, thr_bin: float = 0.0,
+                     bin_source: int = 0):
+    """Overlap-save search of a strain longer than the bank's segment.
+    Returns (TRIGGER_NP array with stream samples, Stats)."""
+    if isinstance(bases, Basis):
+        bases = [bases]
+    arr = (C.c_void_p * len(bases))(*[b.h.value for b in bases])
+    o = FilterOpts(thr1, thr2, stage2, int(bin_w), float(thr_bin), int(bin_source), 0)
+    buf = _triggers_out(cap, False)
+    n = C.c_int64()
+    st = Stats()
+    _check(lib().rb_filter_stream(ctx.h, arr, len(bases), bank.h, _ptr(strain), int(strain.shape[0]), C.byref(o),
+                                  _ptr(buf), buf.shape[0], C.byref(n), C.byref(st)), "rb_filter_stream")
+    return _as_np_triggers(buf, n.value), st
 
 
 def mf_full(ctx: Context, bank: Bank, strain, thr: float, cap: int = 1 << 20, peaks: bool = False,
