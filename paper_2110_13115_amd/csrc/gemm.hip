@@ -304,19 +304,25 @@ __device__ __forceinline__ void recon_f32_tile(const GemmArgs& a, int rb0, int64
   epilogue_lane<RB, CB>(a, acc, rb0, q0);
 }
 
+// One workgroup = one row tile of RB 16-template blocks; its four waves take
+// adjacent column tiles of CB 32-sample blocks (so every wave of a workgroup
+// has the same share of padding rows, and a sub-bank whose template count is
+// not a multiple of 128 leaves no wave idle beside busy ones).
 template <int RB, int CB, int G>
 __global__ __launch_bounds__(256, 2) void k_recon_f32(GemmArgs a) {   // at least 2 waves per SIMD
-  constexpr int TT = WAVES * RB * 16;   // templates per workgroup
-  constexpr int TN = CB * 32;           // G: k-steps per pipeline group
+  constexpr int TT = RB * 16;           // templates per workgroup
+  constexpr int TN = CB * 32;           // samples per wave; G: k-steps per pipeline group
   const int ntt = a.Tp / TT;
-  const int64_t nwg = (int64_t)ntt * (a.N / TN);
+  const int64_t ncol = (a.N + WAVES * TN - 1) / (WAVES * TN);
+  const int64_t nwg = (int64_t)ntt * ncol;
   int tt;
   int64_t st;
   if (!xcd_tile(ntt, nwg, tt, st)) return;
   const int wave = threadIdx.x >> 6;
-  const int rb0 = tt * (TT / 16) + wave * RB;     // first 16-template row block
-  if (rb0 * 16 >= a.T) return;                             // all of this wave's rows are padding
-  const int64_t q0 = st * TN;
+  const int rb0 = tt * RB;                                 // first 16-template row block
+  if (rb0 * 16 >= a.T) return;                             // all of this tile's rows are padding
+  const int64_t q0 = (st * WAVES + wave) * TN;
+  if (q0 >= a.N) return;                                   // (N is a multiple of TN)
   // a wave whose second row block is all padding runs the one-block tile
   if (RB == 2 && (rb0 + 1) * 16 >= a.T)
     recon_f32_tile<1, CB, G>(a, rb0, q0);
@@ -586,7 +592,7 @@ hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
                         // variant 0 = 2 x 2 / 4, 1 = 2 x 4 / 4, 2 = 1 x 4 / 4, 3 = 2 x 4 / 2
     const int rbw = a.variant == 2 ? 1 : 2;
     const int TN = a.variant == 0 ? 64 : 128;
-    const int64_t nwg = (int64_t)(a.Tp / (WAVES * rbw * 16)) * (a.N / TN);
+    const int64_t nwg = (int64_t)(a.Tp / (rbw * 16)) * ((a.N + WAVES * TN - 1) / (WAVES * TN));
     const int64_t launch = ((nwg + 7) / 8) * 8;
     if (a.variant == 3)
       hipLaunchKernelGGL((k_recon_f32<2, 4, 2>), dim3((unsigned)launch), dim3(256), 0, st, a);
