@@ -10,9 +10,10 @@
 // Workgroup (x, y) takes template list[x] and its crossing groups y, y + G,
 // y + 2G, ... (G = gridDim.y, groups of up to SP_M crossings), streaming w_j
 // once per group; G > 1 spreads templates with many crossings (near a loud
-// signal) over several workgroups.  A thread owns 8 consecutive bins of each 2048-bin tile:
+// signal) over several workgroups.  A thread owns the bins t, t + 256, ...,
+// t + 7 * 256 of each 2048-bin tile (so every load of a wave is contiguous):
 // the twiddle of its first bin comes exactly from the two-level table
-// (e = f n mod N), the next seven by multiplication with e^{2 pi i n / N}
+// (e = f n mod N), the next seven by multiplication with e^{2 pi i 256 n / N}
 // (error <= 8 ulp).
 #include "internal.h"
 
@@ -34,9 +35,9 @@ __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 
-// One group of M (a power of two, >= m) crossings of template j: slots m..M-1
-// repeat the last crossing and are discarded, so the sums are straight-line
-// code across the M crossings.
+// One group of M (>= m) crossings of template j: slots m..M-1 repeat the last
+// crossing and are discarded, so the sums are straight-line code across the
+// M crossings (the caller instantiates M = m).
 template <int M>
 __device__ __forceinline__ void sparse_group(const SparseArgs& a, const float2* tlo, const float2* thi,
                                              float2 (*red)[SP_T / 64], int j, int c0, int m, int lo, int hi,
@@ -49,12 +50,12 @@ __device__ __forceinline__ void sparse_group(const SparseArgs& a, const float2* 
   const int off = a.offsets[j];
   int ns[M], e[M], inc[M];
   float2 step[M], acc[M];
-  const int f00 = lo + threadIdx.x * SP_R;
+  const int f00 = lo + threadIdx.x;
 #pragma unroll
   for (int i = 0; i < M; ++i) ns[i] = a.recs[off + c0 + min(i, m - 1)].sample;
 #pragma unroll
   for (int i = 0; i < M; ++i) {
-    step[i] = tw(ns[i]);
+    step[i] = tw((int)(((int64_t)SP_T * ns[i]) % N));
     acc[i] = make_float2(0.f, 0.f);
     e[i] = (int)(((int64_t)f00 * ns[i]) % N);                   // exponent of this thread's first bin
     inc[i] = (int)(((int64_t)(SP_T * SP_R) * ns[i]) % N);       // advance per tile
@@ -65,7 +66,7 @@ __device__ __forceinline__ void sparse_group(const SparseArgs& a, const float2* 
   auto fetch = [&](int f0) {
 #pragma unroll
     for (int r = 0; r < SP_R; ++r) {
-      const int f = min(f0 + r, hi);
+      const int f = min(f0 + r * SP_T, hi);
       dn[r] = d[f];
       wn[r] = wj[f];
     }
@@ -76,7 +77,7 @@ __device__ __forceinline__ void sparse_group(const SparseArgs& a, const float2* 
 #pragma unroll
     for (int r = 0; r < SP_R; ++r) {
       const float2 dv = dn[r], wv = wn[r];
-      const float mk = (f0 + r <= hi) ? 1.f : 0.f;
+      const float mk = (f0 + r * SP_T <= hi) ? 1.f : 0.f;
       x[r] = make_float2(mk * fmaf(dv.x, wv.x, dv.y * wv.y), mk * fmaf(dv.y, wv.x, -(dv.x * wv.y)));   // d conj(w)
     }
     fetch(f0 + SP_T * SP_R);
@@ -164,14 +165,16 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
   unsigned long long best = 0ull;
   for (int c0 = blockIdx.y * SP_M; c0 < cnt; c0 += gridDim.y * SP_M) {
     const int m = min(SP_M, cnt - c0);            // uniform over the workgroup
-    if (m <= 1)
-      sparse_group<1>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best);
-    else if (m <= 2)
-      sparse_group<2>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best);
-    else if (m <= 4)
-      sparse_group<4>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best);
-    else
-      sparse_group<8>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best);
+    switch (m) {   // straight-line sums over exactly m crossings
+      case 1: sparse_group<1>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
+      case 2: sparse_group<2>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
+      case 3: sparse_group<3>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
+      case 4: sparse_group<4>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
+      case 5: sparse_group<5>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
+      case 6: sparse_group<6>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
+      case 7: sparse_group<7>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
+      default: sparse_group<8>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
+    }
   }
   if (a.tmpl_max != nullptr && threadIdx.x < SP_M && best != 0ull) atomicMax(&a.tmpl_max[j], best);
 }
