@@ -294,9 +294,10 @@ typedef struct {
 
 /* Batched hierarchical search (Sec. III.B sub-banks x segments of any length;
  * one item per (segment, bank)).  Each item runs the same steps as rb_filter
- * (FULL or SPARSE second stage, bin_w 0 or 1; RB_ERR_UNSUPPORTED otherwise)
- * with device-side counts, so the whole batch is a sequence of kernel
- * launches with no host synchronisation inside.
+ * (FULL, SPARSE or RECON second stage, any bin_w with bin_source 0;
+ * RB_ERR_UNSUPPORTED for AUTO or bin_source 1) with device-side counts, so
+ * the whole batch is a sequence of kernel launches with no host
+ * synchronisation inside.
  *   use_graph  1: the batch is captured once into a hipGraph (keyed by the
  *              item pointers, thresholds and capacities) and replayed on later
  *              calls with the same key: refill the strain buffers and call

@@ -2136,9 +2136,26 @@ rb_status enqueue_item(rb_ctx ctx, const rb_batch_item& it, const rb_filter_opts
   RB_TRY(fill32(ctx, ctx->counters.p, 0u, 4));
   RB_TRY(fill32(ctx, ctx->cnt1.p, 0u, T));
   const float thr1sq = (float)(opts->thr1 * opts->thr1);
-  for (int32_t m = 0; m < it.nbases; ++m) {
-    RB_TRY(step_basis_outputs(ctx, it.bases[m], g, tw));
-    RB_TRY(stage1_gemm(ctx, it.bases[m], g, thr1sq, nullptr));
+  const int w = opts->bin_w >= 2 ? opts->bin_w : 1;
+  if (w > 1) {   // binned first stage: bins appended after the snapshot of their counter, per basis
+    const FftGeom gb = binned_geom(g, w);
+    RB_TRY(fill32(ctx, ctx->counters.as<unsigned long long>() + 2, 0u, 2));
+    RB_TRY(fill32(ctx, ctx->cntB.p, 0u, T));
+    RB_TRY(ctx->snap.ensure((size_t)it.nbases * 8));
+    for (int32_t m = 0; m < it.nbases; ++m) {
+      RB_TRY(step_basis_outputs_binned(ctx, it.bases[m], gb, tw, w));
+      unsigned long long* snap = ctx->snap.as<unsigned long long>() + m;
+      RB_HIP(launch_copy_u64(ctx->counters.as<unsigned long long>() + 2, snap, ctx->stream));
+      RB_TRY(stage1_gemm(ctx, it.bases[m], gb, (float)(opts->thr_bin * opts->thr_bin), nullptr, w));
+      RB_TRY(step_fine(ctx, it.bases[m], gb, w, thr1sq, snap));
+    }
+    RB_HIP(launch_copy_u64(ctx->counters.as<unsigned long long>() + 2, reinterpret_cast<unsigned long long*>(sm + 7),
+                           ctx->stream));
+  } else {
+    for (int32_t m = 0; m < it.nbases; ++m) {
+      RB_TRY(step_basis_outputs(ctx, it.bases[m], g, tw));
+      RB_TRY(stage1_gemm(ctx, it.bases[m], g, thr1sq, nullptr));
+    }
   }
   RB_HIP(launch_scan_counts(ctx->cnt1.as<int32_t>(), T, ctx->off1.as<int32_t>(), ctx->fill1.as<int32_t>(),
                             ctx->list1.as<int32_t>(), sm, ctx->stream));
@@ -2146,7 +2163,24 @@ rb_status enqueue_item(rb_ctx ctx, const rb_batch_item& it, const rb_filter_opts
   RB_TRY(fill32(ctx, ctx->tmax.p, 0u, 2 * (int64_t)T));
   // the low word of sm[1] (little-endian int64, < 2^31) is the stage-1 template count
   const int32_t* nsel = reinterpret_cast<const int32_t*>(sm + 1);
-  if (opts->stage2 == RB_STAGE2_SPARSE) {
+  if (opts->stage2 == RB_STAGE2_RECON) {   // the candidates' own reconstruction is final above thr2
+    float* inv = nullptr;
+    bool scaled = false;
+    for (int32_t m = 0; m < it.nbases; ++m) scaled |= w == 1 && it.bases[m]->dtype != RB_F32;
+    if (scaled) {
+      RB_TRY(ctx->tinv.ensure((size_t)T * 4));
+      for (int32_t m = 0; m < it.nbases; ++m)
+        RB_HIP(hipMemcpyAsync(ctx->tinv.as<float>() + it.bases[m]->t0, it.bases[m]->row_inv.p,
+                              (size_t)it.bases[m]->T * 4, hipMemcpyDeviceToDevice, ctx->stream));
+      inv = ctx->tinv.as<float>();
+    }
+    RB_TRY(fill32(ctx, ctx->counters.as<unsigned long long>() + 1, 0u, 2));
+    RB_HIP(launch_select_final(ctx->trig1.as<TrigRec>(), ctx->counters.as<unsigned long long>(),
+                               trig_capacity(ctx->trig1), inv, (float)(opts->thr2 * opts->thr2),
+                               ctx->trig2.as<TrigRec>(), trig_capacity(ctx->trig2),
+                               ctx->counters.as<unsigned long long>() + 1, ctx->cnt2.as<int32_t>(), nullptr,
+                               trig_capacity(ctx->trig1), ctx->stream));
+  } else if (opts->stage2 == RB_STAGE2_SPARSE) {
     // group the stage-1 records by template (skipped, like the stage itself, when they overflowed)
     const int64_t cap1 = trig_capacity(ctx->trig1);
     RB_HIP(launch_scatter_triggers(ctx->trig1.as<TrigRec>(), cap1, sm, ctx->off1.as<int32_t>(),
@@ -2190,7 +2224,8 @@ std::string batch_key(int32_t n, const rb_batch_item* items, const rb_filter_opt
   }
   const void* bufs[] = {ctx->work.p, ctx->work64.p, ctx->dspec.p, ctx->z.p, ctx->trig1.p, ctx->trig2.p,
                         ctx->recs.p, ctx->tmp.p, ctx->bsum.p, ctx->bout.p, ctx->cnt1.p, ctx->cnt2.p,
-                        ctx->recs1.p};
+                        ctx->recs1.p, ctx->zfine.p, ctx->zpart.p, ctx->trigB.p, ctx->cntB.p, ctx->snap.p,
+                        ctx->tinv.p};
   add(bufs, sizeof(bufs));
   return k;
 }
@@ -2205,12 +2240,19 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
   RB_CHECK(cap_item >= 0 && (out != nullptr || cap_item == 0), RB_ERR_ARG, "bad output buffer");
   RB_CHECK(std::isfinite(opts->thr1) && opts->thr1 > 0, RB_ERR_ARG, "thr1 must be > 0");
   RB_CHECK(std::isfinite(opts->thr2) && opts->thr2 >= opts->thr1, RB_ERR_ARG, "thr2 must be >= thr1");
-  RB_CHECK(opts->stage2 != RB_STAGE2_AUTO && opts->stage2 != RB_STAGE2_RECON, RB_ERR_UNSUPPORTED,
-           "the batch search takes FULL or SPARSE");
-  RB_CHECK(opts->bin_w <= 1, RB_ERR_UNSUPPORTED, "the batch search takes bin_w 0 or 1");
-  RB_CHECK(opts->stage2 == RB_STAGE2_FULL || opts->stage2 == RB_STAGE2_SPARSE, RB_ERR_ARG, "bad stage2 mode");
-  RB_CHECK(opts->bin_w >= 0, RB_ERR_ARG, "bin_w must be >= 0");
-  RB_CHECK(opts->bin_source == 0 && opts->reserved == 0, RB_ERR_ARG, "bin_source and reserved must be 0");
+  RB_CHECK(opts->stage2 != RB_STAGE2_AUTO, RB_ERR_UNSUPPORTED, "the batch search takes FULL, SPARSE or RECON");
+  RB_CHECK(opts->bin_source == 0, RB_ERR_UNSUPPORTED, "the batch search takes bin_source 0");
+  RB_CHECK(opts->stage2 == RB_STAGE2_FULL || opts->stage2 == RB_STAGE2_SPARSE || opts->stage2 == RB_STAGE2_RECON,
+           RB_ERR_ARG, "bad stage2 mode");
+  RB_CHECK(opts->reserved == 0, RB_ERR_ARG, "reserved must be 0");
+  {
+    const int w = opts->bin_w >= 2 ? opts->bin_w : 1;
+    RB_CHECK(opts->bin_w >= 0 && opts->bin_w <= 64 && (w & (w - 1)) == 0, RB_ERR_ARG,
+             "bin_w must be 0, 1 or a power of two <= 64");
+    RB_CHECK(w == 1 || (std::isfinite(opts->thr_bin) && opts->thr_bin > 0), RB_ERR_ARG, "thr_bin must be > 0");
+    for (int32_t i = 0; i < nitems; ++i)
+      RB_CHECK(items[i].bank == nullptr || items[i].bank->grid.N / w >= 256, RB_ERR_ARG, "N / bin_w must be >= 256");
+  }
   int Tmax = 0;
   for (int32_t i = 0; i < nitems; ++i) {
     const rb_batch_item& it = items[i];
@@ -2286,6 +2328,10 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
         RB_TRY(ctx->recs1.ensure(c * sizeof(TrigRec)));
         grow = true;
       }
+      if (opts->bin_w >= 2 && q[7] > trig_capacity(ctx->trigB)) {
+        RB_TRY(ctx->trigB.ensure((size_t)(q[7] + q[7] / 4) * sizeof(TrigRec)));
+        grow = true;
+      }
       if (q[4] > trig_capacity(ctx->trig2)) {
         const size_t c = (size_t)(q[4] + q[4] / 4);
         RB_TRY(ctx->trig2.ensure(c * sizeof(TrigRec)));
@@ -2313,6 +2359,7 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
     for (int32_t i = 0; i < nitems; ++i) {
       stats->n_stage1 += sm[8 * (size_t)i];
       stats->n_refiltered += (int32_t)sm[8 * (size_t)i + 1];
+      if (opts->bin_w >= 2) stats->n_bins += sm[8 * (size_t)i + 7];
     }
     stats->ms[6] = elapsed(ctx, 0, 2);
   }

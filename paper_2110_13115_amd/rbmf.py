@@ -373,7 +373,8 @@ class BatchItem(C.Structure):
 
 
 def rb_filter_batch(ctx: Context, items, thr1: float, thr2: float, use_graph: bool = True,
-                    cap_item: int = 1 << 16, out=None, stage2: int = RB_STAGE2_FULL):
+                    cap_item: int = 1 << 16, out=None, stage2: int = RB_STAGE2_FULL, bin_w: int = 0,
+                    thr_bin: float = 0.0):
     """items: list of (device strain tensor, Bank, [Basis, ...]).  Returns
     (list of per-item TRIGGER_NP arrays, Stats); with a device `out` buffer
     (nitems * cap_item x 4 int32) returns (counts, Stats) instead."""
@@ -386,7 +387,7 @@ def rb_filter_batch(ctx: Context, items, thr1: float, thr2: float, use_graph: bo
         bp = (C.c_void_p * len(bases))(*[b.h.value for b in bases])
         keep.append(bp)
         arr[i] = BatchItem(_ptr(s), bank.h.value, C.cast(bp, C.POINTER(C.c_void_p)), len(bases))
-    o = FilterOpts(thr1, thr2, stage2, 0, 0.0, 0, 0)
+    o = FilterOpts(thr1, thr2, stage2, int(bin_w), float(thr_bin), 0, 0)
     dev = out is not None and not isinstance(out, np.ndarray)
     buf = out if out is not None else np.empty(max(1, n * cap_item), dtype=TRIGGER_NP)
     counts = (C.c_int64 * n)()

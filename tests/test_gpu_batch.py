@@ -114,6 +114,26 @@ def test_batch_sparse_stage2(batch):
     log("sparse batch ok", [len(x) for x in eager], "full-stage extras", missed)
 
 
+@pytest.mark.parametrize("stage2", ["recon", "sparse"])
+def test_batch_binned(batch, stage2):
+    """The binned first stage in the batch (eager and graph replays) gives
+    each item exactly the triggers of its own binned rb_filter call, at
+    several bin widths (the items' grids need different FFT splits)."""
+    ctx, setups, items, strains = batch
+    mode = rbmf.RB_STAGE2_RECON if stage2 == "recon" else rbmf.RB_STAGE2_SPARSE
+    for w, tb in ((4, 3.5), (8, 3.0)):
+        eager, _ = rbmf.rb_filter_batch(ctx, items, 5.0, 6.0, use_graph=False, stage2=mode, bin_w=w, thr_bin=tb)
+        graph, st = rbmf.rb_filter_batch(ctx, items, 5.0, 6.0, use_graph=True, stage2=mode, bin_w=w, thr_bin=tb)
+        again, _ = rbmf.rb_filter_batch(ctx, items, 5.0, 6.0, use_graph=True, stage2=mode, bin_w=w, thr_bin=tb)
+        for i, (sd, bank, bases) in enumerate(items):
+            one, _, s1 = rbmf.rb_filter(ctx, bases, bank, sd, 5.0, 6.0, stage2=mode, bin_w=w, thr_bin=tb)
+            assert one.tobytes() == eager[i].tobytes(), (w, i)
+            assert one.tobytes() == graph[i].tobytes(), (w, i)
+            assert one.tobytes() == again[i].tobytes(), (w, i)
+        log("binned batch", stage2, w, [len(x) for x in graph], "bins", st.n_bins)
+        assert sum(len(x) for x in graph) > 0
+
+
 def test_batch_rejects_auto_stage2(batch):
     ctx, setups, items, strains = batch
     with pytest.raises(rbmf.RbError) as ei:
