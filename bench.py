@@ -231,6 +231,35 @@ def run_batch(args, wname):
     t_g, (res, st) = time_calls(replay, args.steps, args.warmup, torch)
     t_e, _ = time_calls(eager_run, max(1, args.steps // 2), 0, torch)
     tsec = sum(bw.T * n / bw.fs for n in lens)
+    # the binned first stage with the paper's own second stage, rho_I by the target-SNR
+    # rule on an independent segment of the most frequent length
+    from paper_2110_13115_amd import tuning
+    Nt = max(set(lens), key=lens.count)
+    bd, psd, bank_t, bases_t = per_n[Nt]
+
+    def sigma_t(h):
+        b = rbmf.Bank(ctx, Nt, bw.fs, bw.f_low, psd, 1, lambda t0, t1, k0, k1: h[None, k0:k1])
+        s = b.info()[3][0]
+        b.close()
+        return s
+    st_t = torch.from_numpy(bw.strain(bw.nseg, Nt, bd, sigma_t)).cuda()
+    thr_bin, table = tuning.tune_bin_threshold(ctx, bases_t, bank_t, st_t, bw.bin_w, bw.thr1, bw.thr2,
+                                               bw.thr_bin_grid)
+    log(f"binned w={bw.bin_w}: rho_I = {thr_bin} from the tuning segment "
+        f"{[(r['thr_bin'], r['target_snr']) for r in table]}")
+
+    def replay_binned():
+        return rbmf.rb_filter_batch(ctx, items, bw.thr1, bw.thr2, use_graph=True, cap_item=cap_item,
+                                    stage2=rbmf.RB_STAGE2_RECON, bin_w=bw.bin_w, thr_bin=thr_bin)
+    t_b, (res_b, st_b) = time_calls(replay_binned, args.steps, args.warmup, torch)
+    exact = sum(len(x) for x in res)
+    kept = sum(len(set(zip(a["tmpl"].tolist(), a["sample"].tolist())) & set(zip(b["tmpl"].tolist(),
+                                                                              b["sample"].tolist())))
+               for a, b in zip(res, res_b))
+    binned = {"value": tsec / t_b, "ms_per_step": t_b * 1e3, "w": bw.bin_w, "thr_bin": thr_bin,
+              "stage2": "recon", "kept_of_exact": kept / max(1, exact), "bins": int(st_b.n_bins),
+              "final_triggers": int(sum(len(x) for x in res_b)), "tuning_segment": table}
+    log(f"binned batch: {t_b * 1e3:.1f} ms/step (exact {t_g * 1e3:.1f}), kept {kept}/{exact}")
     line = {
         "metric": "template-seconds filtered/s: batched RB search (hipGraph), 1 MI355X",
         "value": tsec / t_g, "unit": "template-s/s", "n_gpus": 1, "steps": args.steps,
@@ -241,7 +270,7 @@ def run_batch(args, wname):
                    "thr1": bw.thr1, "thr2": bw.thr2, "stage2": "sparse exact"},
         "eager_ms_per_step": t_e * 1e3, "graph_equals_eager": bool(same),
         "final_triggers": int(sum(len(x) for x in res)), "stage1_crossings": int(st.n_stage1),
-        "refiltered": int(st.n_refiltered), "prep_s": prep_s,
+        "refiltered": int(st.n_refiltered), "prep_s": prep_s, "binned_recon": binned,
     }
     print(json.dumps(line), flush=True)
 

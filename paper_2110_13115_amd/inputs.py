@@ -421,6 +421,8 @@ class BatchWorkload:
     thr1: float = 5.0
     thr2: float = 6.0
     inj_snr: Tuple[float, float] = (6.0, 12.0)
+    bin_w: int = 4                 # binned first stage: samples per bin
+    thr_bin_grid: Tuple[float, ...] = (3.0, 3.25, 3.5, 3.75, 4.0)   # rho_I values tried
 
     def segment_lengths(self) -> List[int]:
         rng = rng_for(self.cfg, PURPOSE_LEN)
