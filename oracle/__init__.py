@@ -18,6 +18,11 @@ hier    the binned (hierarchical) first stage: bin means of the basis
         the target SNR of Eq. target_snr_criteria (Sec. III.C-D, III.F).
 stream  overlap-save segmentation of a long strain (Sec. III.E): segment
         starts, valid windows, stitched trigger lists.
+nonuniform
+        PCA of the bank sampled at the non-uniform frequency set (zero
+        crossings of a reference template, a few frequencies per bin, a
+        floor on the spacing) and linear interpolation of the basis onto the
+        uniform grid (Sec. III.A, the interpolation step of Sec. III.C).
 grad    loss sum g |rho|^2 over a frozen trigger set and its gradients with
         respect to the coefficients and the strain (torch CPU float64
         autograd through an independent plain forward).
