@@ -147,6 +147,55 @@ def binned_runs(ctx, wl, bank_def, bank, bases_by_dt, sd, out, mf_trig, t_mf, si
     return res
 
 
+def nonuniform_runs(ctx, wl, bank_def, bank, sd, out, mf_trig, s1_uniform, prep_uniform_s, args, torch):
+    """Sub-bank bases by PCA on the non-uniform frequency set (zero crossings
+    of the longest template, five frequencies per bin, spacing floor = the
+    grid step, f_ISCO cuts as extra nodes), interpolated onto the grid: set
+    size, build time beside the uniform bases', kept energy, and the search
+    with them (FP32, sparse exact second stage)."""
+    from paper_2110_13115_amd import inputs as gi
+    from paper_2110_13115_amd import rbmf
+    df = bank_def.df
+    k_lo, k_hi = int(np.ceil(wl.f_low / df - 1e-9)), wl.N // 2 - 1
+    j = bank_def.longest()
+    f = k_lo * df + (df / 8) * np.arange(8 * (k_hi - k_lo) + 1, dtype=np.float64)
+    t0 = time.time()
+    nodes = rbmf.nonuniform_freqs(f, bank_def.fill_at(j, j + 1, f)[0].real, 5, df, bank_def.support_ends())
+    t_set = time.time() - t0
+    psd_n = gi.aligo_psd(nodes)
+    b = wl.bounds()
+    fill_s = [0.0]
+
+    def fill_at(t0, t1, fr):        # the host template generator, timed apart from the build
+        t = time.time()
+        h = bank_def.fill_at(t0, t1, fr)
+        fill_s[0] += time.time() - t
+        return h
+    t0 = time.time()
+    nu = [rbmf.Basis.nonuniform(ctx, bank, nodes, psd_n, fill_at, rank=r, tol=wl.tol, dtype="f32",
+                                t0=b[i], t1=b[i + 1]) for i, r in enumerate(wl.sub_ranks())]
+    t_nu = time.time() - t0
+    log(f"non-uniform set: {len(nodes)} of {k_hi - k_lo + 1} band bins ({t_set:.2f} s); bases K={[x.K for x in nu]} "
+        f"in {t_nu:.2f} s, of which {fill_s[0]:.2f} s host template generation (uniform {prep_uniform_s:.2f} s)")
+
+    def call():
+        n, _, st = rbmf.rb_filter(ctx, nu, bank, sd, wl.thr1, wl.thr2, stage2=rbmf.RB_STAGE2_SPARSE, out=out)
+        return n, st
+    t, (n, st) = time_calls(call, args.steps, args.warmup, torch)
+    tr = out[:n].cpu().numpy().view(rbmf.TRIGGER_NP).reshape(-1)
+    same = n == len(mf_trig) and np.array_equal(tr[["tmpl", "sample"]], mf_trig[["tmpl", "sample"]])
+    res = {"nodes": int(len(nodes)), "band_bins": int(k_hi - k_lo + 1), "set_s": t_set, "build_s": t_nu,
+           "host_template_s": fill_s[0],
+           "uniform_build_s": prep_uniform_s, "ranks": [x.K for x in nu],
+           "min_energy": min(x.energy for x in nu), "ms_per_step": t * 1e3,
+           "value": wl.T * wl.seconds / t, "final_triggers_equal_mf": bool(same),
+           "stage1_crossings": int(st.n_stage1), "stage1_crossings_uniform_basis": int(s1_uniform)}
+    log(f"rb_filter with non-uniform bases: {t * 1e3:.2f} ms/step, final == mf: {same}")
+    for x in nu:
+        x.close()
+    return res
+
+
 def paper_regime(args, torch):
     """The paper's regime: one dense tau0 sub-bank (6250 templates of a
     200 000-template bank, K ~ 40 at 0.999 energy), 128 s: the template method,
@@ -293,6 +342,7 @@ def main():
     ap.add_argument("--thr-bin", type=float, default=4.0, help="rho_I of --binned-only")
     ap.add_argument("--dtypes", default="f32,bf16", help="storage types of --binned-only")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense sub-bank (paper regime) runs")
+    ap.add_argument("--no-nonuniform", action="store_true", help="skip the non-uniform-frequency basis runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device-to-device copy of MIB MiB and exit (scales HBM byte "
                          "counters)")
@@ -441,6 +491,9 @@ def main():
                                       t_mf, sigma_of, args, torch)
         for b in b16:
             b.close()
+    if not args.no_nonuniform:
+        extra["nonuniform_basis"] = nonuniform_runs(ctx, wl, bank_def, bank, sd, out, mf_trig, s1[-1],
+                                                    prep_basis_s, args, torch)
     if not args.no_dense:
         extra["paper_regime"] = paper_regime(args, torch)
 

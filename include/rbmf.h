@@ -156,6 +156,14 @@ typedef struct {
 typedef int (*rb_bank_fill_fn)(void* user, int32_t t0, int32_t t1, int64_t k0, int64_t k1,
                                double* out);
 
+/* Template source at arbitrary frequencies.  Fills out[(t1-t0) * nf * 2]
+ * with the complex128 values h_j(f[i]) (interleaved re, im; row-major over
+ * templates) of templates [t0, t1) at the nf host frequencies f (Hz).
+ * Returns 0 on success.  Called from the thread that called the builder,
+ * never concurrently. */
+typedef int (*rb_fill_at_fn)(void* user, int32_t t0, int32_t t1, const double* f, int64_t nf,
+                             double* out);
+
 /* ------------------------------------------------------------------ context */
 
 /* Create a context on HIP device `device`, ordering all work on `hip_stream`
@@ -217,6 +225,63 @@ rb_status rb_build_basis(rb_ctx ctx, rb_bank bank, int32_t rank, double tol, rb_
 rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, int32_t t1, int32_t rank,
                                double tol, rb_dtype dtype, rb_basis* out, int32_t* rank_out,
                                double* energy_out);
+
+/* Non-uniform frequency set for the PCA (Sec. III.A, PCA using non-uniform
+ * sampling).  Host only: touches no device.
+ *   f, h_re  host, n >= 2 samples of one reference template (the longest
+ *            of the bank) over [f[0], f[n-1]]: strictly increasing finite
+ *            frequencies and the finite real part of h there.  The samples
+ *            must resolve its oscillation (several per half-cycle).
+ *   per_bin  frequencies per bin, 1..1024 (the paper takes five).
+ *   df_min   floor on the spacing (> 0; the paper takes 1/128 Hz, the grid
+ *            step of its 128 s segments).
+ *   extra    host, n_extra frequencies merged into the set where they fall
+ *            strictly inside (f[0], f[n-1]) (may be NULL when n_extra == 0);
+ *            e.g. the uniform frequencies on either side of each template's
+ *            f_ISCO cut, which linear interpolation could not follow else.
+ * The zero crossings of h_re (a sign change between consecutive samples,
+ * located by linear interpolation, or an interior sample exactly zero) cut
+ * [f[0], f[n-1]] into bins [e_b, e_{b+1}); a bin takes the per_bin
+ * frequencies e_b + m (e_{b+1} - e_b) / per_bin, or, when that spacing is
+ * below df_min, the multiples k df_min inside it (so with df_min equal to a
+ * segment's grid step the dense part of the set is that grid itself); f[n-1]
+ * closes the set.  Output: the strictly increasing set in out[0 .. *n_out).
+ * RB_ERR_CAPACITY (with *n_out = the size needed) when it has more than
+ * cap entries; out may be NULL with cap == 0 to ask for the size.
+ * RB_ERR_ARG for bad arguments. */
+rb_status rb_nonuniform_freqs(const double* f, const double* h_re, int64_t n, int32_t per_bin, double df_min,
+                              const double* extra, int64_t n_extra, double* out, int64_t cap,
+                              int64_t* n_out);
+
+/* Basis of templates [t0, t1) built by PCA on a non-uniform frequency set
+ * and interpolated onto the bank's uniform grid (Sec. III.A; the
+ * interpolation step of Sec. III.C).
+ *   nodes      host, nt >= 2 strictly increasing frequencies covering the
+ *              band: nodes[0] <= k_lo df and nodes[nt-1] >= k_hi df
+ *              (typically from rb_nonuniform_freqs).
+ *   psd_nodes  host, nt one-sided PSD values Sn(nodes[i]), finite and > 0.
+ *   fill       the templates [t0, t1) at the nodes (the bank's own
+ *              templates, global indices).
+ *   rank, tol, dtype  as rb_build_basis_range (the rank rule runs on the
+ *              eigenvalues on the set).
+ * FP64 throughout: node i weighs omega_i, the width of its cell between the
+ * midpoints to its neighbours (end cells mirrored); the templates are
+ * whitened and normalised in that inner product,
+ * V[j][i] = h_j(f_i) sqrt(4 omega_i / Sn_i) / sigma_j, rounded to complex64
+ * on the device; the leading right singular vectors of V (eigenvectors of
+ * the covariance V^H V) by the same subspace iteration as the uniform
+ * basis; each, divided by sqrt(omega_i), interpolated linearly to the
+ * uniform frequencies k df of the band and multiplied by sqrt(df); the K
+ * interpolated vectors orthonormalised on the uniform grid; coefficients
+ * c_jk = <w_j, v_k> against the bank's uniform templates.  The rank can
+ * drop below the requested one only if interpolation made vectors linearly
+ * dependent.  energy_out: sum |c|^2 / sum |w_j|^2 on the uniform grid.
+ * rb_basis_export's lambda are the eigenvalues on the set.
+ * RB_ERR_ARG for bad nodes, PSD or range; RB_ERR_CALLBACK if fill fails. */
+rb_status rb_build_basis_nonuniform(rb_ctx ctx, rb_bank bank, int32_t t0, int32_t t1, const double* nodes,
+                                    int64_t nt, const double* psd_nodes, rb_fill_at_fn fill, void* user,
+                                    int32_t rank, double tol, rb_dtype dtype, rb_basis* out,
+                                    int32_t* rank_out, double* energy_out);
 
 /* Basis facts (outputs may be NULL). */
 rb_status rb_basis_info(rb_basis basis, int32_t* t0, int32_t* t1, int32_t* rank, double* energy);

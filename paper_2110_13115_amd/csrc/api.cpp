@@ -22,6 +22,7 @@
 
 #include "internal.h"
 #include "linalg.h"
+#include "nonuniform.h"
 
 namespace rbmf {
 
@@ -1045,41 +1046,24 @@ extern "C" rb_status rb_basis_info(rb_basis basis, int32_t* t0, int32_t* t1, int
   return RB_OK;
 }
 
-extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, int32_t t1, int32_t rank,
-                                          double tol, rb_dtype dtype, rb_basis* out, int32_t* rank_out,
-                                          double* energy_out) {
-  RB_TRY(validate_ctx(ctx));
-  RB_CHECK(bank != nullptr && out != nullptr, RB_ERR_ARG, "NULL argument");
-  RB_CHECK(bank->ctx == ctx, RB_ERR_ARG, "bank belongs to another context");
-  RB_CHECK(t0 >= 0 && t0 < t1 && t1 <= bank->T, RB_ERR_ARG, "template range must satisfy 0 <= t0 < t1 <= T");
-  RB_CHECK(rank >= 0, RB_ERR_ARG, "rank must be >= 0");
-  RB_CHECK(rank > 0 || (tol > 0 && tol < 1), RB_ERR_ARG, "tol must be in (0, 1) when rank == 0");
-  RB_CHECK(dtype == RB_F32 || dtype == RB_BF16 || dtype == RB_F16 || dtype == RB_BF16X3, RB_ERR_ARG,
-           "bad dtype");
-  *out = nullptr;
-  const int64_t T = t1 - t0;
-  const int64_t nb = bank->k_hi - bank->k_lo + 1, off = bank->k_lo - bank->kb, nbs = bank->nbs;
-  hipStream_t s = ctx->stream;
-  BasisWork bw;
-  RB_TRY(bw.ws.ensure((size_t)64 << 20 << 4));   // 64 Mi complex128 split-K partials (1 GiB)
-  // trace of the Gram = sum of stored squared norms
-  RB_TRY(bw.norms.ensure((size_t)T * 8));
-  const float2* W = bank->w.as<float2>() + (size_t)t0 * nbs + off;
-  RB_HIP(launch_row_norms(W, T, nb, nbs, bw.norms.as<double>(), s));
-  std::vector<double> norms(T);
-  RB_HIP(hipMemcpyAsync(norms.data(), bw.norms.p, T * 8, hipMemcpyDeviceToHost, s));
-  RB_HIP(hipStreamSynchronize(s));
-  double trace = 0.0;
-  for (double v : norms) trace += v;
+namespace {
 
-  const ZOperand Wop{W, 1, nbs, 1, 0};    // T x nb
-  const ZOperand WHop{W, 1, 1, nbs, 1};   // nb x T  (conjugate transpose)
+// Leading right singular subspace of the stored rows W (T x n complex64, row
+// stride ld), i.e. the leading eigenvectors of the covariance W^H W
+// (Sec. II.A; Sec. III.A-B): randomized subspace iteration with SVQB
+// orthonormalisation and a Rayleigh-Ritz step, the subspace doubled until
+// the rank rule is met with spare vectors.  On return bw.B = W^H Q (n x Lc),
+// theta / S the Ritz values and vectors of Q^H W W^H Q, K the kept rank.
+rb_status subspace_pca(rb_ctx ctx, BasisWork& bw, const float2* W, int64_t T, int64_t n, int64_t ld, double trace,
+                       int32_t rank, double tol, std::vector<double>& theta, std::vector<cd>& S, int& Lc, int& K) {
+  hipStream_t s = ctx->stream;
+  const ZOperand Wop{W, 1, ld, 1, 0};    // T x n
+  const ZOperand WHop{W, 1, 1, ld, 1};   // n x T  (conjugate transpose)
   const int over = 32;
   int L = (int)std::min<int64_t>(T, rank > 0 ? (int64_t)rank + std::max(over, rank / 4) : 160);
   const int q = 4;
-  std::vector<double> theta;
-  std::vector<cd> S;
-  int Lc = 0, K = 0;
+  Lc = 0;
+  K = 0;
   std::mt19937_64 rng(0x2110131150ull);
   std::normal_distribution<double> nd;
   for (;;) {
@@ -1090,14 +1074,14 @@ extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, 
     RB_TRY(bw.Y.ensure((size_t)T * L * 16));
     RB_HIP(hipMemcpyAsync(bw.Y.p, Om.data(), Om.size() * 16, hipMemcpyHostToDevice, s));
     RB_TRY(svqb(ctx, bw, bw.Y.as<double2>(), T, L, bw.Q.as<double2>(), &Lc));
-    RB_TRY(bw.B.ensure((size_t)nb * Lc * 16));
+    RB_TRY(bw.B.ensure((size_t)n * Lc * 16));
     if (Lc < T) {
       for (int it = 0; it < q; ++it) {
         ZOperand Qop{bw.Q.p, 0, Lc, 1, 0};
-        RB_HIP(launch_zgemm(nb, Lc, T, WHop, Qop, bw.B.as<double2>(), Lc, 0, bw.ws.as<double2>(),
+        RB_HIP(launch_zgemm(n, Lc, T, WHop, Qop, bw.B.as<double2>(), Lc, 0, bw.ws.as<double2>(),
                             (int64_t)(bw.ws.bytes / 16), s));
         ZOperand Bop{bw.B.p, 0, Lc, 1, 0};
-        RB_HIP(launch_zgemm(T, Lc, nb, Wop, Bop, bw.Y.as<double2>(), Lc, 0, bw.ws.as<double2>(),
+        RB_HIP(launch_zgemm(T, Lc, n, Wop, Bop, bw.Y.as<double2>(), Lc, 0, bw.ws.as<double2>(),
                             (int64_t)(bw.ws.bytes / 16), s));
         int Ln = 0;   // one SVQB pass between products, two after the last
         RB_TRY(svqb(ctx, bw, bw.Y.as<double2>(), T, Lc, bw.Q.as<double2>(), &Ln, it + 1 < q ? 1 : 2));
@@ -1107,12 +1091,12 @@ extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, 
     // Rayleigh-Ritz: B = W^H Q, M = B^H B = Q^H G Q
     {
       ZOperand Qop{bw.Q.p, 0, Lc, 1, 0};
-      RB_HIP(launch_zgemm(nb, Lc, T, WHop, Qop, bw.B.as<double2>(), Lc, 0, bw.ws.as<double2>(),
+      RB_HIP(launch_zgemm(n, Lc, T, WHop, Qop, bw.B.as<double2>(), Lc, 0, bw.ws.as<double2>(),
                           (int64_t)(bw.ws.bytes / 16), s));
       RB_TRY(bw.M.ensure((size_t)Lc * Lc * 16));
       ZOperand BH{bw.B.p, 0, 1, Lc, 1};
       ZOperand Bo{bw.B.p, 0, Lc, 1, 0};
-      RB_HIP(launch_zgemm(Lc, Lc, nb, BH, Bo, bw.M.as<double2>(), Lc, 0, bw.ws.as<double2>(),
+      RB_HIP(launch_zgemm(Lc, Lc, n, BH, Bo, bw.M.as<double2>(), Lc, 0, bw.ws.as<double2>(),
                           (int64_t)(bw.ws.bytes / 16), s));
       std::vector<cd> Mh((size_t)Lc * Lc);
       RB_HIP(hipMemcpyAsync(Mh.data(), bw.M.p, Mh.size() * 16, hipMemcpyDeviceToHost, s));
@@ -1142,6 +1126,39 @@ extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, 
     L = (int)std::min<int64_t>(T, 2 * (int64_t)L);
   }
   RB_CHECK(K >= 1, RB_ERR_NUMERIC, "basis has rank zero");
+  return RB_OK;
+}
+
+// The K leading Ritz vectors BS = B S[:, :K] (n x K, complex128).
+rb_status ritz_vectors(rb_ctx ctx, BasisWork& bw, int64_t n, int Lc, int K, const std::vector<cd>& S, DevBuf& BS) {
+  hipStream_t s = ctx->stream;
+  std::vector<cd> Sk((size_t)Lc * K);
+  for (int i = 0; i < Lc; ++i)
+    for (int k = 0; k < K; ++k) Sk[(size_t)i * K + k] = S[(size_t)i * Lc + k];
+  DevBuf Sd;
+  RB_TRY(Sd.ensure(Sk.size() * 16));
+  RB_HIP(hipMemcpyAsync(Sd.p, Sk.data(), Sk.size() * 16, hipMemcpyHostToDevice, s));
+  RB_TRY(BS.ensure((size_t)n * K * 16));
+  ZOperand Bo{bw.B.p, 0, Lc, 1, 0};
+  ZOperand So{Sd.p, 0, K, 1, 0};
+  RB_HIP(launch_zgemm(n, K, Lc, Bo, So, BS.as<double2>(), K, 0, bw.ws.as<double2>(), (int64_t)(bw.ws.bytes / 16),
+                      s));
+  RB_HIP(hipStreamSynchronize(s));   // Sk is pageable and local
+  return RB_OK;
+}
+
+// Stores the basis of templates [t0, t0 + T): rows v_k = conj(BS[:, k]) sc[k]
+// over the band (BS: nb x K complex128 on the device), coefficients
+// c = W BS diag(sc) against the bank's uniform templates, C = conj(c) packed
+// for the reconstruction GEMM in `dtype`.  lambda: K values kept for export;
+// energy < 0: take sum |c|^2 / trace.
+rb_status finish_basis(rb_ctx ctx, rb_bank bank, int32_t t0, int64_t T, int K, const double2* BS,
+                       const std::vector<double>& sc, const double* lambda, double trace, double energy,
+                       rb_dtype dtype, BasisWork& bw, rb_basis* out, int32_t* rank_out, double* energy_out) {
+  hipStream_t s = ctx->stream;
+  const int64_t nb = bank->k_hi - bank->k_lo + 1, off = bank->k_lo - bank->kb, nbs = bank->nbs;
+  const float2* W = bank->w.as<float2>() + (size_t)t0 * nbs + off;
+  const ZOperand Wop{W, 1, nbs, 1, 0};
   std::unique_ptr<rb_basis_s> bs(new (std::nothrow) rb_basis_s);
   RB_CHECK(bs != nullptr, RB_ERR_OOM, "host allocation failed");
   bs->ctx = ctx;
@@ -1154,42 +1171,29 @@ extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, 
   bs->Tp = (int)(((T + tile - 1) / tile) * tile);
   bs->dtype = dtype;
   bs->trace = trace;
-  bs->lambda.assign(theta.begin(), theta.begin() + K);
-  double e = 0.0;
-  for (int k = 0; k < K; ++k) e += theta[k];
-  bs->energy = e / trace;
-  // BS = B S[:, :K]  (nb x K)
-  std::vector<cd> Sk((size_t)Lc * K);
-  for (int i = 0; i < Lc; ++i)
-    for (int k = 0; k < K; ++k) Sk[(size_t)i * K + k] = S[(size_t)i * Lc + k];
-  DevBuf Sd, BS, cdev, scale;
-  RB_TRY(Sd.ensure(Sk.size() * 16));
-  RB_HIP(hipMemcpyAsync(Sd.p, Sk.data(), Sk.size() * 16, hipMemcpyHostToDevice, s));
-  RB_TRY(BS.ensure((size_t)nb * K * 16));
-  {
-    ZOperand Bo{bw.B.p, 0, Lc, 1, 0};
-    ZOperand So{Sd.p, 0, K, 1, 0};
-    RB_HIP(launch_zgemm(nb, K, Lc, Bo, So, BS.as<double2>(), K, 0, bw.ws.as<double2>(),
-                        (int64_t)(bw.ws.bytes / 16), s));
-  }
-  std::vector<double> sc(K);
-  for (int k = 0; k < K; ++k) sc[k] = 1.0 / std::sqrt(theta[k]);
+  bs->lambda.assign(lambda, lambda + K);
+  DevBuf cdev, scale;
   RB_TRY(scale.ensure(K * 8));
   RB_HIP(hipMemcpyAsync(scale.p, sc.data(), K * 8, hipMemcpyHostToDevice, s));
   RB_TRY(bs->P.ensure((size_t)K * nbs * sizeof(float2)));
-  RB_HIP(launch_basis_rows(BS.as<double2>(), nb, K, K, scale.as<double>(), off, nbs, bs->P.as<float2>(), s));
+  RB_HIP(launch_basis_rows(BS, nb, K, K, scale.as<double>(), off, nbs, bs->P.as<float2>(), s));
   // c = W BS diag(theta^-1/2)  (T x K)
   RB_TRY(cdev.ensure((size_t)T * K * 16));
   {
-    ZOperand BSo{BS.p, 0, K, 1, 0};
+    ZOperand BSo{BS, 0, K, 1, 0};
     RB_HIP(launch_zgemm(T, K, nb, Wop, BSo, cdev.as<double2>(), K, 0, bw.ws.as<double2>(),
                         (int64_t)(bw.ws.bytes / 16), s));
   }
   bs->c.resize((size_t)T * K);
   RB_HIP(hipMemcpyAsync(bs->c.data(), cdev.p, bs->c.size() * 16, hipMemcpyDeviceToHost, s));
   RB_HIP(hipStreamSynchronize(s));
+  double csum = 0.0;
   for (int64_t j = 0; j < T; ++j)
-    for (int k = 0; k < K; ++k) bs->c[(size_t)j * K + k] *= sc[k];
+    for (int k = 0; k < K; ++k) {
+      bs->c[(size_t)j * K + k] *= sc[k];
+      csum += std::norm(bs->c[(size_t)j * K + k]);
+    }
+  bs->energy = energy >= 0 ? energy : csum / trace;
   // C = conj(c) as complex64 (unscaled), row scales for FP16
   std::vector<float2> C32((size_t)T * K);
   bs->row_scale.assign(bs->Tp, 1.f);
@@ -1227,6 +1231,171 @@ extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, 
   ctx->live++;
   *out = bs.release();
   return RB_OK;
+}
+
+}  // namespace
+
+extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, int32_t t1, int32_t rank,
+                                          double tol, rb_dtype dtype, rb_basis* out, int32_t* rank_out,
+                                          double* energy_out) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(bank != nullptr && out != nullptr, RB_ERR_ARG, "NULL argument");
+  RB_CHECK(bank->ctx == ctx, RB_ERR_ARG, "bank belongs to another context");
+  RB_CHECK(t0 >= 0 && t0 < t1 && t1 <= bank->T, RB_ERR_ARG, "template range must satisfy 0 <= t0 < t1 <= T");
+  RB_CHECK(rank >= 0, RB_ERR_ARG, "rank must be >= 0");
+  RB_CHECK(rank > 0 || (tol > 0 && tol < 1), RB_ERR_ARG, "tol must be in (0, 1) when rank == 0");
+  RB_CHECK(dtype == RB_F32 || dtype == RB_BF16 || dtype == RB_F16 || dtype == RB_BF16X3, RB_ERR_ARG,
+           "bad dtype");
+  *out = nullptr;
+  const int64_t T = t1 - t0;
+  const int64_t nb = bank->k_hi - bank->k_lo + 1, off = bank->k_lo - bank->kb, nbs = bank->nbs;
+  hipStream_t s = ctx->stream;
+  BasisWork bw;
+  RB_TRY(bw.ws.ensure((size_t)64 << 20 << 4));   // 64 Mi complex128 split-K partials (1 GiB)
+  // trace of the Gram = sum of stored squared norms
+  RB_TRY(bw.norms.ensure((size_t)T * 8));
+  const float2* W = bank->w.as<float2>() + (size_t)t0 * nbs + off;
+  RB_HIP(launch_row_norms(W, T, nb, nbs, bw.norms.as<double>(), s));
+  std::vector<double> norms(T);
+  RB_HIP(hipMemcpyAsync(norms.data(), bw.norms.p, T * 8, hipMemcpyDeviceToHost, s));
+  RB_HIP(hipStreamSynchronize(s));
+  double trace = 0.0;
+  for (double v : norms) trace += v;
+  std::vector<double> theta;
+  std::vector<cd> S;
+  int Lc = 0, K = 0;
+  RB_TRY(subspace_pca(ctx, bw, W, T, nb, nbs, trace, rank, tol, theta, S, Lc, K));
+  DevBuf BS;
+  RB_TRY(ritz_vectors(ctx, bw, nb, Lc, K, S, BS));
+  std::vector<double> sc(K);
+  double e = 0.0;
+  for (int k = 0; k < K; ++k) {
+    sc[k] = 1.0 / std::sqrt(theta[k]);
+    e += theta[k];
+  }
+  return finish_basis(ctx, bank, t0, T, K, BS.as<double2>(), sc, theta.data(), trace, e / trace, dtype, bw, out,
+                      rank_out, energy_out);
+}
+
+extern "C" rb_status rb_build_basis_nonuniform(rb_ctx ctx, rb_bank bank, int32_t t0, int32_t t1,
+                                               const double* nodes, int64_t nt, const double* psd_nodes,
+                                               rb_fill_at_fn fill, void* user, int32_t rank, double tol,
+                                               rb_dtype dtype, rb_basis* out, int32_t* rank_out,
+                                               double* energy_out) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(bank != nullptr && out != nullptr && nodes != nullptr && psd_nodes != nullptr && fill != nullptr,
+           RB_ERR_ARG, "NULL argument");
+  RB_CHECK(bank->ctx == ctx, RB_ERR_ARG, "bank belongs to another context");
+  RB_CHECK(t0 >= 0 && t0 < t1 && t1 <= bank->T, RB_ERR_ARG, "template range must satisfy 0 <= t0 < t1 <= T");
+  RB_CHECK(rank >= 0, RB_ERR_ARG, "rank must be >= 0");
+  RB_CHECK(rank > 0 || (tol > 0 && tol < 1), RB_ERR_ARG, "tol must be in (0, 1) when rank == 0");
+  RB_CHECK(dtype == RB_F32 || dtype == RB_BF16 || dtype == RB_F16 || dtype == RB_BF16X3, RB_ERR_ARG,
+           "bad dtype");
+  RB_CHECK(nt >= 2 && nt <= (int64_t(1) << 26), RB_ERR_ARG, "nt must be in [2, 2^26]");
+  *out = nullptr;
+  const double df = bank->grid.fs / (double)bank->grid.N;
+  for (int64_t i = 0; i < nt; ++i) {
+    RB_CHECK(std::isfinite(nodes[i]) && (i == 0 || nodes[i] > nodes[i - 1]), RB_ERR_ARG,
+             "nodes must be finite and strictly increasing");
+    RB_CHECK(std::isfinite(psd_nodes[i]) && psd_nodes[i] > 0, RB_ERR_ARG,
+             "PSD at the nodes must be finite and positive");
+  }
+  RB_CHECK(nodes[0] <= (double)bank->k_lo * df && nodes[nt - 1] >= (double)bank->k_hi * df, RB_ERR_ARG,
+           "nodes must cover the band [k_lo df, k_hi df]");
+  const int64_t T = t1 - t0;
+  const int64_t nb = bank->k_hi - bank->k_lo + 1, off = bank->k_lo - bank->kb, nbs = bank->nbs;
+  hipStream_t s = ctx->stream;
+  // whitened unit templates on the set, V[j][i] = h_j(f_i) g_i / sigma_j with
+  // g_i = sqrt(4 omega_i / Sn_i), FP64 on the host, complex64 on the device
+  std::vector<double> om, g(nt);
+  cell_weights(nodes, nt, om);
+  for (int64_t i = 0; i < nt; ++i) g[i] = std::sqrt(4.0 * om[i] / psd_nodes[i]);
+  DevBuf V;
+  RB_TRY(V.ensure((size_t)T * nt * sizeof(float2)));
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(T, (int64_t(64) << 20) / (nt * 16)));
+  std::vector<double> hbuf((size_t)chunk * nt * 2);
+  HostPinned stage;
+  RB_TRY(stage.ensure((size_t)chunk * nt * sizeof(float2)));
+  for (int64_t c0 = 0; c0 < T; c0 += chunk) {
+    const int64_t c1 = std::min<int64_t>(T, c0 + chunk);
+    RB_HIP(hipStreamSynchronize(s));   // staging buffer reuse
+    const int rc = fill(user, (int32_t)(t0 + c0), (int32_t)(t0 + c1), nodes, nt, hbuf.data());
+    RB_CHECK(rc == 0, RB_ERR_CALLBACK, "template fill callback returned " + std::to_string(rc));
+    float2* st = static_cast<float2*>(stage.p);
+    std::atomic<int> nbad(0);
+    parallel_for(c1 - c0, [&](int64_t r) {
+      const double* h = &hbuf[(size_t)r * nt * 2];
+      double s2 = 0.0;
+      for (int64_t i = 0; i < nt; ++i) {
+        const double re = h[2 * i] * g[i], im = h[2 * i + 1] * g[i];
+        s2 += re * re + im * im;
+      }
+      const double sg = std::sqrt(s2);
+      if (!(sg > 0.0) || !std::isfinite(sg)) {
+        nbad++;
+        return;
+      }
+      float2* o = st + (size_t)r * nt;
+      for (int64_t i = 0; i < nt; ++i) {
+        const double fct = g[i] / sg;
+        o[i] = make_float2((float)(h[2 * i] * fct), (float)(h[2 * i + 1] * fct));
+      }
+    });
+    RB_CHECK(nbad.load() == 0, RB_ERR_ARG, "a template has zero or non-finite norm on the nodes");
+    RB_HIP(hipMemcpyAsync(V.as<float2>() + (size_t)c0 * nt, st, (size_t)(c1 - c0) * nt * sizeof(float2),
+                          hipMemcpyHostToDevice, s));
+  }
+  BasisWork bw;
+  RB_TRY(bw.ws.ensure((size_t)64 << 20 << 4));
+  RB_TRY(bw.norms.ensure((size_t)T * 8));
+  std::vector<double> norms(T);
+  RB_HIP(launch_row_norms(V.as<float2>(), T, nt, nt, bw.norms.as<double>(), s));
+  RB_HIP(hipMemcpyAsync(norms.data(), bw.norms.p, T * 8, hipMemcpyDeviceToHost, s));
+  RB_HIP(hipStreamSynchronize(s));
+  double trace_set = 0.0;
+  for (double v : norms) trace_set += v;
+  std::vector<double> theta;
+  std::vector<cd> S;
+  int Lc = 0, K = 0;
+  RB_TRY(subspace_pca(ctx, bw, V.as<float2>(), T, nt, nt, trace_set, rank, tol, theta, S, Lc, K));
+  DevBuf BSn;
+  RB_TRY(ritz_vectors(ctx, bw, nt, Lc, K, S, BSn));
+  // interpolation onto the band: r_i = 1/sqrt(omega_i), per-vector scale
+  // sqrt(df) theta_k^{-1/2} (unit vectors on the set -> densities -> grid)
+  std::vector<int32_t> idx;
+  std::vector<double> frac, r(nt), scv(K);
+  interp_table(nodes, nt, bank->k_lo, bank->k_hi, df, idx, frac);
+  for (int64_t i = 0; i < nt; ++i) r[i] = 1.0 / std::sqrt(om[i]);
+  for (int k = 0; k < K; ++k) scv[k] = std::sqrt(df) / std::sqrt(theta[k]);
+  DevBuf idx_d, frac_d, r_d, sc_d, BSu, BSo;
+  RB_TRY(idx_d.ensure((size_t)nb * 4));
+  RB_TRY(frac_d.ensure((size_t)nb * 8));
+  RB_TRY(r_d.ensure((size_t)nt * 8));
+  RB_TRY(sc_d.ensure((size_t)K * 8));
+  RB_HIP(hipMemcpyAsync(idx_d.p, idx.data(), (size_t)nb * 4, hipMemcpyHostToDevice, s));
+  RB_HIP(hipMemcpyAsync(frac_d.p, frac.data(), (size_t)nb * 8, hipMemcpyHostToDevice, s));
+  RB_HIP(hipMemcpyAsync(r_d.p, r.data(), (size_t)nt * 8, hipMemcpyHostToDevice, s));
+  RB_HIP(hipMemcpyAsync(sc_d.p, scv.data(), (size_t)K * 8, hipMemcpyHostToDevice, s));
+  RB_TRY(BSu.ensure((size_t)nb * K * 16));
+  RB_HIP(launch_interp_rows(BSn.as<double2>(), nt, K, idx_d.as<int32_t>(), frac_d.as<double>(), r_d.as<double>(),
+                            sc_d.as<double>(), nb, BSu.as<double2>(), s));
+  // orthonormal on the uniform grid (two SVQB passes over the nb x K columns)
+  RB_TRY(BSo.ensure((size_t)nb * K * 16));
+  RB_TRY(bw.Y.ensure((size_t)nb * K * 16));
+  int K2 = 0;
+  RB_TRY(svqb(ctx, bw, BSu.as<double2>(), nb, K, BSo.as<double2>(), &K2));
+  RB_HIP(hipStreamSynchronize(s));   // host tables are local
+  // trace of the uniform templates for the kept energy
+  RB_TRY(bw.norms.ensure((size_t)T * 8));
+  const float2* Wu = bank->w.as<float2>() + (size_t)t0 * nbs + off;
+  RB_HIP(launch_row_norms(Wu, T, nb, nbs, bw.norms.as<double>(), s));
+  RB_HIP(hipMemcpyAsync(norms.data(), bw.norms.p, T * 8, hipMemcpyDeviceToHost, s));
+  RB_HIP(hipStreamSynchronize(s));
+  double trace = 0.0;
+  for (double v : norms) trace += v;
+  std::vector<double> ones(K2, 1.0);
+  return finish_basis(ctx, bank, t0, T, K2, BSo.as<double2>(), ones, theta.data(), trace, -1.0, dtype, bw, out,
+                      rank_out, energy_out);
 }
 
 extern "C" rb_status rb_basis_free(rb_basis basis) {

@@ -266,6 +266,9 @@ hipError_t launch_basis_rows(const double2* BS, int64_t nb, int K, int64_t ld, c
                              int64_t off, int64_t nbs, float2* out, hipStream_t s);
 hipError_t launch_row_norms(const float2* w, int64_t rows, int64_t len, int64_t ld, double* out,
                             hipStream_t s);
+// B: nt x K complex128 (row-major); idx[f] in [0, nt - 2] for f < nb.
+hipError_t launch_interp_rows(const double2* B, int64_t nt, int K, const int32_t* idx, const double* frac,
+                              const double* r, const double* scale, int64_t nb, double2* out, hipStream_t s);
 
 // ---------------------------------------------------------------- misc
 hipError_t launch_check_finite(const float* x, int64_t n, int64_t* flag, hipStream_t s);

@@ -7,6 +7,8 @@
 // reduction slabs staged in LDS, 4 x 4 complex outputs per thread, split over
 // the reduction dimension into deterministic partial sums when the output
 // alone cannot fill the GPU.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace rbmf {
@@ -155,7 +157,35 @@ __global__ __launch_bounds__(256) void k_row_norms(const float2* w, int64_t len,
   if (threadIdx.x == 0) out[r] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// Linear interpolation of basis columns from a non-uniform frequency set to
+// the uniform band: out[f][k] = scale[k] ((1 - a_f) r_i B[i][k] + a_f r_{i+1}
+// B[i+1][k]) with i = idx[f], a_f = frac[f], r = 1/sqrt(cell weight).  One
+// thread per (f, k), k fastest: the B rows i and i+1 and the out row f are
+// read and written contiguously.
+__global__ __launch_bounds__(256) void k_interp_rows(const double2* B, int K, const int32_t* idx, const double* frac,
+                                                     const double* r, const double* scale, int64_t nb, double2* out) {
+  const int64_t total = nb * (int64_t)K;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f = t / K;
+    const int k = (int)(t - f * K);
+    const int64_t i = idx[f];
+    const double a = frac[f];
+    const double w0 = (1.0 - a) * r[i] * scale[k], w1 = a * r[i + 1] * scale[k];
+    const double2 b0 = B[i * K + k], b1 = B[(i + 1) * K + k];
+    out[t] = make_double2(w0 * b0.x + w1 * b1.x, w0 * b0.y + w1 * b1.y);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_interp_rows(const double2* B, int64_t nt, int K, const int32_t* idx, const double* frac,
+                              const double* r, const double* scale, int64_t nb, double2* out, hipStream_t s) {
+  if (nt < 2 || K < 1 || nb < 1) return hipErrorInvalidValue;
+  const int64_t total = nb * (int64_t)K;
+  const int64_t blocks = std::min<int64_t>(8192, (total + 255) / 256);
+  hipLaunchKernelGGL(k_interp_rows, dim3((unsigned)blocks), dim3(256), 0, s, B, K, idx, frac, r, scale, nb, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_zgemm(int64_t M, int64_t Nn, int64_t Kd, ZOperand A, ZOperand B, double2* C, int64_t ldc,
                         int accumulate, double2* workspace, int64_t workspace_elems, hipStream_t s) {

@@ -253,6 +253,24 @@ class Bank:
                 one(i)
         return out
 
+    def fill_at(self, t0: int, t1: int, f: np.ndarray) -> np.ndarray:
+        """Templates [t0, t1) at arbitrary frequencies f: complex128 (t1-t0, len(f))."""
+        f = np.asarray(f, dtype=np.float64)
+        out = np.zeros((t1 - t0, f.shape[0]), dtype=np.complex128)
+        pre = _FreqPowers(f)
+        for i in range(t1 - t0):
+            out[i] = _taylorf2_pre(pre, float(self.m1[t0 + i]), float(self.m2[t0 + i]), self.order, self.f_low)
+        return out
+
+    def longest(self) -> int:
+        """Index of the template with the largest tau0 at f_low."""
+        return int(np.argmax(tau0_array(self.m1, self.m2, self.f_low)))
+
+    def support_ends(self) -> np.ndarray:
+        """The grid frequencies on either side of every template's f_ISCO cut."""
+        kc = np.floor(np.array([f_isco(a, b) for a, b in zip(self.m1, self.m2)]) / self.df)
+        return np.unique(np.concatenate([kc, kc + 1])) * self.df
+
     def full(self) -> np.ndarray:
         """All templates on all N/2+1 bins (small banks only)."""
         return self.fill(0, self.T, 0, self.N // 2 + 1)

@@ -26,7 +26,7 @@ FUNCTIONS = ["rb_ctx_create", "rb_ctx_destroy", "rb_last_error", "rb_bank_create
              "rb_bank_info", "rb_build_basis", "rb_build_basis_range", "rb_basis_info",
              "rb_basis_free", "rb_basis_export", "rb_filter",
              "rb_filter_stream", "rb_filter_batch", "mf_full", "rb_rho_at", "rb_backward", "rb_cluster_peaks", "rb_debug_rho",
-             "rb_debug_rho_binned", "rb_debug_basis_outputs"]
+             "rb_debug_rho_binned", "rb_debug_basis_outputs", "rb_nonuniform_freqs", "rb_build_basis_nonuniform"]
 
 
 class Grid(C.Structure):
@@ -58,6 +58,8 @@ PEAK_NP = np.dtype([("snr", np.float32), ("sample", np.int32)])
 
 FILL_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int64,
                       C.POINTER(C.c_double))
+FILL_AT_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64,
+                         C.POINTER(C.c_double))
 
 _lib = None
 
@@ -75,6 +77,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library {LIB_PATH} is missing: run __graft_entry__.build() "
                                "(or python -m paper_2110_13115_amd.build) first")
+        # torch first: it brings its own HIP runtime, and the library must bind
+        # to that one (loaded first, the system runtime would be the one torch
+        # finds, and device discovery fails in the mixed process)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         L.rb_ctx_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
@@ -103,6 +112,9 @@ def lib():
         L.rb_debug_rho.argtypes = [vp, vp, vp, vp, vp]
         L.rb_debug_rho_binned.argtypes = [vp, vp, vp, i32, vp]
         L.rb_debug_basis_outputs.argtypes = [vp, vp, vp, vp]
+        L.rb_nonuniform_freqs.argtypes = [vp, vp, i64, i32, dbl, vp, i64, vp, i64, C.POINTER(i64)]
+        L.rb_build_basis_nonuniform.argtypes = [vp, vp, i32, i32, vp, i64, vp, FILL_AT_FN, vp, i32, dbl,
+                                                C.c_int, C.POINTER(vp), C.POINTER(i32), C.POINTER(dbl)]
         for f in FUNCTIONS:
             if f != "rb_last_error":
                 getattr(L, f).restype = C.c_int
@@ -213,6 +225,47 @@ class Basis:
                                           C.byref(self.h), C.byref(K), C.byref(e)), "rb_build_basis_range")
         self.K, self.energy, self.dtype = K.value, e.value, dt
 
+    @classmethod
+    def nonuniform(cls, ctx: Context, bank: Bank, nodes: np.ndarray, psd_nodes: np.ndarray,
+                   fill_at: Callable[[int, int, np.ndarray], np.ndarray], rank: int = 0, tol: float = 1e-3,
+                   dtype="f32", t0: int = 0, t1: Optional[int] = None) -> "Basis":
+        """Basis by PCA on the non-uniform frequency set `nodes`, interpolated
+        onto the bank's grid (rb_build_basis_nonuniform).  fill_at(t0, t1, f)
+        must return the complex128 templates [t0, t1) at the frequencies f."""
+        self = cls.__new__(cls)
+        self.ctx, self.bank = ctx, bank
+        self.t0 = int(t0)
+        self.t1 = bank.T if t1 is None else int(t1)
+        self.T = self.t1 - self.t0
+        self.h = C.c_void_p()
+        nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        psd_nodes = np.ascontiguousarray(psd_nodes, dtype=np.float64)
+        err = []
+
+        def cb(user, a, b, f, nf, out):
+            try:
+                fr = np.ctypeslib.as_array(f, shape=(nf,)).copy()
+                h = np.asarray(fill_at(int(a), int(b), fr), dtype=np.complex128)
+                dst = np.ctypeslib.as_array(out, shape=(2 * (b - a) * nf,))
+                dst[:] = h.reshape(-1).view(np.float64)
+                return 0
+            except Exception as e:        # reported after the call returns
+                err.append(e)
+                return 1
+
+        fn = FILL_AT_FN(cb)
+        K = C.c_int32()
+        e = C.c_double()
+        dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        st = lib().rb_build_basis_nonuniform(ctx.h, bank.h, self.t0, self.t1, _ptr(nodes), nodes.shape[0],
+                                             _ptr(psd_nodes), fn, None, int(rank), float(tol), dt,
+                                             C.byref(self.h), C.byref(K), C.byref(e))
+        if err:
+            raise err[0]
+        _check(st, "rb_build_basis_nonuniform")
+        self.K, self.energy, self.dtype = K.value, e.value, dt
+        return self
+
     def export(self):
         _, klo, khi, _ = self.bank.info()
         nb = khi - klo + 1
@@ -226,6 +279,25 @@ class Basis:
         if self.h:
             _check(lib().rb_basis_free(self.h), "rb_basis_free")
             self.h = C.c_void_p()
+
+
+def nonuniform_freqs(f: np.ndarray, h_re: np.ndarray, per_bin: int = 5, df_min: float = 1.0 / 128,
+                     extra: Optional[np.ndarray] = None) -> np.ndarray:
+    """The non-uniform frequency set (rb_nonuniform_freqs) from samples of a
+    reference template's real part."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    h_re = np.ascontiguousarray(h_re, dtype=np.float64)
+    ex = None if extra is None else np.ascontiguousarray(extra, dtype=np.float64)
+    n_ex = 0 if ex is None else ex.shape[0]
+    n = C.c_int64()
+    st = lib().rb_nonuniform_freqs(_ptr(f), _ptr(h_re), f.shape[0], int(per_bin), float(df_min), _ptr(ex), n_ex,
+                                   None, 0, C.byref(n))
+    if st != RB_ERR_CAPACITY:
+        _check(st, "rb_nonuniform_freqs")
+    out = np.empty(max(1, n.value), dtype=np.float64)
+    _check(lib().rb_nonuniform_freqs(_ptr(f), _ptr(h_re), f.shape[0], int(per_bin), float(df_min), _ptr(ex), n_ex,
+                                     _ptr(out), out.shape[0], C.byref(n)), "rb_nonuniform_freqs")
+    return out[:n.value].copy()
 
 
 def _triggers_out(cap: int, like_device: bool):
