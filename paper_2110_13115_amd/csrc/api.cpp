@@ -1218,7 +1218,7 @@ rb_status finish_basis(rb_ctx ctx, rb_bank bank, int32_t t0, int64_t T, int K, c
   RB_TRY(bs->row_scale_dev.ensure((size_t)bs->Tp * 4));
   RB_HIP(hipMemcpyAsync(bs->row_inv.p, rinv.data(), (size_t)bs->Tp * 4, hipMemcpyHostToDevice, s));
   RB_HIP(hipMemcpyAsync(bs->row_scale_dev.p, bs->row_scale.data(), (size_t)bs->Tp * 4, hipMemcpyHostToDevice, s));
-  const size_t cpk_bytes = (dtype == RB_F32) ? (size_t)(bs->Tp / 16) * K * 64 * 4
+  const size_t cpk_bytes = (dtype == RB_F32) ? (size_t)(bs->Tp / 32) * ((K + 1) / 2) * 64 * 4 * 4
                                              : (size_t)(bs->Tp / 16) * (bs->Kp / 8) * 64 * 8 * 2 *
                                                    (dtype == RB_BF16X3 ? 2 : 1);
   RB_TRY(bs->cpk.ensure(cpk_bytes));
@@ -1474,7 +1474,7 @@ rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq
     // with infinite thresholds (no trigger is appended), keep the fastest
     const char* force = std::getenv("RBMF_GEMM_VARIANT");
     const char* at = std::getenv("RBMF_AUTOTUNE");
-    const std::string key = ctx->arch + "/gemm/dt=" + std::to_string(ga.dtype) + "/K=" + std::to_string(ga.K) +
+    const std::string key = ctx->arch + "/gemm2/dt=" + std::to_string(ga.dtype) + "/K=" + std::to_string(ga.K) +
                             "/T=" + std::to_string(ga.T) + "/N=" + std::to_string(ga.N);
     int choice = 0, cached = -1;
     if (force) {

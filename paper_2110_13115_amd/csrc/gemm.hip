@@ -39,12 +39,27 @@ __device__ __forceinline__ void epilogue_lane(const GemmArgs& a, const f32x16 (&
                                               int64_t q0) {
   const int lane = __lane_id();
   const int l1 = __builtin_ctz((unsigned)a.N1);            // N1 is a power of two
+  // a lane's outputs cover 8 templates per row block and CB samples: their
+  // thresholds and sample indices are fetched / computed once
+  float th[RB][8];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int j = (rb0 + rb) * 16 + 4 * (h >> 1) + 2 * (lane >> 5) + (h & 1);
+      th[rb][h] = j < a.T ? a.thr2_row[j] : __builtin_inff();
+    }
+  int nn[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int q = (int)q0 + CB * (lane & 31) + cb;          // q < N < 2^31 (column CB l + cb)
+    nn[cb] = (q >> l1) + a.N2 * (q & (a.N1 - 1));
+  }
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
-      const int q = (int)q0 + cb * 32 + (lane & 31);        // q < N < 2^31
-      const int n = (q >> l1) + a.N2 * (q & (a.N1 - 1));
+      const int n = nn[cb];
 #pragma unroll
       for (int i = 0; i < 16; i += 2) {
         const int m = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);   // even: Re row
@@ -55,7 +70,7 @@ __device__ __forceinline__ void epilogue_lane(const GemmArgs& a, const f32x16 (&
           const float s = a.row_inv ? a.row_inv[j] : 1.f;
           a.rho_out[(int64_t)j * a.N + n] = make_float2(re * s, im * s);
         }
-        if (j < a.T && p >= a.thr2_row[j]) {
+        if (p >= th[rb][i >> 1]) {
           atomicAdd(&a.tmpl_count[j], 1);
           const unsigned long long idx = atomicAdd(a.trig_count, 1ull);
           if ((int64_t)idx < a.trig_cap) {
@@ -210,19 +225,44 @@ __device__ __forceinline__ bool xcd_tile(int ntt, int64_t nwg, int& tt, int64_t&
 }
 
 // RB x CB: 16-template row blocks x 32-sample column blocks per wave.
-// Operands of G k-steps are loaded into one of two register buffers while the
-// MFMAs of the other run (the steady state has no branch, so the loads of the
-// next group stay in flight); the last K mod 2G steps run one at a time.
+// Operands of G k-steps (a group, G even) are loaded into one of three
+// register buffers two groups before their MFMAs run; the last K mod G
+// k-steps run one at a time.  All operand loads are 8 or 16 bytes wide: lane l
+// holds, in block cb, the column CB (l % 32) + cb of the wave's 32 CB samples,
+// so one load gives its B values of all CB blocks, and the packed A holds a
+// lane's values of both row blocks and two k-steps in one float4.  (With one
+// 4-byte load per block and k-step, the vector memory path, not the MFMAs,
+// bounds the loop.)
 // Main loop and epilogue of one wave's RB x CB tile (templates from row
-// block rb0, samples from q0).
+// block rb0, samples from q0); RB = 1 uses the first row block of the packed
+// pair only.
+template <int CB>
+struct BVec;
+template <>
+struct BVec<4> {
+  typedef float4 T;
+  static __device__ __forceinline__ float at(const float4& v, int c) {
+    return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
+  }
+};
+template <>
+struct BVec<2> {
+  typedef float2 T;
+  static __device__ __forceinline__ float at(const float2& v, int c) { return c == 0 ? v.x : v.y; }
+};
+
 template <int RB, int CB, int G>
 __device__ __forceinline__ void recon_f32_tile(const GemmArgs& a, int rb0, int64_t q0) {
+  static_assert(G % 2 == 0, "groups hold whole k-pairs");
+  typedef typename BVec<CB>::T bvec;
   const int lane = threadIdx.x & 63;
   const int K = a.K;
   const int64_t N = a.N;
-  const int64_t astr = (int64_t)K * 64;                    // floats per packed row block
-  const float* __restrict__ ap = static_cast<const float*>(a.cpk) + (int64_t)rb0 * astr + lane;
-  const float* __restrict__ bp = static_cast<const float*>(a.z) + (int64_t)(lane >> 5) * N + q0 + (lane & 31);
+  const int KP = (K + 1) / 2;                              // packed k-pairs
+  const float4* __restrict__ ap = static_cast<const float4*>(a.cpk) + (int64_t)(rb0 / 2) * KP * 64 + lane;
+  const float* zrow = static_cast<const float*>(a.z) + (int64_t)(lane >> 5) * N + q0 + CB * (lane & 31);
+  const bvec* __restrict__ bp = reinterpret_cast<const bvec*>(zrow);
+  const int64_t rstep = (2 * N) / CB;                      // one k-step (two reduction rows), in bvec
 
   f32x16 acc[RB][CB];
 #pragma unroll
@@ -230,104 +270,108 @@ __device__ __forceinline__ void recon_f32_tile(const GemmArgs& a, int rb0, int64
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = (f32x16){};
 
-  // A: one pointer per row block, k-steps at immediate offsets; B: one pointer
-  // per k-step of a group (rows 2k are 2N floats apart); all advance by a group.
-  const float* pa[RB];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb) pa[rb] = ap + rb * astr;
-  const float* pb[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) pb[g] = bp + (int64_t)(2 * g) * N;
-  const int64_t bstep = (int64_t)(2 * G) * N;
-  // three register buffers: group i lives in buffer i % 3 and is loaded two
-  // groups before its MFMAs run, so HBM latency hides behind two groups of work
-  float fa[3][G][RB], fb[3][G][CB];
+  const float4* pa = ap;
+  const bvec* pb = bp;
+  float4 fa[3][G / 2];
+  bvec fb[3][G];
   auto load = [&](int s) {   // loads the group at the pointers, then advances them
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
+    for (int h = 0; h < G / 2; ++h) fa[s][h] = pa[h * 64];
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) fa[s][g][rb] = pa[rb][g * 64];
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) fb[s][g][cb] = pb[g][cb * 32];
-    }
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) pa[rb] += G * 64;
-#pragma unroll
-    for (int g = 0; g < G; ++g) pb[g] += bstep;
+    for (int g = 0; g < G; ++g) fb[s][g] = pb[g * rstep];
+    pa += (G / 2) * 64;
+    pb += G * rstep;
   };
   auto mma = [&](int s) {
 #pragma unroll
-    for (int g = 0; g < G; ++g)
+    for (int g = 0; g < G; ++g) {
+      const float4 v = fa[s][g / 2];
+      const float av[2] = {(g & 1) ? v.z : v.x, (g & 1) ? v.w : v.y};
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[s][g][rb], fb[s][g][cb], acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], BVec<CB>::at(fb[s][g], cb), acc[rb][cb], 0, 0,
+                                                            0);
+    }
   };
   const int ng = K / G;                 // full groups; the last K mod G k-steps run singly
   const int Kmain = ng * G;
-  if (ng > 0) load(0);
-  if (ng > 1) load(1);
   int gi = 0;
-  // the scheduling barriers keep each load batch ahead of the MFMAs that follow it
-  for (; gi + 3 <= ng; gi += 3) {
-    if (gi + 2 < ng) load(2);
+  // Steady state: groups gi and gi + 1 are in buffers 0 and 1, and the three
+  // loads of an iteration (groups gi + 2 .. gi + 4) all exist.  Neither the
+  // body nor the path into it has a conditional load: on a path with fewer
+  // loads in flight the compiler's wait counts would cover that path too and
+  // stall on loads issued just before.  The scheduling barriers keep each
+  // load batch ahead of the MFMAs that follow.
+  if (ng >= 5) {
+    load(0);
+    __builtin_amdgcn_sched_barrier(0);   // issued in the loop's order
+    load(1);
     __builtin_amdgcn_sched_barrier(0);
-    mma(0);
-    __builtin_amdgcn_sched_barrier(0);
-    if (gi + 3 < ng) load(0);
-    __builtin_amdgcn_sched_barrier(0);
-    mma(1);
-    __builtin_amdgcn_sched_barrier(0);
-    if (gi + 4 < ng) load(1);
-    __builtin_amdgcn_sched_barrier(0);
-    mma(2);
-    __builtin_amdgcn_sched_barrier(0);
+    do {
+      load(2);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(0);
+      __builtin_amdgcn_sched_barrier(0);
+      load(0);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(1);
+      __builtin_amdgcn_sched_barrier(0);
+      load(1);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(2);
+      __builtin_amdgcn_sched_barrier(0);
+      gi += 3;
+    } while (gi + 4 < ng);
+  } else {
+    if (ng > 0) load(0);
+    if (ng > 1) load(1);
   }
-  if (gi < ng) {   // at most two groups remain, in buffers 0 and 1
-    mma(0);
-    ++gi;
-  }
-  if (gi < ng) mma(1);
+  // at most four groups remain (gi .. gi + 3), the first two already loaded
+  if (gi + 2 < ng) load(2);
+  if (gi < ng) mma(0);
+  if (gi + 3 < ng) load(0);
+  if (gi + 1 < ng) mma(1);
+  if (gi + 2 < ng) mma(2);
+  if (gi + 3 < ng) mma(0);
   for (int k = Kmain; k < K; ++k) {
-    float av[RB], bv[CB];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) av[rb] = ap[rb * astr + (int64_t)k * 64];
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) bv[cb] = bp[(int64_t)(2 * k) * N + cb * 32];
+    const float4 v = ap[(int64_t)(k >> 1) * 64];
+    const float av[2] = {(k & 1) ? v.z : v.x, (k & 1) ? v.w : v.y};
+    const bvec bv = bp[(int64_t)k * rstep];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], BVec<CB>::at(bv, cb), acc[rb][cb], 0, 0, 0);
   }
   epilogue_lane<RB, CB>(a, acc, rb0, q0);
 }
 
-// One workgroup = one row tile of RB 16-template blocks; its four waves take
-// adjacent column tiles of CB 32-sample blocks (so every wave of a workgroup
-// has the same share of padding rows, and a sub-bank whose template count is
-// not a multiple of 128 leaves no wave idle beside busy ones).
-template <int RB, int CB, int G>
+// One workgroup = one row tile of 32 templates (two 16-template blocks); its
+// four waves take adjacent column tiles of CB 32-sample blocks (so every wave
+// of a workgroup has the same share of padding rows, and a sub-bank whose
+// template count is not a multiple of 128 leaves no wave idle beside busy
+// ones).
+template <int CB, int G>
 __global__ __launch_bounds__(256, 2) void k_recon_f32(GemmArgs a) {   // at least 2 waves per SIMD
-  constexpr int TT = RB * 16;           // templates per workgroup
   constexpr int TN = CB * 32;           // samples per wave; G: k-steps per pipeline group
-  const int ntt = a.Tp / TT;
+  const int ntt = a.Tp / 32;
   const int64_t ncol = (a.N + WAVES * TN - 1) / (WAVES * TN);
   const int64_t nwg = (int64_t)ntt * ncol;
   int tt;
   int64_t st;
   if (!xcd_tile(ntt, nwg, tt, st)) return;
   const int wave = threadIdx.x >> 6;
-  const int rb0 = tt * RB;                                 // first 16-template row block
+  const int rb0 = tt * 2;                                  // first 16-template row block
   if (rb0 * 16 >= a.T) return;                             // all of this tile's rows are padding
   const int64_t q0 = (st * WAVES + wave) * TN;
   if (q0 >= a.N) return;                                   // (N is a multiple of TN)
   // a wave whose second row block is all padding runs the one-block tile
-  if (RB == 2 && (rb0 + 1) * 16 >= a.T)
+  if ((rb0 + 1) * 16 >= a.T)
     recon_f32_tile<1, CB, G>(a, rb0, q0);
   else
-    recon_f32_tile<RB, CB, G>(a, rb0, q0);
+    recon_f32_tile<2, CB, G>(a, rb0, q0);
 }
 
 // 16-bit operands: one instruction reduces over 16 realified entries = 8
@@ -550,15 +594,20 @@ __device__ __forceinline__ float a_entry(const float2* C, int T, int K, int rb, 
   return t == 0 ? c.y : c.x;
 }
 
+// FP32 A, packed [32-template tile][k-pair][lane][4]: entries (block 0, k),
+// (block 1, k), (block 0, k + 1), (block 1, k + 1) for k = 2 * pair; a k = K
+// entry (K odd) is zero.
 __global__ void k_pack_f32(const float2* C, int T, int Tp, int K, float* out) {
-  const int64_t total = (int64_t)(Tp / 16) * K * 64;
+  const int KP = (K + 1) / 2;
+  const int64_t total = (int64_t)(Tp / 32) * KP * 64 * 4;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int l = (int)(i & 63);
-    const int64_t rk = i >> 6;
-    const int k = (int)(rk % K);
-    const int rb = (int)(rk / K);
-    out[i] = a_entry(C, T, K, rb, l & 31, k, l >> 5, nullptr);
+    const int e = (int)(i & 3);
+    const int l = (int)((i >> 2) & 63);
+    const int64_t tk = i >> 8;
+    const int kp = (int)(tk % KP);
+    const int tile = (int)(tk / KP);
+    out[i] = a_entry(C, T, K, 2 * tile + (e & 1), l & 31, 2 * kp + (e >> 1), l >> 5, nullptr);
   }
 }
 
@@ -588,20 +637,20 @@ int recon_variants(int dtype) { return dtype == 0 ? 4 : 3; }
 
 hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
   if (a.Tp % TILE_T != 0 || a.N % 128 != 0) return hipErrorInvalidValue;
-  if (a.dtype == 0) {   // per-wave tiles (row x column blocks, k-steps per pipeline group):
-                        // variant 0 = 2 x 2 / 4, 1 = 2 x 4 / 4, 2 = 1 x 4 / 4, 3 = 2 x 4 / 2
-    const int rbw = a.variant == 2 ? 1 : 2;
-    const int TN = a.variant == 0 ? 64 : 128;
-    const int64_t nwg = (int64_t)(a.Tp / (rbw * 16)) * ((a.N + WAVES * TN - 1) / (WAVES * TN));
+  if (a.dtype == 0) {   // per-wave tiles: 32 templates x 32 CB samples, G k-steps per pipeline group:
+                        // variant 0 = CB 4 / G 2, 1 = 4 / 4, 2 = 2 / 2, 3 = 2 / 4
+    const int cbw = a.variant < 2 ? 4 : 2;
+    const int TN = cbw * 32;
+    const int64_t nwg = (int64_t)(a.Tp / 32) * ((a.N + WAVES * TN - 1) / (WAVES * TN));
     const int64_t launch = ((nwg + 7) / 8) * 8;
-    if (a.variant == 3)
-      hipLaunchKernelGGL((k_recon_f32<2, 4, 2>), dim3((unsigned)launch), dim3(256), 0, st, a);
-    else if (a.variant == 2)
-      hipLaunchKernelGGL((k_recon_f32<1, 4, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
+    if (a.variant == 0)
+      hipLaunchKernelGGL((k_recon_f32<4, 2>), dim3((unsigned)launch), dim3(256), 0, st, a);
     else if (a.variant == 1)
-      hipLaunchKernelGGL((k_recon_f32<2, 4, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_recon_f32<4, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
+    else if (a.variant == 2)
+      hipLaunchKernelGGL((k_recon_f32<2, 2>), dim3((unsigned)launch), dim3(256), 0, st, a);
     else
-      hipLaunchKernelGGL((k_recon_f32<2, 2, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
+      hipLaunchKernelGGL((k_recon_f32<2, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
     return hipGetLastError();
   }
   // 16-bit: variant 0 / 2 stage a 64 / 128-sample Z tile in LDS (when it fits),
