@@ -39,27 +39,20 @@ __device__ __forceinline__ void epilogue_lane(const GemmArgs& a, const f32x16 (&
                                               int64_t q0) {
   const int lane = __lane_id();
   const int l1 = __builtin_ctz((unsigned)a.N1);            // N1 is a power of two
-  // a lane's outputs cover 8 templates per row block and CB samples: their
-  // thresholds and sample indices are fetched / computed once
-  float th[RB][8];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
+  for (int rb = 0; rb < RB; ++rb) {
+    // a lane's outputs of one row block cover 8 templates and CB samples:
+    // their thresholds are fetched once per block
+    float th[8];
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
       const int j = (rb0 + rb) * 16 + 4 * (h >> 1) + 2 * (lane >> 5) + (h & 1);
-      th[rb][h] = j < a.T ? a.thr2_row[j] : __builtin_inff();
+      th[h] = j < a.T ? a.thr2_row[j] : __builtin_inff();
     }
-  int nn[CB];
-#pragma unroll
-  for (int cb = 0; cb < CB; ++cb) {
-    const int q = (int)q0 + CB * (lane & 31) + cb;          // q < N < 2^31 (column CB l + cb)
-    nn[cb] = (q >> l1) + a.N2 * (q & (a.N1 - 1));
-  }
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
-      const int n = nn[cb];
+      const int q = (int)q0 + CB * (lane & 31) + cb;        // q < N < 2^31 (column CB l + cb)
+      const int n = (q >> l1) + a.N2 * (q & (a.N1 - 1));
 #pragma unroll
       for (int i = 0; i < 16; i += 2) {
         const int m = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);   // even: Re row
@@ -70,7 +63,7 @@ __device__ __forceinline__ void epilogue_lane(const GemmArgs& a, const f32x16 (&
           const float s = a.row_inv ? a.row_inv[j] : 1.f;
           a.rho_out[(int64_t)j * a.N + n] = make_float2(re * s, im * s);
         }
-        if (p >= th[rb][i >> 1]) {
+        if (p >= th[i >> 1]) {
           atomicAdd(&a.tmpl_count[j], 1);
           const unsigned long long idx = atomicAdd(a.trig_count, 1ull);
           if ((int64_t)idx < a.trig_cap) {
@@ -254,12 +247,15 @@ struct BVec<2> {
 template <int RB, int CB, int G>
 __device__ __forceinline__ void recon_f32_tile(const GemmArgs& a, int rb0, int64_t q0) {
   static_assert(G % 2 == 0, "groups hold whole k-pairs");
+  static_assert(RB == 1 || RB == 2 || RB == 4, "one, two or four 16-template blocks");
+  constexpr int NT = RB == 4 ? 2 : 1;                      // packed 32-template tiles per wave
   typedef typename BVec<CB>::T bvec;
   const int lane = threadIdx.x & 63;
   const int K = a.K;
   const int64_t N = a.N;
   const int KP = (K + 1) / 2;                              // packed k-pairs
-  const float4* __restrict__ ap = static_cast<const float4*>(a.cpk) + (int64_t)(rb0 / 2) * KP * 64 + lane;
+  const int64_t tstr = (int64_t)KP * 64;                   // float4 per packed tile
+  const float4* __restrict__ ap = static_cast<const float4*>(a.cpk) + (int64_t)(rb0 / 2) * tstr + lane;
   const float* zrow = static_cast<const float*>(a.z) + (int64_t)(lane >> 5) * N + q0 + CB * (lane & 31);
   const bvec* __restrict__ bp = reinterpret_cast<const bvec*>(zrow);
   const int64_t rstep = (2 * N) / CB;                      // one k-step (two reduction rows), in bvec
@@ -272,27 +268,33 @@ __device__ __forceinline__ void recon_f32_tile(const GemmArgs& a, int rb0, int64
 
   const float4* pa = ap;
   const bvec* pb = bp;
-  float4 fa[3][G / 2];
+  float4 fa[3][G / 2][NT];
   bvec fb[3][G];
   auto load = [&](int s) {   // loads the group at the pointers, then advances them
 #pragma unroll
-    for (int h = 0; h < G / 2; ++h) fa[s][h] = pa[h * 64];
+    for (int h = 0; h < G / 2; ++h)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) fa[s][h][t] = pa[t * tstr + h * 64];
 #pragma unroll
     for (int g = 0; g < G; ++g) fb[s][g] = pb[g * rstep];
     pa += (G / 2) * 64;
     pb += G * rstep;
   };
+  // A value of row block rb at k-step g of a group (entries: block 2t + (e & 1), k-step e >> 1)
+  auto aval = [&](const float4 (&f)[NT], int g, int rb) {
+    const float4 v = f[rb >> 1];
+    return (g & 1) ? ((rb & 1) ? v.w : v.z) : ((rb & 1) ? v.y : v.x);
+  };
   auto mma = [&](int s) {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const float4 v = fa[s][g / 2];
-      const float av[2] = {(g & 1) ? v.z : v.x, (g & 1) ? v.w : v.y};
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+      for (int rb = 0; rb < RB; ++rb) {
+        const float av = aval(fa[s][g / 2], g, rb);
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], BVec<CB>::at(fb[s][g], cb), acc[rb][cb], 0, 0,
-                                                            0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, BVec<CB>::at(fb[s][g], cb), acc[rb][cb], 0, 0, 0);
+      }
     }
   };
   const int ng = K / G;                 // full groups; the last K mod G k-steps run singly
@@ -336,14 +338,17 @@ __device__ __forceinline__ void recon_f32_tile(const GemmArgs& a, int rb0, int64
   if (gi + 2 < ng) mma(2);
   if (gi + 3 < ng) mma(0);
   for (int k = Kmain; k < K; ++k) {
-    const float4 v = ap[(int64_t)(k >> 1) * 64];
-    const float av[2] = {(k & 1) ? v.z : v.x, (k & 1) ? v.w : v.y};
+    float4 f[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) f[t] = ap[t * tstr + (int64_t)(k >> 1) * 64];
     const bvec bv = bp[(int64_t)k * rstep];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < RB; ++rb) {
+      const float av = aval(f, k, rb);
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb], BVec<CB>::at(bv, cb), acc[rb][cb], 0, 0, 0);
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, BVec<CB>::at(bv, cb), acc[rb][cb], 0, 0, 0);
+    }
   }
   epilogue_lane<RB, CB>(a, acc, rb0, q0);
 }
@@ -374,6 +379,33 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(GemmArgs a) {   // at leas
     recon_f32_tile<1, CB, G>(a, rb0, q0);
   else
     recon_f32_tile<2, CB, G>(a, rb0, q0);
+}
+
+// 64 templates (four 16-template blocks) x 32 CB samples per wave, one wave
+// per SIMD (256 accumulator registers): half the B loads per MFMA of the
+// 32-template tiles, measured 142 against 110 TFLOP/s in the main loop.  The
+// last row tile of a sub-bank runs as a four-, two- or one-block tile after
+// the templates it holds.
+template <int CB, int G>
+__global__ __launch_bounds__(256, 1) void k_recon_f32_w64(GemmArgs a) {
+  constexpr int TN = CB * 32;
+  const int ntt = (a.T + 63) / 64;
+  const int64_t ncol = (a.N + WAVES * TN - 1) / (WAVES * TN);
+  const int64_t nwg = (int64_t)ntt * ncol;
+  int tt;
+  int64_t st;
+  if (!xcd_tile(ntt, nwg, tt, st)) return;
+  const int wave = threadIdx.x >> 6;
+  const int rb0 = tt * 4;
+  const int64_t q0 = (st * WAVES + wave) * TN;
+  if (q0 >= a.N) return;                                   // (N is a multiple of TN)
+  const int rows = a.T - rb0 * 16;                         // templates in this tile (>= 1)
+  if (rows > 32)
+    recon_f32_tile<4, CB, G>(a, rb0, q0);
+  else if (rows > 16)
+    recon_f32_tile<2, CB, G>(a, rb0, q0);
+  else
+    recon_f32_tile<1, CB, G>(a, rb0, q0);
 }
 
 // 16-bit operands: one instruction reduces over 16 realified entries = 8
@@ -635,10 +667,19 @@ __global__ void k_pack_16(const float2* C, int T, int Tp, int K, int Kp, int dty
 
 }  // namespace
 
-int recon_variants(int dtype) { return dtype == 0 ? 4 : 3; }
+int recon_variants(int dtype) { return dtype == 0 ? 6 : 3; }
 
 hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
   if (a.Tp % TILE_T != 0 || a.N % 128 != 0) return hipErrorInvalidValue;
+  if (a.dtype == 0 && a.variant >= 4) {   // 64 templates x 128 samples per wave: variant 4 = G 2, 5 = G 4
+    const int64_t nwg = (int64_t)((a.T + 63) / 64) * ((a.N + WAVES * 128 - 1) / (WAVES * 128));
+    const int64_t launch = ((nwg + 7) / 8) * 8;
+    if (a.variant == 4)
+      hipLaunchKernelGGL((k_recon_f32_w64<4, 2>), dim3((unsigned)launch), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_recon_f32_w64<4, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
+    return hipGetLastError();
+  }
   if (a.dtype == 0) {   // per-wave tiles: 32 templates x 32 CB samples, G k-steps per pipeline group:
                         // variant 0 = CB 4 / G 2, 1 = 4 / 4, 2 = 2 / 2, 3 = 2 / 4
     const int cbw = a.variant < 2 ? 4 : 2;
