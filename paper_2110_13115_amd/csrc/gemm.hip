@@ -383,9 +383,9 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(GemmArgs a) {   // at leas
 
 // 64 templates (four 16-template blocks) x 32 CB samples per wave, one wave
 // per SIMD (256 accumulator registers): half the B loads per MFMA of the
-// 32-template tiles, measured 142 against 110 TFLOP/s in the main loop.  The
-// last row tile of a sub-bank runs as a four-, two- or one-block tile after
-// the templates it holds.
+// 32-template tiles, measured 142 against 110 TFLOP/s in the main loop.  A
+// row tile with fewer templates runs as a two- or one-block tile (the
+// launcher gives this kernel whole 64-template tiles only).
 template <int CB, int G>
 __global__ __launch_bounds__(256, 1) void k_recon_f32_w64(GemmArgs a) {
   constexpr int TN = CB * 32;
@@ -672,12 +672,37 @@ int recon_variants(int dtype) { return dtype == 0 ? 6 : 3; }
 hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
   if (a.Tp % TILE_T != 0 || a.N % 128 != 0) return hipErrorInvalidValue;
   if (a.dtype == 0 && a.variant >= 4) {   // 64 templates x 128 samples per wave: variant 4 = G 2, 5 = G 4
-    const int64_t nwg = (int64_t)((a.T + 63) / 64) * ((a.N + WAVES * 128 - 1) / (WAVES * 128));
-    const int64_t launch = ((nwg + 7) / 8) * 8;
-    if (a.variant == 4)
-      hipLaunchKernelGGL((k_recon_f32_w64<4, 2>), dim3((unsigned)launch), dim3(256), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_recon_f32_w64<4, 4>), dim3((unsigned)launch), dim3(256), 0, st, a);
+    // The whole 64-template tiles run here; the T mod 64 templates left
+    // would run as a one- or two-block tile at one wave per SIMD, whose few
+    // MFMAs per load cannot cover the load latency (measured: as long as a
+    // full tile), so they run as the 32-template kernel's tiles, a second
+    // launch on the same template-shifted arguments.
+    const int full = (a.T / 64) * 64;
+    if (full > 0) {
+      GemmArgs a1 = a;
+      a1.T = full;
+      const int64_t nwg = (int64_t)(full / 64) * ((a.N + WAVES * 128 - 1) / (WAVES * 128));
+      const int64_t launch = ((nwg + 7) / 8) * 8;
+      if (a.variant == 4)
+        hipLaunchKernelGGL((k_recon_f32_w64<4, 2>), dim3((unsigned)launch), dim3(256), 0, st, a1);
+      else
+        hipLaunchKernelGGL((k_recon_f32_w64<4, 4>), dim3((unsigned)launch), dim3(256), 0, st, a1);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (a.T > full) {
+      GemmArgs a2 = a;                   // templates [full, T): every per-template array shifted
+      a2.T = a.T - full;
+      a2.cpk = static_cast<const float4*>(a.cpk) + (int64_t)(full / 32) * ((a.K + 1) / 2) * 64;
+      a2.thr2_row = a.thr2_row + full;
+      a2.tmpl_base = a.tmpl_base + full;
+      a2.tmpl_count = a.tmpl_count + full;
+      if (a.rho_out) a2.rho_out = a.rho_out + (int64_t)full * a.N;
+      if (a.row_inv) a2.row_inv = a.row_inv + full;
+      const int64_t nwg = (int64_t)((a2.T + 31) / 32) * ((a.N + WAVES * 128 - 1) / (WAVES * 128));
+      const int64_t launch = ((nwg + 7) / 8) * 8;
+      hipLaunchKernelGGL((k_recon_f32<4, 2>), dim3((unsigned)launch), dim3(256), 0, st, a2);
+    }
     return hipGetLastError();
   }
   if (a.dtype == 0) {   // per-wave tiles: 32 templates x 32 CB samples, G k-steps per pipeline group:
