@@ -502,10 +502,10 @@ def main():
     achieved = flops / (gm * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"], "unit": "TFLOP/s",
             "frac": achieved / PEAK["f32"], "traffic": gemm_traffic(),
-            "kernel": "k_recon_f32 (rho = C Z, realified complex GEMM, FP32 MFMA 32x32x2)",
+            "kernel": "k_recon_f32 / k_recon_f32_w64 (rho = C Z, realified complex GEMM, FP32 MFMA 32x32x2)",
             "per_step": f"sum over sub-banks of 8*K_m*T_m*N = {flops:.4g} flop", "avg_ms_per_step": gm,
-            "traffic_unit": "HBM bytes per launch (mean of the sub-bank launches; "
-                            "profiles/recon_gemm_f32_traffic_rb_256s_2000t.md)"}
+            "traffic_unit": "HBM bytes per sub-bank GEMM launch (its one or two dispatches; mean of the "
+                            "ten; profiles/recon_gemm_f32_traffic_rb_256s_2000t.md)"}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, bank_def, psd, strain)
