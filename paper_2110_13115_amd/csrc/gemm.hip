@@ -111,9 +111,22 @@ __device__ __forceinline__ void stage_flush(const GemmArgs& a, WaveStage& s, int
 // epilogue a large part of a tile): one threshold load and one ballot per
 // template-row step after a maximum over the columns; crossings are staged
 // per wave (stage_flush appends them).
+// The thresholds of a lane's template rows (h = i / 2 of accumulator element i).
+template <int RB>
+__device__ __forceinline__ void epi_thresholds(const GemmArgs& a, int rb0, float (&th)[RB][8]) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int j = (rb0 + rb) * 16 + 4 * (h >> 1) + 2 * (lane >> 5) + (h & 1);
+      th[rb][h] = a.thr2_row[j];   // padded rows: C = 0, so |rho|^2 = 0 never reaches it
+    }
+}
+
 template <int RB, int CB>
 __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[RB][CB], int rb0,
-                                         int64_t q0, WaveStage& stg) {
+                                         int64_t q0, WaveStage& stg, const float (&th)[RB][8]) {
   const int lane = __lane_id();
   const int l1 = __builtin_ctz((unsigned)a.N1);            // N1 is a power of two
   if (a.rho_out != nullptr) {   // debug dump (thresholds are infinite then: nothing is appended)
@@ -143,7 +156,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[
       // rows have C = 0, so |rho|^2 = 0 never reaches a positive threshold)
       const int m = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
       const int j = (rb0 + rb) * 16 + (m >> 1);
-      const float thr = a.thr2_row[j];
+      const float thr = th[rb][i >> 1];
       float pmax = 0.f;
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
@@ -462,7 +475,9 @@ __global__ __launch_bounds__(256) void k_recon_16(GemmArgs a) {
   }
   __shared__ TrigRec stage_mem[WAVES][kStage];
   WaveStage stg{stage_mem[wave], 0};
-  epilogue<WT_ROWB, WT_COLB>(a, acc, rb0, q0, stg);
+  float th[WT_ROWB][8];
+  epi_thresholds<WT_ROWB>(a, rb0, th);
+  epilogue<WT_ROWB, WT_COLB>(a, acc, rb0, q0, stg, th);
   if (stg.n > 0) stage_flush(a, stg, lane);
 }
 
@@ -524,77 +539,122 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
   const u16x8* __restrict__ cpk = static_cast<const u16x8*>(a.cpk);
   const int ntt = a.Tp / TILE_T;
   const int64_t cplane = (int64_t)ntt * (TILE_T / 16) * KB * 64;
-  // A fragments of G k-steps prefetched into one of two register buffers while
-  // the other group's MFMAs run; B fragments come from LDS just before use.
-  constexpr int G = NP == 2 ? 2 : 4;
-  const int Kmain = (KB / (2 * G)) * (2 * G);
+  // A fragments of G k-steps (a group) go into one of three register buffers
+  // two groups before their MFMAs; B fragments come from LDS just before use.
+  // The first two groups of the next template tile are loaded before the
+  // current tile's epilogue (after its threshold loads), so a short k-loop
+  // (small rank) does not start every tile with a full load latency.  A
+  // long k-loop runs a branch-free steady state, with the same two groups in
+  // flight on every path into it (otherwise the compiler's wait counts would
+  // stall on the loads just issued).
+  constexpr int G = (CB == 4 || NP == 2) ? 1 : 2;   // (register budget at two waves per SIMD)
+  const int ng = KB / G;
   const uint16_t* zl = zs + (lane & 31) * RS + 8 * (lane >> 5);
-  for (int tt = 0; tt < ntt; ++tt) {
-    const int rb0 = tt * (TILE_T / 16) + wave * WT_ROWB;
-    if (rb0 * 16 >= a.T) break;                            // the rest of the rows are padding
+  auto tile_rb0 = [&](int t) { return t * (TILE_T / 16) + wave * WT_ROWB; };
+  u16x8 fa[3][G][NP][WT_ROWB];
+  const u16x8* pa = nullptr;
+  auto load = [&](int s) {   // the group at pa, then advance pa
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int rb = 0; rb < WT_ROWB; ++rb) fa[s][g][p][rb] = pa[p * cplane + ((int64_t)rb * KB + g) * 64];
+    pa += G * 64;
+  };
+  f32x16 acc[WT_ROWB][CB];
+  auto step = [&](const u16x8 (&av)[NP][WT_ROWB], int kb) {
+    u16x8 bv[NP][CB];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+        bv[p][cb] = *reinterpret_cast<const u16x8*>(zl + cb * 32 * RS + p * R2 + 16 * kb);
+#pragma unroll
+    for (int rb = 0; rb < WT_ROWB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+        acc[rb][cb] = kstep<DT>(av[0][rb], av[NP - 1][rb], bv[0][cb], bv[NP - 1][cb], acc[rb][cb]);
+  };
+  auto mma = [&](int s, int grp) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) step(fa[s][g], grp * G + g);
+  };
+  // one template tile: the groups (the first two already loaded), the last
+  // KB mod G k-step, then the next tile's first groups and the epilogue
+  auto tile = [&](int tt, bool steady) {
+    const int rb0 = tile_rb0(tt);
     const u16x8* __restrict__ ap = cpk + (int64_t)rb0 * KB * 64 + lane;
-    f32x16 acc[WT_ROWB][CB];
 #pragma unroll
     for (int rb = 0; rb < WT_ROWB; ++rb)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = (f32x16){};
-    u16x8 fa[2][G][NP][WT_ROWB];
-    auto load = [&](int s, int kb0) {
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int p = 0; p < NP; ++p)
-#pragma unroll
-          for (int rb = 0; rb < WT_ROWB; ++rb)
-            fa[s][g][p][rb] = ap[p * cplane + ((int64_t)rb * KB + kb0 + g) * 64];
-    };
-    auto step = [&](const u16x8 (&av)[NP][WT_ROWB], int kb) {
-      u16x8 bv[NP][CB];
+    int gi = 0;
+    if (steady) {
+      do {
+        load(2);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(0, gi);
+        __builtin_amdgcn_sched_barrier(0);
+        load(0);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(1, gi + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        load(1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(2, gi + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        gi += 3;
+      } while (gi + 4 < ng);
+    }
+    // at most four groups remain (gi .. gi + 3), the first two already loaded
+    if (gi + 2 < ng) load(2);
+    if (gi < ng) mma(0, gi);
+    if (gi + 3 < ng) load(0);
+    if (gi + 1 < ng) mma(1, gi + 1);
+    if (gi + 2 < ng) mma(2, gi + 2);
+    if (gi + 3 < ng) mma(0, gi + 3);
+    if (KB % G) {
+      u16x8 av[NP][WT_ROWB];
 #pragma unroll
       for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-          bv[p][cb] = *reinterpret_cast<const u16x8*>(zl + cb * 32 * RS + p * R2 + 16 * kb);
-#pragma unroll
-      for (int rb = 0; rb < WT_ROWB; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-          acc[rb][cb] = kstep<DT>(av[0][rb], av[NP - 1][rb], bv[0][cb], bv[NP - 1][cb], acc[rb][cb]);
-    };
-    if (Kmain > 0) {
-      load(0, 0);
-      for (int kb0 = 0; kb0 < Kmain; kb0 += 2 * G) {
-        // the barriers keep each group's A loads ahead of the other group's MFMAs
-        load(1, kb0 + G);
+        for (int rb = 0; rb < WT_ROWB; ++rb) av[p][rb] = ap[p * cplane + ((int64_t)rb * KB + KB - 1) * 64];
+      step(av, KB - 1);
+    }
+    float th[WT_ROWB][8];
+    epi_thresholds<WT_ROWB>(a, rb0, th);
+    const bool more = tt + 1 < ntt && tile_rb0(tt + 1) * 16 < a.T;
+    if (more) {
+      pa = cpk + (int64_t)tile_rb0(tt + 1) * KB * 64 + lane;
+      if (steady) {
+        load(0);
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int g = 0; g < G; ++g) step(fa[0][g], kb0 + g);
+        load(1);
         __builtin_amdgcn_sched_barrier(0);
-        if (kb0 + 2 * G < Kmain) load(0, kb0 + 2 * G);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int g = 0; g < G; ++g) step(fa[1][g], kb0 + G + g);
-        __builtin_amdgcn_sched_barrier(0);
+      } else {
+        if (ng > 0) load(0);
+        if (ng > 1) load(1);
       }
     }
-    // the last KB - Kmain (< 2G) k-steps: all their A loads issue together
-    // (into the two group buffers) before the first of their MFMAs, so a
-    // short k-loop (small rank) waits for one load latency, not one per step
-    const int nt = KB - Kmain;
-    if (nt > 0) {
-#pragma unroll
-      for (int g = 0; g < 2 * G; ++g)
-        if (g < nt)
-#pragma unroll
-          for (int p = 0; p < NP; ++p)
-#pragma unroll
-            for (int rb = 0; rb < WT_ROWB; ++rb)
-              fa[g / G][g % G][p][rb] = ap[p * cplane + ((int64_t)rb * KB + Kmain + g) * 64];
-#pragma unroll
-      for (int g = 0; g < 2 * G; ++g)
-        if (g < nt) step(fa[g / G][g % G], Kmain + g);
+    epilogue<WT_ROWB, CB>(a, acc, rb0, q0, stg, th);
+    return more;
+  };
+  if (tile_rb0(0) * 16 < a.T) {
+    pa = cpk + (int64_t)tile_rb0(0) * KB * 64 + lane;
+    if (ng >= 5) {
+      load(0);
+      __builtin_amdgcn_sched_barrier(0);
+      load(1);
+      __builtin_amdgcn_sched_barrier(0);
+      for (int tt = 0; tile(tt, true); ++tt) {
+      }
+    } else {
+      if (ng > 0) load(0);
+      if (ng > 1) load(1);
+      for (int tt = 0; tile(tt, false); ++tt) {
+      }
     }
-    epilogue<WT_ROWB, CB>(a, acc, rb0, q0, stg);
   }
   if (stg.n > 0) stage_flush(a, stg, lane);
 }
