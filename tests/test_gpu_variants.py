@@ -1,0 +1,80 @@
+"""Every reconstruction-GEMM variant the autotuner may pick (forced with
+RBMF_GEMM_VARIANT, read when a basis first runs), on sub-banks whose template
+counts exercise whole 64-template tiles, a remainder, and a sub-bank smaller
+than one tile: the FP32 variants against the oracle's reduced-basis SNR, the
+16-bit ones against their own first variant (same quantised operands, FP32
+accumulation), and the threshold epilogues through the reconstruction second
+stage."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import basis as ob
+from oracle import mf as om
+from paper_2110_13115_amd import rbmf
+from tests.helpers import Case
+
+pytestmark = pytest.mark.gpu
+
+BOUNDS = [0, 64, 104, 300]        # 64 (one whole tile), 40 (remainder only), 196 (three tiles + 4)
+VARIANTS = {"f32": 6, "bf16": 3, "f16": 3, "bf16x3": 3}
+
+
+def log(*a):
+    print("[gpu-test]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def vcase():
+    case = Case(N=32768, T=300, f_low=30.0, mrange=(5.0, 9.0), order=7, cfg=21,
+                inj=((7, 12.0), (150, 8.0), (299, 6.5)))
+    ctx = rbmf.Context(0)
+    bank = rbmf.Bank(ctx, case.N, case.fs, case.f_low, case.psd, case.T, case.fill)
+    yield case, ctx, bank
+    bank.close()
+
+
+def bases_for(ctx, bank, dtype, variant, monkeypatch):
+    monkeypatch.setenv("RBMF_GEMM_VARIANT", str(variant))
+    monkeypatch.delenv("RBMF_TUNE_FILE", raising=False)
+    return [rbmf.Basis(ctx, bank, rank=r, dtype=dtype, t0=a, t1=b)
+            for a, b, r in zip(BOUNDS[:-1], BOUNDS[1:], (21, 13, 37))]
+
+
+def keyset(tr, lo):
+    return {(int(a), int(b)) for a, b, s in zip(tr["tmpl"], tr["sample"], tr["snr"]) if s >= lo}
+
+
+@pytest.mark.parametrize("dtype", list(VARIANTS))
+def test_every_variant(vcase, dtype, monkeypatch):
+    case, ctx, bank = vcase
+    k_lo, _ = om.band_limits(case.N, case.fs, case.f_low)
+    d = ob.whitened_data(case.s64, case.psd, case.fs, case.f_low)
+    ref_rho, ref_trig = None, None
+    for v in range(VARIANTS[dtype]):
+        bs = bases_for(ctx, bank, dtype, v, monkeypatch)
+        rho = np.concatenate([rbmf.debug_rho(ctx, bank, case.strain, b) for b in bs])
+        trig, _, _ = rbmf.rb_filter(ctx, bs, bank, case.strain, 5.0, 6.0, stage2=rbmf.RB_STAGE2_RECON)
+        if dtype == "f32":
+            # against the oracle's reduced-basis SNR with the exported bases
+            ref = []
+            for b in bs:
+                V, c, _ = b.export()
+                ref.append(ob.rb_snr(ob.basis_outputs(d, V, case.N, k_lo), c))
+            ref = np.concatenate(ref)
+            err = (np.abs(rho - ref) / np.maximum(np.abs(ref), 1.0)).max()
+            log(dtype, "variant", v, "rho err vs oracle", err)
+            assert err <= 1e-4, (v, err)
+        if ref_rho is None:
+            ref_rho, ref_trig = rho, trig
+        else:
+            err = (np.abs(rho - ref_rho) / np.maximum(np.abs(ref_rho), 1.0)).max()
+            log(dtype, "variant", v, "rho diff vs variant 0", err)
+            assert err <= 2e-5, (v, err)
+            # the epilogue's appends: the same crossings away from the threshold
+            a, b = keyset(trig, 6.0 * (1 + 1e-4)), keyset(ref_trig, 6.0 * (1 + 1e-4))
+            assert a <= keyset(ref_trig, 6.0 * (1 - 1e-4)) and b <= keyset(trig, 6.0 * (1 - 1e-4))
+        assert len(trig) > 0
+        for b in bs:
+            b.close()
