@@ -193,6 +193,7 @@ struct rb_basis_s {
   std::vector<float> row_scale;  // per-template power-of-two scale (16-bit), 1 otherwise
   DevBuf P;                    // K x nbs complex64
   DevBuf cpk;                  // packed realified C
+  DevBuf cpk3;                 // FP32: C packed for the three-product GEMM
   DevBuf C32;                  // T x K complex64 (conj(c)), unscaled, for the adjoint
   DevBuf row_inv;              // Tp floats 1/row_scale
   DevBuf row_scale_dev;        // Tp floats
@@ -1224,6 +1225,10 @@ rb_status finish_basis(rb_ctx ctx, rb_bank bank, int32_t t0, int64_t T, int K, c
   RB_TRY(bs->cpk.ensure(cpk_bytes));
   RB_HIP(launch_pack_c(bs->C32.as<float2>(), (int)T, bs->Tp, K, bs->Kp, (int)dtype,
                        dtype == RB_F16 ? bs->row_scale_dev.as<float>() : nullptr, bs->cpk.p, s));
+  if (dtype == RB_F32) {
+    RB_TRY(bs->cpk3.ensure((size_t)(bs->Tp / 32) * ((K + 1) / 2) * 64 * 16));
+    RB_HIP(launch_pack_c3(bs->C32.as<float2>(), (int)T, bs->Tp, K, bs->cpk3.p, s));
+  }
   RB_HIP(hipStreamSynchronize(s));
   if (rank_out) *rank_out = K;
   if (energy_out) *energy_out = bs->energy;
@@ -1457,6 +1462,7 @@ rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq
   ga.Kp = basis->Kp;
   ga.dtype = (int)basis->dtype;
   ga.cpk = basis->cpk.p;
+  ga.cpk3 = basis->cpk3.p;
   ga.z = ctx->z.p;
   ga.thr2_row = basis->thr_row.as<float>();
   ga.N1 = g.N1;

@@ -421,6 +421,131 @@ __global__ __launch_bounds__(256, 1) void k_recon_f32_w64(GemmArgs a) {
     recon_f32_tile<1, CB, G>(a, rb0, q0);
 }
 
+// FP32 by Gauss's three real products instead of the realified four:
+//   P1 = Cr Zr, P2 = Ci Zi, P3 = (Cr + Ci)(Zr + Zi);  Re rho = P1 - P2,
+//   Im rho = P3 - P1 - P2
+// (three MFMAs where the realified form needs four; the cancellation in Im
+// costs about one more rounding of sum |C||Z|, far below the FP32 tolerance).
+// One instruction reduces over a k-pair: lanes 0-31 hold k = 2 kp, lanes
+// 32-63 k = 2 kp + 1, rows are templates.  A wave takes 32 templates x 128
+// samples (three accumulator sets of four 32 x 32 blocks); the workgroup's
+// four waves take adjacent sample tiles.  Pipeline as in recon_f32_tile, one
+// k-pair per group.
+__global__ __launch_bounds__(256, 2) void k_recon_f32_3m(GemmArgs a) {
+  constexpr int CB = 4, TN = 128;
+  const int ntt = (a.T + 31) / 32;
+  const int64_t ncol = (a.N + WAVES * TN - 1) / (WAVES * TN);
+  int tt;
+  int64_t st;
+  if (!xcd_tile(ntt, (int64_t)ntt * ncol, tt, st)) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t q0 = (st * WAVES + wave) * TN;
+  if (q0 >= a.N) return;
+  const int K = a.K;
+  const int64_t N = a.N;
+  const int KP = (K + 1) / 2;
+  const float4* __restrict__ ap = static_cast<const float4*>(a.cpk3) + (int64_t)tt * KP * 64 + lane;
+  // rows 2k (Re) and 2k + 1 (Im) of k = 2 kp + lane / 32
+  const float* zb = static_cast<const float*>(a.z) + (int64_t)(2 * (lane >> 5)) * N + q0 + CB * (lane & 31);
+  f32x16 p1[CB], p2[CB], p3[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) p1[c] = p2[c] = p3[c] = (f32x16){};
+  const float4* pa = ap;
+  const float* pz = zb;
+  float4 fa[3], fr[3], fi[3];
+  auto load = [&](int s) {
+    fa[s] = *pa;
+    fr[s] = *reinterpret_cast<const float4*>(pz);
+    fi[s] = *reinterpret_cast<const float4*>(pz + N);
+    pa += 64;
+    pz += 4 * N;
+  };
+  auto mma3 = [&](const float4& av, const float4& br4, const float4& bi4) {
+    const float br[4] = {br4.x, br4.y, br4.z, br4.w};
+    const float bi[4] = {bi4.x, bi4.y, bi4.z, bi4.w};
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      p1[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, br[c], p1[c], 0, 0, 0);
+      p2[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bi[c], p2[c], 0, 0, 0);
+      p3[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, br[c] + bi[c], p3[c], 0, 0, 0);
+    }
+  };
+  auto mma = [&](int s) { mma3(fa[s], fr[s], fi[s]); };
+  const int ng = K / 2;                 // whole k-pairs; an odd K's last k runs after them
+  int gi = 0;
+  if (ng >= 5) {
+    load(0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(1);
+    __builtin_amdgcn_sched_barrier(0);
+    do {
+      load(2);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(0);
+      __builtin_amdgcn_sched_barrier(0);
+      load(0);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(1);
+      __builtin_amdgcn_sched_barrier(0);
+      load(1);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(2);
+      __builtin_amdgcn_sched_barrier(0);
+      gi += 3;
+    } while (gi + 4 < ng);
+  } else {
+    if (ng > 0) load(0);
+    if (ng > 1) load(1);
+  }
+  if (gi + 2 < ng) load(2);
+  if (gi < ng) mma(0);
+  if (gi + 3 < ng) load(0);
+  if (gi + 1 < ng) mma(1);
+  if (gi + 2 < ng) mma(2);
+  if (gi + 3 < ng) mma(0);
+  if (K & 1) {
+    // k = K - 1 in lanes 0-31; lanes 32-63 (k = K, zero coefficients) read
+    // the same rows, which exist
+    const float* zk = static_cast<const float*>(a.z) + (int64_t)(2 * (K - 1)) * N + q0 + CB * (lane & 31);
+    mma3(ap[(int64_t)ng * 64], *reinterpret_cast<const float4*>(zk), *reinterpret_cast<const float4*>(zk + N));
+  }
+  // epilogue: element i of a block is template row 8 (i / 4) + 4 (lane / 32) + i % 4
+  const int l1 = __builtin_ctz((unsigned)a.N1);
+  float th[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int j = tt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+    th[i] = j < a.T ? a.thr2_row[j] : __builtin_inff();
+  }
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const int q = (int)q0 + CB * (lane & 31) + c;
+    const int n = (q >> l1) + a.N2 * (q & (a.N1 - 1));
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int j = tt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+      const float re = p1[c][i] - p2[c][i];
+      const float im = p3[c][i] - p1[c][i] - p2[c][i];
+      if (a.rho_out != nullptr && j < a.T) {
+        const float sc = a.row_inv ? a.row_inv[j] : 1.f;
+        a.rho_out[(int64_t)j * a.N + n] = make_float2(re * sc, im * sc);
+      }
+      if (re * re + im * im >= th[i]) {
+        atomicAdd(&a.tmpl_count[j], 1);
+        const unsigned long long idx = atomicAdd(a.trig_count, 1ull);
+        if ((int64_t)idx < a.trig_cap) {
+          TrigRec t;
+          t.tmpl = a.tmpl_base + j;
+          t.sample = n;
+          t.re = re;
+          t.im = im;
+          a.trig[idx] = t;
+        }
+      }
+    }
+  }
+}
+
 // 16-bit operands: one instruction reduces over 16 realified entries = 8
 // complex k.  A lane l holds entries [8 (l/32), 8 (l/32) + 8) of row l%32
 // (4 complex k, Re/Im interleaved); B lane l holds the same 8 reduction rows
@@ -705,6 +830,27 @@ __global__ void k_pack_f32(const float2* C, int T, int Tp, int K, float* out) {
   }
 }
 
+// C for k_recon_f32_3m: [32-template tile][k-pair][lane] float4 (Cr, Ci, Cr + Ci, 0)
+// of template l % 32 of the tile and k = 2 pair + l / 32 (zero past T or K).
+__global__ void k_pack_f32_3m(const float2* C, int T, int Tp, int K, float4* out) {
+  const int KP = (K + 1) / 2;
+  const int64_t total = (int64_t)(Tp / 32) * KP * 64;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(i & 63);
+    const int64_t tk = i >> 6;
+    const int kp = (int)(tk % KP);
+    const int tile = (int)(tk / KP);
+    const int j = tile * 32 + (l & 31), k = 2 * kp + (l >> 5);
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (j < T && k < K) {
+      const float2 c = C[(int64_t)j * K + k];
+      v = make_float4(c.x, c.y, c.x + c.y, 0.f);
+    }
+    out[i] = v;
+  }
+}
+
 __global__ void k_pack_16(const float2* C, int T, int Tp, int K, int Kp, int dtype,
                           const float* row_scale, uint16_t* out) {
   const int KB = Kp / 8;
@@ -727,10 +873,17 @@ __global__ void k_pack_16(const float2* C, int T, int Tp, int K, int Kp, int dty
 
 }  // namespace
 
-int recon_variants(int dtype) { return dtype == 0 ? 6 : 3; }
+int recon_variants(int dtype) { return dtype == 0 ? 7 : 3; }
 
 hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
   if (a.Tp % TILE_T != 0 || a.N % 128 != 0) return hipErrorInvalidValue;
+  if (a.dtype == 0 && a.variant == 6) {   // three real products per k-pair (Gauss)
+    if (a.cpk3 == nullptr) return hipErrorInvalidValue;
+    const int64_t nwg = (int64_t)((a.T + 31) / 32) * ((a.N + WAVES * 128 - 1) / (WAVES * 128));
+    const int64_t launch = ((nwg + 7) / 8) * 8;
+    hipLaunchKernelGGL(k_recon_f32_3m, dim3((unsigned)launch), dim3(256), 0, st, a);
+    return hipGetLastError();
+  }
   if (a.dtype == 0 && a.variant >= 4) {   // 64 templates x 128 samples per wave: variant 4 = G 2, 5 = G 4
     // The whole 64-template tiles run here; the T mod 64 templates left
     // would run as a one- or two-block tile at one wave per SIMD, whose few
@@ -835,6 +988,11 @@ hipError_t launch_pack_c(const float2* C, int T, int Tp, int K, int Kp, int dtyp
   else
     hipLaunchKernelGGL(k_pack_16, dim3(1024), dim3(256), 0, st, C, T, Tp, K, Kp, dtype, row_scale,
                        static_cast<uint16_t*>(cpk));
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_c3(const float2* C, int T, int Tp, int K, void* cpk3, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_f32_3m, dim3(1024), dim3(256), 0, st, C, T, Tp, K, static_cast<float4*>(cpk3));
   return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ from tests.helpers import Case
 pytestmark = pytest.mark.gpu
 
 BOUNDS = [0, 64, 104, 300]        # 64 (one whole tile), 40 (remainder only), 196 (three tiles + 4)
-VARIANTS = {"f32": 6, "bf16": 3, "f16": 3, "bf16x3": 3}
+VARIANTS = {"f32": 7, "bf16": 3, "f16": 3, "bf16x3": 3}
 
 
 def log(*a):
