@@ -502,7 +502,10 @@ def main():
     achieved = flops / (gm * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"], "unit": "TFLOP/s",
             "frac": achieved / PEAK["f32"], "traffic": gemm_traffic(),
-            "kernel": "k_recon_f32 / k_recon_f32_w64 (rho = C Z, realified complex GEMM, FP32 MFMA 32x32x2)",
+            "kernel": "k_recon_f32_3m / k_recon_f32 / k_recon_f32_w64 (rho = C Z complex GEMM on FP32 MFMA "
+                      "32x32x2, variant autotuned per sub-bank)",
+            "flop_convention": "8*K*T*N per sub-bank (a complex multiply-add = 8 real flop); the three-product "
+                               "(Gauss) kernel issues 6*K*T*N of it on the MFMA units, the realified ones 8*K*T*N",
             "per_step": f"sum over sub-banks of 8*K_m*T_m*N = {flops:.4g} flop", "avg_ms_per_step": gm,
             "traffic_unit": "HBM bytes per sub-bank GEMM launch (its one or two dispatches; mean of the "
                             "ten; profiles/recon_gemm_f32_traffic_rb_256s_2000t.md)"}
