@@ -149,7 +149,7 @@ struct rb_ctx_s {
   DevBuf work, work64, dspec, strain, z, z32, recs1, thr_inf, adjA, adjAhat, adjB, adjT, adjS, adjRho, adjG, adjC, adjGC,
       adjOrd, adjSeg, trig1, trig2, recs, tmp, final_out, cnt1, cnt2, off1, off2, fill1, fill2,
       list1, list2, tmax, summary, counters, thr_row, peaks, flag, rho_tmp, zws, listH, listL, nsplit,
-      zfine, zpart, trigB, cntB, snap, tinv, gfold, offB, fillB, listB, recsB, sstrain, segout, wout, wcount;
+      zfine, zpart, trigB, cntB, snap, tinv, gfold, offB, fillB, listB, recsB, sstrain, segout, wout, wcount, goffB;
   int64_t gfold_N = 0;             // grid and bin width of the table in gfold
   int gfold_w = 0;
   hipEvent_t ev[8] = {};
@@ -1777,11 +1777,15 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
     if (sparse && nsplit[1] > 0) {
       SparseArgs sa = sparse_args(ctx, bank, g, tw, opts->thr2, nullptr, nullptr, 0);
       if (autom) sa.list = ctx->listL.as<int32_t>();
-      // enough workgroups per template that the busiest one is not a straggler
+      // one workgroup per group of crossings: offsets on the device, the grid
+      // an upper bound (sum of ceil(c / per) <= templates + crossings / per)
       const int64_t per = sparse_crossings_per_group();
-      const int64_t mx = autom ? std::min<int64_t>(sum1[2], split - 1) : sum1[2];
-      const int groups = (int)std::min<int64_t>(64, std::max<int64_t>(1, (mx + per - 1) / per));
-      RB_HIP(launch_sparse_exact(sa, nsplit[1], groups, ctx->stream));
+      RB_TRY(ctx->goffB.ensure((size_t)(T + 1) * 4));
+      RB_HIP(launch_group_offsets(sa.list, nsplit[1], sa.counts, (int)per, ctx->goffB.as<int32_t>(), ctx->stream));
+      sa.goff = ctx->goffB.as<int32_t>();
+      sa.nlist = nsplit[1];
+      const int64_t grid = std::min<int64_t>((int64_t)nsplit[1] + sum1[0] / per, (int64_t(1) << 31) - 1);
+      RB_HIP(launch_sparse_exact(sa, (int)grid, 1, ctx->stream));
     }
     if (!sparse && !recon)
       RB_TRY(step_mf(ctx, bank, g, tw, ctx->list1.as<int32_t>(), sum1[1], (float)(opts->thr2 * opts->thr2)));

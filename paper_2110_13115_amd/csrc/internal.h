@@ -197,7 +197,12 @@ struct SparseArgs {
   unsigned long long* out_count;
   int32_t* tmpl_count;
   unsigned long long* tmpl_max;
+  const int32_t* goff;        // optional: workgroup b takes group b - goff[i] of list[i] (goff[i] <= b < goff[i + 1])
+  int32_t nlist;              //   over the nlist listed templates (else: gridDim.y groups per template)
 };
+// goff[0..n]: exclusive prefix sums of ceil(counts[list[i]] / per) (goff[n] = total).
+hipError_t launch_group_offsets(const int32_t* list, int n, const int32_t* counts, int per, int32_t* goff,
+                                hipStream_t s);
 // grid: listed templates (upper bound with d_count); groups: workgroups that
 // share one template's crossings (each takes every groups-th group of 8).
 hipError_t launch_sparse_exact(const SparseArgs& a, int grid, int groups, hipStream_t s);

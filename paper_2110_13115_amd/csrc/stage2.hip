@@ -7,10 +7,13 @@
 // reconstruction error stays below thr2 - thr1, so the final trigger set equals
 // the template method's.
 //
-// Workgroup (x, y) takes template list[x] and its crossing groups y, y + G,
-// y + 2G, ... (G = gridDim.y, groups of up to SP_M crossings), streaming w_j
-// once per group; G > 1 spreads templates with many crossings (near a loud
-// signal) over several workgroups.  A thread owns the bins t, t + 256, ...,
+// With workgroup offsets (host-known list), workgroup b takes one group of up
+// to SP_M crossings of one template, so a template with many crossings (near
+// a loud signal) spreads over as many workgroups as it has groups and no
+// workgroup is launched for a group that does not exist.  Without them
+// (device-side counts), workgroup (x, y) takes template list[x] and its
+// crossing groups y, y + G, y + 2G, ... (G = gridDim.y).  A workgroup streams
+// w_j once per group.  A thread owns the bins t, t + 256, ...,
 // t + 7 * 256 of each 2048-bin tile (so every load of a wave is contiguous):
 // the twiddle of its first bin comes exactly from the two-level table
 // (e = f n mod N), the next seven by multiplication with e^{2 pi i 256 n / N}
@@ -139,9 +142,28 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
   __shared__ float2 red[SP_M][SP_T / 64];
   if (a.d_count != nullptr && (int)blockIdx.x >= *a.d_count) return;
   if (a.n1_dev != nullptr && *a.n1_dev > a.n1_cap) return;
-  const int j = a.list[blockIdx.x];
-  const int cnt = a.counts[j];
-  if ((int)blockIdx.y * SP_M >= cnt) return;   // no group of this template for this workgroup
+  int j, cnt, cfirst, cstep;
+  if (a.goff != nullptr) {
+    // one group per workgroup: list entry i with goff[i] <= b < goff[i + 1]
+    const int b = (int)blockIdx.x;
+    if (b >= a.goff[a.nlist]) return;   // (the grid is an upper bound)
+    int lo = 0, hi = a.nlist - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.goff[mid] <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    j = a.list[lo];
+    cnt = a.counts[j];
+    cfirst = (b - a.goff[lo]) * SP_M;
+    cstep = cnt;                        // a single group
+  } else {
+    j = a.list[blockIdx.x];
+    cnt = a.counts[j];
+    if ((int)blockIdx.y * SP_M >= cnt) return;   // no group of this template for this workgroup
+    cfirst = blockIdx.y * SP_M;
+    cstep = gridDim.y * SP_M;
+  }
   const int nlo = 1 << a.s_lo, nhi = (int)(a.N >> a.s_lo);
   // table copies: every load of a thread (clamped in bounds) issued before its LDS stores
   {
@@ -163,7 +185,7 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
   const float2* __restrict__ wj = a.tmpl + (int64_t)j * a.nbs - a.kb;   // indexed by absolute bin
   const float2* __restrict__ d = a.d - a.kb;
   unsigned long long best = 0ull;
-  for (int c0 = blockIdx.y * SP_M; c0 < cnt; c0 += gridDim.y * SP_M) {
+  for (int c0 = cfirst; c0 < cnt; c0 += cstep) {
     const int m = min(SP_M, cnt - c0);            // uniform over the workgroup
     switch (m) {   // straight-line sums over exactly m crossings
       case 1: sparse_group<1>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
@@ -183,7 +205,7 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
 
 hipError_t launch_sparse_exact(const SparseArgs& a, int grid, int groups, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  groups = groups < 1 ? 1 : (groups > 64 ? 64 : groups);
+  groups = a.goff != nullptr ? 1 : (groups < 1 ? 1 : (groups > 64 ? 64 : groups));
   hipLaunchKernelGGL(k_sparse_exact, dim3(grid, groups), dim3(SP_T), 0, s, a);
   return hipGetLastError();
 }

@@ -84,6 +84,23 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_counts(const int32_t* counts, i
   }
 }
 
+// Workgroup offsets of the sparse second stage: template list[i] takes
+// ceil(counts[list[i]] / per) workgroups, goff = their exclusive prefix sums.
+__global__ __launch_bounds__(SCAN_T) void k_group_offsets(const int32_t* list, int n, const int32_t* counts, int per,
+                                                          int32_t* goff) {
+  __shared__ int sh[64];
+  int carry = 0;
+  for (int base = 0; base < n; base += SCAN_T) {
+    const int i = base + threadIdx.x;
+    const int g = i < n ? (counts[list[i]] + per - 1) / per : 0;
+    int tot;
+    const int ex = block_excl_scan(g, sh, tot);
+    if (i < n) goff[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) goff[n] = carry;
+}
+
 // n_dev (optional): device record count; nothing is scattered when it exceeds
 // n (records were dropped at capacity; the caller reports it).
 __global__ void k_scatter(const TrigRec* in, int64_t n, const int64_t* n_dev, const int32_t* offsets,
@@ -312,6 +329,12 @@ hipError_t launch_window(const void* in, int64_t n, int64_t shift, int64_t lo, i
                          int64_t* n_out, hipStream_t s) {
   hipLaunchKernelGGL(k_window, dim3(1), dim3(SCAN_T), 0, s, static_cast<const rb_trigger*>(in), n, shift, lo, hi,
                      static_cast<rb_trigger*>(out), cap, n_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_offsets(const int32_t* list, int n, const int32_t* counts, int per, int32_t* goff,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_group_offsets, dim3(1), dim3(SCAN_T), 0, s, list, n, counts, per, goff);
   return hipGetLastError();
 }
 
