@@ -43,22 +43,30 @@ __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
 // M crossings (the caller instantiates M = m).
 template <int M>
 __device__ __forceinline__ void sparse_group(const SparseArgs& a, const float2* tlo, const float2* thi,
-                                             float2 (*red)[SP_T / 64], int j, int c0, int m, int lo, int hi,
-                                             const float2* __restrict__ d, const float2* __restrict__ wj,
-                                             unsigned long long& best) {
+                                             float2 (*red)[SP_T / 64], float2 (*sp)[SP_R], int j, int c0, int m,
+                                             int lo, int hi, const float2* __restrict__ d,
+                                             const float2* __restrict__ wj, unsigned long long& best) {
   const int mask = (1 << a.s_lo) - 1;
   const int N = (int)a.N;                       // N <= 2^30
   auto tw = [&](int e) { return cmulf(thi[e >> a.s_lo], tlo[e & mask]); };   // e in [0, N)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int off = a.offsets[j];
   int ns[M], e[M], inc[M];
-  float2 step[M], acc[M];
+  float2 acc[M];
   const int f00 = lo + threadIdx.x;
 #pragma unroll
   for (int i = 0; i < M; ++i) ns[i] = a.recs[off + c0 + min(i, m - 1)].sample;
+  // the phases of the bin offsets r SP_T within a thread's eight bins,
+  // e^{2 pi i r SP_T n / N}, one table per crossing in LDS (the same for
+  // every thread), exact from the twiddle table
+  __syncthreads();   // (the previous group's readers are done)
+  if ((int)threadIdx.x < M * SP_R) {
+    const int i = threadIdx.x / SP_R, r = threadIdx.x % SP_R;
+    sp[i][r] = tw((int)(((int64_t)(r * SP_T) * ns[i]) % N));
+  }
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < M; ++i) {
-    step[i] = tw((int)(((int64_t)SP_T * ns[i]) % N));
     acc[i] = make_float2(0.f, 0.f);
     e[i] = (int)(((int64_t)f00 * ns[i]) % N);                   // exponent of this thread's first bin
     inc[i] = (int)(((int64_t)(SP_T * SP_R) * ns[i]) % N);       // advance per tile
@@ -86,13 +94,17 @@ __device__ __forceinline__ void sparse_group(const SparseArgs& a, const float2* 
     fetch(f0 + SP_T * SP_R);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      float2 w = tw(e[i]);
+      // y = sum_r x_r e^{2 pi i r SP_T n / N}, then acc += y e^{2 pi i f0 n / N}
+      float2 y = make_float2(0.f, 0.f);
 #pragma unroll
       for (int r = 0; r < SP_R; ++r) {
-        acc[i].x = fmaf(-x[r].y, w.y, fmaf(x[r].x, w.x, acc[i].x));
-        acc[i].y = fmaf(x[r].y, w.x, fmaf(x[r].x, w.y, acc[i].y));
-        w = cmulf(w, step[i]);
+        const float2 sv = sp[i][r];
+        y.x = fmaf(-x[r].y, sv.y, fmaf(x[r].x, sv.x, y.x));
+        y.y = fmaf(x[r].y, sv.x, fmaf(x[r].x, sv.y, y.y));
       }
+      const float2 w = tw(e[i]);
+      acc[i].x = fmaf(-y.y, w.y, fmaf(y.x, w.x, acc[i].x));
+      acc[i].y = fmaf(y.y, w.x, fmaf(y.x, w.y, acc[i].y));
       e[i] += inc[i];
       if (e[i] >= N) e[i] -= N;
     }
@@ -140,6 +152,7 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
   __shared__ float2 tlo[2048];
   __shared__ float2 thi[1024];
   __shared__ float2 red[SP_M][SP_T / 64];
+  __shared__ float2 sp[SP_M][SP_R];
   if (a.d_count != nullptr && (int)blockIdx.x >= *a.d_count) return;
   if (a.n1_dev != nullptr && *a.n1_dev > a.n1_cap) return;
   int j, cnt, cfirst, cstep;
@@ -188,14 +201,14 @@ __global__ __launch_bounds__(SP_T) void k_sparse_exact(SparseArgs a) {
   for (int c0 = cfirst; c0 < cnt; c0 += cstep) {
     const int m = min(SP_M, cnt - c0);            // uniform over the workgroup
     switch (m) {   // straight-line sums over exactly m crossings
-      case 1: sparse_group<1>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
-      case 2: sparse_group<2>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
-      case 3: sparse_group<3>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
-      case 4: sparse_group<4>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
-      case 5: sparse_group<5>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
-      case 6: sparse_group<6>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
-      case 7: sparse_group<7>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
-      default: sparse_group<8>(a, tlo, thi, red, j, c0, m, lo, hi, d, wj, best); break;
+      case 1: sparse_group<1>(a, tlo, thi, red, sp, j, c0, m, lo, hi, d, wj, best); break;
+      case 2: sparse_group<2>(a, tlo, thi, red, sp, j, c0, m, lo, hi, d, wj, best); break;
+      case 3: sparse_group<3>(a, tlo, thi, red, sp, j, c0, m, lo, hi, d, wj, best); break;
+      case 4: sparse_group<4>(a, tlo, thi, red, sp, j, c0, m, lo, hi, d, wj, best); break;
+      case 5: sparse_group<5>(a, tlo, thi, red, sp, j, c0, m, lo, hi, d, wj, best); break;
+      case 6: sparse_group<6>(a, tlo, thi, red, sp, j, c0, m, lo, hi, d, wj, best); break;
+      case 7: sparse_group<7>(a, tlo, thi, red, sp, j, c0, m, lo, hi, d, wj, best); break;
+      default: sparse_group<8>(a, tlo, thi, red, sp, j, c0, m, lo, hi, d, wj, best); break;
     }
   }
   if (a.tmpl_max != nullptr && threadIdx.x < SP_M && best != 0ull) atomicMax(&a.tmpl_max[j], best);
