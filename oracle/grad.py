@@ -55,7 +55,7 @@ def loss_and_grads(s: np.ndarray, C: np.ndarray, V: np.ndarray, w: np.ndarray, k
                  torch.as_tensor(np.asarray(samp, np.int64)),
                  torch.as_tensor(np.asarray(g, np.float64)))
     L.backward()
-    return float(L), Ct.grad.numpy().copy(), st.grad.numpy().copy()
+    return float(L.detach()), Ct.grad.numpy().copy(), st.grad.numpy().copy()
 
 
 def refine_optimum(Zn: np.ndarray, span: np.ndarray) -> Tuple[np.ndarray, float]:

@@ -49,7 +49,8 @@ def test_mf_equals_time_domain_circular_cross_correlation():
     s = rng.standard_normal(N) * 1e-21
     H = bank.full()
     df = fs / N
-    k_lo, k_hi = om.band_limits(N, fs, f_low)
+    k_lo = next(k for k in range(N) if k * df >= f_low)       # first bin at or above f_low
+    k_hi = N // 2 - 1                                          # Nyquist excluded
     k = np.arange(k_lo, k_hi + 1)
     m = np.arange(N)
     E_fwd = np.exp(-2j * np.pi * np.outer(k, m) / N)          # band x N
@@ -64,6 +65,28 @@ def test_mf_equals_time_domain_circular_cross_correlation():
         ref = np.array([N * np.sum(np.roll(a, -n) * np.conj(b)) for n in range(N)])
         got = om.snr_series(s, H[j], psd, fs, f_low)
         np.testing.assert_allclose(got, ref, rtol=0, atol=1e-10 * np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("N,fs,f_low,k_lo", [
+    (4096, 1000.0, 20.0, 82),       # f_low / df = 81.92: first bin above f_low
+    (4096, 4096.0, 20.0, 20),       # f_low on a bin: that bin is in the band (inclusive)
+    (1024, 256.0, 12.1, 49),        # df = 0.25: 12.1 / 0.25 = 48.4
+])
+def test_band_edges_by_hand(N, fs, f_low, k_lo):
+    """Band = [ceil(f_low / df), N/2 - 1]; DC and Nyquist excluded (values
+    worked out by hand for each grid)."""
+    assert om.band_limits(N, fs, f_low) == (k_lo, N // 2 - 1)
+    m = om.band_mask(N, fs, f_low)
+    assert m.sum() == N // 2 - k_lo and m[k_lo] and not m[k_lo - 1] and not m[0] and not m[N // 2]
+    # a tone exactly on the bin below the band leaves the filter output at zero,
+    # one on the first band bin passes
+    psd = np.ones(N // 2 + 1)
+    h = np.zeros(N // 2 + 1, complex)
+    h[k_lo - 1:] = 1.0
+    for kk, passes in ((k_lo - 1, False), (k_lo, True)):
+        s = np.cos(2 * np.pi * kk * np.arange(N) / N)
+        z = om.complex_filter(om.strain_tilde(s, fs), h, psd, N, fs, f_low)
+        assert (np.abs(z).max() > 1e-6) == passes
 
 
 def test_parseval():
@@ -255,6 +278,46 @@ def test_gradients_match_central_differences():
         e = 1e-3 * np.sqrt(np.mean(s ** 2))
         fd = (og.loss(s + e * v, C, *args) - og.loss(s - e * v, C, *args)) / (2 * e)
         assert fd == pytest.approx(float(gs @ v), rel=1e-7)
+
+
+def _grad_case(rank):
+    N, fs, f_low = 1024, 256.0, 12.0
+    bank, psd = small_setup(N, fs, f_low, T=8)
+    H = bank.full()
+    W, _ = ob.whitened_unit_templates(H, psd, N, fs, f_low)
+    V, c, *_ = ob.svd_basis(W, rank=rank)
+    k_lo, _ = om.band_limits(N, fs, f_low)
+    w = ob.whiten_weights(psd, N, fs, f_low)[k_lo:k_lo + V.shape[1]]
+    rng = np.random.default_rng(17)
+    s = gi.strain_from_tilde(gi.coloured_noise_tilde(psd, N, fs, rng), N, fs)
+    s = s + 0.3 * np.sqrt(np.mean(s ** 2)) * np.sin(0.37 * np.arange(N))   # breaks any symmetry of the noise
+    return N, fs, f_low, H, psd, V, c, k_lo, w, s
+
+
+def test_gradient_loss_equals_ifft_route():
+    """The loss of the gradient oracle (direct sums at the trigger samples)
+    equals sum g |rho_RB|^2 taken from the inverse-FFT route of the basis
+    outputs (Eqs. basis_SNR, Beta_eqn) at the same samples."""
+    N, fs, f_low, H, psd, V, c, k_lo, w, s = _grad_case(rank=5)
+    tmpl = np.array([0, 0, 3, 5, 7, 2])
+    samp = np.array([10, 11, 500, 1023, 0, 333])
+    g = np.array([1.0, 0.5, 2.0, 1.0, 1.5, 0.25])
+    rho = ob.rb_snr(ob.basis_outputs(ob.whitened_data(s, psd, fs, f_low), V, N, k_lo), c)
+    ref = float(np.sum(g * np.abs(rho[tmpl, samp]) ** 2))
+    L = og.loss(s, np.conj(c), V, w, k_lo, fs, tmpl, samp, g)
+    assert L == pytest.approx(ref, rel=1e-12)
+
+
+def test_gradient_loss_at_full_rank_equals_template_method():
+    """At full rank the loss is sum g |rho_j[n]|^2 of the template method
+    (Eq. IFFT / SNR_def, per template, no basis)."""
+    N, fs, f_low, H, psd, V, c, k_lo, w, s = _grad_case(rank=8)
+    tmpl = np.array([1, 4, 4, 6])
+    samp = np.array([7, 100, 101, 900])
+    g = np.array([1.0, 2.0, 0.5, 1.0])
+    ref = sum(gg * abs(om.snr_series(s, H[j], psd, fs, f_low)[n]) ** 2 for j, n, gg in zip(tmpl, samp, g))
+    L = og.loss(s, np.conj(c), V, w, k_lo, fs, tmpl, samp, g)
+    assert L == pytest.approx(ref, rel=1e-10)
 
 
 def test_refine_optimum_is_projection():
