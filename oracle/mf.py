@@ -18,9 +18,14 @@ Conventions (readings of the paper where it is silent or garbled):
 from __future__ import annotations
 
 import math
+import os
 from typing import Iterator, Tuple
 
 import numpy as np
+import scipy.fft as sfft
+
+# threads of the batched inverse transforms (a host CPU share, not the machine's core count)
+WORKERS = max(1, min(16, int(os.environ.get("ORACLE_WORKERS", "0")) or (os.cpu_count() or 1)))
 
 
 def band_limits(N: int, fs: float, f_low: float) -> Tuple[int, int]:
@@ -58,6 +63,21 @@ def complex_filter(s_t: np.ndarray, h: np.ndarray, psd: np.ndarray, N: int, fs: 
     X[: N // 2 + 1][m] = s_t[m] * np.conj(h[m]) / psd[m]
     # numpy's ifft carries 1/N; the sum in Eq. IFFT has none.
     return 4.0 * df * N * np.fft.ifft(X)
+
+
+def snr_rows(s_t: np.ndarray, H: np.ndarray, psd: np.ndarray, N: int, fs: float, f_low: float,
+             workers: int = 0) -> np.ndarray:
+    """rho_j[n] = z_j[n] / sigma_j for every row of H (templates on all N/2+1
+    bins): the same sums as complex_filter and sigma, one inverse transform
+    per row, `workers` threads (0: WORKERS)."""
+    df = fs / N
+    m = band_mask(N, fs, f_low)
+    H = np.asarray(H, dtype=np.complex128)
+    X = np.zeros((H.shape[0], N), dtype=np.complex128)
+    X[:, : N // 2 + 1][:, m] = s_t[m][None, :] * np.conj(H[:, m]) / psd[m][None, :]
+    z = (4.0 * df * N) * sfft.ifft(X, axis=1, workers=workers or WORKERS)
+    sig = np.sqrt(4.0 * df * np.sum(np.abs(H[:, m]) ** 2 / psd[m][None, :], axis=1))
+    return z / sig[:, None]
 
 
 def snr_series(s: np.ndarray, h: np.ndarray, psd: np.ndarray, fs: float, f_low: float) -> np.ndarray:
