@@ -64,6 +64,20 @@ struct DevBuf {
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
   ~DevBuf() { release(); }
   void release() {
     if (p) (void)hipFree(p);
@@ -149,7 +163,8 @@ struct rb_ctx_s {
   DevBuf work, work64, dspec, strain, z, z32, recs1, thr_inf, adjA, adjAhat, adjB, adjT, adjS, adjRho, adjG, adjC, adjGC,
       adjOrd, adjSeg, trig1, trig2, recs, tmp, final_out, cnt1, cnt2, off1, off2, fill1, fill2,
       list1, list2, tmax, summary, counters, thr_row, peaks, flag, rho_tmp, zws, listH, listL, nsplit,
-      zfine, zpart, trigB, cntB, snap, tinv, gfold, offB, fillB, listB, recsB, sstrain, segout, wout, wcount, goffB;
+      zfine, zpart, trigB, cntB, snap, tinv, gfold, offB, fillB, listB, recsB, sstrain, segout, wout, wcount, goffB,
+      refOv, refQ, refC, refN, refP;
   int64_t gfold_N = 0;             // grid and bin width of the table in gfold
   int gfold_w = 0;
   hipEvent_t ev[8] = {};
@@ -699,6 +714,15 @@ rb_status step_fold(rb_ctx ctx, rb_bank bank, const FftGeom& gM, int w, float th
   return RB_OK;
 }
 
+// Records of a context's trigger buffers when they are first allocated;
+// RBMF_TRIG_RECORDS=<n> starts every buffer at n records instead (the growth
+// paths then run on small searches too).
+int64_t initial_records(int64_t dflt) {
+  const char* e = std::getenv("RBMF_TRIG_RECORDS");
+  const int64_t n = e ? std::atoll(e) : dflt;
+  return std::max<int64_t>(1, std::min<int64_t>(n, int64_t(1) << 28));
+}
+
 rb_status ensure_trigger_scratch(rb_ctx ctx, int T) {
   RB_TRY(ctx->cnt1.ensure((size_t)T * 4));
   RB_TRY(ctx->cnt2.ensure((size_t)T * 4));
@@ -713,9 +737,9 @@ rb_status ensure_trigger_scratch(rb_ctx ctx, int T) {
   RB_TRY(ctx->counters.ensure(4 * 8));
   RB_TRY(ctx->cntB.ensure((size_t)T * 4));
   RB_TRY(ctx->flag.ensure(8));
-  if (ctx->trig1.bytes == 0) RB_TRY(ctx->trig1.ensure((size_t)1 << 22 << 4));
-  if (ctx->trig2.bytes == 0) RB_TRY(ctx->trig2.ensure((size_t)1 << 20 << 4));
-  if (ctx->trigB.bytes == 0) RB_TRY(ctx->trigB.ensure((size_t)1 << 20 << 4));
+  if (ctx->trig1.bytes == 0) RB_TRY(ctx->trig1.ensure((size_t)initial_records(1 << 22) * sizeof(TrigRec)));
+  if (ctx->trig2.bytes == 0) RB_TRY(ctx->trig2.ensure((size_t)initial_records(1 << 20) * sizeof(TrigRec)));
+  if (ctx->trigB.bytes == 0) RB_TRY(ctx->trigB.ensure((size_t)initial_records(1 << 20) * sizeof(TrigRec)));
   return RB_OK;
 }
 
@@ -1131,7 +1155,8 @@ rb_status subspace_pca(rb_ctx ctx, BasisWork& bw, const float2* W, int64_t T, in
 }
 
 // The K leading Ritz vectors BS = B S[:, :K] (n x K, complex128).
-rb_status ritz_vectors(rb_ctx ctx, BasisWork& bw, int64_t n, int Lc, int K, const std::vector<cd>& S, DevBuf& BS) {
+rb_status ritz_vectors(rb_ctx ctx, BasisWork& bw, int64_t n, int Lc, int K, const std::vector<cd>& S, DevBuf& BS,
+                       int64_t ldb = 0) {
   hipStream_t s = ctx->stream;
   std::vector<cd> Sk((size_t)Lc * K);
   for (int i = 0; i < Lc; ++i)
@@ -1140,11 +1165,213 @@ rb_status ritz_vectors(rb_ctx ctx, BasisWork& bw, int64_t n, int Lc, int K, cons
   RB_TRY(Sd.ensure(Sk.size() * 16));
   RB_HIP(hipMemcpyAsync(Sd.p, Sk.data(), Sk.size() * 16, hipMemcpyHostToDevice, s));
   RB_TRY(BS.ensure((size_t)n * K * 16));
-  ZOperand Bo{bw.B.p, 0, Lc, 1, 0};
+  ZOperand Bo{bw.B.p, 0, ldb > 0 ? ldb : Lc, 1, 0};
   ZOperand So{Sd.p, 0, K, 1, 0};
   RB_HIP(launch_zgemm(n, K, Lc, Bo, So, BS.as<double2>(), K, 0, bw.ws.as<double2>(), (int64_t)(bw.ws.bytes / 16),
                       s));
   RB_HIP(hipStreamSynchronize(s));   // Sk is pageable and local
+  return RB_OK;
+}
+
+// Block Lanczos with full reorthogonalisation for the leading eigenpairs of
+// the Gram matrix G = W W^H (T x T) of the stored rows (Sec. II.A: its
+// eigenvectors give the basis; the paper runs a Lanczos eigensolver on the
+// covariance, Sec. III.B), applied as G X = W (W^H X) without forming G.
+// Krylov blocks X_0, X_1, ... of `b` columns: X_{j+1} orthonormalises
+// G X_j after two passes of classical Gram-Schmidt against every earlier
+// block (columns that vanish are dropped; an empty block means the Krylov
+// space is invariant).  After each block the Rayleigh-Ritz problem
+// M = V^H G V is solved on the host; the residual of Ritz pair (theta, s) is
+// |G V s - theta V s|^2 = s^H P s - theta^2 with P = (G V)^H (G V).  Stops
+// when the pairs that the rank rule keeps have residuals <= 1e-7 theta_1 (or
+// the space reaches T).  On return bw.B holds W^H V (n x ldb, ldb >= Lc), and
+// theta / S / Lc / K as subspace_pca's.
+rb_status lanczos_pca(rb_ctx ctx, BasisWork& bw, const float2* W, int64_t T, int64_t n, int64_t ld, double trace,
+                      int32_t rank, double tol, std::vector<double>& theta, std::vector<cd>& S, int& Lc, int& K,
+                      int64_t& ldb) {
+  hipStream_t s = ctx->stream;
+  const ZOperand Wop{W, 1, ld, 1, 0};    // T x n
+  const ZOperand WHop{W, 1, 1, ld, 1};   // n x T  (conjugate transpose)
+  const int b = (int)std::min<int64_t>(T, rank > 0 ? std::max(16, std::min(64, rank / 4)) : 32);
+  // Krylov dimension cap: the rank (or a first guess) several times over, at most T
+  const int64_t want = rank > 0 ? rank : 160;
+  int64_t cap = std::min<int64_t>(T, std::max<int64_t>(4 * want + 4 * b, 8 * b));
+  DevBuf V, GV, Y, H, P;
+  auto grow = [&](int64_t c) -> rb_status {    // column capacity of V, GV, B
+    cap = c;
+    DevBuf v2, g2, b2;
+    RB_TRY(v2.ensure((size_t)T * cap * 16));
+    RB_TRY(g2.ensure((size_t)T * cap * 16));
+    RB_TRY(b2.ensure((size_t)n * cap * 16));
+    if (Lc > 0) {
+      RB_HIP(hipMemcpy2DAsync(v2.p, cap * 16, V.p, ldb * 16, (size_t)Lc * 16, T, hipMemcpyDeviceToDevice, s));
+      RB_HIP(hipMemcpy2DAsync(g2.p, cap * 16, GV.p, ldb * 16, (size_t)Lc * 16, T, hipMemcpyDeviceToDevice, s));
+      RB_HIP(hipMemcpy2DAsync(b2.p, cap * 16, bw.B.p, ldb * 16, (size_t)Lc * 16, n, hipMemcpyDeviceToDevice, s));
+      RB_HIP(hipStreamSynchronize(s));
+    }
+    V = std::move(v2);
+    GV = std::move(g2);
+    bw.B = std::move(b2);
+    ldb = cap;
+    return RB_OK;
+  };
+  Lc = 0;
+  K = 0;
+  ldb = 0;
+  RB_TRY(grow(cap));
+  RB_TRY(Y.ensure((size_t)T * b * 16));
+  RB_TRY(bw.Y.ensure((size_t)T * b * 16));
+  RB_TRY(bw.Q.ensure((size_t)T * b * 16));
+  // random start block, orthonormalised
+  std::mt19937_64 rng(0x2110131151ull);
+  std::normal_distribution<double> nd;
+  {
+    std::vector<cd> Om((size_t)T * b);
+    for (auto& v : Om) v = cd(nd(rng), nd(rng));
+    RB_HIP(hipMemcpyAsync(Y.p, Om.data(), Om.size() * 16, hipMemcpyHostToDevice, s));
+    int kept = 0;
+    RB_TRY(svqb(ctx, bw, Y.as<double2>(), T, b, bw.Q.as<double2>(), &kept));
+    RB_HIP(hipMemcpy2DAsync(V.p, ldb * 16, bw.Q.p, (size_t)kept * 16, (size_t)kept * 16, T, hipMemcpyDeviceToDevice,
+                            s));
+    RB_HIP(hipStreamSynchronize(s));   // Om is pageable and local
+    Lc = kept;
+  }
+  int64_t c0 = 0;          // first column of the newest block
+  bool final_pass = false; // the Krylov space stopped growing: solve once more on it and stop
+  for (;;) {
+    const int bj = (int)(Lc - c0);
+    // W^H X_j -> B columns [c0, Lc); G X_j -> GV columns [c0, Lc)
+    {
+      ZOperand Xop{V.as<double2>() + c0, 0, ldb, 1, 0};
+      RB_HIP(launch_zgemm(n, bj, T, WHop, Xop, bw.B.as<double2>() + c0, ldb, 0, bw.ws.as<double2>(),
+                          (int64_t)(bw.ws.bytes / 16), s));
+      ZOperand Bop{bw.B.as<double2>() + c0, 0, ldb, 1, 0};
+      RB_HIP(launch_zgemm(T, bj, n, Wop, Bop, GV.as<double2>() + c0, ldb, 0, bw.ws.as<double2>(),
+                          (int64_t)(bw.ws.bytes / 16), s));
+    }
+    const bool too_small = !final_pass && rank > 0 && Lc < std::min<int64_t>(T, (int64_t)rank + b) && Lc + b <= T;
+    // Rayleigh-Ritz on V (Lc columns): M = V^H GV, P = GV^H GV
+    std::vector<cd> Mh((size_t)Lc * Lc);
+    if (!too_small) {
+      RB_TRY(H.ensure((size_t)Lc * Lc * 16));
+      RB_TRY(P.ensure((size_t)Lc * Lc * 16));
+      ZOperand VH{V.p, 0, 1, ldb, 1};
+      ZOperand GVo{GV.p, 0, ldb, 1, 0};
+      ZOperand GVH{GV.p, 0, 1, ldb, 1};
+      RB_HIP(launch_zgemm(Lc, Lc, T, VH, GVo, H.as<double2>(), Lc, 0, bw.ws.as<double2>(),
+                          (int64_t)(bw.ws.bytes / 16), s));
+      RB_HIP(launch_zgemm(Lc, Lc, T, GVH, GVo, P.as<double2>(), Lc, 0, bw.ws.as<double2>(),
+                          (int64_t)(bw.ws.bytes / 16), s));
+      RB_HIP(hipMemcpyAsync(Mh.data(), H.p, Mh.size() * 16, hipMemcpyDeviceToHost, s));
+      RB_HIP(hipStreamSynchronize(s));
+    }
+    double worst = 0.0;
+    int npos = 0;
+    if (!too_small) {
+    // symmetrise (rounding) and solve
+    for (int i = 0; i < Lc; ++i)
+      for (int j = 0; j < i; ++j) {
+        const cd a = 0.5 * (Mh[(size_t)i * Lc + j] + std::conj(Mh[(size_t)j * Lc + i]));
+        Mh[(size_t)i * Lc + j] = a;
+        Mh[(size_t)j * Lc + i] = std::conj(a);
+      }
+    RB_CHECK(herm_eig_desc((int)Lc, Mh, theta, S), RB_ERR_NUMERIC, "eigensolver did not converge");
+    npos = 0;
+    while (npos < Lc && theta[npos] > 1e-14 * theta[0]) ++npos;
+    if (rank > 0) {
+      K = (int)std::min<int64_t>(rank, npos);
+    } else {
+      double cum = 0.0;
+      K = 0;
+      while (K < npos && cum < (1.0 - tol) * trace) cum += theta[K++];
+    }
+    // residuals of the pairs that are kept: s_k^H P s_k - theta_k^2, P S_K on the device
+    {
+      std::vector<cd> Sk((size_t)Lc * K), PS((size_t)Lc * K);
+      for (int i = 0; i < Lc; ++i)
+        for (int k = 0; k < K; ++k) Sk[(size_t)i * K + k] = S[(size_t)i * Lc + k];
+      DevBuf Sd, PSd;
+      RB_TRY(Sd.ensure(Sk.size() * 16));
+      RB_TRY(PSd.ensure(PS.size() * 16));
+      RB_HIP(hipMemcpyAsync(Sd.p, Sk.data(), Sk.size() * 16, hipMemcpyHostToDevice, s));
+      ZOperand Po{P.p, 0, Lc, 1, 0};
+      ZOperand So{Sd.p, 0, K, 1, 0};
+      RB_HIP(launch_zgemm(Lc, K, Lc, Po, So, PSd.as<double2>(), K, 0, bw.ws.as<double2>(),
+                          (int64_t)(bw.ws.bytes / 16), s));
+      RB_HIP(hipMemcpyAsync(PS.data(), PSd.p, PS.size() * 16, hipMemcpyDeviceToHost, s));
+      RB_HIP(hipStreamSynchronize(s));
+      for (int k = 0; k < K; ++k) {
+        double q = 0.0;
+        for (int i = 0; i < Lc; ++i) q += (std::conj(Sk[(size_t)i * K + k]) * PS[(size_t)i * K + k]).real();
+        worst = std::max(worst, std::sqrt(std::max(0.0, q - theta[k] * theta[k])));
+      }
+    }
+    }
+    const bool energy_ok = too_small || rank > 0 || K < npos || Lc >= T;   // the rule is met inside the space
+    const bool spare = Lc >= K + b;
+    if (std::getenv("RBMF_VERBOSE") && !too_small)
+      std::fprintf(stderr, "[rbmf] lanczos T=%lld: %d columns, K %d, worst residual %.3e theta_1 %.3e\n",
+                   (long long)T, Lc, K, worst, theta[0]);
+    if (final_pass || (!too_small && ((energy_ok && spare && worst <= 1e-7 * theta[0]) || Lc >= T))) break;
+    // next block: G X_j orthogonalised against every block (two passes), then orthonormalised
+    const int64_t nb_next = std::min<int64_t>(b, T - Lc);
+    if (Lc + nb_next > cap) RB_TRY(grow(std::min<int64_t>(T, 2 * cap)));
+    RB_HIP(hipMemcpy2DAsync(Y.p, (size_t)bj * 16, GV.as<double2>() + c0, ldb * 16, (size_t)bj * 16, T,
+                            hipMemcpyDeviceToDevice, s));
+    auto col_norms = [&](std::vector<double>& out) -> rb_status {   // |Y e_i|^2
+      RB_TRY(P.ensure((size_t)bj * bj * 16));
+      ZOperand YH{Y.p, 0, 1, bj, 1};
+      ZOperand Yo{Y.p, 0, bj, 1, 0};
+      RB_HIP(launch_zgemm(bj, bj, T, YH, Yo, P.as<double2>(), bj, 0, bw.ws.as<double2>(),
+                          (int64_t)(bw.ws.bytes / 16), s));
+      std::vector<cd> g((size_t)bj * bj);
+      RB_HIP(hipMemcpyAsync(g.data(), P.p, g.size() * 16, hipMemcpyDeviceToHost, s));
+      RB_HIP(hipStreamSynchronize(s));
+      out.resize(bj);
+      for (int i = 0; i < bj; ++i) out[i] = g[(size_t)i * bj + i].real();
+      return RB_OK;
+    };
+    std::vector<double> n0, n1;
+    RB_TRY(col_norms(n0));
+    for (int pass = 0; pass < 2; ++pass) {
+      RB_TRY(H.ensure((size_t)Lc * bj * 16));
+      ZOperand VH{V.p, 0, 1, ldb, 1};
+      ZOperand Yo{Y.p, 0, bj, 1, 0};
+      RB_HIP(launch_zgemm(Lc, bj, T, VH, Yo, H.as<double2>(), bj, 0, bw.ws.as<double2>(),
+                          (int64_t)(bw.ws.bytes / 16), s));
+      std::vector<cd> Hh((size_t)Lc * bj);
+      RB_HIP(hipMemcpyAsync(Hh.data(), H.p, Hh.size() * 16, hipMemcpyDeviceToHost, s));
+      RB_HIP(hipStreamSynchronize(s));
+      for (auto& v : Hh) v = -v;
+      RB_HIP(hipMemcpyAsync(H.p, Hh.data(), Hh.size() * 16, hipMemcpyHostToDevice, s));
+      ZOperand Vo{V.p, 0, ldb, 1, 0};
+      ZOperand Ho{H.p, 0, bj, 1, 0};
+      RB_HIP(launch_zgemm(T, bj, Lc, Vo, Ho, Y.as<double2>(), bj, 1, bw.ws.as<double2>(),
+                          (int64_t)(bw.ws.bytes / 16), s));
+      RB_HIP(hipStreamSynchronize(s));   // Hh is pageable and local
+    }
+    // a column reduced below 1e-10 of its norm is rounding noise, not a new direction: zero it, so the
+    // orthonormalisation drops it
+    RB_TRY(col_norms(n1));
+    for (int i = 0; i < bj; ++i)
+      if (!(n1[i] > 1e-20 * n0[i]))
+        RB_HIP(hipMemset2DAsync(Y.as<double2>() + i, (size_t)bj * 16, 0, 16, T, s));
+    int kept = 0;
+    const rb_status st = svqb(ctx, bw, Y.as<double2>(), T, bj, bw.Q.as<double2>(), &kept);
+    // a block that vanishes entirely (the Krylov space is invariant) ends the iteration
+    if (st != RB_OK) {
+      final_pass = true;
+      continue;
+    }
+    kept = (int)std::min<int64_t>(kept, nb_next);
+    RB_HIP(hipMemcpy2DAsync(V.as<double2>() + Lc, ldb * 16, bw.Q.p, (size_t)kept * 16, (size_t)kept * 16, T,
+                            hipMemcpyDeviceToDevice, s));
+    c0 = Lc;
+    Lc += kept;
+  }
+  RB_CHECK(K >= 1, RB_ERR_NUMERIC, "basis has rank zero");
+  RB_CHECK(rank > 0 || K < Lc || Lc >= T, RB_ERR_NUMERIC, "Lanczos space exhausted before the rank rule was met");
+  set_error("");
   return RB_OK;
 }
 
@@ -1243,7 +1470,14 @@ rb_status finish_basis(rb_ctx ctx, rb_bank bank, int32_t t0, int64_t T, int K, c
 extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, int32_t t1, int32_t rank,
                                           double tol, rb_dtype dtype, rb_basis* out, int32_t* rank_out,
                                           double* energy_out) {
+  return rb_build_basis_solver(ctx, bank, t0, t1, rank, tol, dtype, RB_EIG_SUBSPACE, out, rank_out, energy_out);
+}
+
+extern "C" rb_status rb_build_basis_solver(rb_ctx ctx, rb_bank bank, int32_t t0, int32_t t1, int32_t rank,
+                                           double tol, rb_dtype dtype, int32_t solver, rb_basis* out,
+                                           int32_t* rank_out, double* energy_out) {
   RB_TRY(validate_ctx(ctx));
+  RB_CHECK(solver == RB_EIG_SUBSPACE || solver == RB_EIG_LANCZOS, RB_ERR_ARG, "bad eigensolver");
   RB_CHECK(bank != nullptr && out != nullptr, RB_ERR_ARG, "NULL argument");
   RB_CHECK(bank->ctx == ctx, RB_ERR_ARG, "bank belongs to another context");
   RB_CHECK(t0 >= 0 && t0 < t1 && t1 <= bank->T, RB_ERR_ARG, "template range must satisfy 0 <= t0 < t1 <= T");
@@ -1269,9 +1503,13 @@ extern "C" rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, 
   std::vector<double> theta;
   std::vector<cd> S;
   int Lc = 0, K = 0;
-  RB_TRY(subspace_pca(ctx, bw, W, T, nb, nbs, trace, rank, tol, theta, S, Lc, K));
+  int64_t ldb = 0;
+  if (solver == RB_EIG_LANCZOS)
+    RB_TRY(lanczos_pca(ctx, bw, W, T, nb, nbs, trace, rank, tol, theta, S, Lc, K, ldb));
+  else
+    RB_TRY(subspace_pca(ctx, bw, W, T, nb, nbs, trace, rank, tol, theta, S, Lc, K));
   DevBuf BS;
-  RB_TRY(ritz_vectors(ctx, bw, nb, Lc, K, S, BS));
+  RB_TRY(ritz_vectors(ctx, bw, nb, Lc, K, S, BS, ldb));
   std::vector<double> sc(K);
   double e = 0.0;
   for (int k = 0; k < K; ++k) {
@@ -2293,6 +2531,53 @@ extern "C" rb_status rb_backward(rb_ctx ctx, rb_basis basis, const float* strain
   return RB_OK;
 }
 
+extern "C" rb_status rb_refine(rb_ctx ctx, rb_basis basis, const float* strain, const rb_trigger* S, int64_t n,
+                               int32_t neighbours, int32_t iters, float* c_out, int32_t* nbr_out, float* p_out) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(basis != nullptr && basis->ctx == ctx, RB_ERR_ARG, "basis is NULL or from another context");
+  RB_CHECK(n >= 0, RB_ERR_ARG, "n must be >= 0");
+  if (n == 0) return RB_OK;
+  RB_CHECK(S != nullptr && c_out != nullptr, RB_ERR_ARG, "NULL argument");
+  const int T = basis->T, K = basis->K;
+  RB_CHECK(neighbours >= 0 && neighbours <= 32 && neighbours <= T - 1, RB_ERR_ARG,
+           "neighbours must lie in [0, min(32, templates of the basis - 1)]");
+  RB_CHECK(iters >= 0 && iters <= 100000, RB_ERR_ARG, "iters must lie in [0, 100000]");
+  RB_CHECK(K <= refine_max_rank(), RB_ERR_UNSUPPORTED,
+           "refinement supports ranks up to " + std::to_string(refine_max_rank()));
+  FftGeom g;
+  RB_TRY(geom_for(ctx, basis->bank, &g));
+  FftTables tw;
+  RB_TRY(get_tables(ctx, g, tw));
+  std::vector<int32_t> tm, sp;
+  RB_TRY(host_triggers(ctx, S, n, basis->t0, T, g.N, tm, sp));
+  const float* s;
+  RB_TRY(strain_device(ctx, strain, g.N, &s));
+  RB_TRY(step_spectrum(ctx, basis->bank, g, tw, s));
+  RB_TRY(step_basis_outputs(ctx, basis, g, tw, true));
+  RB_TRY(upload(ctx, ctx->adjT, tm.data(), tm.size() * 4));
+  RB_TRY(upload(ctx, ctx->adjS, sp.data(), sp.size() * 4));
+  const int m = neighbours;
+  const int64_t chunk = 512;                      // triggers per launch pair (bounds the scratch)
+  const int64_t nc = std::min<int64_t>(n, chunk);
+  RB_TRY(ctx->refOv.ensure((size_t)nc * T * sizeof(double)));
+  RB_TRY(ctx->refQ.ensure((size_t)nc * (m + 1) * K * sizeof(double2)));
+  RB_TRY(ctx->refC.ensure((size_t)n * K * sizeof(float2)));
+  RB_TRY(ctx->refN.ensure(std::max<size_t>(16, (size_t)n * m * 4)));
+  RB_TRY(ctx->refP.ensure((size_t)n * 2 * sizeof(float)));
+  for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+    const int cnt = (int)std::min<int64_t>(chunk, n - i0);
+    RB_HIP(launch_refine(ctx->z32.as<float>(), g.N, g.N1, g.N2, K, T, basis->t0, basis->C32.as<float2>(),
+                         ctx->adjT.as<int32_t>() + i0, ctx->adjS.as<int32_t>() + i0, cnt, m, iters,
+                         ctx->refOv.as<double>(), ctx->refQ.as<double2>(), ctx->refC.as<float2>() + i0 * K,
+                         ctx->refN.as<int32_t>() + i0 * m, ctx->refP.as<float>() + 2 * i0, ctx->stream));
+  }
+  RB_TRY(copy_out(ctx, c_out, ctx->refC.p, (size_t)n * K * sizeof(float2)));
+  if (nbr_out && m > 0) RB_TRY(copy_out(ctx, nbr_out, ctx->refN.p, (size_t)n * m * 4));
+  if (p_out) RB_TRY(copy_out(ctx, p_out, ctx->refP.p, (size_t)n * 2 * sizeof(float)));
+  RB_HIP(hipStreamSynchronize(ctx->stream));
+  return RB_OK;
+}
+
 // ====================================================================== batch
 namespace {
 
@@ -2451,7 +2736,11 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
   RB_TRY(ctx->recs1.ensure((size_t)trig_capacity(ctx->trig1) * sizeof(TrigRec)));
   std::vector<int64_t> sm((size_t)nitems * 8);
   const bool tm = stats != nullptr;
-  for (int attempt = 0; attempt < 3; ++attempt) {
+  // Each attempt counts every level whose input fitted, so overflows that
+  // cascade (bins -> stage-1 records -> stage-2 records) settle within one
+  // attempt per level; the loop ends only on an attempt with nothing to grow.
+  bool settled = false;
+  for (int attempt = 0; attempt < 6 && !settled; ++attempt) {
     if (tm) RB_TRY(event(ctx, 0));
     if (use_graph) {
       std::string key = batch_key(nitems, items, opts, cap_item, ctx);
@@ -2519,9 +2808,13 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
         grow = true;
       }
     }
-    if (!grow) break;
-    ctx->gkey.clear();   // buffers moved: re-record
+    if (!grow) {
+      settled = true;
+    } else {
+      ctx->gkey.clear();   // buffers moved: re-record
+    }
   }
+  RB_CHECK(settled, RB_ERR_CAPACITY, "internal trigger buffers still overflowed after six attempts");
   bool over = false;
   for (int32_t i = 0; i < nitems; ++i) {
     n_out[i] = sm[8 * (size_t)i + 4];

@@ -146,3 +146,48 @@ def test_batch_capacity(batch):
     with pytest.raises(rbmf.RbError) as ei:
         rbmf.rb_filter_batch(ctx, items, 3.0, 3.5, use_graph=True, cap_item=2)
     assert ei.value.status == rbmf.RB_ERR_CAPACITY
+
+
+def test_batch_small_initial_buffers():
+    """Trigger buffers that start at a few records (RBMF_TRIG_RECORDS) must
+    grow through every cascading overflow (bins -> stage-1 records -> stage-2
+    records) and give the same triggers as buffers that fit at once."""
+    import os
+
+    import torch
+    wl = gi.Workload("b_small", 41, 8192, 2048.0, 25.0, 120, 2.0, 12.0, 7, subbanks=2)
+    bank_def = wl.bank()
+    psd = gi.psd_on_grid(wl.N, wl.fs)
+    strains = [torch.from_numpy(strain_for(wl, bank_def, psd, 300 + i)).cuda() for i in range(3)]
+
+    def run():
+        ctx = rbmf.Context(0)
+        bank = rbmf.Bank(ctx, wl.N, wl.fs, wl.f_low, psd, wl.T, bank_def.fill)
+        bases = rbmf.subbank_bases(ctx, bank, wl.bounds(), rank=[16, 24], dtype="bf16")
+        items = [(s, bank, bases) for s in strains]
+        out = []
+        for mode, w, tb in ((rbmf.RB_STAGE2_SPARSE, 4, 3.0), (rbmf.RB_STAGE2_RECON, 4, 3.0),
+                            (rbmf.RB_STAGE2_FULL, 0, 0.0)):
+            for graph in (False, True):
+                r, st = rbmf.rb_filter_batch(ctx, items, 4.5, 5.0, use_graph=graph, stage2=mode, bin_w=w, thr_bin=tb)
+                out.append(([x.tobytes() for x in r], int(st.n_stage1), int(st.n_bins)))
+        for b in bases:
+            b.close()
+        bank.close()
+        ctx.close()
+        return out
+
+    ref = run()
+    old = os.environ.get("RBMF_TRIG_RECORDS")
+    os.environ["RBMF_TRIG_RECORDS"] = "3"
+    try:
+        small = run()
+    finally:
+        if old is None:
+            del os.environ["RBMF_TRIG_RECORDS"]
+        else:
+            os.environ["RBMF_TRIG_RECORDS"] = old
+    assert all(n1 > 3 for _, n1, _ in ref), "the case must overflow the small buffers"
+    for a, b in zip(ref, small):
+        assert a == b
+    log("small initial buffers ok", [(n1, nb) for _, n1, nb in ref])
