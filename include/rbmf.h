@@ -226,6 +226,28 @@ rb_status rb_build_basis_range(rb_ctx ctx, rb_bank bank, int32_t t0, int32_t t1,
                                double tol, rb_dtype dtype, rb_basis* out, int32_t* rank_out,
                                double* energy_out);
 
+/* Eigensolvers of the basis construction. */
+typedef enum {
+  RB_EIG_SUBSPACE = 0, /* randomized subspace iteration with Rayleigh-Ritz (the default) */
+  RB_EIG_LANCZOS = 1   /* block Lanczos with full reorthogonalisation (Sec. III.B runs a Lanczos
+                          eigensolver on the covariance) */
+} rb_eig_solver;
+
+/* rb_build_basis_range with a choice of FP64 eigensolver for the leading
+ * eigenpairs of the Gram matrix W W^H of the sub-bank's whitened unit
+ * templates (applied as W (W^H X), never formed).  RB_EIG_LANCZOS: Krylov
+ * blocks of b = 32 columns (rank / 4 clamped to [16, 64] for a fixed rank),
+ * each G X_j orthogonalised against every earlier block by two passes of
+ * classical Gram-Schmidt (columns reduced below 1e-10 of their norm
+ * dropped), Rayleigh-Ritz on the whole space after each block, stopping when
+ * the pairs the rank rule keeps have residual norms |G u - theta u| <=
+ * 1e-7 theta_1 with at least b spare columns, or the space reaches t1 - t0.
+ * Both solvers feed the same basis rows, coefficients and storage.
+ * RB_ERR_ARG for a bad solver; other arguments as rb_build_basis_range. */
+rb_status rb_build_basis_solver(rb_ctx ctx, rb_bank bank, int32_t t0, int32_t t1, int32_t rank,
+                                double tol, rb_dtype dtype, int32_t solver, rb_basis* out,
+                                int32_t* rank_out, double* energy_out);
+
 /* Non-uniform frequency set for the PCA (Sec. III.A, PCA using non-uniform
  * sampling).  Host only: touches no device.
  *   f, h_re  host, n >= 2 samples of one reference template (the longest
@@ -406,6 +428,33 @@ rb_status rb_rho_at(rb_ctx ctx, rb_basis basis, const float* strain, const rb_tr
 rb_status rb_backward(rb_ctx ctx, rb_basis basis, const float* strain, const rb_trigger* S,
                       const float* seed, int64_t n, const float* C, float* grad_C,
                       float* grad_strain, double* loss);
+
+/* Refinement of trigger coefficient vectors between bank points (Sec. II.A:
+ * the basis spans the bank, so a unit coefficient vector near a template's
+ * describes a template between bank points; the gradient is the adjoint of
+ * the reconstruction, Eq. Beta_eqn).  For each trigger i = (j, n):
+ *   1. the `neighbours` templates l != j of the basis with the largest
+ *      |<c_j, c_l>| (ties to the lower index);
+ *   2. an orthonormal basis (FP64, modified Gram-Schmidt twice, dependent
+ *      rows dropped) of the span of the coefficient rows C_j, C_l (C = conj(c));
+ *   3. `iters` steps of projected gradient ascent of |rho|^2,
+ *      rho = sum_k C_k beta_k[n], from C = C_j:
+ *        C <- C + (2 rho conj(beta[:, n])) / (2 |rho|^2); C <- Proj C; C <- C / |C|.
+ *      The maximiser over unit vectors of the span is the normalised
+ *      projection of conj(beta[:, n]) onto it (Cauchy-Schwarz).
+ * beta from `strain` on the FP32 path, whatever the basis storage type.
+ *   S         host or device, n triggers (tmpl in the basis's range, sample in
+ *             [0, N), else RB_ERR_ARG).
+ *   neighbours 0 ... min(32, t1 - t0 - 1); iters 0 ... 100000.
+ *   c_out     host or device, n x K complex64 (interleaved): refined rows of C.
+ *   nbr_out   host or device or NULL: n x neighbours global template indices,
+ *             nearest first.
+ *   p_out     host or device or NULL: n x 2 floats, |rho|^2 of the trigger's
+ *             own row C_j and of the refined row.
+ * RB_ERR_UNSUPPORTED for ranks above 2048.  Outputs are written only on
+ * success. */
+rb_status rb_refine(rb_ctx ctx, rb_basis basis, const float* strain, const rb_trigger* S, int64_t n,
+                    int32_t neighbours, int32_t iters, float* c_out, int32_t* nbr_out, float* p_out);
 
 /* Clustered peaks of a (tmpl, sample)-sorted trigger list: is_peak[i] = 1 if
  * no trigger of the same template within +-W samples (circular over N) has a

@@ -67,3 +67,11 @@ def refine_optimum(Zn: np.ndarray, span: np.ndarray) -> Tuple[np.ndarray, float]
     p = Q @ (Q.conj().T @ Zn)
     nrm = float(np.linalg.norm(p))
     return p / nrm, nrm ** 2
+
+
+def nearest_neighbours(c: np.ndarray, j: int) -> np.ndarray:
+    """Templates l != j ordered by decreasing |<c_j, c_l>| (ties to the lower
+    index), and those overlaps: the neighbour order of the refinement."""
+    ov = np.abs(np.asarray(c, np.complex128) @ np.conj(np.asarray(c[j], np.complex128)))
+    idx = np.array([l for l in np.lexsort((np.arange(len(ov)), -ov)) if l != j])
+    return idx, ov

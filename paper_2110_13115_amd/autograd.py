@@ -5,14 +5,15 @@ with rho = C beta (Eq. Beta_eqn) computed by the library (rb_rho_at) and
 gradients with respect to the strain and the coefficient matrix C from the
 adjoint kernels (rb_backward, seeded with the incoming gradient).
 
-refine_coefficients(): projected gradient ascent of |rho|^2 over unit-norm
-coefficient vectors in the span of a trigger template's coefficients and those
-of its nearest bank neighbours (largest |<c_j, c_l>|): the search for a better
-template "between bank points" that the basis representation makes cheap.
+refine_coefficients(): marshals rb_refine, the library's projected gradient
+ascent of |rho|^2 over unit-norm coefficient vectors in the span of a trigger
+template's coefficients and those of its nearest bank neighbours (largest
+|<c_j, c_l>|): the search for a better template "between bank points" that
+the basis representation makes cheap.
 """
 from __future__ import annotations
 
-from typing import List, Optional, Tuple
+from typing import Tuple
 
 import numpy as np
 import torch
@@ -49,57 +50,13 @@ def trigger_power(strain, C, lib_ctx, basis, S):
     return TriggerPower.apply(strain, C, lib_ctx, basis, S)
 
 
-def nearest_neighbours(c: np.ndarray, j: int, m: int) -> np.ndarray:
-    """Indices of the m templates with the largest |<c_j, c_l>| (l != j)."""
-    ov = np.abs(c @ np.conj(c[j]))
-    ov[j] = -1.0
-    return np.argsort(-ov, kind="stable")[:m]
+def refine_coefficients(lib_ctx, basis, strain, trig: np.ndarray, neighbours: int = 8, iters: int = 40
+                        ) -> Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+    """Refinement of every trigger in `trig` (rb_refine: neighbour search,
+    span basis and projected gradient ascent all run in the library).
 
-
-def refine_coefficients(lib_ctx, basis, strain: torch.Tensor, trig: np.ndarray, neighbours: int = 8,
-                        iters: int = 40, step: Optional[float] = None
-                        ) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
-    """One trigger per template (the first occurrence in `trig` is used).
-
-    Returns (C_refined rows for those templates (n x K complex64), initial
-    |rho|^2, final |rho|^2)."""
-    V, c, lam = basis.export()
-    T, K = c.shape
-    _, first = np.unique(trig["tmpl"], return_index=True)
-    S = np.ascontiguousarray(trig[np.sort(first)])
-    n = S.shape[0]
-    dev = strain.device
-    # orthonormal span (in C = conj(c) space) per trigger
-    Q = np.zeros((n, K, neighbours + 1), dtype=np.complex128)
-    C0 = np.conj(c).astype(np.complex64)
-    for i, j in enumerate(S["tmpl"]):
-        idx = np.concatenate([[j], nearest_neighbours(c, int(j), neighbours)])
-        q, _ = np.linalg.qr(np.conj(c[idx]).T)
-        Q[i] = q
-    Qt = torch.from_numpy(Q.astype(np.complex64)).to(dev)
-    C = torch.from_numpy(C0).to(dev)
-    rows = torch.from_numpy(S["tmpl"].astype(np.int64)).to(dev)
-    # S rows point at their own template rows of C
-    hist = []
-    for it in range(iters + 1):
-        Cv = C.clone().requires_grad_(True)
-        p = trigger_power(strain, Cv, lib_ctx, basis, S)
-        hist.append(p.detach().cpu().numpy())
-        if it == iters:
-            break
-        p.sum().backward()
-        g = Cv.grad[rows]                                   # n x K
-        cur = C[rows]
-        if step is None:
-            # step 1/(2 |rho|^2 / |C|^2)-like scale: |rho|^2 <= |Z|^2 for unit C
-            lr = 0.5 / torch.clamp(p.detach(), min=1e-12)
-        else:
-            lr = torch.full_like(p.detach(), step)
-        new = cur + lr[:, None] * g
-        # project onto the span and renormalise
-        coef = torch.einsum("nkr,nk->nr", Qt.conj(), new)
-        new = torch.einsum("nkr,nr->nk", Qt, coef)
-        new = new / torch.linalg.vector_norm(new, dim=1, keepdim=True)
-        C = C.clone()
-        C[rows] = new
-    return C[rows].cpu().numpy(), hist[0], hist[-1]
+    Returns (refined coefficient rows (n x K complex64), neighbours used
+    (n x neighbours global template indices), initial |rho|^2, final |rho|^2)."""
+    S = np.ascontiguousarray(trig, dtype=rbmf.TRIGGER_NP)
+    c, nbr, p = rbmf.refine(lib_ctx, basis, strain, S, neighbours=neighbours, iters=iters)
+    return c, nbr, p[:, 0].copy(), p[:, 1].copy()

@@ -300,4 +300,16 @@ hipError_t launch_bsum(const float2* Ahat, const float2* P, const double* wd, in
                        hipStream_t s);
 hipError_t launch_real2(const float2* x, int64_t N, float* out, hipStream_t s);
 
+// ---------------------------------------------------------------- refinement
+// Per trigger (local template rows[i], sample samp[i]; n triggers): the m
+// nearest bank neighbours by |<c_j, c_l>|, an orthonormal basis of the span
+// of their coefficient rows and the trigger's own, and `iters` steps of
+// projected gradient ascent of |rho|^2 from C_j.  Scratch: ov (n x T
+// doubles), Q (n x (m + 1) x K complex128).  Outputs: c_out (n x K),
+// nbr_out (n x m global indices), p_out (n x 2).
+int refine_max_rank();
+hipError_t launch_refine(const float* z, int64_t N, int N1, int N2, int K, int T, int t0, const float2* C,
+                         const int32_t* rows, const int32_t* samp, int n, int m, int iters, double* ov,
+                         double2* Q, float2* c_out, int32_t* nbr_out, float* p_out, hipStream_t s);
+
 }  // namespace rbmf

@@ -20,12 +20,14 @@ RB_OK, RB_ERR_ARG, RB_ERR_OOM, RB_ERR_DEVICE, RB_ERR_CAPACITY, RB_ERR_NUMERIC, R
     RB_ERR_CALLBACK = range(8)
 RB_F32, RB_BF16, RB_F16, RB_BF16X3 = 0, 1, 2, 3
 RB_STAGE2_FULL, RB_STAGE2_SPARSE, RB_STAGE2_AUTO, RB_STAGE2_RECON = 0, 1, 2, 3
+RB_EIG_SUBSPACE, RB_EIG_LANCZOS = 0, 1
+SOLVERS = {"subspace": RB_EIG_SUBSPACE, "lanczos": RB_EIG_LANCZOS}
 DTYPES = {"f32": RB_F32, "bf16": RB_BF16, "f16": RB_F16, "bf16x3": RB_BF16X3}
 
 FUNCTIONS = ["rb_ctx_create", "rb_ctx_destroy", "rb_last_error", "rb_bank_create", "rb_bank_free",
-             "rb_bank_info", "rb_build_basis", "rb_build_basis_range", "rb_basis_info",
+             "rb_bank_info", "rb_build_basis", "rb_build_basis_range", "rb_build_basis_solver", "rb_basis_info",
              "rb_basis_free", "rb_basis_export", "rb_filter",
-             "rb_filter_stream", "rb_filter_batch", "mf_full", "rb_rho_at", "rb_backward", "rb_cluster_peaks", "rb_debug_rho",
+             "rb_filter_stream", "rb_filter_batch", "mf_full", "rb_rho_at", "rb_backward", "rb_refine", "rb_cluster_peaks", "rb_debug_rho",
              "rb_debug_rho_binned", "rb_debug_basis_outputs", "rb_nonuniform_freqs", "rb_build_basis_nonuniform"]
 
 
@@ -96,6 +98,8 @@ def lib():
                                      C.POINTER(dbl)]
         L.rb_build_basis_range.argtypes = [vp, vp, i32, i32, i32, dbl, C.c_int, C.POINTER(vp),
                                            C.POINTER(i32), C.POINTER(dbl)]
+        L.rb_build_basis_solver.argtypes = [vp, vp, i32, i32, i32, dbl, C.c_int, i32, C.POINTER(vp),
+                                            C.POINTER(i32), C.POINTER(dbl)]
         L.rb_basis_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl)]
         L.rb_basis_free.argtypes = [vp]
         L.rb_basis_export.argtypes = [vp, vp, vp, vp]
@@ -108,6 +112,7 @@ def lib():
                                       C.POINTER(Stats)]
         L.rb_rho_at.argtypes = [vp, vp, vp, vp, i64, vp, vp]
         L.rb_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, C.POINTER(dbl)]
+        L.rb_refine.argtypes = [vp, vp, vp, vp, i64, i32, i32, vp, vp, vp]
         L.rb_cluster_peaks.argtypes = [vp, vp, i64, i32, i64, vp]
         L.rb_debug_rho.argtypes = [vp, vp, vp, vp, vp]
         L.rb_debug_rho_binned.argtypes = [vp, vp, vp, i32, vp]
@@ -212,7 +217,7 @@ class Basis:
     """Reduced basis of templates [t0, t1) of a bank (default: the whole bank)."""
 
     def __init__(self, ctx: Context, bank: Bank, rank: int = 0, tol: float = 1e-3, dtype="f32",
-                 t0: int = 0, t1: Optional[int] = None):
+                 t0: int = 0, t1: Optional[int] = None, solver: str = "subspace"):
         self.ctx, self.bank = ctx, bank
         self.t0 = int(t0)
         self.t1 = bank.T if t1 is None else int(t1)
@@ -221,8 +226,9 @@ class Basis:
         K = C.c_int32()
         e = C.c_double()
         dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
-        _check(lib().rb_build_basis_range(ctx.h, bank.h, self.t0, self.t1, int(rank), float(tol), dt,
-                                          C.byref(self.h), C.byref(K), C.byref(e)), "rb_build_basis_range")
+        _check(lib().rb_build_basis_solver(ctx.h, bank.h, self.t0, self.t1, int(rank), float(tol), dt,
+                                           SOLVERS[solver], C.byref(self.h), C.byref(K), C.byref(e)),
+               "rb_build_basis_solver")
         self.K, self.energy, self.dtype = K.value, e.value, dt
 
     @classmethod
@@ -313,10 +319,10 @@ def _as_np_triggers(buf, n: int) -> np.ndarray:
     return buf[:n].cpu().numpy().view(TRIGGER_NP).reshape(-1)
 
 
-def subbank_bases(ctx: Context, bank: Bank, bounds, rank=0, tol: float = 1e-3, dtype="f32"):
+def subbank_bases(ctx: Context, bank: Bank, bounds, rank=0, tol: float = 1e-3, dtype="f32", solver="subspace"):
     """One basis per sub-bank; bounds = [0, b1, ..., T]; rank an int or a list."""
     ranks = rank if isinstance(rank, (list, tuple)) else [rank] * (len(bounds) - 1)
-    return [Basis(ctx, bank, rank=r, tol=tol, dtype=dtype, t0=a, t1=b)
+    return [Basis(ctx, bank, rank=r, tol=tol, dtype=dtype, t0=a, t1=b, solver=solver)
             for a, b, r in zip(bounds[:-1], bounds[1:], ranks)]
 
 
@@ -392,12 +398,13 @@ def rho_at(ctx: Context, basis: Basis, strain, S, coeffs=None, out=None):
 
 def rb_backward(ctx: Context, basis: Basis, strain, S, seed=None, coeffs=None, want_C=True,
                 want_strain=True, grad_C=None, grad_strain=None):
-    """Returns (loss, grad_C (T x K complex64) or None, grad_strain (N) or None).
+    """Returns (loss, grad_C (basis.T x K complex64, the basis's rows) or None,
+    grad_strain (N) or None).
     Outputs are host arrays unless device buffers are passed in."""
     S = _trig_arg(S)
     n = S.shape[0]
     gC = grad_C if grad_C is not None else (
-        np.zeros((basis.bank.T, basis.K), dtype=np.complex64) if want_C else None)
+        np.zeros((basis.T, basis.K), dtype=np.complex64) if want_C else None)
     gs = grad_strain if grad_strain is not None else (
         np.zeros(basis.bank.N, dtype=np.float32) if want_strain else None)
     loss = C.c_double()
@@ -409,6 +416,21 @@ def rb_backward(ctx: Context, basis: Basis, strain, S, seed=None, coeffs=None, w
     return loss.value, gC, gs
 
 
+def refine(ctx: Context, basis: Basis, strain, S, neighbours: int = 8, iters: int = 40, c_out=None, nbr_out=None,
+           p_out=None):
+    """rb_refine: refined coefficient rows (n x K complex64), the neighbours
+    used (n x neighbours global template indices) and |rho|^2 before / after
+    (n x 2).  Host arrays unless device buffers are passed in."""
+    S = _trig_arg(S)
+    n = S.shape[0]
+    c = c_out if c_out is not None else np.empty((n, basis.K), dtype=np.complex64)
+    nb = nbr_out if nbr_out is not None else np.empty((n, max(neighbours, 1)), dtype=np.int32)
+    p = p_out if p_out is not None else np.empty((n, 2), dtype=np.float32)
+    _check(lib().rb_refine(ctx.h, basis.h, _ptr(strain), _ptr(S), n, int(neighbours), int(iters), _ptr(c),
+                           _ptr(nb), _ptr(p)), "rb_refine")
+    return c, (nb[:, :neighbours] if nbr_out is None else nb), p
+
+
 def cluster_peaks(ctx: Context, trig: np.ndarray, W: int, N: int) -> np.ndarray:
     trig = np.ascontiguousarray(trig, dtype=TRIGGER_NP)
     out = np.zeros(trig.shape[0], dtype=np.uint8)
@@ -417,8 +439,9 @@ def cluster_peaks(ctx: Context, trig: np.ndarray, W: int, N: int) -> np.ndarray:
     return out.astype(bool)
 
 
-def debug_rho(ctx: Context, bank: Bank, strain, basis: Optional[Basis] = None) -> np.ndarray:
-    rho = np.empty((basis.T if basis else bank.T, bank.N), dtype=np.complex64)
+def debug_rho(ctx: Context, bank: Bank, strain, basis: Optional[Basis] = None, out=None):
+    """rb_debug_rho: (rows, N) complex64, into `out` (host or device) when given."""
+    rho = out if out is not None else np.empty((basis.T if basis else bank.T, bank.N), dtype=np.complex64)
     _check(lib().rb_debug_rho(ctx.h, basis.h if basis else None, bank.h, _ptr(strain), _ptr(rho)),
            "rb_debug_rho")
     return rho
