@@ -127,6 +127,19 @@ typedef struct {
                               [5] sort + output, [6] total, [7] of [2], the
                               fine reconstruction of triggering bins         */
   int64_t n_bins;          /* triggering (template, bin) pairs (bin_w >= 2)  */
+  double  min_energy;      /* smallest retained energy sum_k |c_jk|^2 of any
+                              template of the bases used (1 for mf_full).
+                              The part of a unit template outside its basis
+                              has norm r = sqrt(1 - min_energy): a signal
+                              matching the template at optimal SNR A loses
+                              at most A r in the first stage, and noise adds
+                              a Rayleigh term of scale r.  The second stages
+                              that evaluate the exact SNR only where the
+                              first stage crossed (SPARSE, AUTO) therefore
+                              keep every final trigger while A r plus that
+                              noise term stays below thr2 - thr1; FULL
+                              needs only a crossing anywhere in the
+                              template's series.                             */
 } rb_stats;
 
 typedef struct {
@@ -241,7 +254,8 @@ typedef enum {
  * classical Gram-Schmidt (columns reduced below 1e-10 of their norm
  * dropped), Rayleigh-Ritz on the whole space after each block, stopping when
  * the pairs the rank rule keeps have residual norms |G u - theta u| <=
- * 1e-7 theta_1 with at least b spare columns, or the space reaches t1 - t0.
+ * 1e-10 theta_1 (residuals formed directly) with at least b spare columns,
+ * or the space reaches t1 - t0.
  * Both solvers feed the same basis rows, coefficients and storage.
  * RB_ERR_ARG for a bad solver; other arguments as rb_build_basis_range. */
 rb_status rb_build_basis_solver(rb_ctx ctx, rb_bank bank, int32_t t0, int32_t t1, int32_t rank,

@@ -203,6 +203,7 @@ struct rb_basis_s {
   int32_t K = 0, Kp = 0, Tp = 0;
   rb_dtype dtype = RB_F32;
   double energy = 0.0, trace = 0.0;
+  double min_energy = 1.0;     // smallest per-template retained energy sum_k |c_jk|^2
   std::vector<double> lambda;
   std::vector<cd> c;           // T x K FP64 coefficients
   std::vector<float> row_scale;  // per-template power-of-two scale (16-bit), 1 otherwise
@@ -505,6 +506,22 @@ rb_status strain_device(rb_ctx ctx, const float* strain, int64_t N, const float*
   return RB_OK;
 }
 
+// a1 into caller-provided buffers: work64 (N double2), dspec (nbs float2)
+rb_status spectrum_into(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTables& tw, const FftTables64& tw64,
+                        const float* s, double2* work64, float2* dspec) {
+  RB_TRY(fill32(ctx, dspec, 0u, bank->nbs * 2));
+  PassArgs a = base_args(bank, g, tw);
+  a.sign = -1;
+  a.nvec = 1;
+  a.real_in = s;
+  a.tw64 = tw64;
+  a.work64 = work64;
+  RB_HIP(launch_pass1(a, IN_REAL, ctx->stream));
+  a.cout = dspec;
+  RB_HIP(launch_pass2(a, OUT_SPECTRUM, ctx->stream));
+  return RB_OK;
+}
+
 // a1: whitened band spectrum d[k - kb] = dt w[k] DFT(s)[k] (zero below k_lo)
 rb_status step_spectrum(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTables& tw, const float* s) {
   FftTables tw32;
@@ -512,17 +529,7 @@ rb_status step_spectrum(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTab
   RB_TRY(get_tables(ctx, g, tw32, &tw64));
   RB_TRY(ctx->work64.ensure((size_t)g.N * 16));
   RB_TRY(ctx->dspec.ensure((size_t)bank->nbs * 8));
-  RB_TRY(fill32(ctx, ctx->dspec.p, 0u, bank->nbs * 2));
-  PassArgs a = base_args(bank, g, tw);
-  a.sign = -1;
-  a.nvec = 1;
-  a.real_in = s;
-  a.tw64 = tw64;
-  a.work64 = ctx->work64.as<double2>();
-  RB_HIP(launch_pass1(a, IN_REAL, ctx->stream));
-  a.cout = ctx->dspec.as<float2>();
-  RB_HIP(launch_pass2(a, OUT_SPECTRUM, ctx->stream));
-  return RB_OK;
+  return spectrum_into(ctx, bank, g, tw, tw64, s, ctx->work64.as<double2>(), ctx->dspec.as<float2>());
 }
 
 // a2 + a3: Z = IFFT(d conj(P_k)) for all basis vectors, planar storage
@@ -1181,10 +1188,9 @@ rb_status ritz_vectors(rb_ctx ctx, BasisWork& bw, int64_t n, int Lc, int K, cons
 // G X_j after two passes of classical Gram-Schmidt against every earlier
 // block (columns that vanish are dropped; an empty block means the Krylov
 // space is invariant).  After each block the Rayleigh-Ritz problem
-// M = V^H G V is solved on the host; the residual of Ritz pair (theta, s) is
-// |G V s - theta V s|^2 = s^H P s - theta^2 with P = (G V)^H (G V).  Stops
-// when the pairs that the rank rule keeps have residuals <= 1e-7 theta_1 (or
-// the space reaches T).  On return bw.B holds W^H V (n x ldb, ldb >= Lc), and
+// M = V^H G V is solved on the host; the residuals G V s - theta V s of the
+// Ritz pairs that the rank rule keeps are formed on the device.  Stops when
+// their norms are <= 1e-10 theta_1 (or the space reaches T).  On return bw.B holds W^H V (n x ldb, ldb >= Lc), and
 // theta / S / Lc / K as subspace_pca's.
 rb_status lanczos_pca(rb_ctx ctx, BasisWork& bw, const float2* W, int64_t T, int64_t n, int64_t ld, double trace,
                       int32_t rank, double tol, std::vector<double>& theta, std::vector<cd>& S, int& Lc, int& K,
@@ -1250,17 +1256,13 @@ rb_status lanczos_pca(rb_ctx ctx, BasisWork& bw, const float2* W, int64_t T, int
                           (int64_t)(bw.ws.bytes / 16), s));
     }
     const bool too_small = !final_pass && rank > 0 && Lc < std::min<int64_t>(T, (int64_t)rank + b) && Lc + b <= T;
-    // Rayleigh-Ritz on V (Lc columns): M = V^H GV, P = GV^H GV
+    // Rayleigh-Ritz on V (Lc columns): M = V^H GV
     std::vector<cd> Mh((size_t)Lc * Lc);
     if (!too_small) {
       RB_TRY(H.ensure((size_t)Lc * Lc * 16));
-      RB_TRY(P.ensure((size_t)Lc * Lc * 16));
       ZOperand VH{V.p, 0, 1, ldb, 1};
       ZOperand GVo{GV.p, 0, ldb, 1, 0};
-      ZOperand GVH{GV.p, 0, 1, ldb, 1};
       RB_HIP(launch_zgemm(Lc, Lc, T, VH, GVo, H.as<double2>(), Lc, 0, bw.ws.as<double2>(),
-                          (int64_t)(bw.ws.bytes / 16), s));
-      RB_HIP(launch_zgemm(Lc, Lc, T, GVH, GVo, P.as<double2>(), Lc, 0, bw.ws.as<double2>(),
                           (int64_t)(bw.ws.bytes / 16), s));
       RB_HIP(hipMemcpyAsync(Mh.data(), H.p, Mh.size() * 16, hipMemcpyDeviceToHost, s));
       RB_HIP(hipStreamSynchronize(s));
@@ -1285,26 +1287,39 @@ rb_status lanczos_pca(rb_ctx ctx, BasisWork& bw, const float2* W, int64_t T, int
       K = 0;
       while (K < npos && cum < (1.0 - tol) * trace) cum += theta[K++];
     }
-    // residuals of the pairs that are kept: s_k^H P s_k - theta_k^2, P S_K on the device
+    // residuals of the pairs that are kept, formed directly (the difference
+    // s^H (GV)^H GV s - theta^2 cannot resolve residuals below ~1e-8 theta_1):
+    // R = GV S_K - V S_K diag(theta) (T x K), |R e_k| from the diagonal of R^H R
     {
-      std::vector<cd> Sk((size_t)Lc * K), PS((size_t)Lc * K);
+      std::vector<cd> Sk((size_t)Lc * K), St((size_t)Lc * K);
       for (int i = 0; i < Lc; ++i)
-        for (int k = 0; k < K; ++k) Sk[(size_t)i * K + k] = S[(size_t)i * Lc + k];
-      DevBuf Sd, PSd;
+        for (int k = 0; k < K; ++k) {
+          Sk[(size_t)i * K + k] = S[(size_t)i * Lc + k];
+          St[(size_t)i * K + k] = -theta[k] * S[(size_t)i * Lc + k];
+        }
+      DevBuf Sd, Std, Rd, RR;
       RB_TRY(Sd.ensure(Sk.size() * 16));
-      RB_TRY(PSd.ensure(PS.size() * 16));
+      RB_TRY(Std.ensure(St.size() * 16));
+      RB_TRY(Rd.ensure((size_t)T * K * 16));
+      RB_TRY(RR.ensure((size_t)K * K * 16));
       RB_HIP(hipMemcpyAsync(Sd.p, Sk.data(), Sk.size() * 16, hipMemcpyHostToDevice, s));
-      ZOperand Po{P.p, 0, Lc, 1, 0};
+      RB_HIP(hipMemcpyAsync(Std.p, St.data(), St.size() * 16, hipMemcpyHostToDevice, s));
+      ZOperand GVo{GV.p, 0, ldb, 1, 0};
+      ZOperand Vo{V.p, 0, ldb, 1, 0};
       ZOperand So{Sd.p, 0, K, 1, 0};
-      RB_HIP(launch_zgemm(Lc, K, Lc, Po, So, PSd.as<double2>(), K, 0, bw.ws.as<double2>(),
+      ZOperand Sto{Std.p, 0, K, 1, 0};
+      RB_HIP(launch_zgemm(T, K, Lc, GVo, So, Rd.as<double2>(), K, 0, bw.ws.as<double2>(),
                           (int64_t)(bw.ws.bytes / 16), s));
-      RB_HIP(hipMemcpyAsync(PS.data(), PSd.p, PS.size() * 16, hipMemcpyDeviceToHost, s));
-      RB_HIP(hipStreamSynchronize(s));
-      for (int k = 0; k < K; ++k) {
-        double q = 0.0;
-        for (int i = 0; i < Lc; ++i) q += (std::conj(Sk[(size_t)i * K + k]) * PS[(size_t)i * K + k]).real();
-        worst = std::max(worst, std::sqrt(std::max(0.0, q - theta[k] * theta[k])));
-      }
+      RB_HIP(launch_zgemm(T, K, Lc, Vo, Sto, Rd.as<double2>(), K, 1, bw.ws.as<double2>(),
+                          (int64_t)(bw.ws.bytes / 16), s));
+      ZOperand RH{Rd.p, 0, 1, K, 1};
+      ZOperand Ro{Rd.p, 0, K, 1, 0};
+      RB_HIP(launch_zgemm(K, K, T, RH, Ro, RR.as<double2>(), K, 0, bw.ws.as<double2>(),
+                          (int64_t)(bw.ws.bytes / 16), s));
+      std::vector<cd> rr((size_t)K * K);
+      RB_HIP(hipMemcpyAsync(rr.data(), RR.p, rr.size() * 16, hipMemcpyDeviceToHost, s));
+      RB_HIP(hipStreamSynchronize(s));   // Sk / St are pageable and local
+      for (int k = 0; k < K; ++k) worst = std::max(worst, std::sqrt(std::max(0.0, rr[(size_t)k * K + k].real())));
     }
     }
     const bool energy_ok = too_small || rank > 0 || K < npos || Lc >= T;   // the rule is met inside the space
@@ -1312,7 +1327,7 @@ rb_status lanczos_pca(rb_ctx ctx, BasisWork& bw, const float2* W, int64_t T, int
     if (std::getenv("RBMF_VERBOSE") && !too_small)
       std::fprintf(stderr, "[rbmf] lanczos T=%lld: %d columns, K %d, worst residual %.3e theta_1 %.3e\n",
                    (long long)T, Lc, K, worst, theta[0]);
-    if (final_pass || (!too_small && ((energy_ok && spare && worst <= 1e-7 * theta[0]) || Lc >= T))) break;
+    if (final_pass || (!too_small && ((energy_ok && spare && worst <= 1e-10 * theta[0]) || Lc >= T))) break;
     // next block: G X_j orthogonalised against every block (two passes), then orthonormalised
     const int64_t nb_next = std::min<int64_t>(b, T - Lc);
     if (Lc + nb_next > cap) RB_TRY(grow(std::min<int64_t>(T, 2 * cap)));
@@ -1415,13 +1430,18 @@ rb_status finish_basis(rb_ctx ctx, rb_bank bank, int32_t t0, int64_t T, int K, c
   bs->c.resize((size_t)T * K);
   RB_HIP(hipMemcpyAsync(bs->c.data(), cdev.p, bs->c.size() * 16, hipMemcpyDeviceToHost, s));
   RB_HIP(hipStreamSynchronize(s));
-  double csum = 0.0;
-  for (int64_t j = 0; j < T; ++j)
+  double csum = 0.0, cmin = 1.0;
+  for (int64_t j = 0; j < T; ++j) {
+    double cj = 0.0;
     for (int k = 0; k < K; ++k) {
       bs->c[(size_t)j * K + k] *= sc[k];
-      csum += std::norm(bs->c[(size_t)j * K + k]);
+      cj += std::norm(bs->c[(size_t)j * K + k]);
     }
+    csum += cj;
+    cmin = std::min(cmin, cj);
+  }
   bs->energy = energy >= 0 ? energy : csum / trace;
+  bs->min_energy = std::min(1.0, cmin);
   // C = conj(c) as complex64 (unscaled), row scales for FP16
   std::vector<float2> C32((size_t)T * K);
   bs->row_scale.assign(bs->Tp, 1.f);
@@ -2043,7 +2063,11 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
     stats->n_refiltered = (int32_t)sum1[1];
     stats->n_bins = nbins;
     int kmax = 0;
-    for (int32_t m = 0; m < nbases; ++m) kmax = std::max(kmax, (int)bases[m]->K);
+    stats->min_energy = 1.0;
+    for (int32_t m = 0; m < nbases; ++m) {
+      kmax = std::max(kmax, (int)bases[m]->K);
+      stats->min_energy = std::min(stats->min_energy, bases[m]->min_energy);
+    }
     stats->rank = kmax;
     stats->ms[0] = elapsed(ctx, 0, 1);
     for (int32_t m = 0; m < nbases; ++m) {
@@ -2115,6 +2139,7 @@ extern "C" rb_status rb_filter_stream(rb_ctx ctx, const rb_basis* bases, int32_t
       acc.n_refiltered += st.n_refiltered;
       acc.rank = std::max(acc.rank, st.rank);
       acc.n_bins += st.n_bins;
+      acc.min_energy = st.min_energy;
       for (int k = 0; k < 8; ++k) acc.ms[k] += st.ms[k];
     }
     lo = hi;
@@ -2177,6 +2202,7 @@ extern "C" rb_status mf_full(rb_ctx ctx, rb_bank bank, const float* strain, doub
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     stats->n_refiltered = T;
+    stats->min_energy = 1.0;     // the exact filter of every template
     float ms;
     if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) stats->ms[0] = ms;
     if (hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]) == hipSuccess) stats->ms[4] = ms;
@@ -2828,7 +2854,10 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
   RB_HIP(hipStreamSynchronize(ctx->stream));
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
+    stats->min_energy = 1.0;
     for (int32_t i = 0; i < nitems; ++i) {
+      for (int32_t m = 0; m < items[i].nbases; ++m)
+        stats->min_energy = std::min(stats->min_energy, items[i].bases[m]->min_energy);
       stats->n_stage1 += sm[8 * (size_t)i];
       stats->n_refiltered += (int32_t)sm[8 * (size_t)i + 1];
       if (opts->bin_w >= 2) stats->n_bins += sm[8 * (size_t)i + 7];

@@ -81,3 +81,27 @@ def compare_triggers(got: np.ndarray, rho: np.ndarray, thr: float, templates=Non
     order = np.lexsort((got["sample"], got["tmpl"]))
     assert np.all(order == np.arange(len(got))), "triggers not sorted by (tmpl, sample)"
     return int(ora.sum()), len(got), int((band & (ora | G)).sum())
+
+
+def quant(x, dtype):
+    """Round-to-nearest-even of float32 values to bf16 / f16 (numpy emulation), as float64."""
+    x = np.asarray(x, np.float32)
+    if dtype == "f16":
+        return x.astype(np.float16).astype(np.float64)
+    u = x.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def quantised_coefficients(c, dtype):
+    """C = conj(c) as the 16-bit reconstruction stores it (complex128 values):
+    complex64, then (FP16) each row scaled by the power of two that puts its
+    largest component in [0.5, 1), rounded to the storage type, scale removed."""
+    Cc = np.conj(c).astype(np.complex64)
+    if dtype == "f16":
+        mx = np.maximum(np.abs(Cc.real), np.abs(Cc.imag)).max(axis=1)
+        a = 2.0 ** (-np.frexp(mx)[1])
+    else:
+        a = np.ones(Cc.shape[0])
+    Cs = Cc * a[:, None].astype(np.float32)
+    return (quant(Cs.real, dtype) + 1j * quant(Cs.imag, dtype)) / a[:, None]

@@ -1,0 +1,135 @@
+"""Precision of the 16-bit reconstruction on the 10 000-template workload
+(16 s at 2048 Hz, N = 2^15, 0PN templates with m1, m2 uniform in [1, 20],
+one basis keeping >= 0.999 of the energy, one on-bank injection at SNR 10):
+C and Z stored in BF16 / FP16 (per-row power-of-two scales), FP32
+accumulation; the basis and sigma stay FP64.
+
+For each storage type (and FP32 for reference), on a seeded subset of 256
+templates:
+  * |rho_RB| error against the FP64 reduced-basis SNR of the same basis
+    (precision alone) and against the exact template-method SNR (precision
+    plus truncation), max and rms;
+  * error against the FP64 product of the quantised operands the kernel
+    reads (the kernel's own rounding, bounded by FP32 accumulation);
+  * agreement of the first-stage crossings at 5 and 6 with the FP64
+    reduced-basis SNR's (outside the +-1e-3 band);
+and over all 10 000 templates the final triggers of rb_filter (thresholds
+5 / 6, and 5 / 5) must equal the FP64 oracle's at 6 (and 5)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import basis as ob
+from oracle import mf as om
+from paper_2110_13115_amd import inputs as gi
+from paper_2110_13115_amd import rbmf
+from tests.helpers import quantised_coefficients
+
+pytestmark = pytest.mark.gpu
+NAME = "rb_16s_10000t"
+BAND = 1e-3
+
+
+def log(*a):
+    print("[gpu-prec]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def prec():
+    import torch
+    wl = gi.WORKLOADS[NAME]
+    bank_def = wl.bank()
+    psd = gi.psd_on_grid(wl.N, wl.fs)
+    sig = lambda h: om.sigma(h, psd, wl.N, wl.fs, wl.f_low)
+    strain, inj = gi.make_strain(wl, bank_def, sig, dtype=np.float32)
+    ctx = rbmf.Context(0)
+    bank = rbmf.Bank(ctx, wl.N, wl.fs, wl.f_low, psd, wl.T, bank_def.fill)
+    log("bank uploaded")
+    # the oracle over every template, kept as its crossings at 5 (less the band)
+    st = om.strain_tilde(strain.astype(np.float64), wl.fs)
+    parts = []
+    for t0 in range(0, wl.T, 256):
+        t1 = min(wl.T, t0 + 256)
+        rho = om.snr_rows(st, bank_def.fill(t0, t1, 0, wl.N // 2 + 1), psd, wl.N, wl.fs, wl.f_low)
+        parts.extend(om.triggers_of(t0 + i, rho[i], 5.0 * (1 - BAND)) for i in range(t1 - t0))
+    ora = np.concatenate(parts)
+    ora = ora[np.lexsort((ora["sample"], ora["tmpl"]))]
+    log("oracle crossings >= 4.995:", len(ora))
+    sub = np.sort(np.random.default_rng([13115, 3, 9]).choice(wl.T, size=256, replace=False))
+    Hs = np.stack([bank_def.fill(int(j), int(j) + 1, 0, wl.N // 2 + 1)[0] for j in sub])
+    exact = om.snr_rows(st, Hs, psd, wl.N, wl.fs, wl.f_low)
+    yield wl, psd, strain, ctx, bank, ora, sub, exact, torch.from_numpy(strain).cuda()
+    bank.close()
+
+
+def final_vs_oracle(got, ora, thr, N):
+    """Final triggers against the oracle's list: equal outside the band,
+    |rho| to 1e-4 relative."""
+    a = ora["snr"]
+    key_o = ora["tmpl"].astype(np.int64) * N + ora["sample"]
+    key_g = got["tmpl"].astype(np.int64) * N + got["sample"]
+    band = (a >= thr * (1 - BAND)) & (a <= thr * (1 + BAND))
+    missing = np.setdiff1d(key_o[(a >= thr) & ~band], key_g)
+    assert len(missing) == 0, f"{len(missing)} oracle triggers missing"
+    pos = np.searchsorted(key_o, key_g)
+    ok = (pos < len(key_o)) & (key_o[np.minimum(pos, len(key_o) - 1)] == key_g)
+    assert ok.all(), "GPU trigger below the oracle's 4.995"
+    assert not ((a[pos] < thr) & ~band[pos]).any(), "extra GPU triggers"
+    rel = np.abs(got["snr"] - a[pos]) / a[pos]
+    assert rel.max(initial=0) <= 1e-4
+    return int((a >= thr).sum()), len(got)
+
+
+def crossings(rho, thr, ref):
+    """(j, n) sets of |rho| >= thr, and the symmetric difference with ref's
+    outside the band of ref."""
+    a, r = np.abs(rho), np.abs(ref)
+    band = (r >= thr * (1 - BAND)) & (r <= thr * (1 + BAND))
+    g, o = (a >= thr), (r >= thr)
+    return int(o.sum()), int(g.sum()), int(((g != o) & ~band).sum())
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_precision_config(prec, dtype):
+    import torch
+    wl, psd, strain, ctx, bank, ora, sub, exact, sd = prec
+    basis = rbmf.Basis(ctx, bank, rank=0, tol=wl.tol, dtype=dtype)
+    try:
+        V, c, lam = basis.export()
+        assert basis.energy >= 1 - wl.tol
+        # the GPU first-stage series of the subset (the reconstruction kernel's own output)
+        full = torch.empty((wl.T, wl.N), dtype=torch.complex64, device="cuda")
+        rbmf.debug_rho(ctx, bank, sd, basis, out=full)
+        rho = full[torch.from_numpy(sub).cuda()].cpu().numpy().astype(np.complex128)
+        del full
+        k_lo, _ = om.band_limits(wl.N, wl.fs, wl.f_low)
+        d = ob.whitened_data(strain.astype(np.float64), psd, wl.fs, wl.f_low)
+        beta = ob.basis_outputs(d, V, wl.N, k_lo)
+        rb64 = ob.rb_snr(beta, c[sub])
+        scale = np.maximum(np.abs(rb64), 1.0)
+        e_rb = np.abs(rho - rb64) / scale
+        e_ex = np.abs(rho - exact) / np.maximum(np.abs(exact), 1.0)
+        line = (f"{dtype}: K={basis.K} |rho| err vs FP64 RB max {e_rb.max():.2e} rms {np.sqrt(np.mean(e_rb ** 2)):.2e}; "
+                f"vs exact max {e_ex.max():.2e} rms {np.sqrt(np.mean(e_ex ** 2)):.2e}")
+        if dtype != "f32":
+            Z = rbmf.debug_basis_outputs(ctx, basis, strain).astype(np.complex128)
+            ref = quantised_coefficients(c[sub], dtype) @ Z
+            e_k = (np.abs(rho - ref) / np.maximum(np.abs(ref), 1.0)).max()
+            line += f"; vs quantised-operand product {e_k:.2e}"
+            assert e_k <= 1e-5
+        for thr in (5.0, 6.0):
+            n_o, n_g, n_diff = crossings(rho, thr, rb64)
+            line += f"; crossings at {thr}: FP64 {n_o}, GPU {n_g}, differ {n_diff}"
+            if dtype == "f32":
+                assert n_diff == 0
+        log(line)
+        assert e_rb.max() <= {"f32": 1e-5, "bf16": 3e-2, "f16": 4e-3}[dtype]
+        # exact second stage: the final triggers are the oracle's over all templates
+        for thr1, thr2 in ((5.0, 6.0), (5.0, 5.0)):
+            tr, _, st = rbmf.rb_filter(ctx, basis, bank, sd, thr1, thr2, stage2=rbmf.RB_STAGE2_FULL)
+            n_o, n_g = final_vs_oracle(tr, ora, thr2, wl.N)
+            log(f"  final at {thr2} (first stage {thr1}): oracle {n_o}, GPU {n_g}, stage1 {st.n_stage1}, "
+                f"refiltered {st.n_refiltered}, min template energy {st.min_energy:.6f}")
+    finally:
+        basis.close()

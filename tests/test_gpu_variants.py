@@ -2,9 +2,10 @@
 RBMF_GEMM_VARIANT, read when a basis first runs), on sub-banks whose template
 counts exercise whole 64-template tiles, a remainder, and a sub-bank smaller
 than one tile: the FP32 variants against the oracle's reduced-basis SNR, the
-16-bit ones against their own first variant (same quantised operands, FP32
-accumulation), and the threshold epilogues through the reconstruction second
-stage."""
+BF16 / FP16 ones against the FP64 product of the quantised operands the
+kernels read (stored 16-bit Z, RNE-rounded C), the split-BF16 ones against
+the FP64 split product, every variant against the first, and the threshold
+epilogues through the reconstruction second stage."""
 import sys
 
 import numpy as np
@@ -13,7 +14,7 @@ import pytest
 from oracle import basis as ob
 from oracle import mf as om
 from paper_2110_13115_amd import rbmf
-from tests.helpers import Case
+from tests.helpers import Case, quant, quantised_coefficients
 
 pytestmark = pytest.mark.gpu
 
@@ -66,6 +67,31 @@ def test_every_variant(vcase, dtype, monkeypatch):
             err = (np.abs(rho - ref) / np.maximum(np.abs(ref), 1.0)).max()
             log(dtype, "variant", v, "rho err vs oracle", err)
             assert err <= 1e-4, (v, err)
+        if dtype in ("bf16", "f16"):
+            ref = []
+            for b in bs:
+                V, c, _ = b.export()
+                Z = rbmf.debug_basis_outputs(ctx, b, case.strain).astype(np.complex128)   # stored values
+                ref.append(quantised_coefficients(c, dtype) @ Z)
+            ref = np.concatenate(ref)
+            err = (np.abs(rho - ref) / np.maximum(np.abs(ref), 1.0)).max()
+            log(dtype, "variant", v, "rho err vs FP64 product of the quantised operands", err)
+            assert err <= 1e-5, (v, err)
+        if dtype == "bf16x3":
+            ref = []
+            for b in bs:
+                V, c, _ = b.export()
+                Zh, Zl = rbmf.debug_basis_outputs(ctx, b, case.strain).astype(np.complex128)
+                Cc = np.conj(c).astype(np.complex64)
+                hr, hi_ = quant(Cc.real, "bf16"), quant(Cc.imag, "bf16")
+                lr = quant(np.asarray(Cc.real, np.float64) - hr, "bf16")
+                li = quant(np.asarray(Cc.imag, np.float64) - hi_, "bf16")
+                Ch, Cl = hr + 1j * hi_, lr + 1j * li
+                ref.append(Ch @ Zh + Ch @ Zl + Cl @ Zh)
+            ref = np.concatenate(ref)
+            err = (np.abs(rho - ref) / np.maximum(np.abs(ref), 1.0)).max()
+            log(dtype, "variant", v, "rho err vs FP64 split product", err)
+            assert err <= 1e-5, (v, err)
         if ref_rho is None:
             ref_rho, ref_trig = rho, trig
         else:
