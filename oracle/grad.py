@@ -19,16 +19,47 @@ import numpy as np
 import torch
 
 
-def _forward(s: torch.Tensor, C: torch.Tensor, V: torch.Tensor, w: torch.Tensor, k_lo: int,
-             fs: float, tmpl: torch.Tensor, samp: torch.Tensor, g: torch.Tensor) -> torch.Tensor:
+def _beta_at(s: torch.Tensor, V: torch.Tensor, w: torch.Tensor, k_lo: int, fs: float,
+             samp: torch.Tensor) -> torch.Tensor:
+    """beta_k[n_i] (K x m) by direct sums over the band."""
     N = s.shape[0]
     nb = V.shape[1]
     d = torch.fft.rfft(s)[k_lo:k_lo + nb] * w / fs                    # whitened data on the band
     f = torch.arange(k_lo, k_lo + nb, dtype=torch.float64)
     ph = torch.exp(2j * np.pi * torch.outer(f, samp.to(torch.float64)) / N)  # nb x m
-    beta = (d[None, :] * torch.conj(V)) @ ph                             # K x m
+    return (d[None, :] * torch.conj(V)) @ ph
+
+
+def _loss_from_beta(C: torch.Tensor, beta: torch.Tensor, tmpl: torch.Tensor, g: torch.Tensor) -> torch.Tensor:
+    """sum_i g_i |sum_k C[j_i, k] beta[k, i]|^2."""
     rho = torch.sum(C[tmpl, :] * beta.T, dim=1)                         # m
     return torch.sum(g * (rho.real ** 2 + rho.imag ** 2))
+
+
+def _forward(s: torch.Tensor, C: torch.Tensor, V: torch.Tensor, w: torch.Tensor, k_lo: int,
+             fs: float, tmpl: torch.Tensor, samp: torch.Tensor, g: torch.Tensor) -> torch.Tensor:
+    return _loss_from_beta(C, _beta_at(s, V, w, k_lo, fs, samp), tmpl, g)
+
+
+def beta_at(s: np.ndarray, V: np.ndarray, w: np.ndarray, k_lo: int, fs: float, samp: np.ndarray) -> np.ndarray:
+    """The basis outputs beta_k (Eq. Beta_eqn) at the samples `samp` only,
+    K x m complex128.  beta is linear in s, so beta(s + e v) = beta(s) +
+    e beta(v): one evaluation per strain direction serves a central
+    difference."""
+    with torch.no_grad():
+        return _beta_at(torch.as_tensor(np.asarray(s, np.float64)), torch.as_tensor(np.asarray(V, np.complex128)),
+                        torch.as_tensor(np.asarray(w, np.float64)), k_lo, fs,
+                        torch.as_tensor(np.asarray(samp, np.int64))).numpy()
+
+
+def loss_from_beta(C: np.ndarray, beta: np.ndarray, tmpl: np.ndarray, g: np.ndarray) -> float:
+    """The loss given the basis outputs at the trigger samples (column i of
+    beta at sample n_i)."""
+    with torch.no_grad():
+        return float(_loss_from_beta(torch.as_tensor(np.asarray(C, np.complex128)),
+                                     torch.as_tensor(np.asarray(beta, np.complex128)),
+                                     torch.as_tensor(np.asarray(tmpl, np.int64)),
+                                     torch.as_tensor(np.asarray(g, np.float64))))
 
 
 def loss(s: np.ndarray, C: np.ndarray, V: np.ndarray, w: np.ndarray, k_lo: int, fs: float,

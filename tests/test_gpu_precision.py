@@ -63,14 +63,18 @@ def prec():
     bank.close()
 
 
-def final_vs_oracle(got, ora, thr, N):
+def final_vs_oracle(got, ora, thr, N, silent=None):
     """Final triggers against the oracle's list: equal outside the band,
-    |rho| to 1e-4 relative."""
+    |rho| to 1e-4 relative.  Oracle triggers of templates in `silent` (those
+    whose first-stage series never reaches thr1, so the second stage never
+    sees them) may be missing."""
     a = ora["snr"]
     key_o = ora["tmpl"].astype(np.int64) * N + ora["sample"]
     key_g = got["tmpl"].astype(np.int64) * N + got["sample"]
     band = (a >= thr * (1 - BAND)) & (a <= thr * (1 + BAND))
     missing = np.setdiff1d(key_o[(a >= thr) & ~band], key_g)
+    if silent is not None:
+        missing = missing[~np.isin(missing // N, silent)]
     assert len(missing) == 0, f"{len(missing)} oracle triggers missing"
     pos = np.searchsorted(key_o, key_g)
     ok = (pos < len(key_o)) & (key_o[np.minimum(pos, len(key_o) - 1)] == key_g)
@@ -124,11 +128,26 @@ def test_precision_config(prec, dtype):
             if dtype == "f32":
                 assert n_diff == 0
         log(line)
-        assert e_rb.max() <= {"f32": 1e-5, "bf16": 3e-2, "f16": 4e-3}[dtype]
-        # exact second stage: the final triggers are the oracle's over all templates
+        # FP32: the stated 1e-4 relative tolerance of the FP32 path (measured 1.4e-5 at
+        # K = 487); 16-bit: a few units of the storage format's relative rounding
+        # (2^-9, 2^-12) times sqrt(E|Z|^2) = sqrt(2), at the tail of 8.4e6 samples
+        assert e_rb.max() <= {"f32": 1e-4, "bf16": 3e-2, "f16": 4e-3}[dtype]
+        # full second stage: at thresholds 5 / 6 the final triggers are the oracle's over all
+        # templates; at 5 / 5 (no margin between the stages) a template is refiltered only when its
+        # reduced-basis series crosses 5, so the oracle triggers of templates whose FP64
+        # reduced-basis series stays below 5 (outside the band) may be missing, and no others
         for thr1, thr2 in ((5.0, 6.0), (5.0, 5.0)):
             tr, _, st = rbmf.rb_filter(ctx, basis, bank, sd, thr1, thr2, stage2=rbmf.RB_STAGE2_FULL)
-            n_o, n_g = final_vs_oracle(tr, ora, thr2, wl.N)
+            silent = None
+            if thr1 == thr2:
+                cand = np.unique(ora["tmpl"][ora["snr"] >= thr2])
+                cand = np.setdiff1d(cand, tr["tmpl"])
+                peak = np.abs(ob.rb_snr(beta, c[cand])).max(axis=1) if len(cand) else np.zeros(0)
+                assert (peak < thr1 * (1 + BAND)).all(), "a refiltered template was dropped"
+                silent = cand
+                log(f"  {len(cand)} templates with oracle triggers at {thr2} and none from the GPU: FP64 "
+                    f"reduced-basis peak {peak.max(initial=0):.4f} < {thr1}")
+            n_o, n_g = final_vs_oracle(tr, ora, thr2, wl.N, silent)
             log(f"  final at {thr2} (first stage {thr1}): oracle {n_o}, GPU {n_g}, stage1 {st.n_stage1}, "
                 f"refiltered {st.n_refiltered}, min template energy {st.min_energy:.6f}")
     finally:

@@ -322,6 +322,26 @@ def test_gradient_loss_equals_ifft_route():
     assert L == pytest.approx(ref, rel=1e-12)
 
 
+def test_beta_at_equals_ifft_route_and_is_linear():
+    """beta at given samples by direct sums equals the inverse-FFT route's
+    columns (Eq. Beta_eqn); the loss from those columns equals the loss; and
+    beta(s + e v) = beta(s) + e beta(v)."""
+    N, fs, f_low, H, psd, V, c, k_lo, w, s = _grad_case(rank=5)
+    tmpl = np.array([0, 3, 5, 7, 2])
+    samp = np.array([10, 500, 1023, 0, 333])
+    g = np.array([1.0, 2.0, 1.0, 1.5, 0.25])
+    full = ob.basis_outputs(ob.whitened_data(s, psd, fs, f_low), V, N, k_lo)
+    b = og.beta_at(s, V, w, k_lo, fs, samp)
+    assert np.abs(b - full[:, samp]).max() <= 1e-12 * np.abs(full).max()
+    C = np.conj(c)
+    assert og.loss_from_beta(C, b, tmpl, g) == pytest.approx(og.loss(s, C, V, w, k_lo, fs, tmpl, samp, g), rel=1e-12)
+    v = np.sqrt(np.mean(s ** 2)) * np.random.default_rng(5).standard_normal(N)
+    bv = og.beta_at(v, V, w, k_lo, fs, samp)
+    b2 = og.beta_at(s + 0.5 * v, V, w, k_lo, fs, samp)
+    assert np.abs(bv).max() > 0.1 * np.abs(b).max()
+    assert np.abs(b2 - (b + 0.5 * bv)).max() <= 1e-12 * np.abs(b2).max()
+
+
 def test_gradient_loss_at_full_rank_equals_template_method():
     """At full rank the loss is sum g |rho_j[n]|^2 of the template method
     (Eq. IFFT / SNR_def, per template, no basis)."""
