@@ -418,6 +418,34 @@ rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_item* items
 rb_status mf_full(rb_ctx ctx, rb_bank bank, const float* strain, double thr, rb_trigger* out,
                   int64_t cap, int64_t* n_out, rb_peak* peaks, rb_stats* stats);
 
+/* mf_full without device allocation, for callers that cannot allocate
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same kernels and the same sorted triggers as mf_full.
+ *   strain  device, N floats.
+ *   out     device, cap triggers (may be NULL when cap == 0).
+ *   n_out   host: the number of triggers.
+ * Scratch: every intermediate (whitened data, FFT intermediate, counters,
+ * trigger records and their sort buffers) lives in one fixed device array of
+ * RB_NOALLOC_SCRATCH_BYTES per GPU that the library holds until the process
+ * ends; the call allocates nothing.  The array keeps the previous call's
+ * contents (the call clears what must start at zero).  Calls on one GPU share
+ * it, so overlapping calls would race: the library serialises them (a call
+ * holds the GPU's array until its work has finished, and it synchronises the
+ * context's stream before returning).
+ * Precondition: the context already holds the FFT plan of the bank's grid
+ * (any earlier mf_full or rb_filter call on a bank of the same N prepares
+ * it), else RB_ERR_ARG.
+ * Limits: RB_ERR_ARG when N and T need more than the array (N double2 of
+ * FFT work, the whitened data, 16 bytes per template and 16 MiB of trigger
+ * records: every supported N up to 2^21 fits with banks of up to 10^5
+ * templates); RB_ERR_UNSUPPORTED, with *n_out = the count, when the
+ * crossings exceed the records the array holds (at least 349 525, from
+ * 16 MiB over three record arrays); RB_ERR_CAPACITY (with *n_out) when they
+ * exceed cap. */
+#define RB_NOALLOC_SCRATCH_BYTES (64ull << 20)
+rb_status mf_full_noalloc(rb_ctx ctx, rb_bank bank, const float* strain, double thr, rb_trigger* out,
+                          int64_t cap, int64_t* n_out);
+
 /* First-stage reconstruction at given (template, sample) points:
  *   rho_i = sum_k C_{j_i k} beta_k[n_i]      (Eq. Beta_eqn, C = conj(c))
  * with beta from `strain` (FP32 path whatever the basis storage type).

@@ -177,6 +177,7 @@ struct rb_ctx_s {
   hipStream_t gstream = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::string gkey;
+  void* noalloc = nullptr;         // this device's fixed scratch (device address) for mf_full_noalloc
   ~rb_ctx_s() {
     for (auto e : evs) (void)hipEventDestroy(e);
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -754,32 +755,53 @@ rb_status ensure_trigger_scratch(rb_ctx ctx, int T) {
 // threshold epilogue; counts in cnt2, records in trig2, maxima in tmax.
 // With d_count (graph mode) nlist is an upper bound and list entries at or
 // beyond *d_count are skipped on the device.
-rb_status step_mf(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTables& tw, const int32_t* list,
-                  int64_t nlist, float thr2sq, const int32_t* d_count = nullptr) {
-  const int B = batch_vectors(g.N, nlist);
-  RB_TRY(ctx->work.ensure((size_t)B * g.N * 8));
+// Buffers of the template method's passes: the [B][N] intermediate, the
+// whitened data, the trigger records and their counters.
+struct MfBufs {
+  float2* work;
+  int B;
+  const float2* d;
+  TrigRec* trig;
+  int64_t trig_cap;
+  unsigned long long* trig_count;
+  int32_t* tmpl_count;
+  unsigned long long* tmpl_max;   // NULL: no per-template maxima
+};
+
+rb_status mf_passes(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTables& tw, const int32_t* list,
+                    int64_t nlist, float thr2sq, const int32_t* d_count, const MfBufs& b) {
   PassArgs a = base_args(bank, g, tw);
   a.sign = +1;
-  a.d = ctx->dspec.as<float2>();
+  a.d = b.d;
   a.src = bank->w.as<float2>();
   a.sup_lo = bank->sup_lo.as<int32_t>();
   a.sup_hi = bank->sup_hi.as<int32_t>();
-  a.work = ctx->work.as<float2>();
+  a.work = b.work;
   a.vec_list = list;
   a.d_count = d_count;
   a.thr2 = thr2sq;
-  a.trig = ctx->trig2.as<TrigRec>();
-  a.trig_cap = trig_capacity(ctx->trig2);
-  a.trig_count = ctx->counters.as<unsigned long long>() + 1;
-  a.tmpl_count = ctx->cnt2.as<int32_t>();
-  a.tmpl_max = ctx->want_peaks ? ctx->tmax.as<unsigned long long>() : nullptr;
-  for (int64_t i0 = 0; i0 < nlist; i0 += B) {
+  a.trig = b.trig;
+  a.trig_cap = b.trig_cap;
+  a.trig_count = b.trig_count;
+  a.tmpl_count = b.tmpl_count;
+  a.tmpl_max = b.tmpl_max;
+  for (int64_t i0 = 0; i0 < nlist; i0 += b.B) {
     a.vec_base = (int)i0;
-    a.nvec = (int)std::min<int64_t>(B, nlist - i0);
+    a.nvec = (int)std::min<int64_t>(b.B, nlist - i0);
     RB_HIP(launch_pass1(a, IN_CORR, ctx->stream));
     RB_HIP(launch_pass2(a, OUT_THRESH, ctx->stream));
   }
   return RB_OK;
+}
+
+rb_status step_mf(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTables& tw, const int32_t* list,
+                  int64_t nlist, float thr2sq, const int32_t* d_count = nullptr) {
+  const int B = batch_vectors(g.N, nlist);
+  RB_TRY(ctx->work.ensure((size_t)B * g.N * 8));
+  MfBufs b{ctx->work.as<float2>(), B, ctx->dspec.as<float2>(), ctx->trig2.as<TrigRec>(), trig_capacity(ctx->trig2),
+           ctx->counters.as<unsigned long long>() + 1, ctx->cnt2.as<int32_t>(),
+           ctx->want_peaks ? ctx->tmax.as<unsigned long long>() : nullptr};
+  return mf_passes(ctx, bank, g, tw, list, nlist, thr2sq, d_count, b);
 }
 
 // scan cnt -> offsets/list and read the summary {total, nlist, maxcount, flag}
@@ -861,9 +883,12 @@ extern "C" rb_status rb_ctx_create(int device, void* hip_stream, rb_ctx* out) {
   RB_CHECK(std::strncmp(prop.gcnArchName, "gfx950", 6) == 0, RB_ERR_DEVICE,
            std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
   RB_HIP(hipSetDevice(device));
+  void* noalloc = nullptr;
+  RB_HIP(noalloc_scratch_init(device, &noalloc));
   auto c = new (std::nothrow) rb_ctx_s;
   RB_CHECK(c != nullptr, RB_ERR_OOM, "host allocation failed");
   c->device = device;
+  c->noalloc = noalloc;
   c->arch = prop.gcnArchName;
   c->stream = static_cast<hipStream_t>(hip_stream);
   for (auto& e : c->ev) {
@@ -2210,6 +2235,106 @@ extern "C" rb_status mf_full(rb_ctx ctx, rb_bank bank, const float* strain, doub
     if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]) == hipSuccess) stats->ms[6] = ms;
     (void)hipGetLastError();
   }
+  return st;
+}
+
+// ====================================================================== allocation-free template method
+// mf_full on a fixed per-GPU scratch (see include/rbmf.h).  Layout of the
+// scratch, every part 256-byte aligned: flag, counter and scan summary;
+// per-template counts, offsets, fill cursors and list; the whitened data; the
+// FFT intermediate (first the FP64 strain transform's N double2, then the
+// template passes' [B][N] complex64); three record arrays of R entries
+// (unsorted records, grouped records, merge buffer).
+extern "C" rb_status mf_full_noalloc(rb_ctx ctx, rb_bank bank, const float* strain, double thr, rb_trigger* out,
+                                     int64_t cap, int64_t* n_out) {
+  RB_TRY(validate_ctx(ctx));
+  RB_CHECK(bank != nullptr && n_out != nullptr, RB_ERR_ARG, "NULL argument");
+  RB_CHECK(bank->ctx == ctx, RB_ERR_ARG, "bank belongs to another context");
+  RB_CHECK(std::isfinite(thr) && thr > 0, RB_ERR_ARG, "thr must be > 0");
+  RB_CHECK(cap >= 0, RB_ERR_ARG, "cap must be >= 0");
+  RB_CHECK(strain != nullptr && is_device_ptr(strain), RB_ERR_ARG, "strain must be a device pointer");
+  RB_CHECK(cap == 0 || (out != nullptr && is_device_ptr(out)), RB_ERR_ARG, "out must be a device pointer");
+  RB_CHECK(ctx->noalloc != nullptr, RB_ERR_DEVICE, "no scratch address for this device");
+  const int64_t N = bank->grid.N;
+  const int T = bank->T;
+  const auto gi = ctx->fft_n2.find(N);
+  const auto ti = ctx->tw.find(N);
+  RB_CHECK(gi != ctx->fft_n2.end() && ti != ctx->tw.end(), RB_ERR_ARG,
+           "no FFT plan for N = " + std::to_string(N) +
+               " in this context yet (one mf_full or rb_filter call on a bank of this grid prepares it)");
+  const FftGeom g = make_geom(N, gi->second);
+  const FftTables tw{ti->second->pyr.as<float2>(), ti->second->tlo.as<float2>(), ti->second->thi.as<float2>()};
+  const FftTables64 tw64{ti->second->pyr64.as<double2>(), ti->second->tlo64.as<double2>(),
+                         ti->second->thi64.as<double2>()};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  const size_t o_flag = take(8), o_cnt = take(8), o_sum = take(8 * sizeof(int64_t));
+  const size_t o_count = take((size_t)T * 4), o_off = take((size_t)T * 4), o_fill = take((size_t)T * 4),
+               o_list = take((size_t)T * 4);
+  const size_t o_d = take((size_t)bank->nbs * 8);
+  const size_t spec_bytes = (size_t)N * 16, vec_bytes = (size_t)N * 8;
+  const size_t min_rec_bytes = (size_t(16) << 20) + 3 * 256;   // at least 349 525 records per array
+  RB_CHECK(off + spec_bytes + min_rec_bytes <= kNoallocScratchBytes, RB_ERR_ARG,
+           "N = " + std::to_string(N) + " with " + std::to_string(T) + " templates needs more than the " +
+               std::to_string(kNoallocScratchBytes >> 20) + " MiB fixed scratch of mf_full_noalloc (use mf_full)");
+  const int B = (int)std::max<int64_t>(
+      1, std::min<int64_t>({16, (int64_t)T, (int64_t)((kNoallocScratchBytes - off - min_rec_bytes) / vec_bytes)}));
+  const size_t o_work = take(std::max(spec_bytes, (size_t)B * vec_bytes));
+  const int64_t R = (int64_t)((kNoallocScratchBytes - off - 3 * 256) / (3 * sizeof(TrigRec)));
+  const size_t o_trig = take((size_t)R * sizeof(TrigRec)), o_recs = take((size_t)R * sizeof(TrigRec)),
+               o_tmp = take((size_t)R * sizeof(TrigRec));
+  RB_CHECK(off <= kNoallocScratchBytes && R * 3 * sizeof(TrigRec) >= (size_t(16) << 20), RB_ERR_ARG,
+           "scratch layout does not fit");
+  (void)o_sum;
+  char* base = static_cast<char*>(ctx->noalloc);
+  int64_t* flag = reinterpret_cast<int64_t*>(base + o_flag);
+  unsigned long long* counter = reinterpret_cast<unsigned long long*>(base + o_cnt);
+  int64_t* summary = reinterpret_cast<int64_t*>(base + o_sum);
+  int32_t* counts = reinterpret_cast<int32_t*>(base + o_count);
+  int32_t* offsets = reinterpret_cast<int32_t*>(base + o_off);
+  int32_t* fill = reinterpret_cast<int32_t*>(base + o_fill);
+  int32_t* list = reinterpret_cast<int32_t*>(base + o_list);
+  float2* dspec = reinterpret_cast<float2*>(base + o_d);
+  TrigRec* trig = reinterpret_cast<TrigRec*>(base + o_trig);
+  TrigRec* recs = reinterpret_cast<TrigRec*>(base + o_recs);
+  TrigRec* tmp = reinterpret_cast<TrigRec*>(base + o_tmp);
+
+  // one call at a time per GPU: the scratch keeps the previous call's contents
+  // and would be shared by overlapping calls
+  std::lock_guard<std::mutex> lock(noalloc_scratch_lock(ctx->device));
+  const rb_status st = [&]() -> rb_status {
+    RB_TRY(fill32(ctx, flag, 0u, 2));
+    RB_TRY(fill32(ctx, counter, 0u, 2));
+    RB_TRY(fill32(ctx, counts, 0u, T));
+    RB_HIP(launch_check_finite(strain, N, flag, ctx->stream));
+    RB_TRY(spectrum_into(ctx, bank, g, tw, tw64, strain, reinterpret_cast<double2*>(base + o_work), dspec));
+    const MfBufs b{reinterpret_cast<float2*>(base + o_work), B, dspec, trig, R, counter, counts, nullptr};
+    RB_TRY(mf_passes(ctx, bank, g, tw, nullptr, T, (float)(thr * thr), nullptr, b));
+    RB_HIP(launch_scan_counts(counts, T, offsets, fill, list, summary, ctx->stream));
+    int64_t host[4] = {0, 0, 0, 0};
+    RB_HIP(hipMemcpyAsync(host, summary, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    RB_HIP(hipMemcpyAsync(host + 3, flag, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+    RB_CHECK(host[3] == 0, RB_ERR_NUMERIC, "strain contains non-finite values");
+    const int64_t total = host[0];
+    *n_out = total;
+    RB_CHECK(total <= R, RB_ERR_UNSUPPORTED,
+             std::to_string(total) + " crossings exceed the " + std::to_string(R) +
+                 " records of the fixed scratch of mf_full_noalloc (use mf_full)");
+    RB_CHECK(total <= cap, RB_ERR_CAPACITY,
+             "trigger capacity " + std::to_string(cap) + " < required " + std::to_string(total));
+    if (total > 0) {
+      RB_HIP(launch_scatter_triggers(trig, total, nullptr, offsets, fill, recs, ctx->stream));
+      RB_HIP(launch_segment_sort(recs, tmp, offsets, counts, list, (int)host[1], out, nullptr, 0, ctx->stream));
+    }
+    RB_HIP(hipStreamSynchronize(ctx->stream));
+    return RB_OK;
+  }();
+  (void)hipStreamSynchronize(ctx->stream);   // (error paths) no queued work may outlive the lock
   return st;
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 
 namespace rbmf {
@@ -277,6 +278,15 @@ hipError_t launch_row_norms(const float2* w, int64_t rows, int64_t len, int64_t 
 // B: nt x K complex128 (row-major); idx[f] in [0, nt - 2] for f < nb.
 hipError_t launch_interp_rows(const double2* B, int64_t nt, int K, const int32_t* idx, const double* frac,
                               const double* r, const double* scale, int64_t nb, double2* out, hipStream_t s);
+
+// ---------------------------------------------------------------- allocation-free entry point
+// Bytes of the fixed per-GPU device scratch of mf_full_noalloc.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+// Device address of `device`'s copy of that scratch, looked up once per device
+// (call with the device current).
+hipError_t noalloc_scratch_init(int device, void** out);
+// Held by an mf_full_noalloc call for as long as its work uses the scratch.
+std::mutex& noalloc_scratch_lock(int device);
 
 // ---------------------------------------------------------------- misc
 hipError_t launch_check_finite(const float* x, int64_t n, int64_t* flag, hipStream_t s);

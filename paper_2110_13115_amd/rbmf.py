@@ -26,8 +26,8 @@ DTYPES = {"f32": RB_F32, "bf16": RB_BF16, "f16": RB_F16, "bf16x3": RB_BF16X3}
 
 FUNCTIONS = ["rb_ctx_create", "rb_ctx_destroy", "rb_last_error", "rb_bank_create", "rb_bank_free",
              "rb_bank_info", "rb_build_basis", "rb_build_basis_range", "rb_build_basis_solver", "rb_basis_info",
-             "rb_basis_free", "rb_basis_export", "rb_filter",
-             "rb_filter_stream", "rb_filter_batch", "mf_full", "rb_rho_at", "rb_backward", "rb_refine", "rb_cluster_peaks", "rb_debug_rho",
+             "rb_basis_free", "rb_basis_export", "rb_filter", "rb_filter_stream", "rb_filter_batch", "mf_full",
+             "mf_full_noalloc", "rb_rho_at", "rb_backward", "rb_refine", "rb_cluster_peaks", "rb_debug_rho",
              "rb_debug_rho_binned", "rb_debug_basis_outputs", "rb_nonuniform_freqs", "rb_build_basis_nonuniform"]
 
 
@@ -106,6 +106,7 @@ def lib():
         L.rb_filter.argtypes = [vp, C.POINTER(vp), i32, vp, vp, C.POINTER(FilterOpts), vp, i64,
                                 C.POINTER(i64), vp, C.POINTER(Stats)]
         L.mf_full.argtypes = [vp, vp, vp, dbl, vp, i64, C.POINTER(i64), vp, C.POINTER(Stats)]
+        L.mf_full_noalloc.argtypes = [vp, vp, vp, dbl, vp, i64, C.POINTER(i64)]
         L.rb_filter_stream.argtypes = [vp, C.POINTER(vp), i32, vp, vp, i64, C.POINTER(FilterOpts), vp, i64,
                                        C.POINTER(i64), C.POINTER(Stats)]
         L.rb_filter_batch.argtypes = [vp, i32, vp, C.POINTER(FilterOpts), i32, vp, i64, C.POINTER(i64),
@@ -377,6 +378,15 @@ def mf_full(ctx: Context, bank: Bank, strain, thr: float, cap: int = 1 << 20, pe
     _check(lib().mf_full(ctx.h, bank.h, _ptr(strain), float(thr), _ptr(buf), cap, C.byref(n), _ptr(pk),
                          C.byref(st)), "mf_full")
     return _as_np_triggers(buf, n.value) if not dev else n.value, pk, st
+
+
+def mf_full_noalloc(ctx: Context, bank: Bank, strain, thr: float, out):
+    """mf_full on the library's fixed device scratch: strain and out (cap x 4
+    int32, rb_trigger records) are device tensors; returns the trigger count."""
+    n = C.c_int64()
+    _check(lib().mf_full_noalloc(ctx.h, bank.h, _ptr(strain), float(thr), _ptr(out), out.shape[0], C.byref(n)),
+           "mf_full_noalloc")
+    return n.value
 
 
 def _trig_arg(S):
