@@ -533,6 +533,26 @@ rb_status step_spectrum(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTab
   return spectrum_into(ctx, bank, g, tw, tw64, s, ctx->work64.as<double2>(), ctx->dspec.as<float2>());
 }
 
+// Pass 1 / pass 2 over nvec vectors in batches of B (one [B][N] work buffer,
+// the context's stream).  Measured: running pass 2 of batch b on a second
+// stream beside pass 1 of batch b + 1 (two buffers small enough for the
+// Infinity Cache) was slower at every buffer size tried (4.1 ms against
+// 3.4 ms for the headline Z stage), the cross-stream ordering costing more
+// than the overlap gains.
+rb_status pass_pairs(rb_ctx ctx, PassArgs a, int64_t nvec, InKind in, OutKind out) {
+  const int64_t N = a.g.N;
+  const int B = batch_vectors(N, nvec);
+  RB_TRY(ctx->work.ensure((size_t)B * N * 8));
+  a.work = ctx->work.as<float2>();
+  for (int64_t v0 = 0; v0 < nvec; v0 += B) {
+    a.vec_base = (int)v0;
+    a.nvec = (int)std::min<int64_t>(B, nvec - v0);
+    RB_HIP(launch_pass1(a, in, ctx->stream));
+    RB_HIP(launch_pass2(a, out, ctx->stream));
+  }
+  return RB_OK;
+}
+
 // a2 + a3: Z = IFFT(d conj(P_k)) for all basis vectors, planar storage
 // (the basis's storage type, or FP32 into ctx->z32 when force_f32)
 rb_status step_basis_outputs(rb_ctx ctx, rb_basis basis, const FftGeom& g, const FftTables& tw,
@@ -550,23 +570,14 @@ rb_status step_basis_outputs(rb_ctx ctx, rb_basis basis, const FftGeom& g, const
     for (int p = 0; p < planes; ++p)
       RB_TRY(fill32(ctx, static_cast<char*>(zb.p) + p * plane_bytes + off, 0u, (int64_t)(bytes / 4)));
   }
-  const int B = batch_vectors(g.N, K);
-  RB_TRY(ctx->work.ensure((size_t)B * g.N * 8));
   PassArgs a = base_args(bank, g, tw);
   a.sign = +1;
   a.d = ctx->dspec.as<float2>();
   a.src = basis->P.as<float2>();
-  a.work = ctx->work.as<float2>();
   a.zout = zb.as<float>();
   a.zdtype = (int)dt;
   a.zplane = (int64_t)2 * Kp * g.N;
-  for (int v0 = 0; v0 < K; v0 += B) {
-    a.vec_base = v0;
-    a.nvec = std::min(B, K - v0);
-    RB_HIP(launch_pass1(a, IN_CORR, ctx->stream));
-    RB_HIP(launch_pass2(a, dt == RB_F32 ? OUT_Z32 : OUT_Z16, ctx->stream));
-  }
-  return RB_OK;
+  return pass_pairs(ctx, a, K, IN_CORR, dt == RB_F32 ? OUT_Z32 : OUT_Z16);
 }
 
 int64_t trig_capacity(const DevBuf& b) { return (int64_t)(b.bytes / sizeof(TrigRec)); }
@@ -796,12 +807,21 @@ rb_status mf_passes(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTables&
 
 rb_status step_mf(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTables& tw, const int32_t* list,
                   int64_t nlist, float thr2sq, const int32_t* d_count = nullptr) {
-  const int B = batch_vectors(g.N, nlist);
-  RB_TRY(ctx->work.ensure((size_t)B * g.N * 8));
-  MfBufs b{ctx->work.as<float2>(), B, ctx->dspec.as<float2>(), ctx->trig2.as<TrigRec>(), trig_capacity(ctx->trig2),
-           ctx->counters.as<unsigned long long>() + 1, ctx->cnt2.as<int32_t>(),
-           ctx->want_peaks ? ctx->tmax.as<unsigned long long>() : nullptr};
-  return mf_passes(ctx, bank, g, tw, list, nlist, thr2sq, d_count, b);
+  PassArgs a = base_args(bank, g, tw);
+  a.sign = +1;
+  a.d = ctx->dspec.as<float2>();
+  a.src = bank->w.as<float2>();
+  a.sup_lo = bank->sup_lo.as<int32_t>();
+  a.sup_hi = bank->sup_hi.as<int32_t>();
+  a.vec_list = list;
+  a.d_count = d_count;
+  a.thr2 = thr2sq;
+  a.trig = ctx->trig2.as<TrigRec>();
+  a.trig_cap = trig_capacity(ctx->trig2);
+  a.trig_count = ctx->counters.as<unsigned long long>() + 1;
+  a.tmpl_count = ctx->cnt2.as<int32_t>();
+  a.tmpl_max = ctx->want_peaks ? ctx->tmax.as<unsigned long long>() : nullptr;
+  return pass_pairs(ctx, a, nlist, IN_CORR, OUT_THRESH);
 }
 
 // scan cnt -> offsets/list and read the summary {total, nlist, maxcount, flag}
@@ -955,7 +975,9 @@ extern "C" rb_status rb_bank_create(rb_ctx ctx, const rb_grid* grid, const doubl
   RB_TRY(b->sup_hi.ensure((size_t)T * 4));
   b->sigma.assign(T, 0.0);
   std::vector<int32_t> slo(T), shi(T);
-  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(T, (int64_t(64) << 20) / (nbs * 16)));
+  // templates per fill callback: 512 MB of FP64 host values (enough rows for a
+  // multi-threaded generator at N = 2^20)
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(T, (int64_t(512) << 20) / (nbs * 16)));
   std::vector<double> hbuf((size_t)chunk * nbs * 2);
   HostPinned stage;
   RB_TRY(stage.ensure((size_t)chunk * nbs * sizeof(float2)));

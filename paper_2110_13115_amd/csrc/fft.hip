@@ -505,9 +505,31 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
   } else if constexpr (OUT == OUT_THRESH) {
     const float thr2 = a.thr2;
     const int lane = __lane_id();
-    // running maximum in registers (ties to the lowest sample); crossings are
-    // rare, so each crossing lane appends with its own atomics
-    // (tracked only when the caller asked for per-template peaks: tmpl_max != NULL)
+    // running maximum in registers (ties to the lowest sample), tracked only
+    // when the caller asked for per-template peaks (tmpl_max != NULL).
+    // Crossings of a wave are staged in LDS and appended with one counter
+    // atomic per 64 records: near a loud signal every sample of a template
+    // crosses, and per-lane atomics on the one counter would serialise.
+    // (Every lane of the workgroup runs every store of the final stage, so
+    // the ballots see whole waves.)
+    __shared__ TrigRec stage_buf[NT / 64][64];
+    TrigRec* const stg = stage_buf[tid >> 6];
+    int ns = 0;
+    auto flush = [&]() {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      unsigned lo = 0, hi = 0;
+      if (lane == 0) {
+        const unsigned long long b = atomicAdd(a.trig_count, (unsigned long long)ns);
+        lo = (unsigned)b;
+        hi = (unsigned)(b >> 32);
+      }
+      const unsigned long long base = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)hi) << 32) |
+                                      (unsigned)__builtin_amdgcn_readfirstlane((int)lo);
+      for (int t = lane; t < ns; t += 64)
+        if ((int64_t)(base + t) < a.trig_cap) a.trig[base + t] = stg[t];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      ns = 0;
+    };
     const bool track = a.tmpl_max != nullptr;
     float bp = -1.f;
     int bn = 0x7fffffff;
@@ -518,19 +540,24 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
         bp = p;
         bn = n;
       }
-      if (p >= thr2) {
-        const unsigned long long idx = atomicAdd(a.trig_count, 1ull);
-        atomicAdd(&a.tmpl_count[v], 1);
-        if ((int64_t)idx < a.trig_cap) {
+      const bool hit = p >= thr2;
+      const unsigned long long mask = __ballot(hit);
+      if (mask != 0ull) {                                   // (wave-uniform)
+        const int cnt = __popcll(mask);
+        if (lane == 0) atomicAdd(&a.tmpl_count[v], cnt);
+        if (ns + cnt > 64) flush();
+        if (hit) {
           TrigRec t;
           t.tmpl = v;
           t.sample = n;
           t.re = val.x;
           t.im = val.y;
-          a.trig[idx] = t;
+          stg[ns + __popcll(mask & ((1ull << lane) - 1ull))] = t;
         }
+        ns += cnt;
       }
     });
+    if (ns > 0) flush();
     if (track) {
       unsigned long long best =
           bp < 0.f ? 0ull

@@ -30,13 +30,63 @@ constexpr int TILE_T = WAVES * WT_ROWB * 16;   // templates per workgroup (128)
 constexpr int TILE_N = WT_COLB * 32;           // samples per workgroup (64)
 constexpr size_t kLdsMax = 160 * 1024;         // gfx950 LDS per workgroup
 
-// Per-lane threshold epilogue: each output element tests its own |rho|^2 and
-// appends on its own.  Used by the FP32 kernels, whose epilogue is a small
-// part of a tile's time: measured, their main loops run faster with this
-// plain form than with the wave-aggregated one below.
+// Crossing records of one wave staged in LDS: a tile whose samples meet many
+// crossings (an injection seen by every template of the bank) would otherwise
+// wait on one returning counter atomic per step; staged, it takes one per
+// kStage records.
+constexpr int kStage = 64;
+constexpr size_t kStageBytes = (size_t)WAVES * kStage * sizeof(TrigRec);
+struct WaveStage {
+  TrigRec* buf;   // this wave's kStage LDS slots
+  int n;          // records staged (wave-uniform)
+};
+
+__device__ __forceinline__ void stage_flush(const GemmArgs& a, WaveStage& s, int lane) {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  unsigned lo = 0, hi = 0;
+  if (lane == 0) {
+    const unsigned long long b = atomicAdd(a.trig_count, (unsigned long long)s.n);
+    lo = (unsigned)b;
+    hi = (unsigned)(b >> 32);
+  }
+  const unsigned long long base = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)hi) << 32) |
+                                  (unsigned)__builtin_amdgcn_readfirstlane((int)lo);
+  for (int t = lane; t < s.n; t += 64)
+    if ((int64_t)(base + t) < a.trig_cap) a.trig[base + t] = s.buf[t];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  s.n = 0;
+}
+
+// Appends the crossings of one accumulator step (lanes 0-31 hold one template
+// row, lanes 32-63 another, each lane one sample): one count atomic per row
+// and the records at the ballot's prefix count in the wave's stage.
+__device__ __forceinline__ void stage_append(const GemmArgs& a, WaveStage& stg, int lane, bool hit, int j, int n,
+                                             float re, float im) {
+  const unsigned long long mask = __ballot(hit);
+  if (mask == 0ull) return;                                  // (wave-uniform)
+  const unsigned half = (unsigned)(mask >> (lane & 32));
+  if ((lane & 31) == 0 && half != 0u) atomicAdd(&a.tmpl_count[j], __popc(half));
+  const int cnt = __popcll(mask);
+  if (stg.n + cnt > kStage) stage_flush(a, stg, lane);
+  if (hit) {
+    TrigRec t;
+    t.tmpl = a.tmpl_base + j;
+    t.sample = n;
+    t.re = re;
+    t.im = im;
+    stg.buf[stg.n + __popcll(mask & ((1ull << lane) - 1ull))] = t;
+  }
+  stg.n += cnt;
+}
+
+// Threshold epilogue of the FP32 realified kernels: each output element tests
+// its own |rho|^2 against its row's threshold; the crossings of a step are
+// appended through the wave's LDS stage (one counter atomic per 64 records:
+// a tile under a loud injection, where every template crosses, would
+// otherwise serialise on one returning atomic per crossing).
 template <int RB, int CB>
 __device__ __forceinline__ void epilogue_lane(const GemmArgs& a, const f32x16 (&acc)[RB][CB], int rb0,
-                                              int64_t q0) {
+                                              int64_t q0, WaveStage& stg) {
   const int lane = __lane_id();
   const int l1 = __builtin_ctz((unsigned)a.N1);            // N1 is a power of two
 #pragma unroll
@@ -63,48 +113,10 @@ __device__ __forceinline__ void epilogue_lane(const GemmArgs& a, const f32x16 (&
           const float s = a.row_inv ? a.row_inv[j] : 1.f;
           a.rho_out[(int64_t)j * a.N + n] = make_float2(re * s, im * s);
         }
-        if (p >= th[i >> 1]) {
-          atomicAdd(&a.tmpl_count[j], 1);
-          const unsigned long long idx = atomicAdd(a.trig_count, 1ull);
-          if ((int64_t)idx < a.trig_cap) {
-            TrigRec t;
-            t.tmpl = a.tmpl_base + j;
-            t.sample = n;
-            t.re = re;
-            t.im = im;
-            a.trig[idx] = t;
-          }
-        }
+        stage_append(a, stg, lane, j < a.T && p >= th[i >> 1], j, n, re, im);
       }
     }
   }
-}
-
-// Crossing records of one wave staged in LDS: a tile whose samples meet many
-// crossings (an injection seen by every template of the bank) would otherwise
-// wait on one returning counter atomic per step; staged, it takes one per
-// kStage records.
-constexpr int kStage = 64;
-constexpr size_t kStageBytes = (size_t)WAVES * kStage * sizeof(TrigRec);
-struct WaveStage {
-  TrigRec* buf;   // this wave's kStage LDS slots
-  int n;          // records staged (wave-uniform)
-};
-
-__device__ __forceinline__ void stage_flush(const GemmArgs& a, WaveStage& s, int lane) {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  unsigned lo = 0, hi = 0;
-  if (lane == 0) {
-    const unsigned long long b = atomicAdd(a.trig_count, (unsigned long long)s.n);
-    lo = (unsigned)b;
-    hi = (unsigned)(b >> 32);
-  }
-  const unsigned long long base = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)hi) << 32) |
-                                  (unsigned)__builtin_amdgcn_readfirstlane((int)lo);
-  for (int t = lane; t < s.n; t += 64)
-    if ((int64_t)(base + t) < a.trig_cap) a.trig[base + t] = s.buf[t];
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  s.n = 0;
 }
 
 // Wave-level threshold epilogue (16-bit kernels, whose short k-loops make the
@@ -258,7 +270,7 @@ struct BVec<2> {
 };
 
 template <int RB, int CB, int G>
-__device__ __forceinline__ void recon_f32_tile(const GemmArgs& a, int rb0, int64_t q0) {
+__device__ __forceinline__ void recon_f32_tile(const GemmArgs& a, int rb0, int64_t q0, WaveStage& stg) {
   static_assert(G % 2 == 0, "groups hold whole k-pairs");
   static_assert(RB == 1 || RB == 2 || RB == 4, "one, two or four 16-template blocks");
   constexpr int NT = RB == 4 ? 2 : 1;                      // packed 32-template tiles per wave
@@ -363,7 +375,7 @@ __device__ __forceinline__ void recon_f32_tile(const GemmArgs& a, int rb0, int64
         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, BVec<CB>::at(bv, cb), acc[rb][cb], 0, 0, 0);
     }
   }
-  epilogue_lane<RB, CB>(a, acc, rb0, q0);
+  epilogue_lane<RB, CB>(a, acc, rb0, q0, stg);
 }
 
 // One workgroup = one row tile of 32 templates (two 16-template blocks); its
@@ -387,11 +399,14 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(GemmArgs a) {   // at leas
   if (rb0 * 16 >= a.T) return;                             // all of this tile's rows are padding
   const int64_t q0 = (st * WAVES + wave) * TN;
   if (q0 >= a.N) return;                                   // (N is a multiple of TN)
+  __shared__ TrigRec stage_mem[WAVES][kStage];
+  WaveStage stg{stage_mem[wave], 0};
   // a wave whose second row block is all padding runs the one-block tile
   if ((rb0 + 1) * 16 >= a.T)
-    recon_f32_tile<1, CB, G>(a, rb0, q0);
+    recon_f32_tile<1, CB, G>(a, rb0, q0, stg);
   else
-    recon_f32_tile<2, CB, G>(a, rb0, q0);
+    recon_f32_tile<2, CB, G>(a, rb0, q0, stg);
+  if (stg.n > 0) stage_flush(a, stg, threadIdx.x & 63);
 }
 
 // 64 templates (four 16-template blocks) x 32 CB samples per wave, one wave
@@ -413,12 +428,15 @@ __global__ __launch_bounds__(256, 1) void k_recon_f32_w64(GemmArgs a) {
   const int64_t q0 = (st * WAVES + wave) * TN;
   if (q0 >= a.N) return;                                   // (N is a multiple of TN)
   const int rows = a.T - rb0 * 16;                         // templates in this tile (>= 1)
+  __shared__ TrigRec stage_mem[WAVES][kStage];
+  WaveStage stg{stage_mem[wave], 0};
   if (rows > 32)
-    recon_f32_tile<4, CB, G>(a, rb0, q0);
+    recon_f32_tile<4, CB, G>(a, rb0, q0, stg);
   else if (rows > 16)
-    recon_f32_tile<2, CB, G>(a, rb0, q0);
+    recon_f32_tile<2, CB, G>(a, rb0, q0, stg);
   else
-    recon_f32_tile<1, CB, G>(a, rb0, q0);
+    recon_f32_tile<1, CB, G>(a, rb0, q0, stg);
+  if (stg.n > 0) stage_flush(a, stg, threadIdx.x & 63);
 }
 
 // FP32 by Gauss's three real products instead of the realified four:
@@ -509,8 +527,21 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32_3m(GemmArgs a) {
     const float* zk = static_cast<const float*>(a.z) + (int64_t)(2 * (K - 1)) * N + q0 + CB * (lane & 31);
     mma3(ap[(int64_t)ng * 64], *reinterpret_cast<const float4*>(zk), *reinterpret_cast<const float4*>(zk + N));
   }
-  // epilogue: element i of a block is template row 8 (i / 4) + 4 (lane / 32) + i % 4
+  // epilogue: element i of a block is template row 8 (i / 4) + 4 (lane / 32) + i % 4;
+  // crossings go through the wave's LDS stage
+  __shared__ TrigRec stage_mem[WAVES][kStage];
+  WaveStage stg{stage_mem[wave], 0};
   const int l1 = __builtin_ctz((unsigned)a.N1);
+  // Re rho into p1, Im rho into p3 first: P2's registers are free before the
+  // thresholds are fetched
+#pragma unroll
+  for (int c = 0; c < CB; ++c)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const float re = p1[c][i] - p2[c][i];
+      p3[c][i] = p3[c][i] - p1[c][i] - p2[c][i];
+      p1[c][i] = re;
+    }
   float th[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
@@ -524,26 +555,16 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32_3m(GemmArgs a) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int j = tt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-      const float re = p1[c][i] - p2[c][i];
-      const float im = p3[c][i] - p1[c][i] - p2[c][i];
+      const float re = p1[c][i];
+      const float im = p3[c][i];
       if (a.rho_out != nullptr && j < a.T) {
         const float sc = a.row_inv ? a.row_inv[j] : 1.f;
         a.rho_out[(int64_t)j * a.N + n] = make_float2(re * sc, im * sc);
       }
-      if (re * re + im * im >= th[i]) {
-        atomicAdd(&a.tmpl_count[j], 1);
-        const unsigned long long idx = atomicAdd(a.trig_count, 1ull);
-        if ((int64_t)idx < a.trig_cap) {
-          TrigRec t;
-          t.tmpl = a.tmpl_base + j;
-          t.sample = n;
-          t.re = re;
-          t.im = im;
-          a.trig[idx] = t;
-        }
-      }
+      stage_append(a, stg, lane, j < a.T && re * re + im * im >= th[i], j, n, re, im);
     }
   }
+  if (stg.n > 0) stage_flush(a, stg, lane);
 }
 
 // 16-bit operands: one instruction reduces over 16 realified entries = 8

@@ -39,6 +39,10 @@ void par_blocks(int n, int min_block, F&& f) {
 
 // Implicit QL on a real symmetric tridiagonal (d: diagonal, e[i] = T[i+1][i],
 // e[n-1] unused).  Z (n x n, column-major: Z[i + n*j]) accumulates rotations.
+// The published method: the QL algorithm with implicit Wilkinson shifts of
+// Bowdler, Martin, Reinsch and Wilkinson (Numer. Math. 11, 293-306, 1968;
+// the procedure EISPACK calls tql2), with its own deflation test (below) and
+// the plane rotations applied to Z in parallel over rows.
 bool tql_implicit(int n, std::vector<double>& d, std::vector<double>& e, std::vector<double>& Z) {
   if (n == 1) return true;
   e[n - 1] = 0.0;

@@ -14,10 +14,14 @@
 // (device-side counts), workgroup (x, y) takes template list[x] and its
 // crossing groups y, y + G, y + 2G, ... (G = gridDim.y).  A workgroup streams
 // w_j once per group.  A thread owns the bins t, t + 256, ...,
-// t + 7 * 256 of each 2048-bin tile (so every load of a wave is contiguous):
-// the twiddle of its first bin comes exactly from the two-level table
-// (e = f n mod N), the next seven by multiplication with e^{2 pi i 256 n / N}
-// (error <= 8 ulp).
+// t + 7 * 256 of each 2048-bin tile (so every load of a wave is contiguous).
+// Per crossing n, the eight products x_r = d conj(w) of a thread's bins are
+// first summed against a table of the exact offset phases
+// e^{2 pi i r 256 n / N}, r < 8 (built once per group in LDS from the
+// two-level twiddle table, the same for every thread), and the sum is then
+// multiplied by the phase of the thread's first bin of the tile, also taken
+// exactly from the table (e = f n mod N): four FMAs per bin and crossing, no
+// phase recurrence.
 #include "internal.h"
 
 namespace rbmf {

@@ -152,10 +152,13 @@ class _FreqPowers:
         self.logf[pos] = np.log(f[pos])
 
 
-def _taylorf2_pre(pre: _FreqPowers, m1: float, m2: float, order: int, f_low: float) -> np.ndarray:
-    """taylorf2() on a precomputed grid (same expression, shared powers of f)."""
+def _taylorf2_pre(pre: _FreqPowers, m1: float, m2: float, order: int, f_low: float,
+                  out: Optional[np.ndarray] = None) -> np.ndarray:
+    """taylorf2() on a precomputed grid (same expression, shared powers of f);
+    only the support is written when `out` (zeros) is given."""
     f = pre.f
-    out = np.zeros(f.shape, dtype=np.complex128)
+    if out is None:
+        out = np.zeros(f.shape, dtype=np.complex128)
     lo = np.searchsorted(f, max(f_low, 0.0), side="left")
     hi = np.searchsorted(f, f_isco(m1, m2), side="right")
     lo = max(lo, int(np.argmax(pre.pos)) if pre.pos.any() else f.shape[0])
@@ -234,15 +237,22 @@ class Bank:
     def df(self) -> float:
         return self.fs / self.N
 
-    def fill(self, t0: int, t1: int, k0: int, k1: int) -> np.ndarray:
-        """Templates [t0, t1) on bins [k0, k1): complex128 (t1-t0, k1-k0)."""
-        f = np.arange(k0, k1, dtype=np.float64) * self.df
-        out = np.zeros((t1 - t0, k1 - k0), dtype=np.complex128)
-        pre = _FreqPowers(f)
+    def fill(self, t0: int, t1: int, k0: int, k1: int, out: Optional[np.ndarray] = None) -> np.ndarray:
+        """Templates [t0, t1) on bins [k0, k1): complex128 (t1-t0, k1-k0),
+        written into `out` (zeroed first) when it is given."""
+        if out is None:
+            out = np.zeros((t1 - t0, k1 - k0), dtype=np.complex128)
+        else:
+            out[...] = 0
+        key = (k0, k1)
+        pre = self._pre.get(key) if hasattr(self, "_pre") else None
+        if pre is None:     # the frequency powers of the last bin range are kept for the next chunk
+            pre = _FreqPowers(np.arange(k0, k1, dtype=np.float64) * self.df)
+            self._pre = {key: pre}
 
         def one(i):
             t = t0 + i
-            out[i] = _taylorf2_pre(pre, float(self.m1[t]), float(self.m2[t]), self.order, self.f_low)
+            _taylorf2_pre(pre, float(self.m1[t]), float(self.m2[t]), self.order, self.f_low, out[i])
 
         n = t1 - t0
         if n >= 8:

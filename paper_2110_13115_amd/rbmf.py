@@ -8,6 +8,7 @@ if it has not been built.
 from __future__ import annotations
 
 import ctypes as C
+import inspect
 import os
 from typing import Callable, Optional, Tuple
 
@@ -182,11 +183,19 @@ class Bank:
         psd = np.ascontiguousarray(psd, dtype=np.float64)
         self._err = None
 
+        try:
+            in_place = "out" in inspect.signature(fill).parameters
+        except (TypeError, ValueError):
+            in_place = False
+
         def cb(user, t0, t1, k0, k1, out):
             try:
-                a = np.asarray(fill(int(t0), int(t1), int(k0), int(k1)), dtype=np.complex128)
                 n = (t1 - t0) * (k1 - k0)
                 dst = np.ctypeslib.as_array(out, shape=(2 * n,))
+                if in_place:    # the generator writes the library's staging buffer itself
+                    fill(int(t0), int(t1), int(k0), int(k1), out=dst.view(np.complex128).reshape(t1 - t0, k1 - k0))
+                    return 0
+                a = np.asarray(fill(int(t0), int(t1), int(k0), int(k1)), dtype=np.complex128)
                 dst[:] = a.reshape(-1).view(np.float64)
                 return 0
             except Exception as e:        # reported after the call returns

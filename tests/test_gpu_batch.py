@@ -6,6 +6,7 @@ import sys
 import numpy as np
 import pytest
 
+from oracle import basis as ob
 from oracle import mf as om
 from paper_2110_13115_amd import inputs as gi
 from paper_2110_13115_amd import rbmf
@@ -112,6 +113,61 @@ def test_batch_sparse_stage2(batch):
         np.testing.assert_allclose(eager[i]["snr"][idx >= 0], full[i]["snr"][idx[idx >= 0]], rtol=1e-4)
         missed.append(len(full[i]) - len(eager[i]))
     log("sparse batch ok", [len(x) for x in eager], "full-stage extras", missed)
+
+
+def test_batch_sparse_against_oracle(batch):
+    """The sparse second stage evaluates the exact SNR only at first-stage
+    crossings, so its result is defined by the oracle and the first stage:
+    the final triggers are the oracle's (|rho| >= thr2) at the samples where
+    the first-stage series reaches thr1.  These bases store C and Z in BF16,
+    so that decision is taken on the kernel's own BF16 reconstruction (read
+    back with rb_debug_rho), which is checked against the FP64 reduced-basis
+    SNR of the same bases to the BF16 bound of the precision test (3e-2 of
+    max(|rho|, 1)).  Checked on every item (graph replay) outside the +-1e-3
+    band of thr2 and a 1e-5 band of thr1 (the epilogue compares squares);
+    the stage-1 recall (oracle final triggers kept) is reported, and it is
+    below 1 here: the low fixed ranks leave reconstruction errors above
+    thr2 - thr1."""
+    ctx, setups, items, strains = batch
+    thr1, thr2, band = 5.0, 6.0, 1e-3
+    got, _ = rbmf.rb_filter_batch(ctx, items, thr1, thr2, use_graph=True, stage2=rbmf.RB_STAGE2_SPARSE)
+    kept = total = 0
+    for i, (_, sd, si) in enumerate(strains):
+        wl, bank_def, psd, bank, bases = setups[si]
+        s = sd.cpu().numpy()        # (an earlier test of the module refills the device strains)
+        H = bank_def.full()
+        st_ = om.strain_tilde(s.astype(np.float64), wl.fs)
+        rho = np.abs(om.snr_rows(st_, H, psd, wl.N, wl.fs, wl.f_low))
+        k_lo, _ = om.band_limits(wl.N, wl.fs, wl.f_low)
+        d = ob.whitened_data(s.astype(np.float64), psd, wl.fs, wl.f_low)
+        rb64 = np.zeros_like(rho)
+        rbg = np.zeros_like(rho)
+        for b in bases:
+            V, c, _ = b.export()
+            rb64[b.t0:b.t0 + b.T] = np.abs(ob.rb_snr(ob.basis_outputs(d, V, wl.N, k_lo), c))
+            rbg[b.t0:b.t0 + b.T] = np.abs(rbmf.debug_rho(ctx, bank, sd, b))
+        e = np.abs(rbg - rb64) / np.maximum(rb64, 1.0)
+        assert e.max() <= 3e-2, f"item {i}: BF16 first stage {e.max():.3e} from the FP64 reduced basis"
+        final = rho >= thr2
+        in_band2 = np.abs(rho - thr2) <= band * thr2
+        in_band1 = np.abs(rbg - thr1) <= 1e-5 * thr1
+        want = final & (rbg >= thr1)
+        G = np.zeros_like(final)
+        G[got[i]["tmpl"], got[i]["sample"]] = True
+        assert len(got[i]) == int(G.sum())
+        sure = ~in_band1 & ~in_band2
+        miss = want & ~G & sure
+        extra = G & ~want & sure
+        assert not miss.any(), (f"item {i}: {int(miss.sum())} oracle triggers at first-stage crossings missing, e.g. "
+                                f"{[(int(j), int(n), rho[j, n], rbg[j, n], rb64[j, n]) for j, n in np.argwhere(miss)[:4]]}")
+        assert not extra.any(), (f"item {i}: {int(extra.sum())} triggers the oracle does not define, e.g. "
+                                 f"{[(int(j), int(n), rho[j, n], rbg[j, n]) for j, n in np.argwhere(extra)[:4]]}")
+        ref = rho[got[i]["tmpl"], got[i]["sample"]]
+        assert np.abs(got[i]["snr"] - ref).max(initial=0) <= 1e-4 * ref.max(initial=1)
+        kept += int((G & final).sum())
+        total += int(final.sum())
+    log(f"sparse batch vs oracle: stage-1 recall {kept}/{total} of the oracle's final triggers")
+    assert total > 0
 
 
 @pytest.mark.parametrize("stage2", ["recon", "sparse"])
