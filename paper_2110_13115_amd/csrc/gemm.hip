@@ -627,6 +627,20 @@ __global__ __launch_bounds__(256) void k_recon_16(GemmArgs a) {
   if (stg.n > 0) stage_flush(a, stg, lane);
 }
 
+// LDS layout of the staged Z tile: one row per sample holding the 32-bit
+// (Re, Im) words of every plane and k (word p Kp + k), rows padded to a
+// multiple of 64 words plus 4, so the 16-byte fragment reads of sixteen
+// consecutive samples cover 64 distinct banks.  Word w of sample s is stored
+// at w ^ zs_swizzle(s), a swizzle constant over each 16 samples (the
+// fragment reads keep their banks) that separates the sixteen staging
+// threads writing one k for samples 8 apart: their row offsets alternate
+// between two bank halves and the swizzle spreads each half over eight bank
+// quads (measured: a third of the kernel's cycles were LDS bank-conflict
+// stalls without it).  A fragment's four words (w a multiple of 4) stay
+// together.
+__host__ __device__ __forceinline__ int zs_row_u16(int np, int kp) { return 2 * (((np * kp + 63) & ~63) + 4); }
+__device__ __forceinline__ int zs_swizzle(int s) { return ((s >> 4) & 7) << 2; }
+
 // 16-bit operands, Z tile staged in LDS.  One workgroup owns 32 CB samples and
 // loops over every 128-template tile of the (sub-)bank: the planar Z tile
 // (2Kp rows x 64 samples) is read from HBM once with 16-byte loads and stored
@@ -644,7 +658,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
   WaveStage stg{stage_mem[wave], 0};
   const int64_t q0 = (int64_t)blockIdx.x * TNS;
   const int Kp = a.Kp, KB = Kp / 8, R2 = 2 * Kp;
-  const int RS = NP * R2 + 8;       // LDS row stride (u16) of one sample: planes side by side
+  const int RS = zs_row_u16(NP, Kp);   // LDS row stride (u16) of one sample: planes side by side
   const int64_t N = a.N;
   const int64_t zplane = (int64_t)R2 * N;
   const uint16_t* __restrict__ z = static_cast<const uint16_t*>(a.z);
@@ -676,7 +690,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
           const int pk = idx / (TNS / 8), c8 = (idx % (TNS / 8)) * 8;
 #pragma unroll
           for (int e = 0; e < 8; ++e)
-            zs32[(c8 + e) * RS2 + pk] = (uint32_t)vr[c][e] | ((uint32_t)vi[c][e] << 16);
+            zs32[(c8 + e) * RS2 + (pk ^ zs_swizzle(c8))] = (uint32_t)vr[c][e] | ((uint32_t)vi[c][e] << 16);
         }
       }
     }
@@ -695,7 +709,10 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
   // stall on the loads just issued).
   constexpr int G = (CB == 4 || NP == 2) ? 1 : 2;   // (register budget at two waves per SIMD)
   const int ng = KB / G;
-  const uint16_t* zl = zs + (lane & 31) * RS + 8 * (lane >> 5);
+  const uint16_t* zl = zs + (lane & 31) * RS;
+  int zsw[CB];   // the swizzle of this lane's sample row in each 32-sample block
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) zsw[cb] = zs_swizzle(cb * 32 + (lane & 31));
   auto tile_rb0 = [&](int t) { return t * (TILE_T / 16) + wave * WT_ROWB; };
   u16x8 fa[3][G][NP][WT_ROWB];
   const u16x8* pa = nullptr;
@@ -715,7 +732,8 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
     for (int p = 0; p < NP; ++p)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
-        bv[p][cb] = *reinterpret_cast<const u16x8*>(zl + cb * 32 * RS + p * R2 + 16 * kb);
+        bv[p][cb] = *reinterpret_cast<const u16x8*>(
+            zl + cb * 32 * RS + 2 * ((p * Kp + 8 * kb + 4 * (lane >> 5)) ^ zsw[cb]));
 #pragma unroll
     for (int rb = 0; rb < WT_ROWB; ++rb)
 #pragma unroll
@@ -959,7 +977,7 @@ hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
   // variant 1 loads fragments directly
   const int np = a.dtype == 3 ? 2 : 1;
   const int tns = (a.variant == 2 && a.dtype != 3) ? 128 : 64;   // (the split-BF16 operands do not fit 128)
-  const size_t lds = (size_t)tns * (np * 2 * a.Kp + 8) * 2;   // dynamic part (the staging is static)
+  const size_t lds = (size_t)tns * zs_row_u16(np, a.Kp) * 2;   // dynamic part (the staging is static)
   if (a.variant != 1 && lds + kStageBytes <= kLdsMax) {
     static bool attr_set = false;
     if (!attr_set) {
