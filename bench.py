@@ -608,8 +608,8 @@ def main():
     ctx = rbmf.Context(0)
     bank_def, bank, psd, strain, inj, sigma_of = make_inputs(wl, rbmf, ctx, with_sigma=True)
     t0 = time.time()
-    bases = rbmf.subbank_bases(ctx, bank, wl.bounds(), rank=wl.sub_ranks(), tol=wl.tol,
-                               dtype=args.headline_dtype if args.headline_only else "f32")
+    head_dt = args.headline_dtype if args.headline_only else "f32"
+    bases = rbmf.subbank_bases(ctx, bank, wl.bounds(), rank=wl.sub_ranks(), tol=wl.tol, dtype=head_dt)
     prep_basis_s = time.time() - t0
     ranks = [b.K for b in bases]
     log(f"bases K={ranks} min energy={min(b.energy for b in bases):.6f} built in {prep_basis_s:.1f} s")
@@ -663,7 +663,7 @@ def main():
     gemm_ms = gemm_ms[args.warmup:]
     z_ms = z_ms[args.warmup:]
     rb_trig = out[:n_rb].cpu().numpy().view(rbmf.TRIGGER_NP).reshape(-1).copy()
-    log(f"rb_filter f32 (sparse stage 2): {t_rb * 1e3:.2f} ms/step, final {n_rb}, stage-1 {s1[-1]}, refiltered "
+    log(f"rb_filter {head_dt} (sparse stage 2): {t_rb * 1e3:.2f} ms/step, final {n_rb}, stage-1 {s1[-1]}, refiltered "
         f"{nref[-1]}, stage ms {[round(x, 3) for x in st_rb.ms[:7]]}")
 
     if args.headline_only:

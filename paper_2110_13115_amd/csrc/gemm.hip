@@ -523,13 +523,18 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32_3m(GemmArgs a) {
   if (gi + 3 < ng) mma(0);
   if (K & 1) {
     // k = K - 1 in lanes 0-31; lanes 32-63 (k = K, zero coefficients) read
-    // the same rows, which exist
-    const float* zk = static_cast<const float*>(a.z) + (int64_t)(2 * (K - 1)) * N + q0 + CB * (lane & 31);
-    mma3(ap[(int64_t)ng * 64], *reinterpret_cast<const float4*>(zk), *reinterpret_cast<const float4*>(zk + N));
+    // the same rows, which exist.  The pointers have advanced past the ng
+    // k-pairs (pa to the last packed pair, pz to rows 2 (K - 1) + 2 (lane / 32)),
+    // so no base pointer stays live across the loop.
+    const float* zk = pz - (int64_t)(2 * (lane >> 5)) * N;
+    mma3(*pa, *reinterpret_cast<const float4*>(zk), *reinterpret_cast<const float4*>(zk + N));
   }
   // epilogue: element i of a block is template row 8 (i / 4) + 4 (lane / 32) + i % 4;
   // crossings go through the wave's LDS stage
   __shared__ TrigRec stage_mem[WAVES][kStage];
+  // (the lane id again, from mbcnt: a value derived from it before the k-loop
+  // would be kept across the loop, which has no register to spare)
+  const int el = __lane_id();
   WaveStage stg{stage_mem[wave], 0};
   const int l1 = __builtin_ctz((unsigned)a.N1);
   // Re rho into p1, Im rho into p3 first: P2's registers are free before the
@@ -545,26 +550,26 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32_3m(GemmArgs a) {
   float th[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    const int j = tt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+    const int j = tt * 32 + 8 * (i >> 2) + 4 * (el >> 5) + (i & 3);
     th[i] = j < a.T ? a.thr2_row[j] : __builtin_inff();
   }
 #pragma unroll
   for (int c = 0; c < CB; ++c) {
-    const int q = (int)q0 + CB * (lane & 31) + c;
+    const int q = (int)q0 + CB * (el & 31) + c;
     const int n = (q >> l1) + a.N2 * (q & (a.N1 - 1));
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int j = tt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+      const int j = tt * 32 + 8 * (i >> 2) + 4 * (el >> 5) + (i & 3);
       const float re = p1[c][i];
       const float im = p3[c][i];
       if (a.rho_out != nullptr && j < a.T) {
         const float sc = a.row_inv ? a.row_inv[j] : 1.f;
         a.rho_out[(int64_t)j * a.N + n] = make_float2(re * sc, im * sc);
       }
-      stage_append(a, stg, lane, j < a.T && re * re + im * im >= th[i], j, n, re, im);
+      stage_append(a, stg, el, j < a.T && re * re + im * im >= th[i], j, n, re, im);
     }
   }
-  if (stg.n > 0) stage_flush(a, stg, lane);
+  if (stg.n > 0) stage_flush(a, stg, el);
 }
 
 // 16-bit operands: one instruction reduces over 16 realified entries = 8
@@ -709,10 +714,12 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
   // stall on the loads just issued).
   constexpr int G = (CB == 4 || NP == 2) ? 1 : 2;   // (register budget at two waves per SIMD)
   const int ng = KB / G;
-  const uint16_t* zl = zs + (lane & 31) * RS;
-  int zsw[CB];   // the swizzle of this lane's sample row in each 32-sample block
-#pragma unroll
-  for (int cb = 0; cb < CB; ++cb) zsw[cb] = zs_swizzle(cb * 32 + (lane & 31));
+  // Sample row s = 32 cb + (lane & 31) has swizzle 8 cb + 4 h, h = (lane & 31) / 16
+  // (disjoint bits), and the fragment's first word is 8 (p Kp / 8 + kb) + 4 (lane / 32):
+  // the swizzled word is 8 ((p Kp / 8 + kb) ^ cb) + 4 ((lane / 32) ^ h), so the lane's part
+  // goes into its base pointer and only an XOR with the unrolled cb remains per read.
+  const uint16_t* zl = zs + (lane & 31) * RS + 8 * ((lane >> 5) ^ ((lane & 31) >> 4));
+  const int K8 = Kp >> 3;
   auto tile_rb0 = [&](int t) { return t * (TILE_T / 16) + wave * WT_ROWB; };
   u16x8 fa[3][G][NP][WT_ROWB];
   const u16x8* pa = nullptr;
@@ -732,8 +739,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
     for (int p = 0; p < NP; ++p)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
-        bv[p][cb] = *reinterpret_cast<const u16x8*>(
-            zl + cb * 32 * RS + 2 * ((p * Kp + 8 * kb + 4 * (lane >> 5)) ^ zsw[cb]));
+        bv[p][cb] = *reinterpret_cast<const u16x8*>(zl + cb * 32 * RS + 16 * ((p * K8 + kb) ^ cb));
 #pragma unroll
     for (int rb = 0; rb < WT_ROWB; ++rb)
 #pragma unroll
