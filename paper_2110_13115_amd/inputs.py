@@ -382,7 +382,8 @@ class Workload:
     thr2: float = 6.0
     inj_snrs: Tuple[float, ...] = ()
     on_bank: bool = True
-    subbanks: int = 1              # equal tau0-ordered sub-banks, one basis each
+    subbanks: int = 1              # tau0-ordered sub-banks of about T / subbanks templates, one basis each
+    sub_align: int = 1             # inner sub-bank boundaries rounded to multiples of this
     ranks: Tuple[int, ...] = ()    # fixed rank per sub-bank (empty: by energy / `rank`)
     parent: int = 0                # > T: the bank is the central tau0 slice of a parent bank
     bin_w: int = 4                 # binned first stage: samples per bin
@@ -397,8 +398,14 @@ class Workload:
                            self.order, sort_tau0=self.subbanks > 1, parent=self.parent)
 
     def bounds(self) -> List[int]:
-        """Sub-bank template boundaries [0, ..., T]."""
-        return [int(round(i * self.T / self.subbanks)) for i in range(self.subbanks + 1)]
+        """Sub-bank template boundaries [0, ..., T]: the equal split, inner
+        boundaries rounded to the nearest multiple of sub_align (ties to the
+        even multiple), so that every sub-bank but the last fills whole
+        reconstruction tiles when sub_align is the tile height."""
+        a = self.sub_align
+        b = [a * int(round(i * self.T / self.subbanks / a)) for i in range(self.subbanks)] + [self.T]
+        assert all(x < y for x, y in zip(b, b[1:])), b
+        return b
 
     def sub_ranks(self) -> List[int]:
         return list(self.ranks) if self.ranks else [self.rank] * self.subbanks
@@ -409,11 +416,12 @@ WORKLOADS = {
     "full_mf_16s_64t": Workload("full_mf_16s_64t", 1, 32768, 2048.0, 30.0, 64, 5.0, 20.0, 0,
                                 thr1=5.0, thr2=6.0, inj_snrs=(10.0,)),
     # 2000 templates, 3.5PN, 256 s, f_low 20 Hz, 8 off-bank injections; split along tau0
-    # into 10 sub-banks of 200, each basis keeping >= 0.999 of its energy
+    # into 10 sub-banks of 192 to 224 templates (boundaries on multiples of the 32-template
+    # reconstruction tile), each basis keeping >= 0.999 of its energy
     "rb_256s_2000t": Workload("rb_256s_2000t", 2, 524288, 2048.0, 20.0, 2000, 1.0, 3.0, 7,
                               tol=1e-3, thr1=5.0, thr2=6.0,
                               inj_snrs=(5.0, 6.0, 7.0, 8.0, 9.0, 10.0, 11.0, 12.0), on_bank=False,
-                              subbanks=10),
+                              subbanks=10, sub_align=32),
     # 10000 templates, 0PN, 16 s, f_low 30 Hz, m in [1, 20]
     "rb_16s_10000t": Workload("rb_16s_10000t", 3, 32768, 2048.0, 30.0, 10000, 1.0, 20.0, 0,
                               tol=1e-3, thr1=5.0, thr2=6.0, inj_snrs=(10.0,)),
