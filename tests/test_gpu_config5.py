@@ -4,7 +4,8 @@
 the segment.
 
 On a seeded subset of 32 templates that have crossings (S restricted to
-them, seeds g uniform in [0.5, 2]):
+them, seeds g uniform in [0.5, 2]), split over four tests that share the
+module's fixtures (so that no single test runs for minutes):
   * rb_backward's loss, d|rho|^2/dC and d|rho|^2/d(strain) against the FP64
     oracle gradient (torch CPU autograd through direct sums at the trigger
     samples), 1e-4 relative to the largest entry;
@@ -61,7 +62,10 @@ def cfg5():
     bank.close()
 
 
-def test_backward_at_size_matches_oracle_and_fd(cfg5):
+@pytest.fixture(scope="module")
+def at_size(cfg5):
+    """The trigger set S on a seeded 32-template subset, rb_backward on it, and
+    the FP64 oracle's loss and gradients."""
     wl, psd, strain, ctx, bank, basis, sd, S_all = cfg5
     rng = gi.rng_for(wl.cfg, gi.PURPOSE_FD)
     have = np.unique(S_all["tmpl"])
@@ -81,34 +85,68 @@ def test_backward_at_size_matches_oracle_and_fd(cfg5):
     t = time.time()
     L, gC_ref, gs_ref = og.loss_and_grads(s64, C, V, w, k_lo, wl.fs, tmpl, samp, g64)
     log(f"oracle gradient in {time.time() - t:.1f} s; loss GPU {loss:.8g} oracle {L:.8g}")
-    assert abs(loss - L) <= 1e-4 * L
-    eC = np.abs(gC - gC_ref).max() / np.abs(gC_ref).max()
-    es = np.abs(gs - gs_ref).max() / np.abs(gs_ref).max()
+    # beta at the distinct trigger samples only (beta is a function of the sample)
+    uniq, inv = np.unique(samp, return_inverse=True)
+    beta_of = lambda v: og.beta_at(v, V, w, k_lo, wl.fs, uniq)[:, inv]
+    return dict(sub=sub, S=S, loss=loss, gC=gC, gs=gs, C=C, L=L, gC_ref=gC_ref, gs_ref=gs_ref, s64=s64,
+                tmpl=tmpl, g64=g64, beta_of=beta_of, T=basis.T, N=wl.N)
+
+
+def test_backward_at_size_matches_oracle(at_size):
+    r = at_size
+    assert abs(r["loss"] - r["L"]) <= 1e-4 * r["L"]
+    eC = np.abs(r["gC"] - r["gC_ref"]).max() / np.abs(r["gC_ref"]).max()
+    es = np.abs(r["gs"] - r["gs_ref"]).max() / np.abs(r["gs_ref"]).max()
     log(f"max |grad C - oracle| / max {eC:.2e}; max |grad s - oracle| / max {es:.2e}")
     assert eC <= 1e-4 and es <= 1e-4
-    assert np.all(gC[np.setdiff1d(np.arange(basis.T), sub)] == 0)
+    assert np.all(r["gC"][np.setdiff1d(np.arange(r["T"]), r["sub"])] == 0)
 
-    beta = og.beta_at(s64, V, w, k_lo, wl.fs, samp)
-    assert og.loss_from_beta(C, beta, tmpl, g64) == pytest.approx(L, rel=1e-10)
+
+@pytest.fixture(scope="module")
+def beta_s(at_size):
+    r = at_size
+    t = time.time()
+    beta = r["beta_of"](r["s64"])
+    log(f"beta at {beta.shape[1]} trigger samples in {time.time() - t:.1f} s")
+    assert og.loss_from_beta(r["C"], beta, r["tmpl"], r["g64"]) == pytest.approx(r["L"], rel=1e-10)
+    return beta
+
+
+def test_fd_coefficient_directions(at_size, beta_s):
+    """FP64 central differences along 8 seeded directions in C (all entries of
+    the 32 rows, step 1e-3) against both gradients."""
+    r = at_size
+    C, tmpl, g64, gC_ref, gC = r["C"], r["tmpl"], r["g64"], r["gC_ref"], r["gC"]
+    rng = np.random.default_rng([13115, 5, 71])
     eps = 1e-3
     for i in range(8):
         D = np.zeros_like(C)
-        D[sub] = rng.standard_normal((32, C.shape[1])) + 1j * rng.standard_normal((32, C.shape[1]))
-        fd = (og.loss_from_beta(C + eps * D, beta, tmpl, g64) - og.loss_from_beta(C - eps * D, beta, tmpl, g64)) / (2 * eps)
+        D[r["sub"]] = rng.standard_normal((32, C.shape[1])) + 1j * rng.standard_normal((32, C.shape[1]))
+        fd = (og.loss_from_beta(C + eps * D, beta_s, tmpl, g64) - og.loss_from_beta(C - eps * D, beta_s, tmpl, g64)) / (2 * eps)
         an_ref = float(np.sum(gC_ref.real * D.real + gC_ref.imag * D.imag))
         an = float(np.sum(gC.real.astype(np.float64) * D.real + gC.imag.astype(np.float64) * D.imag))
         scale = float(np.sum(np.abs(gC_ref) * np.abs(D)))
         log(f"C direction {i}: fd {fd:.8g} oracle {an_ref:.8g} GPU {an:.8g}")
         assert abs(fd - an_ref) <= 1e-9 * scale
         assert abs(fd - an) <= 1e-4 * scale
-    rms = np.sqrt(np.mean(s64 ** 2))
-    for i in range(8):
-        v = rms * rng.standard_normal(wl.N)
-        bv = og.beta_at(v, V, w, k_lo, wl.fs, samp)
+
+
+@pytest.mark.parametrize("half", [0, 1])
+def test_fd_strain_directions(at_size, beta_s, half):
+    """FP64 central differences along 8 seeded strain directions (step
+    1e-3 rms(s)), four per test: beta is linear in the strain, so each
+    direction needs one more evaluation of beta at the trigger samples."""
+    r = at_size
+    C, tmpl, g64, gs_ref, gs = r["C"], r["tmpl"], r["g64"], r["gs_ref"], r["gs"]
+    rng = np.random.default_rng([13115, 5, 72, half])
+    rms = np.sqrt(np.mean(r["s64"] ** 2))
+    for i in range(4):
+        v = rms * rng.standard_normal(r["N"])
+        bv = r["beta_of"](v)
         e = 1e-3
-        fd = (og.loss_from_beta(C, beta + e * bv, tmpl, g64) - og.loss_from_beta(C, beta - e * bv, tmpl, g64)) / (2 * e)
+        fd = (og.loss_from_beta(C, beta_s + e * bv, tmpl, g64) - og.loss_from_beta(C, beta_s - e * bv, tmpl, g64)) / (2 * e)
         an_ref, an = float(gs_ref @ v), float(gs.astype(np.float64) @ v)
         scale = float(np.abs(gs_ref) @ np.abs(v))
-        log(f"strain direction {i}: fd {fd:.8g} oracle {an_ref:.8g} GPU {an:.8g}")
+        log(f"strain direction {4 * half + i}: fd {fd:.8g} oracle {an_ref:.8g} GPU {an:.8g}")
         assert abs(fd - an_ref) <= 1e-9 * scale
         assert abs(fd - an) <= 1e-4 * scale
