@@ -140,6 +140,14 @@ typedef struct {
                               noise term stays below thr2 - thr1; FULL
                               needs only a crossing anywhere in the
                               template's series.                             */
+  double  gemm_mfma_flop;  /* rb_filter: floating-point operations its
+                              first-stage reconstruction GEMMs issued on the
+                              matrix cores (the time of ms[2]), padding rows
+                              and steps included: 6 K' T' N for the FP32
+                              three-product kernel (below the 8 K T N of a
+                              complex product), 8 K T' N for the realified
+                              FP32 kernels, 8 K' T' N (x 3 split-BF16) for
+                              the 16-bit ones.  0 from the other calls.      */
 } rb_stats;
 
 typedef struct {

@@ -172,6 +172,7 @@ struct rb_ctx_s {
   std::map<int64_t, int> fft_n2;   // autotuned four-step split per N (log2 N2)
   std::string arch;                // device architecture name (tuning cache key prefix)
   bool want_peaks = false;         // the current call returns per-template peaks (tmax is needed)
+  double mfma_flop = 0;            // matrix-core flop of the reconstruction GEMMs launched since reset
   // batch search: per-item summaries and outputs, captured graph
   DevBuf bsum, bout;
   hipStream_t gstream = nullptr;
@@ -1830,6 +1831,7 @@ rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq
   }
   ga.variant = basis->gemm_variant[ga.N];
   RB_HIP(launch_recon_gemm(ga, ctx->stream));
+  ctx->mfma_flop += recon_mfma_flop(ga);
   return RB_OK;
 }
 
@@ -1985,6 +1987,7 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
     if (tm) RB_TRY(event(ctx, e_end + 2 + (size_t)nbases));
   }
   for (;;) {
+    ctx->mfma_flop = 0;   // (the GEMMs of the last attempt, the one the stage times cover)
     RB_TRY(fill32(ctx, ctx->counters.p, 0u, 2));
     RB_TRY(fill32(ctx, ctx->cnt1.p, 0u, T));
     if (w > 1 && !fold) {
@@ -2109,6 +2112,7 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
     stats->n_stage1 = sum1[0];
     stats->n_refiltered = (int32_t)sum1[1];
     stats->n_bins = nbins;
+    stats->gemm_mfma_flop = ctx->mfma_flop;
     int kmax = 0;
     stats->min_energy = 1.0;
     for (int32_t m = 0; m < nbases; ++m) {

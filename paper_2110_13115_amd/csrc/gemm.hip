@@ -920,6 +920,18 @@ __global__ void k_pack_16(const float2* C, int T, int Tp, int K, int Kp, int dty
 
 int recon_variants(int dtype) { return dtype == 0 ? 7 : 3; }
 
+double recon_mfma_flop(const GemmArgs& a) {
+  const double N = (double)a.N;
+  auto up = [](int x, int m) { return (double)((x + m - 1) / m * m); };
+  if (a.dtype == 0 && a.variant == 6)   // three real products per k-pair over 32-template tiles
+    return 6.0 * up(a.T, 32) * up(a.K, 2) * N;
+  if (a.dtype == 0)                     // realified, 16-template blocks (a block of padding only is skipped)
+    return 8.0 * up(a.T, 16) * a.K * N;
+  // 16-bit: waves of 32 templates (skipped when all padding), k-steps of 8
+  // complex values; the split-BF16 form issues three products per step
+  return 8.0 * up(a.T, 32) * a.Kp * N * (a.dtype == 3 ? 3.0 : 1.0);
+}
+
 hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
   if (a.Tp % TILE_T != 0 || a.N % 128 != 0) return hipErrorInvalidValue;
   if (a.dtype == 0 && a.variant == 6) {   // three real products per k-pair (Gauss)

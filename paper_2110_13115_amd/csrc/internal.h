@@ -145,6 +145,9 @@ struct GemmArgs {
 };
 int recon_variants(int dtype);
 hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t stream);
+// Floating-point operations launch_recon_gemm(a) issues on the matrix cores,
+// padding rows and reduction steps included.
+double recon_mfma_flop(const GemmArgs& a);
 // FP32 C for the three-product kernel: [Tp/32][ceil(K/2)][64] float4.
 hipError_t launch_pack_c3(const float2* C, int T, int Tp, int K, void* cpk3, hipStream_t stream);
 // Packs C (T x K complex, FP32 interleaved, device) into the kernel's layout.

@@ -46,7 +46,8 @@ class Peak(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("n_stage1", C.c_int64), ("n_refiltered", C.c_int32), ("rank", C.c_int32),
-                ("ms", C.c_float * 8), ("n_bins", C.c_int64), ("min_energy", C.c_double)]
+                ("ms", C.c_float * 8), ("n_bins", C.c_int64), ("min_energy", C.c_double),
+                ("gemm_mfma_flop", C.c_double)]
 
 
 class FilterOpts(C.Structure):
