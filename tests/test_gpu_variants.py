@@ -43,6 +43,15 @@ def bases_for(ctx, bank, dtype, variant, monkeypatch):
             for a, b, r in zip(BOUNDS[:-1], BOUNDS[1:], (21, 7, 37))]   # rank 7: a k-loop too short to pipeline
 
 
+def issued_flop(dtype, variant, T, K, N):
+    up = lambda x, m: -(-x // m) * m
+    if dtype == "f32" and variant == 6:        # three real products per k-pair, 32-template tiles
+        return 6 * up(T, 32) * up(K, 2) * N
+    if dtype == "f32":                         # realified, 16-template blocks
+        return 8 * up(T, 16) * K * N
+    return 8 * up(T, 32) * up(K, 8) * N * (3 if dtype == "bf16x3" else 1)   # 32-template waves, 8-k steps
+
+
 def keyset(tr, lo):
     return {(int(a), int(b)) for a, b, s in zip(tr["tmpl"], tr["sample"], tr["snr"]) if s >= lo}
 
@@ -56,7 +65,10 @@ def test_every_variant(vcase, dtype, monkeypatch):
     for v in range(VARIANTS[dtype]):
         bs = bases_for(ctx, bank, dtype, v, monkeypatch)
         rho = np.concatenate([rbmf.debug_rho(ctx, bank, case.strain, b) for b in bs])
-        trig, _, _ = rbmf.rb_filter(ctx, bs, bank, case.strain, 5.0, 6.0, stage2=rbmf.RB_STAGE2_RECON)
+        trig, _, st = rbmf.rb_filter(ctx, bs, bank, case.strain, 5.0, 6.0, stage2=rbmf.RB_STAGE2_RECON)
+        # the matrix-core work the call reports: every sub-bank's GEMM at this
+        # variant's tiling (padding rows and reduction steps included)
+        assert st.gemm_mfma_flop == sum(issued_flop(dtype, v, b.T, b.K, case.N) for b in bs), v
         if dtype == "f32":
             # against the oracle's reduced-basis SNR with the exported bases
             ref = []
