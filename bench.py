@@ -720,7 +720,8 @@ def main():
             ok16 = n16 == n_mf and np.array_equal(tr16[["tmpl", "sample"]], mf_trig[["tmpl", "sample"]])
             gm = float(np.mean(g16[args.warmup:]))
             fl16 = sum(8.0 * b.K * b.T * wl.N for b in b16)
-            extra[f"rb_{dt}_sparse_stage2"] = {"value": seg / t16, "ms_per_step": t16 * 1e3, "final_triggers_equal_mf": bool(ok16),
+            extra[f"rb_{dt}_sparse_stage2"] = {"value": seg / t16, "ms_per_step": t16 * 1e3,
+                                 "rb_over_mf": t_mf / t16, "final_triggers_equal_mf": bool(ok16),
                                  "vs_oracle": oracle_agreement(tr16, ora, wl.thr2, wl.N),
                                  "gemm_ms": gm, "gemm_tflops": fl16 / (gm * 1e-3) / 1e12,
                                  "gemm_frac": fl16 / (gm * 1e-3) / 1e12 / PEAK[dt],
