@@ -704,15 +704,16 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
   const u16x8* __restrict__ cpk = static_cast<const u16x8*>(a.cpk);
   const int ntt = a.Tp / TILE_T;
   const int64_t cplane = (int64_t)ntt * (TILE_T / 16) * KB * 64;
-  // A fragments of G k-steps (a group) go into one of three register buffers
-  // two groups before their MFMAs; B fragments come from LDS just before use.
-  // The first two groups of the next template tile are loaded before the
-  // current tile's epilogue (after its threshold loads), so a short k-loop
-  // (small rank) does not start every tile with a full load latency.  A
-  // long k-loop runs a branch-free steady state, with the same two groups in
-  // flight on every path into it (otherwise the compiler's wait counts would
-  // stall on the loads just issued).
+  // A fragments of G k-steps (a group) go into a ring of D + 1 register
+  // buffers D groups before their MFMAs; B fragments come from LDS just
+  // before use.  The first D groups of the next template tile are loaded
+  // before the current tile's epilogue (after its threshold loads), so a
+  // short k-loop (small rank) does not start every tile with a full load
+  // latency.  A long k-loop runs a branch-free steady state, with the same D
+  // groups in flight on every path into it (otherwise the compiler's wait
+  // counts would stall on the loads just issued).
   constexpr int G = (CB == 4 || NP == 2) ? 1 : 2;   // (register budget at two waves per SIMD)
+  constexpr int D = 3;                              // groups in flight
   const int ng = KB / G;
   // Sample row s = 32 cb + (lane & 31) has swizzle 8 cb + 4 h, h = (lane & 31) / 16
   // (disjoint bits), and the fragment's first word is 8 (p Kp / 8 + kb) + 4 (lane / 32):
@@ -721,7 +722,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
   const uint16_t* zl = zs + (lane & 31) * RS + 8 * ((lane >> 5) ^ ((lane & 31) >> 4));
   const int K8 = Kp >> 3;
   auto tile_rb0 = [&](int t) { return t * (TILE_T / 16) + wave * WT_ROWB; };
-  u16x8 fa[3][G][NP][WT_ROWB];
+  u16x8 fa[D + 1][G][NP][WT_ROWB];
   const u16x8* pa = nullptr;
   auto load = [&](int s) {   // the group at pa, then advance pa
 #pragma unroll
@@ -731,6 +732,21 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
 #pragma unroll
         for (int rb = 0; rb < WT_ROWB; ++rb) fa[s][g][p][rb] = pa[p * cplane + ((int64_t)rb * KB + g) * 64];
     pa += G * 64;
+  };
+  // the first D groups of a tile (pa at its start): all of them on the steady
+  // path (ng >= 2 D + 1), the ones that exist otherwise
+  auto first_groups = [&](bool steady) {
+    if (steady) {
+#pragma unroll
+      for (int s = 0; s < D; ++s) {
+        load(s);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < D; ++s)
+        if (s < ng) load(s);
+    }
   };
   f32x16 acc[WT_ROWB][CB];
   auto step = [&](const u16x8 (&av)[NP][WT_ROWB], int kb) {
@@ -750,7 +766,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
 #pragma unroll
     for (int g = 0; g < G; ++g) step(fa[s][g], grp * G + g);
   };
-  // one template tile: the groups (the first two already loaded), the last
+  // one template tile: the groups (the first D already loaded), the last
   // KB mod G k-step, then the next tile's first groups and the epilogue
   auto tile = [&](int tt, bool steady) {
     const int rb0 = tile_rb0(tt);
@@ -761,29 +777,26 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
       for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = (f32x16){};
     int gi = 0;
     if (steady) {
+      // groups gi .. gi + D - 1 sit in buffers 0 .. D - 1; sub-step s loads
+      // group gi + s + D into buffer (s + D) mod (D + 1) and runs group gi + s
       do {
-        load(2);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(0, gi);
-        __builtin_amdgcn_sched_barrier(0);
-        load(0);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(1, gi + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        load(1);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(2, gi + 2);
-        __builtin_amdgcn_sched_barrier(0);
-        gi += 3;
-      } while (gi + 4 < ng);
+#pragma unroll
+        for (int s = 0; s <= D; ++s) {
+          load((s + D) % (D + 1));
+          __builtin_amdgcn_sched_barrier(0);
+          mma(s, gi + s);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        gi += D + 1;
+      } while (gi + 2 * D + 1 <= ng);
     }
-    // at most four groups remain (gi .. gi + 3), the first two already loaded
-    if (gi + 2 < ng) load(2);
-    if (gi < ng) mma(0, gi);
-    if (gi + 3 < ng) load(0);
-    if (gi + 1 < ng) mma(1, gi + 1);
-    if (gi + 2 < ng) mma(2, gi + 2);
-    if (gi + 3 < ng) mma(0, gi + 3);
+    // at most 2 D groups remain (gi .. gi + 2 D - 1), the first D already
+    // loaded; group gi + t is in buffer t mod (D + 1)
+#pragma unroll
+    for (int t = 0; t < 2 * D; ++t) {
+      if (t < D && gi + t + D < ng) load((t + D) % (D + 1));
+      if (gi + t < ng) mma(t % (D + 1), gi + t);
+    }
     if (KB % G) {
       u16x8 av[NP][WT_ROWB];
 #pragma unroll
@@ -797,31 +810,19 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
     const bool more = tt + 1 < ntt && tile_rb0(tt + 1) * 16 < a.T;
     if (more) {
       pa = cpk + (int64_t)tile_rb0(tt + 1) * KB * 64 + lane;
-      if (steady) {
-        load(0);
-        __builtin_amdgcn_sched_barrier(0);
-        load(1);
-        __builtin_amdgcn_sched_barrier(0);
-      } else {
-        if (ng > 0) load(0);
-        if (ng > 1) load(1);
-      }
+      first_groups(steady);
     }
     epilogue<WT_ROWB, CB>(a, acc, rb0, q0, stg, th);
     return more;
   };
   if (tile_rb0(0) * 16 < a.T) {
     pa = cpk + (int64_t)tile_rb0(0) * KB * 64 + lane;
-    if (ng >= 5) {
-      load(0);
-      __builtin_amdgcn_sched_barrier(0);
-      load(1);
-      __builtin_amdgcn_sched_barrier(0);
+    if (ng >= 2 * D + 1) {
+      first_groups(true);
       for (int tt = 0; tile(tt, true); ++tt) {
       }
     } else {
-      if (ng > 0) load(0);
-      if (ng > 1) load(1);
+      first_groups(false);
       for (int tt = 0; tile(tt, false); ++tt) {
       }
     }
