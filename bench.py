@@ -649,7 +649,7 @@ def main():
 
     # --- headline: rb_filter, FP32 (the workload's precision), exact second stage evaluated at the
     # first-stage crossings
-    gemm_ms, z_ms, s1, nref, issued = [], [], [], [], []
+    gemm_ms, z_ms, s1, nref, issued, s2_ms = [], [], [], [], [], []
 
     def rb_timed():
         n, _, st = rbmf.rb_filter(ctx, bases, bank, sd, wl.thr1, wl.thr2, stage2=rbmf.RB_STAGE2_SPARSE, out=out)
@@ -658,6 +658,7 @@ def main():
         z_ms.append(st.ms[1])
         s1.append(st.n_stage1)
         nref.append(st.n_refiltered)
+        s2_ms.append(st.ms[4])
         return n, st
 
     t_rb, (n_rb, st_rb) = time_calls(rb_timed, args.steps, args.warmup, torch)
@@ -788,6 +789,18 @@ def main():
                "per_step": f"sum over templates of 8 * support bins = {mfbytes:.4g} B (nothing written but "
                            f"triggers); the four-step intermediate adds 16*N B per template that is not counted",
                "avg_ms_per_step": mf_pass_ms}
+    # the sparse exact second stage reads each refiltered template's support once per group
+    # of at most 8 of its crossings (algorithmic: once per template)
+    s2m = float(np.mean(s2_ms[args.warmup:]))
+    sup = (kh - k_lo + 1).astype(np.float64)
+    s2bytes = float(np.mean(nref[args.warmup:])) * 8.0 * float(np.mean(sup))
+    roof_s2 = {"bound": "hbm", "achieved": s2bytes / (s2m * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": s2bytes / (s2m * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "kernel": "k_sparse_exact (direct frequency sums at the first-stage crossings)",
+               "per_step": f"refiltered templates x 8 * mean support bins = {s2bytes:.4g} B (every template of this "
+                           f"bank spans {int(sup.min())}-{int(sup.max())} bins); the data spectrum, read by every "
+                           f"workgroup from L2, is not counted",
+               "avg_ms_per_step": s2m}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, bank_def, psd, strain)
@@ -822,6 +835,7 @@ def main():
         "roofline": roof,
         "roofline_z_stage": roof_z,
         "roofline_mf_full": roof_mf,
+        "roofline_sparse_stage2": roof_s2,
         "cpu_baseline": cpu,
         **extra,
     }
