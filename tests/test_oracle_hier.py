@@ -201,3 +201,20 @@ def test_stream_triggers_report_every_sample_once():
     assert np.array_equal(t["snr"], strain)                 # shifted to the right sample
     with pytest.raises(ValueError):
         osm.segments(10, 64)
+
+
+def test_thresholds_are_inclusive():
+    """A bin whose |rho_avg| equals rho_I triggers, and a candidate whose
+    reconstructed SNR equals thr2 is a final trigger of the reconstruction
+    second stage (values chosen exact in binary)."""
+    rho_avg = np.array([[0.0, 4.0, 3.5, 4.0 + 2 ** -40, -4.0]], dtype=complex)
+    bins = oh.triggering_bins(rho_avg, 4.0)
+    assert list(bins["bin"]) == [1, 3, 4]
+    assert list(oh.triggering_bins(rho_avg, 4.0 + 2 ** -40)["bin"]) == [3]
+    cand = np.zeros(3, dtype=om.TRIGGER_DTYPE)
+    cand["tmpl"] = [0, 0, 1]
+    cand["sample"] = [3, 9, 4]
+    cand["snr"] = [6.0, 6.0 - 2 ** -40, 6.5]
+    fin = oh.second_stage(cand, 6.0, "recon")
+    assert list(zip(fin["tmpl"], fin["sample"])) == [(0, 3), (1, 4)]
+

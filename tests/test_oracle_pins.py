@@ -193,6 +193,12 @@ def test_trigger_set_and_peak_helpers():
     assert list(keep) == [False, True, True, True]
     keep = om.cluster_peaks(trig, W=30, N=100)          # circular: |90-12| -> 22
     assert list(keep) == [False, True, False, True]
+    # an exact tie inside the window goes to the lower sample, also across the wrap
+    trig["snr"] = [7.0, 7.0, 6.5, 5.0]
+    assert list(om.cluster_peaks(trig, W=4, N=100)) == [True, False, True, True]
+    trig["sample"] = [10, 12, 98, 5]
+    trig["snr"] = [6.0, 6.0, 6.0, 5.0]                   # 98 is 12 from 10 and 14 from 12 (circular)
+    assert list(om.cluster_peaks(trig, W=12, N=100)) == [True, False, False, True]
 
 
 # ----------------------------------------------------------------- basis
@@ -370,3 +376,21 @@ def test_refine_optimum_is_projection():
         best = max(best, abs(np.vdot(cc, Zn)) ** 2)
     assert best <= val * (1 + 1e-12)
     assert best >= 0.5 * val
+
+
+def test_nearest_neighbours_by_hand():
+    """Overlaps |<c_j, c_l>| written out for unit rows with known inner
+    products: the order is by decreasing overlap, ties to the lower index, j
+    itself left out."""
+    c = np.array([[1.0, 0.0],
+                  [0.6j, 0.8],          # |<c_0, c_1>| = 0.6
+                  [0.0, 1.0],           # 0
+                  [-0.6, 0.8j],         # 0.6
+                  [0.8, 0.6],           # 0.8
+                  [0.6, -0.8]])         # 0.6
+    order, ov = og.nearest_neighbours(c, 0)
+    assert list(order) == [4, 1, 3, 5, 2]
+    assert np.allclose(ov, [1.0, 0.6, 0.0, 0.6, 0.8, 0.6])
+    order, ov = og.nearest_neighbours(c, 2)             # c_2 = (0, 1): overlaps |c_l[1]|
+    assert list(order) == [1, 3, 5, 4, 0]
+    assert np.allclose(ov, [0.0, 0.8, 1.0, 0.8, 0.6, 0.8])
