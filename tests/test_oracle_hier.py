@@ -217,4 +217,12 @@ def test_thresholds_are_inclusive():
     cand["snr"] = [6.0, 6.0 - 2 ** -40, 6.5]
     fin = oh.second_stage(cand, 6.0, "recon")
     assert list(zip(fin["tmpl"], fin["sample"])) == [(0, 3), (1, 4)]
+    # the exact second stages on series with |rho| = thr2 exactly at some samples
+    series = {0: np.array([0, 0, 0, 6.0j, 0, 0, 0, 0, 0, 6.0 - 2 ** -40, 0]),
+              1: np.array([0, 0, 0, 0, -6.0, 0, 0, 0, 0, 0, 0])}
+    rho_exact = lambda j: series[j].astype(complex)
+    fin = oh.second_stage(cand, 6.0, "sparse", rho_exact)
+    assert list(zip(fin["tmpl"], fin["sample"])) == [(0, 3), (1, 4)]
+    fin = oh.second_stage(cand, 6.0, "full", rho_exact)
+    assert list(zip(fin["tmpl"], fin["sample"])) == [(0, 3), (1, 4)]
 

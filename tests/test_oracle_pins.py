@@ -123,6 +123,12 @@ def test_noise_free_injection_recovers_optimal_snr(snr, n0, phi0):
     assert abs(val - snr) <= 1e-10 * snr
     dphi = np.angle(rho[n0] * np.exp(1j * phi0))
     assert abs(dphi) < 1e-9
+    # the trigger record carries that phase and the optimal SNR
+    if snr >= 5.0:
+        t = om.triggers_of(2, rho, 0.999 * snr)
+        assert list(t["sample"]) == [n0]
+        assert abs(np.angle(np.exp(1j * (t["phase"][0] + phi0)))) < 1e-9
+        assert abs(t["snr"][0] - snr) <= 1e-10 * snr
     # A = 1 (no SNR scaling): |rho| equals the template's own sigma
     st = gi.add_injection(np.zeros(N // 2 + 1, complex), h, 1.0, n0, 0.0, N)
     s1 = gi.strain_from_tilde(st, N, fs)
