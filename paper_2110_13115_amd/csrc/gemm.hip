@@ -456,27 +456,34 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32_3m(GemmArgs a) {
   int tt;
   int64_t st;
   if (!xcd_tile(ntt, (int64_t)ntt * ncol, tt, st)) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t q0 = (st * WAVES + wave) * TN;
   if (q0 >= a.N) return;
   const int K = a.K;
   const int64_t N = a.N;
   const int KP = (K + 1) / 2;
-  const float4* __restrict__ ap = static_cast<const float4*>(a.cpk3) + (int64_t)tt * KP * 64 + lane;
-  // rows 2k (Re) and 2k + 1 (Im) of k = 2 kp + lane / 32
-  const float* zb = static_cast<const float*>(a.z) + (int64_t)(2 * (lane >> 5)) * N + q0 + CB * (lane & 31);
+  // Wave-uniform bases (scalar registers, advanced per k-pair) and 32-bit
+  // per-lane byte offsets: the loads take the scalar-base form and the
+  // k-loop holds no per-lane 64-bit addresses, which leaves the registers for
+  // a fourth operand buffer.  A: float4 lane of the packed pair; Z: rows
+  // 2k (Re) and 2k + 1 (Im) of k = 2 kp + lane / 32 (offsets < 2^32 bytes
+  // for N <= 2^26).
+  const char* pa = reinterpret_cast<const char*>(static_cast<const float4*>(a.cpk3) + (int64_t)tt * KP * 64);
+  const char* pz = reinterpret_cast<const char*>(static_cast<const float*>(a.z) + q0);
+  const uint32_t aoff = 16u * (uint32_t)lane;
+  const uint32_t zro = 4u * ((uint32_t)(2 * (lane >> 5)) * (uint32_t)N + (uint32_t)(CB * (lane & 31)));
+  const uint32_t zio = zro + 4u * (uint32_t)N;
   f32x16 p1[CB], p2[CB], p3[CB];
 #pragma unroll
   for (int c = 0; c < CB; ++c) p1[c] = p2[c] = p3[c] = (f32x16){};
-  const float4* pa = ap;
-  const float* pz = zb;
-  float4 fa[3], fr[3], fi[3];
+  constexpr int D = 3;                   // k-pairs in flight (a ring of D + 1 buffers)
+  float4 fa[D + 1], fr[D + 1], fi[D + 1];
   auto load = [&](int s) {
-    fa[s] = *pa;
-    fr[s] = *reinterpret_cast<const float4*>(pz);
-    fi[s] = *reinterpret_cast<const float4*>(pz + N);
-    pa += 64;
-    pz += 4 * N;
+    fa[s] = *reinterpret_cast<const float4*>(pa + aoff);
+    fr[s] = *reinterpret_cast<const float4*>(pz + zro);
+    fi[s] = *reinterpret_cast<const float4*>(pz + zio);
+    pa += 64 * 16;
+    pz += 4 * N * 4;
   };
   auto mma3 = [&](const float4& av, const float4& br4, const float4& bi4) {
     const float br[4] = {br4.x, br4.y, br4.z, br4.w};
@@ -491,43 +498,42 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32_3m(GemmArgs a) {
   auto mma = [&](int s) { mma3(fa[s], fr[s], fi[s]); };
   const int ng = K / 2;                 // whole k-pairs; an odd K's last k runs after them
   int gi = 0;
-  if (ng >= 5) {
-    load(0);
-    __builtin_amdgcn_sched_barrier(0);
-    load(1);
-    __builtin_amdgcn_sched_barrier(0);
+  if (ng >= 2 * D + 1) {
+    // steady state: k-pairs gi .. gi + D - 1 sit in buffers 0 .. D - 1;
+    // sub-step s loads k-pair gi + s + D into buffer (s + D) mod (D + 1)
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      load(s);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     do {
-      load(2);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(0);
-      __builtin_amdgcn_sched_barrier(0);
-      load(0);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(1);
-      __builtin_amdgcn_sched_barrier(0);
-      load(1);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(2);
-      __builtin_amdgcn_sched_barrier(0);
-      gi += 3;
-    } while (gi + 4 < ng);
+#pragma unroll
+      for (int s = 0; s <= D; ++s) {
+        load((s + D) % (D + 1));
+        __builtin_amdgcn_sched_barrier(0);
+        mma(s);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      gi += D + 1;
+    } while (gi + 2 * D + 1 <= ng);
   } else {
-    if (ng > 0) load(0);
-    if (ng > 1) load(1);
+#pragma unroll
+    for (int s = 0; s < D; ++s)
+      if (s < ng) load(s);
   }
-  if (gi + 2 < ng) load(2);
-  if (gi < ng) mma(0);
-  if (gi + 3 < ng) load(0);
-  if (gi + 1 < ng) mma(1);
-  if (gi + 2 < ng) mma(2);
-  if (gi + 3 < ng) mma(0);
+  // at most 2 D k-pairs remain, the first D loaded; pair gi + t is in buffer t mod (D + 1)
+#pragma unroll
+  for (int t = 0; t < 2 * D; ++t) {
+    if (t < D && gi + t + D < ng) load((t + D) % (D + 1));
+    if (gi + t < ng) mma(t % (D + 1));
+  }
   if (K & 1) {
     // k = K - 1 in lanes 0-31; lanes 32-63 (k = K, zero coefficients) read
-    // the same rows, which exist.  The pointers have advanced past the ng
-    // k-pairs (pa to the last packed pair, pz to rows 2 (K - 1) + 2 (lane / 32)),
-    // so no base pointer stays live across the loop.
-    const float* zk = pz - (int64_t)(2 * (lane >> 5)) * N;
-    mma3(*pa, *reinterpret_cast<const float4*>(zk), *reinterpret_cast<const float4*>(zk + N));
+    // the same rows, which exist.  The bases have advanced past the ng
+    // k-pairs (pa to the last packed pair, pz to row 2 (K - 1)).
+    const uint32_t zt = 4u * (uint32_t)(CB * (lane & 31));
+    mma3(*reinterpret_cast<const float4*>(pa + aoff), *reinterpret_cast<const float4*>(pz + zt),
+         *reinterpret_cast<const float4*>(pz + zt + 4 * N));
   }
   // epilogue: element i of a block is template row 8 (i / 4) + 4 (lane / 32) + i % 4;
   // crossings go through the wave's LDS stage
