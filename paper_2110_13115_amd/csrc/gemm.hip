@@ -559,20 +559,38 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32_3m(GemmArgs a) {
     const int j = tt * 32 + 8 * (i >> 2) + 4 * (el >> 5) + (i & 3);
     th[i] = j < a.T ? a.thr2_row[j] : __builtin_inff();
   }
+  if (a.rho_out != nullptr) {   // debug dump of the reconstructed series
 #pragma unroll
-  for (int c = 0; c < CB; ++c) {
-    const int q = (int)q0 + CB * (el & 31) + c;
-    const int n = (q >> l1) + a.N2 * (q & (a.N1 - 1));
+    for (int c = 0; c < CB; ++c) {
+      const int q = (int)q0 + CB * (el & 31) + c;
+      const int n = (q >> l1) + a.N2 * (q & (a.N1 - 1));
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int j = tt * 32 + 8 * (i >> 2) + 4 * (el >> 5) + (i & 3);
-      const float re = p1[c][i];
-      const float im = p3[c][i];
-      if (a.rho_out != nullptr && j < a.T) {
-        const float sc = a.row_inv ? a.row_inv[j] : 1.f;
-        a.rho_out[(int64_t)j * a.N + n] = make_float2(re * sc, im * sc);
+      for (int i = 0; i < 16; ++i) {
+        const int j = tt * 32 + 8 * (i >> 2) + 4 * (el >> 5) + (i & 3);
+        if (j < a.T) {
+          const float sc = a.row_inv ? a.row_inv[j] : 1.f;
+          a.rho_out[(int64_t)j * a.N + n] = make_float2(p1[c][i] * sc, p3[c][i] * sc);
+        }
       }
-      stage_append(a, stg, el, j < a.T && re * re + im * im >= th[i], j, n, re, im);
+    }
+  }
+  // one ballot per template-row step over the maximum of its CB columns (the
+  // common case: no crossing in the step), then the crossings of the step
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int j = tt * 32 + 8 * (i >> 2) + 4 * (el >> 5) + (i & 3);
+    float pw[CB], pmax = 0.f;   // (each |rho|^2 computed once: the test and the append agree)
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      pw[c] = p1[c][i] * p1[c][i] + p3[c][i] * p3[c][i];
+      pmax = fmaxf(pmax, pw[c]);
+    }
+    if (__ballot(j < a.T && pmax >= th[i]) == 0ull) continue;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int q = (int)q0 + CB * (el & 31) + c;
+      const int n = (q >> l1) + a.N2 * (q & (a.N1 - 1));
+      stage_append(a, stg, el, j < a.T && pw[c] >= th[i], j, n, p1[c][i], p3[c][i]);
     }
   }
   if (stg.n > 0) stage_flush(a, stg, el);
