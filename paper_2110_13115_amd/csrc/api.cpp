@@ -2315,7 +2315,6 @@ extern "C" rb_status mf_full_noalloc(rb_ctx ctx, rb_bank bank, const float* stra
                o_tmp = take((size_t)R * sizeof(TrigRec));
   RB_CHECK(off <= kNoallocScratchBytes && R * 3 * sizeof(TrigRec) >= (size_t(16) << 20), RB_ERR_ARG,
            "scratch layout does not fit");
-  (void)o_sum;
   char* base = static_cast<char*>(ctx->noalloc);
   int64_t* flag = reinterpret_cast<int64_t*>(base + o_flag);
   unsigned long long* counter = reinterpret_cast<unsigned long long*>(base + o_cnt);
