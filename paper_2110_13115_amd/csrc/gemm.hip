@@ -1022,19 +1022,31 @@ hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
   const int tns = (a.variant == 2 && a.dtype != 3) ? 128 : 64;   // (the split-BF16 operands do not fit 128)
   const size_t lds = (size_t)tns * zs_row_u16(np, a.Kp) * 2;   // dynamic part (the staging is static)
   if (a.variant != 1 && lds + kStageBytes <= kLdsMax) {
-    static bool attr_set = false;
-    if (!attr_set) {
-      const void* fns[] = {reinterpret_cast<const void*>(&k_recon_16_lds<1, 2>),
-                           reinterpret_cast<const void*>(&k_recon_16_lds<2, 2>),
-                           reinterpret_cast<const void*>(&k_recon_16_lds<3, 2>),
-                           reinterpret_cast<const void*>(&k_recon_16_lds<1, 4>),
-                           reinterpret_cast<const void*>(&k_recon_16_lds<2, 4>)};
-      for (const void* f : fns) {
-        const hipError_t e =
-            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsMax - kStageBytes));
-        if (e != hipSuccess) return e;
+    // the dynamic-LDS limit is raised once per device (calls on several
+    // devices, from several threads, each see their own device's flag)
+    static std::mutex attr_mu;
+    static uint64_t attr_set = 0;   // bit d: done on device d
+    int dev = 0;
+    {
+      const hipError_t e = hipGetDevice(&dev);
+      if (e != hipSuccess) return e;
+    }
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    {
+      std::lock_guard<std::mutex> lock(attr_mu);
+      if (!(attr_set >> dev & 1u)) {
+        const void* fns[] = {reinterpret_cast<const void*>(&k_recon_16_lds<1, 2>),
+                             reinterpret_cast<const void*>(&k_recon_16_lds<2, 2>),
+                             reinterpret_cast<const void*>(&k_recon_16_lds<3, 2>),
+                             reinterpret_cast<const void*>(&k_recon_16_lds<1, 4>),
+                             reinterpret_cast<const void*>(&k_recon_16_lds<2, 4>)};
+        for (const void* f : fns) {
+          const hipError_t e =
+              hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsMax - kStageBytes));
+          if (e != hipSuccess) return e;
+        }
+        attr_set |= uint64_t(1) << dev;
       }
-      attr_set = true;
     }
     const unsigned grid = (unsigned)(a.N / tns);
     if (tns == 128) {
