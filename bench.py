@@ -278,6 +278,57 @@ def nonuniform_runs(ctx, wl, bank_def, bank, sd, out, mf_trig, s1_uniform, prep_
     return res
 
 
+def stream_runs(ctx, wl, bank, bases, args, torch, nseg_unique=4):
+    """Overlap-save search (Sec. III.E: segments of N overlapping by N/2, each
+    reporting its central half) of a stream of nseg_unique * N samples with
+    the headline bank and bases: the strain is high-passed noise with four
+    injections (on templates of the same masses on the stream's grid), in HBM
+    before the timed calls.  Throughput counts unique stream seconds."""
+    from paper_2110_13115_amd import inputs as gi
+    from paper_2110_13115_amd import rbmf
+    n = nseg_unique * wl.N
+    t0 = time.time()
+    psd_n = gi.psd_on_grid(n, wl.fs)
+    f = np.arange(n // 2 + 1) * (wl.fs / n)
+    psd_hp = np.where(f >= wl.f_low, psd_n, 0.0)   # (cutting raw noise would leak its low-frequency power)
+    psd_hp[0] = 0.0
+    st = gi.coloured_noise_tilde(psd_hp, n, wl.fs, gi.rng_for(wl.cfg, gi.PURPOSE_NOISE, 7))
+    bank_n = gi.random_bank(wl.cfg, wl.T, n, wl.fs, wl.f_low, wl.mmin, wl.mmax, wl.order,
+                            sort_tau0=wl.subbanks > 1, parent=wl.parent)
+    sig_n = injection_sigma(psd_n, n, wl.fs, wl.f_low)
+    rng = np.random.default_rng([13115, wl.cfg, 77])
+    inj = []
+    for k in range(4):
+        j = int(rng.integers(0, wl.T))
+        n0 = int(rng.integers(wl.N // 4, n - wl.N // 4))
+        h = bank_n.fill(j, j + 1, 0, n // 2 + 1)[0]
+        snr = float(rng.uniform(8.0, 12.0))
+        st = gi.add_injection(st, h, snr / sig_n(h), n0, float(rng.uniform(0, 2 * np.pi)), n)
+        inj.append((j, n0, snr))
+    strain = gi.strain_from_tilde(st, n, wl.fs).astype(np.float32)
+    sd = torch.from_numpy(strain).cuda()
+    prep = time.time() - t0
+    res = {}
+
+    def call():
+        tr, stt = rbmf.rb_filter_stream(ctx, bases, bank, sd, wl.thr1, wl.thr2, stage2=rbmf.RB_STAGE2_SPARSE)
+        return tr, stt
+    t, (tr, stt) = time_calls(call, args.steps, args.warmup, torch)
+    hop = wl.N // 2
+    nseg = -(-(n - wl.N) // hop) + 1
+    found = sum(1 for j, n0, _ in inj if np.any((tr["tmpl"] == j) & (np.abs(tr["sample"] - n0) <= 2)))
+    res = {"stream_samples": n, "stream_seconds": n / wl.fs, "segments": int(nseg), "N": wl.N,
+           "ms_per_stream": t * 1e3, "value": wl.T * (n / wl.fs) / t, "unit": "template-s/s",
+           "ms_per_segment": t * 1e3 / nseg, "final_triggers": int(len(tr)),
+           "injections_found": f"{found}/{len(inj)}", "stage2": "sparse (exact SNR at the first-stage crossings)",
+           "prep_s": prep, "note": "each stream sample is searched twice (N/2 overlap), so the rate is about "
+                                   "(stream / N) / segments of the single-segment rate; the call returns its "
+                                   "triggers in host memory"}
+    log(f"stream of {n / wl.fs:.0f} s ({nseg} segments): {t * 1e3:.2f} ms, {res['value']:.3g} template-s/s, "
+        f"{len(tr)} triggers, injections found {found}/{len(inj)}")
+    return res
+
+
 def paper_regime(args, torch):
     """The paper's regime: one dense tau0 sub-bank (6250 templates of a
     200 000-template bank, K ~ 40 at 0.999 energy), 128 s: the template method,
@@ -565,6 +616,7 @@ def main():
     ap.add_argument("--mf-only", action="store_true",
                     help="time only the mf_full comparator (for profiler runs)")
     ap.add_argument("--no-binned", action="store_true", help="skip the binned first stage runs")
+    ap.add_argument("--no-stream", action="store_true", help="skip the overlap-save stream leg")
     ap.add_argument("--binned-only", action="store_true",
                     help="time only the binned search (RECON, FP32 and BF16) at --thr-bin (for profiler runs)")
     ap.add_argument("--thr-bin", type=float, default=4.0, help="rho_I of --binned-only")
@@ -743,6 +795,8 @@ def main():
     if not args.no_nonuniform:
         extra["nonuniform_basis"] = nonuniform_runs(ctx, wl, bank_def, bank, sd, out, mf_trig, s1[-1],
                                                     prep_basis_s, args, torch)
+    if not args.no_stream:
+        extra["stream"] = stream_runs(ctx, wl, bank, bases, args, torch)
     if not args.no_dense:
         extra["paper_regime"] = paper_regime(args, torch)
 
