@@ -87,6 +87,26 @@ def gemm_traffic():
     return float(m.group(1))
 
 
+def zstage_traffic(vectors):
+    """HBM bytes per headline step moved by the Z stage's two FFT passes, as
+    measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (copy-calibrated) and
+    recorded in profiles/; None when fft.hip has changed since or the bases
+    hold another number of vectors."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    prof = os.path.join(here, "profiles", "z_stage_traffic_rb_256s_2000t.md")
+    src = os.path.join(here, "paper_2110_13115_amd", "csrc", "fft.hip")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"zstage_bytes_per_step=([0-9.e+]+) vectors=(\d+) fft_hip_sha1=([0-9a-f]+)", text)
+    if not m or m.group(3) != sha or int(m.group(2)) != vectors:
+        return None
+    return float(m.group(1))
+
+
 def stored_oracle(name, strain):
     """The FP64 oracle's whole-bank list of samples with |rho| >= 5.99 for this
     workload (tests/golden/oracle_<name>.txt, written from oracle/ only), when
@@ -843,8 +863,13 @@ def main():
     nb = wl.N // 2 - k_lo
     zm = float(np.mean(z_ms))
     zbytes = sum(b.K for b in bases) * (8.0 * nb + 8.0 * wl.N)
+    ztraffic = zstage_traffic(sum(b.K for b in bases)) if wl.name == "rb_256s_2000t" else None
     roof_z = {"bound": "hbm", "achieved": zbytes / (zm * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": zbytes / (zm * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+              "frac": zbytes / (zm * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": ztraffic,
+              # measured bytes (algorithmic + the intermediate) over the same time: how close the
+              # passes run to the HBM peak in what they actually move
+              "traffic_frac": (ztraffic / (zm * 1e-3) / 1e9 / HBM_PEAK_GBS) if ztraffic else None,
+              "traffic_unit": "HBM bytes per step, both passes (profiles/z_stage_traffic_rb_256s_2000t.md)",
               "kernel": "k_pass1 (correlation prologue, column FFTs) + k_pass2 (row FFTs, planar FP32 Z)",
               "per_step": f"sum over the {sum(b.K for b in bases)} basis vectors of 8*nb (basis row read, nb = "
                           f"{nb}) + 8*N (FP32 Z row written) = {zbytes:.4g} B; the four-step intermediate "
