@@ -212,6 +212,7 @@ struct rb_basis_s {
   DevBuf P;                    // K x nbs complex64
   DevBuf cpk;                  // packed realified C
   DevBuf cpk3;                 // FP32: C packed for the three-product GEMM
+  DevBuf cpkc;                 // 16-bit: C packed for the compact-coefficient GEMM variants
   DevBuf C32;                  // T x K complex64 (conj(c)), unscaled, for the adjoint
   DevBuf row_inv;              // Tp floats 1/row_scale
   DevBuf row_scale_dev;        // Tp floats
@@ -1523,6 +1524,10 @@ rb_status finish_basis(rb_ctx ctx, rb_bank bank, int32_t t0, int64_t T, int K, c
   if (dtype == RB_F32) {
     RB_TRY(bs->cpk3.ensure((size_t)(bs->Tp / 32) * ((K + 1) / 2) * 64 * 16));
     RB_HIP(launch_pack_c3(bs->C32.as<float2>(), (int)T, bs->Tp, K, bs->cpk3.p, s));
+  } else {
+    RB_TRY(bs->cpkc.ensure((size_t)(bs->Tp / 32) * (bs->Kp / 8) * 64 * 8 * 2 * (dtype == RB_BF16X3 ? 2 : 1)));
+    RB_HIP(launch_pack_c16c(bs->C32.as<float2>(), (int)T, bs->Tp, K, bs->Kp, (int)dtype,
+                            dtype == RB_F16 ? bs->row_scale_dev.as<float>() : nullptr, bs->cpkc.p, s));
   }
   RB_HIP(hipStreamSynchronize(s));
   if (rank_out) *rank_out = K;
@@ -1769,6 +1774,7 @@ rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq
   ga.dtype = (int)basis->dtype;
   ga.cpk = basis->cpk.p;
   ga.cpk3 = basis->cpk3.p;
+  ga.cpkc = basis->cpkc.p;
   ga.z = ctx->z.p;
   ga.thr2_row = basis->thr_row.as<float>();
   ga.N1 = g.N1;
@@ -1786,7 +1792,7 @@ rb_status stage1_gemm(rb_ctx ctx, rb_basis basis, const FftGeom& g, float thr1sq
     // with infinite thresholds (no trigger is appended), keep the fastest
     const char* force = std::getenv("RBMF_GEMM_VARIANT");
     const char* at = std::getenv("RBMF_AUTOTUNE");
-    const std::string key = ctx->arch + "/gemm2/dt=" + std::to_string(ga.dtype) + "/K=" + std::to_string(ga.K) +
+    const std::string key = ctx->arch + "/gemm3/dt=" + std::to_string(ga.dtype) + "/K=" + std::to_string(ga.K) +
                             "/T=" + std::to_string(ga.T) + "/N=" + std::to_string(ga.N);
     int choice = 0, cached = -1;
     if (force) {

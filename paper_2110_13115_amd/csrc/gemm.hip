@@ -204,6 +204,71 @@ __device__ __forceinline__ void epilogue(const GemmArgs& a, const f32x16 (&acc)[
   }
 }
 
+// Compact 16-bit form (k_recon_16_lds with CX): acc[0][cb] / acc[1][cb] hold
+// Re / Im rho of 32 templates from j0 x 32 samples; element i of a lane is
+// template j0 + 8 (i / 4) + 4 (lane / 32) + i % 4, whose squared threshold
+// goes to th[i / 8][i % 8].
+__device__ __forceinline__ void epi_thresholds_c(const GemmArgs& a, int j0, float (&th)[2][8]) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) th[i >> 3][i & 7] = a.thr2_row[j0 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3)];
+}
+
+template <int CB>
+__device__ __forceinline__ void epilogue_c(const GemmArgs& a, const f32x16 (&acc)[2][CB], int j0, int64_t q0,
+                                           WaveStage& stg, const float (&th)[2][8]) {
+  const int lane = __lane_id();
+  const int l1 = __builtin_ctz((unsigned)a.N1);            // N1 is a power of two
+  if (a.rho_out != nullptr) {   // debug dump (thresholds are infinite then: nothing is appended)
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int q = (int)q0 + cb * 32 + (lane & 31);        // q < N < 2^31
+      const int n = (q >> l1) + a.N2 * (q & (a.N1 - 1));
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int j = j0 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        if (j < a.T) {
+          const float s = a.row_inv ? a.row_inv[j] : 1.f;
+          a.rho_out[(int64_t)j * a.N + n] = make_float2(acc[0][cb][i] * s, acc[1][cb][i] * s);
+        }
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    // one template per half-wave at this step (padded templates have C = 0)
+    const int j = j0 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+    const float thr = th[i >> 3][i & 7];
+    float pmax = 0.f;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const float re = acc[0][cb][i], im = acc[1][cb][i];
+      pmax = fmaxf(pmax, re * re + im * im);
+    }
+    if (__ballot(pmax >= thr) == 0ull) continue;   // the common case: no crossing in the step
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const float re = acc[0][cb][i], im = acc[1][cb][i];
+      const int q = (int)q0 + cb * 32 + (lane & 31);
+      stage_append(a, stg, lane, j < a.T && re * re + im * im >= thr, j, (q >> l1) + a.N2 * (q & (a.N1 - 1)), re,
+                   im);
+    }
+  }
+}
+
+// The Im-output operand of the compact form from its Re-output operand: each
+// 32-bit word (Re C, -Im C) (low, high half) becomes (Im C, Re C), a rotate by
+// 16 bits and a flip of the new low half's sign bit (exact for BF16 and FP16
+// alike, and for both planes of the split form: the lo plane of -x is -lo).
+__device__ __forceinline__ u16x8 im_operand(u16x8 v) {
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 w = __builtin_bit_cast(u32x4, v);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) w[e] = ((w[e] >> 16) | (w[e] << 16)) ^ 0x8000u;
+  return __builtin_bit_cast(u16x8, w);
+}
+
 // One 16-bit MFMA step; DT 1 = bf16, 2 = f16.
 template <int DT>
 __device__ __forceinline__ f32x16 mfma16(u16x8 a, u16x8 b, f32x16 c) {
@@ -676,7 +741,16 @@ __device__ __forceinline__ int zs_swizzle(int s) { return ((s >> 4) & 7) << 2; }
 // transposed (sample-major, reduction index contiguous, rows padded by 16 B)
 // so each lane's B fragment is a single 16-byte LDS read; the packed C tiles
 // come from L2.
-template <int DT, int CB>
+//
+// CX (compact coefficients): an A fragment holds 32 templates instead of 16
+// realified pairs, lane l carrying template l % 32 and the words
+// (Re C_jk, -Im C_jk) of its four complex k (the k_pack_16c layout).  That
+// fragment gives Re rho directly; the operand for Im rho, words
+// (Im C_jk, Re C_jk), is formed in registers (im_operand), so each wave
+// loads one coefficient fragment per k-step for its 32 templates where the
+// realified form loads two.  The accumulators then pair up as acc[0][cb] =
+// Re rho and acc[1][cb] = Im rho of the same 32 templates x 32 samples.
+template <int DT, int CB, bool CX>
 __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
   constexpr int TNS = CB * 32;          // samples per workgroup
   constexpr int NP = DT == 3 ? 2 : 1;   // operand planes (hi, lo)
@@ -725,9 +799,11 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
     }
   }
   __syncthreads();
-  const u16x8* __restrict__ cpk = static_cast<const u16x8*>(a.cpk);
+  // RU templates per A fragment, RBN fragments per wave and k-step
+  constexpr int RU = CX ? 32 : 16, RBN = CX ? 1 : WT_ROWB;
+  const u16x8* __restrict__ cpk = static_cast<const u16x8*>(CX ? a.cpkc : a.cpk);
   const int ntt = a.Tp / TILE_T;
-  const int64_t cplane = (int64_t)ntt * (TILE_T / 16) * KB * 64;
+  const int64_t cplane = (int64_t)ntt * (TILE_T / RU) * KB * 64;
   // A fragments of G k-steps (a group) go into a ring of D + 1 register
   // buffers D groups before their MFMAs; B fragments come from LDS just
   // before use.  The first D groups of the next template tile are loaded
@@ -736,7 +812,8 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
   // latency.  A long k-loop runs a branch-free steady state, with the same D
   // groups in flight on every path into it (otherwise the compiler's wait
   // counts would stall on the loads just issued).
-  constexpr int G = (CB == 4 || NP == 2) ? 1 : 2;   // (register budget at two waves per SIMD)
+  // (register budget at two waves per SIMD; the compact form's A ring is half as large)
+  constexpr int G = (CB == 4 || NP == 2) ? 1 : 2;
   constexpr int D = 3;                              // groups in flight
   const int ng = KB / G;
   // Sample row s = 32 cb + (lane & 31) has swizzle 8 cb + 4 h, h = (lane & 31) / 16
@@ -745,8 +822,8 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
   // goes into its base pointer and only an XOR with the unrolled cb remains per read.
   const uint16_t* zl = zs + (lane & 31) * RS + 8 * ((lane >> 5) ^ ((lane & 31) >> 4));
   const int K8 = Kp >> 3;
-  auto tile_rb0 = [&](int t) { return t * (TILE_T / 16) + wave * WT_ROWB; };
-  u16x8 fa[D + 1][G][NP][WT_ROWB];
+  auto tile_rb0 = [&](int t) { return t * (TILE_T / RU) + wave * RBN; };   // in units of RU templates
+  u16x8 fa[D + 1][G][NP][RBN];
   const u16x8* pa = nullptr;
   auto load = [&](int s) {   // the group at pa, then advance pa
 #pragma unroll
@@ -754,7 +831,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
 #pragma unroll
       for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int rb = 0; rb < WT_ROWB; ++rb) fa[s][g][p][rb] = pa[p * cplane + ((int64_t)rb * KB + g) * 64];
+        for (int rb = 0; rb < RBN; ++rb) fa[s][g][p][rb] = pa[p * cplane + ((int64_t)rb * KB + g) * 64];
     pa += G * 64;
   };
   // the first D groups of a tile (pa at its start): all of them on the steady
@@ -773,18 +850,32 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
     }
   };
   f32x16 acc[WT_ROWB][CB];
-  auto step = [&](const u16x8 (&av)[NP][WT_ROWB], int kb) {
-    u16x8 bv[NP][CB];
+  auto read_b = [&](int kb, u16x8 (&bv)[NP][CB]) {
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
         bv[p][cb] = *reinterpret_cast<const u16x8*>(zl + cb * 32 * RS + 16 * ((p * K8 + kb) ^ cb));
+  };
+  auto step = [&](const u16x8 (&av)[NP][RBN], int kb) {
+    u16x8 bv[NP][CB];
+    read_b(kb, bv);
+    if constexpr (CX) {
+      u16x8 ai[NP];
 #pragma unroll
-    for (int rb = 0; rb < WT_ROWB; ++rb)
+      for (int p = 0; p < NP; ++p) ai[p] = im_operand(av[p][0]);
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb)
-        acc[rb][cb] = kstep<DT>(av[0][rb], av[NP - 1][rb], bv[0][cb], bv[NP - 1][cb], acc[rb][cb]);
+      for (int cb = 0; cb < CB; ++cb) {
+        acc[0][cb] = kstep<DT>(av[0][0], av[NP - 1][0], bv[0][cb], bv[NP - 1][cb], acc[0][cb]);
+        acc[1][cb] = kstep<DT>(ai[0], ai[NP - 1], bv[0][cb], bv[NP - 1][cb], acc[1][cb]);
+      }
+    } else {
+#pragma unroll
+      for (int rb = 0; rb < WT_ROWB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+          acc[rb][cb] = kstep<DT>(av[0][rb], av[NP - 1][rb], bv[0][cb], bv[NP - 1][cb], acc[rb][cb]);
+    }
   };
   auto mma = [&](int s, int grp) {
 #pragma unroll
@@ -822,24 +913,30 @@ __global__ __launch_bounds__(256, 2) void k_recon_16_lds(GemmArgs a) {
       if (gi + t < ng) mma(t % (D + 1), gi + t);
     }
     if (KB % G) {
-      u16x8 av[NP][WT_ROWB];
+      u16x8 av[NP][RBN];
 #pragma unroll
       for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int rb = 0; rb < WT_ROWB; ++rb) av[p][rb] = ap[p * cplane + ((int64_t)rb * KB + KB - 1) * 64];
+        for (int rb = 0; rb < RBN; ++rb) av[p][rb] = ap[p * cplane + ((int64_t)rb * KB + KB - 1) * 64];
       step(av, KB - 1);
     }
     float th[WT_ROWB][8];
-    epi_thresholds<WT_ROWB>(a, rb0, th);
-    const bool more = tt + 1 < ntt && tile_rb0(tt + 1) * 16 < a.T;
+    if constexpr (CX)
+      epi_thresholds_c(a, rb0 * 32, th);
+    else
+      epi_thresholds<WT_ROWB>(a, rb0, th);
+    const bool more = tt + 1 < ntt && tile_rb0(tt + 1) * RU < a.T;
     if (more) {
       pa = cpk + (int64_t)tile_rb0(tt + 1) * KB * 64 + lane;
       first_groups(steady);
     }
-    epilogue<WT_ROWB, CB>(a, acc, rb0, q0, stg, th);
+    if constexpr (CX)
+      epilogue_c<CB>(a, acc, rb0 * 32, q0, stg, th);
+    else
+      epilogue<WT_ROWB, CB>(a, acc, rb0, q0, stg, th);
     return more;
   };
-  if (tile_rb0(0) * 16 < a.T) {
+  if (tile_rb0(0) * RU < a.T) {
     pa = cpk + (int64_t)tile_rb0(0) * KB * 64 + lane;
     if (ng >= 2 * D + 1) {
       first_groups(true);
@@ -941,9 +1038,40 @@ __global__ void k_pack_16(const float2* C, int T, int Tp, int K, int Kp, int dty
   }
 }
 
+// C for the compact 16-bit form: [32-template block][k-step][lane][8] per
+// plane, lane l holding template 32 block + l % 32 and, for e = 0..7, entry
+// Re C (e even) or -Im C (e odd) of complex k = 8 kb + 4 (l / 32) + e / 2
+// (row-scaled for FP16; zero past T or K); the split form's lo plane follows.
+__global__ void k_pack_16c(const float2* C, int T, int Tp, int K, int Kp, int dtype, const float* row_scale,
+                           uint16_t* out) {
+  const int KB = Kp / 8;
+  const int64_t total = (int64_t)(Tp / 32) * KB * 64 * 8;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(i & 7);
+    const int l = (int)((i >> 3) & 63);
+    const int64_t bkb = i >> 9;
+    const int kb = (int)(bkb % KB);
+    const int blk = (int)(bkb / KB);
+    const int j = blk * 32 + (l & 31), k = kb * 8 + 4 * (l >> 5) + (e >> 1);
+    float x = 0.f;
+    if (j < T && k < K) {
+      float2 c = C[(int64_t)j * K + k];
+      if (row_scale) {
+        c.x *= row_scale[j];
+        c.y *= row_scale[j];
+      }
+      x = (e & 1) ? -c.y : c.x;
+    }
+    const uint16_t h = to16(x, dtype);
+    out[i] = h;
+    if (dtype == 3) out[total + i] = bf16_rne(x - __uint_as_float((uint32_t)h << 16));   // lo plane
+  }
+}
+
 }  // namespace
 
-int recon_variants(int dtype) { return dtype == 0 ? 7 : 3; }
+int recon_variants(int dtype) { return dtype == 0 ? 7 : 5; }
 
 double recon_mfma_flop(const GemmArgs& a) {
   const double N = (double)a.N;
@@ -1017,9 +1145,14 @@ hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
     return hipGetLastError();
   }
   // 16-bit: variant 0 / 2 stage a 64 / 128-sample Z tile in LDS (when it fits),
-  // variant 1 loads fragments directly
+  // variant 1 loads fragments directly; variants 3 / 4 are 0 / 2 with compact
+  // coefficients (a.cpkc)
   const int np = a.dtype == 3 ? 2 : 1;
-  const int tns = (a.variant == 2 && a.dtype != 3) ? 128 : 64;   // (the split-BF16 operands do not fit 128)
+  const bool cx = a.variant >= 3;
+  if (cx && a.cpkc == nullptr) return hipErrorInvalidValue;
+  int tns = (a.variant == 2 && a.dtype != 3) ? 128 : 64;   // (the split-BF16 operands do not fit 128)
+  // (the compact split-BF16 kernel at 128 samples would spill)
+  if (a.variant == 4 && a.dtype != 3 && (size_t)128 * zs_row_u16(np, a.Kp) * 2 + kStageBytes <= kLdsMax) tns = 128;
   const size_t lds = (size_t)tns * zs_row_u16(np, a.Kp) * 2;   // dynamic part (the staging is static)
   if (a.variant != 1 && lds + kStageBytes <= kLdsMax) {
     // the dynamic-LDS limit is raised once per device (calls on several
@@ -1035,11 +1168,16 @@ hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
     {
       std::lock_guard<std::mutex> lock(attr_mu);
       if (!(attr_set >> dev & 1u)) {
-        const void* fns[] = {reinterpret_cast<const void*>(&k_recon_16_lds<1, 2>),
-                             reinterpret_cast<const void*>(&k_recon_16_lds<2, 2>),
-                             reinterpret_cast<const void*>(&k_recon_16_lds<3, 2>),
-                             reinterpret_cast<const void*>(&k_recon_16_lds<1, 4>),
-                             reinterpret_cast<const void*>(&k_recon_16_lds<2, 4>)};
+        const void* fns[] = {reinterpret_cast<const void*>(&k_recon_16_lds<1, 2, false>),
+                             reinterpret_cast<const void*>(&k_recon_16_lds<2, 2, false>),
+                             reinterpret_cast<const void*>(&k_recon_16_lds<3, 2, false>),
+                             reinterpret_cast<const void*>(&k_recon_16_lds<1, 4, false>),
+                             reinterpret_cast<const void*>(&k_recon_16_lds<2, 4, false>),
+                             reinterpret_cast<const void*>(&k_recon_16_lds<1, 2, true>),
+                             reinterpret_cast<const void*>(&k_recon_16_lds<2, 2, true>),
+                             reinterpret_cast<const void*>(&k_recon_16_lds<3, 2, true>),
+                             reinterpret_cast<const void*>(&k_recon_16_lds<1, 4, true>),
+                             reinterpret_cast<const void*>(&k_recon_16_lds<2, 4, true>)};
         for (const void* f : fns) {
           const hipError_t e =
               hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsMax - kStageBytes));
@@ -1049,19 +1187,35 @@ hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t st) {
       }
     }
     const unsigned grid = (unsigned)(a.N / tns);
-    if (tns == 128) {
+#define RB_LAUNCH16(DT, CB, CX_) hipLaunchKernelGGL((k_recon_16_lds<DT, CB, CX_>), dim3(grid), dim3(256), lds, st, a)
+    if (cx) {
+      if (tns == 128) {
+        if (a.dtype == 1)
+          RB_LAUNCH16(1, 4, true);
+        else
+          RB_LAUNCH16(2, 4, true);
+      } else {
+        if (a.dtype == 1)
+          RB_LAUNCH16(1, 2, true);
+        else if (a.dtype == 2)
+          RB_LAUNCH16(2, 2, true);
+        else
+          RB_LAUNCH16(3, 2, true);
+      }
+    } else if (tns == 128) {
       if (a.dtype == 1)
-        hipLaunchKernelGGL((k_recon_16_lds<1, 4>), dim3(grid), dim3(256), lds, st, a);
+        RB_LAUNCH16(1, 4, false);
       else
-        hipLaunchKernelGGL((k_recon_16_lds<2, 4>), dim3(grid), dim3(256), lds, st, a);
+        RB_LAUNCH16(2, 4, false);
     } else {
       if (a.dtype == 1)
-        hipLaunchKernelGGL((k_recon_16_lds<1, 2>), dim3(grid), dim3(256), lds, st, a);
+        RB_LAUNCH16(1, 2, false);
       else if (a.dtype == 2)
-        hipLaunchKernelGGL((k_recon_16_lds<2, 2>), dim3(grid), dim3(256), lds, st, a);
+        RB_LAUNCH16(2, 2, false);
       else
-        hipLaunchKernelGGL((k_recon_16_lds<3, 2>), dim3(grid), dim3(256), lds, st, a);
+        RB_LAUNCH16(3, 2, false);
     }
+#undef RB_LAUNCH16
     return hipGetLastError();
   }
   const int64_t nwg = (int64_t)(a.Tp / TILE_T) * (a.N / TILE_N);
@@ -1082,6 +1236,14 @@ hipError_t launch_pack_c(const float2* C, int T, int Tp, int K, int Kp, int dtyp
   else
     hipLaunchKernelGGL(k_pack_16, dim3(1024), dim3(256), 0, st, C, T, Tp, K, Kp, dtype, row_scale,
                        static_cast<uint16_t*>(cpk));
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_c16c(const float2* C, int T, int Tp, int K, int Kp, int dtype, const float* row_scale,
+                            void* cpkc, hipStream_t st) {
+  if (dtype < 1 || dtype > 3 || Tp % 32 != 0 || Kp % 8 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pack_16c, dim3(1024), dim3(256), 0, st, C, T, Tp, K, Kp, dtype, row_scale,
+                     static_cast<uint16_t*>(cpkc));
   return hipGetLastError();
 }
 

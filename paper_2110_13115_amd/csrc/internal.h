@@ -131,6 +131,7 @@ struct GemmArgs {
   int dtype;                 // 0 f32, 1 bf16, 2 f16
   const void* cpk;           // packed realified coefficients
   const void* cpk3;          // FP32: C packed for the three-product kernel (Cr, Ci, Cr + Ci), or NULL
+  const void* cpkc;          // 16-bit: C packed for the compact-coefficient variants, or NULL
   const void* z;             // planar Z [2Kp][N]
   const float* thr2_row;     // per-template squared threshold (16-bit scales folded in)
   int N1, N2;                // position q -> n = q / N1 + N2 * (q % N1)
@@ -150,6 +151,10 @@ hipError_t launch_recon_gemm(const GemmArgs& a, hipStream_t stream);
 double recon_mfma_flop(const GemmArgs& a);
 // FP32 C for the three-product kernel: [Tp/32][ceil(K/2)][64] float4.
 hipError_t launch_pack_c3(const float2* C, int T, int Tp, int K, void* cpk3, hipStream_t stream);
+// 16-bit C for the compact-coefficient variants: [Tp/32][Kp/8][64][8] u16 per
+// plane (two planes for the split form).
+hipError_t launch_pack_c16c(const float2* C, int T, int Tp, int K, int Kp, int dtype, const float* row_scale,
+                            void* cpkc, hipStream_t stream);
 // Packs C (T x K complex, FP32 interleaved, device) into the kernel's layout.
 hipError_t launch_pack_c(const float2* C, int T, int Tp, int K, int Kp, int dtype,
                          const float* row_scale, void* cpk, hipStream_t stream);

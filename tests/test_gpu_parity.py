@@ -306,7 +306,7 @@ def test_tune_cache_file(ctx, rb_case, tmp_path, monkeypatch):
     rbmf.rb_filter(ctx, basis, bank, case.strain, 5.0, 6.0)
     basis.close()
     table = json.loads(path.read_text())
-    key = f"/gemm2/dt=0/K=7/T={case.T}/N={case.N}"
+    key = f"/gemm3/dt=0/K=7/T={case.T}/N={case.N}"
     hits = [k for k in table if k.endswith(key)]
     assert len(hits) == 1 and 0 <= table[hits[0]] < 7     # one of the seven FP32 variants
     assert all(isinstance(v, int) for v in table.values())
