@@ -164,7 +164,10 @@ struct rb_ctx_s {
       adjOrd, adjSeg, trig1, trig2, recs, tmp, final_out, cnt1, cnt2, off1, off2, fill1, fill2,
       list1, list2, tmax, summary, counters, thr_row, peaks, flag, rho_tmp, zws, listH, listL, nsplit,
       zfine, zpart, trigB, cntB, snap, tinv, gfold, offB, fillB, listB, recsB, sstrain, segout, wout, wcount, goffB,
-      refOv, refQ, refC, refN, refP;
+      refOv, refQ, refC, refN, refP, hscale;
+  // dspec is rewritten by each spectrum (dspec_gen counts them); the FP16
+  // intermediate's scale in hscale belongs to spectrum hscale_gen
+  uint64_t dspec_gen = 0, hscale_gen = ~uint64_t(0);
   int64_t gfold_N = 0;             // grid and bin width of the table in gfold
   int gfold_w = 0;
   hipEvent_t ev[8] = {};
@@ -434,6 +437,7 @@ rb_status geom_for(rb_ctx ctx, rb_bank bank, FftGeom* out) {
       RB_TRY(ctx->dspec.ensure((size_t)bank->nbs * 8));
       RB_TRY(ctx->z32.ensure((size_t)2 * B * N * 4));
       RB_TRY(fill32(ctx, ctx->dspec.p, 0u, bank->nbs * 2));
+      ctx->dspec_gen++;
       hipEvent_t e0, e1;
       RB_HIP(hipEventCreate(&e0));
       RB_HIP(hipEventCreate(&e1));
@@ -532,6 +536,7 @@ rb_status step_spectrum(rb_ctx ctx, rb_bank bank, const FftGeom& g, const FftTab
   RB_TRY(get_tables(ctx, g, tw32, &tw64));
   RB_TRY(ctx->work64.ensure((size_t)g.N * 16));
   RB_TRY(ctx->dspec.ensure((size_t)bank->nbs * 8));
+  ctx->dspec_gen++;
   return spectrum_into(ctx, bank, g, tw, tw64, s, ctx->work64.as<double2>(), ctx->dspec.as<float2>());
 }
 
@@ -556,7 +561,12 @@ rb_status pass_pairs(rb_ctx ctx, PassArgs a, int64_t nvec, InKind in, OutKind ou
 }
 
 // a2 + a3: Z = IFFT(d conj(P_k)) for all basis vectors, planar storage
-// (the basis's storage type, or FP32 into ctx->z32 when force_f32)
+// (the basis's storage type, or FP32 into ctx->z32 when force_f32).  For
+// BF16 / FP16 storage the four-step intermediate between the passes is kept
+// as FP16 pairs scaled by a power of two chosen from max |d| (no overflow for
+// unit-norm vectors; relative rounding 2^-11 per element, below the 16-bit
+// storage rounding of Z itself), half the intermediate's HBM traffic; the
+// split-BF16 form, whose Z carries FP32-level accuracy, keeps it in FP32.
 rb_status step_basis_outputs(rb_ctx ctx, rb_basis basis, const FftGeom& g, const FftTables& tw,
                              bool force_f32 = false) {
   rb_bank bank = basis->bank;
@@ -579,6 +589,16 @@ rb_status step_basis_outputs(rb_ctx ctx, rb_basis basis, const FftGeom& g, const
   a.zout = zb.as<float>();
   a.zdtype = (int)dt;
   a.zplane = (int64_t)2 * Kp * g.N;
+  if (dt == RB_BF16 || dt == RB_F16) {
+    if (ctx->hscale_gen != ctx->dspec_gen) {
+      RB_TRY(ctx->hscale.ensure((size_t)(2 + kHalfScaleParts) * 4));
+      RB_HIP(launch_half_scale(ctx->dspec.as<float2>(), bank->nbs, g.N2, ctx->hscale.as<float>() + 2,
+                               ctx->hscale.as<float>(), ctx->stream));
+      ctx->hscale_gen = ctx->dspec_gen;
+    }
+    a.hscale = ctx->hscale.as<float>();
+    return pass_pairs(ctx, a, K, IN_CORR_H, OUT_Z16_H);
+  }
   return pass_pairs(ctx, a, K, IN_CORR, dt == RB_F32 ? OUT_Z32 : OUT_Z16);
 }
 
@@ -2871,7 +2891,7 @@ std::string batch_key(int32_t n, const rb_batch_item* items, const rb_filter_opt
   const void* bufs[] = {ctx->work.p, ctx->work64.p, ctx->dspec.p, ctx->z.p, ctx->trig1.p, ctx->trig2.p,
                         ctx->recs.p, ctx->tmp.p, ctx->bsum.p, ctx->bout.p, ctx->cnt1.p, ctx->cnt2.p,
                         ctx->recs1.p, ctx->zfine.p, ctx->zpart.p, ctx->trigB.p, ctx->cntB.p, ctx->snap.p,
-                        ctx->tinv.p};
+                        ctx->tinv.p, ctx->hscale.p};
   add(bufs, sizeof(bufs));
   return k;
 }

@@ -280,6 +280,16 @@ template <> struct PassPtr<double2> {
   static __device__ __forceinline__ double2* work(const PassArgs& a) { return a.work64; }
 };
 
+// FP16 (Re, Im) pair in one word (Re in the low half), rounded to nearest even.
+__device__ __forceinline__ uint32_t pack_f16x2(float re, float im) {
+  const __half hr = __float2half_rn(re), hi = __float2half_rn(im);
+  return (uint32_t)__builtin_bit_cast(uint16_t, hr) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+}
+__device__ __forceinline__ float2 unpack_f16x2(uint32_t w) {
+  return make_float2(__half2float(__builtin_bit_cast(__half, (uint16_t)(w & 0xffffu))),
+                     __half2float(__builtin_bit_cast(__half, (uint16_t)(w >> 16))));
+}
+
 // ------------------------------------------------------------------ pass 1
 template <class V, int L, int R1, int R2, int R3, int IN, int S>
 __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
@@ -296,8 +306,9 @@ __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
   const int f1_0 = blockIdx.x * C;
   const V* __restrict__ pyr = PassPtr<V>::pyr(a);
 
+  constexpr bool CORR = (IN == IN_CORR || IN == IN_CORR_H);
   int lo = a.band_lo, hi = a.band_hi;
-  if ((IN == IN_CORR || IN == IN_FOLD) && a.sup_lo != nullptr) {
+  if ((CORR || IN == IN_FOLD) && a.sup_lo != nullptr) {
     lo = a.sup_lo[v];
     hi = a.sup_hi[v];
   }
@@ -305,7 +316,7 @@ __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
   {
     constexpr int NB = C * L / R1;
     constexpr int PER = (NB + NT - 1) / NT;
-    constexpr bool HALF = (IN == IN_CORR);   // one-sided input: rows >= L/2 are zero
+    constexpr bool HALF = CORR;   // one-sided input: rows >= L/2 are zero
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int b = tid + i * NT;
@@ -319,7 +330,7 @@ __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
           if (HALF && r >= R1 / 2) continue;
           const int f2 = j + r * (L / R1);
           const int64_t f = (int64_t)f1 + (int64_t)N1 * f2;
-          if (IN == IN_CORR) {
+          if (CORR) {
             // read at the bin clamped into the support [lo, hi] (always in
             // bounds, no branch around the loads) and mask bins outside it
             const int64_t fc = f < lo ? lo : (f > hi ? hi : f);
@@ -364,6 +375,9 @@ __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
   const V* __restrict__ thi = PassPtr<V>::thi(a);
   const V* __restrict__ tlo = PassPtr<V>::tlo(a);
   V* __restrict__ outv = PassPtr<V>::work(a) + (int64_t)bv * a.g.N;
+  // IN_CORR_H: FP16 (Re, Im) pairs, element for element at the same index
+  uint32_t* __restrict__ outh = reinterpret_cast<uint32_t*>(a.work) + (int64_t)bv * a.g.N;
+  const float hs = (IN == IN_CORR_H) ? a.hscale[0] : 1.f;
   {
     // outputs n2 = j + m Ns of column f1 get w^{f1 n2} = w^{f1 j} (w^{f1 Ns})^m
     constexpr int Ns = L / RL;
@@ -410,8 +424,13 @@ __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
           return s;
         });
 #pragma unroll
-        for (int m = 0; m < RL; ++m)
-          outv[(int64_t)(j + m * Ns) * N1 + f1] = cmul(v[m], cmul(base, sp[m]));
+        for (int m = 0; m < RL; ++m) {
+          const V y = cmul(v[m], cmul(base, sp[m]));
+          if constexpr (IN == IN_CORR_H)
+            outh[(int64_t)(j + m * Ns) * N1 + f1] = pack_f16x2((float)y.x * hs, (float)y.y * hs);
+          else
+            outv[(int64_t)(j + m * Ns) * N1 + f1] = y;
+        }
       }
       }
     }
@@ -455,9 +474,16 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
         int f, j;
         Lay::template split<R1>(b, f, j);
         V x[R1];
-        const V* rowp = inv + (int64_t)(row0 + f) * L;
+        if constexpr (OUT == OUT_Z16_H) {
+          const uint32_t* rowh =
+              reinterpret_cast<const uint32_t*>(a.work) + (int64_t)bv * a.g.N + (int64_t)(row0 + f) * L;
 #pragma unroll
-        for (int r = 0; r < R1; ++r) x[r] = rowp[j + r * (L / R1)];
+          for (int r = 0; r < R1; ++r) x[r] = unpack_f16x2(rowh[j + r * (L / R1)]);
+        } else {
+          const V* rowp = inv + (int64_t)(row0 + f) * L;
+#pragma unroll
+          for (int r = 0; r < R1; ++r) x[r] = rowp[j + r * (L / R1)];
+        }
         Dft<R1, S>::run(x);
 #pragma unroll
         for (int m = 0; m < R1; ++m) lds[Lay::addr(f, j * R1 + m)] = x[m];
@@ -477,10 +503,10 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
       zr[q] = val.x;
       zi[q] = val.y;
     });
-  } else if constexpr (OUT == OUT_Z16) {
+  } else if constexpr (OUT == OUT_Z16 || OUT == OUT_Z16_H) {
     uint16_t* __restrict__ zr = reinterpret_cast<uint16_t*>(a.zout) + (int64_t)(2 * v) * N;
     uint16_t* __restrict__ zi = zr + N;
-    const float sc = a.zscale;
+    const float sc = OUT == OUT_Z16_H ? a.zscale * a.hscale[1] : a.zscale;   // (a power of two: exact)
     if (a.zdtype == 3) {   // hi = bf16(x), lo = bf16(x - hi) in a second plane
       uint16_t* __restrict__ lr = zr + a.zplane;
       uint16_t* __restrict__ li = zi + a.zplane;
@@ -685,6 +711,36 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ FP16 intermediate scale
+// Partial maxima of |d| (one per workgroup, kHalfScaleParts workgroups).
+__global__ __launch_bounds__(256) void k_absmax_part(const float2* d, int64_t n, float* part) {
+  float m = 0.f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float2 x = d[i];
+    m = fmaxf(m, x.x * x.x + x.y * x.y);
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  __shared__ float wm[4];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+}
+
+// {s, 1 / s} from the partial maxima of |d|^2 (one wave).
+__global__ void k_half_scale(const float* part, int n2, float* hs) {
+  float m = 0.f;
+  for (int i = threadIdx.x; i < kHalfScaleParts; i += 64) m = fmaxf(m, part[i]);
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (threadIdx.x == 0) {
+    const float bound = 2.f * sqrtf((float)n2) * sqrtf(m);   // >= every pass-1 output's magnitude
+    int e = 0;
+    if (bound > 0.f) e = (int)floorf(log2f(32768.f / bound));
+    e = e < -120 ? -120 : (e > 120 ? 120 : e);
+    hs[0] = ldexpf(1.f, e);
+    hs[1] = ldexpf(1.f, -e);
+  }
+}
+
 // ------------------------------------------------------------------ dispatch
 template <int L>
 struct Radices;
@@ -753,9 +809,17 @@ bool geom_supported(const FftGeom& g) {
   return g.N2 >= 64 && g.N2 <= 1024 && g.N1 >= 64 && g.N1 <= 2048 && g.N1 * (int64_t)g.N2 == g.N;
 }
 
+hipError_t launch_half_scale(const float2* d, int64_t n, int n2, float* part, float* hs, hipStream_t st) {
+  if (n <= 0 || n2 <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_absmax_part, dim3(kHalfScaleParts), dim3(256), 0, st, d, n, part);
+  hipLaunchKernelGGL(k_half_scale, dim3(1), dim3(64), 0, st, part, n2, hs);
+  return hipGetLastError();
+}
+
 hipError_t launch_pass1(const PassArgs& a, InKind in, hipStream_t st) {
   if (a.nvec <= 0) return hipSuccess;
   if (in == IN_CORR) return a.sign > 0 ? disp1<float2, IN_CORR, 1>(a, st) : disp1<float2, IN_CORR, -1>(a, st);
+  if (in == IN_CORR_H) return a.sign > 0 && a.hscale ? disp1<float2, IN_CORR_H, 1>(a, st) : hipErrorInvalidValue;
   if (in == IN_FOLD) return a.sign > 0 ? disp1<float2, IN_FOLD, 1>(a, st) : hipErrorInvalidValue;
   if (in == IN_REAL) return disp1<double2, IN_REAL, -1>(a, st);     // strain spectrum: FP64
   return a.sign > 0 ? disp1<float2, IN_DENSE, 1>(a, st) : disp1<float2, IN_DENSE, -1>(a, st);
@@ -766,6 +830,7 @@ hipError_t launch_pass2(const PassArgs& a, OutKind out, hipStream_t st) {
   switch (out) {
     case OUT_Z32: return disp2<float2, OUT_Z32, 1>(a, st);
     case OUT_Z16: return disp2<float2, OUT_Z16, 1>(a, st);
+    case OUT_Z16_H: return a.hscale ? disp2<float2, OUT_Z16_H, 1>(a, st) : hipErrorInvalidValue;
     case OUT_THRESH: return disp2<float2, OUT_THRESH, 1>(a, st);
     case OUT_NATURAL:
       return a.sign > 0 ? disp2<float2, OUT_NATURAL, 1>(a, st) : disp2<float2, OUT_NATURAL, -1>(a, st);

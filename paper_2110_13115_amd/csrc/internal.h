@@ -49,7 +49,9 @@ FftGeom make_geom(int64_t N, int n2log = -1);
 bool geom_supported(const FftGeom& g);
 
 // Pass-1 input variants.
-enum InKind { IN_CORR = 0, IN_REAL = 1, IN_DENSE = 2, IN_FOLD = 3 };
+// IN_CORR_H: IN_CORR with the intermediate stored as FP16 (Re, Im) pairs times
+// the power of two hscale[0] (for bases whose Z is stored in 16 bits).
+enum InKind { IN_CORR = 0, IN_REAL = 1, IN_DENSE = 2, IN_FOLD = 3, IN_CORR_H = 4 };
 // Pass-2 output variants.
 enum OutKind {
   OUT_Z32 = 0,       // planar FP32 Z: row 2v = Re, row 2v+1 = Im, row stride N
@@ -58,12 +60,13 @@ enum OutKind {
   OUT_NATURAL = 3,   // complex64 natural order out[v][n]
   OUT_SPECTRUM = 4,  // forward transform of the strain: d[k - kb] = wd[k] X[k], band only
   OUT_TRANSPOSED = 5, // complex64 in the pass order out[v][q] (adjoint)
-  OUT_ZBIN = 6       // binned first stage: Z in zfine (complex64 or 16-bit pairs) with each pass-2 block's F
+  OUT_ZBIN = 6,      // binned first stage: Z in zfine (complex64 or 16-bit pairs) with each pass-2 block's F
                      // rows adjacent per n1 (q = row0 N1 + n1 F + f, F = pass2_rows(N1)),
                      // plus sums over bin_g = min(F, bin_w) consecutive samples: the bin
                      // means in zout (planar, zdtype, plane stride N / bin_w) when
                      // bin_g == bin_w, else partial sums in zpart ([N2 / bin_g][N1]
                      // complex64 per vector)
+  OUT_Z16_H = 7      // OUT_Z16 from the FP16 intermediate of IN_CORR_H (its scale removed)
 };
 
 struct TrigRec {     // device trigger record before sorting
@@ -96,8 +99,9 @@ struct PassArgs {
   const float2* gfold;       // IN_FOLD: G[F] = sum_{r<w} e^{+2 pi i F r / (w g.N)}, F < (w/2) g.N
   int fold_half;             // IN_FOLD: w / 2 (folded bins per output below N/2)
   float fold_inv;            // IN_FOLD: 1 / w
-  // intermediate [nvec][N] complex64
+  // intermediate [nvec][N] complex64 (FP16 pairs for IN_CORR_H / OUT_Z16_H)
   float2* work;
+  const float* hscale;       // IN_CORR_H / OUT_Z16_H: device {s, 1 / s}
   // pass-2 outputs
   float* zout;               // OUT_Z32 / OUT_Z16 (as raw bytes for 16-bit)
   int zdtype;                // 0 f32, 1 bf16, 2 f16, 3 bf16 hi plane + bf16 lo plane
@@ -118,6 +122,15 @@ struct PassArgs {
   int32_t k_lo;              // OUT_SPECTRUM band
   int32_t k_hi;
 };
+
+// {s, 1 / s} of the FP16 intermediate for whitened data d (n bins): s is the
+// largest power of two with 2 sqrt(N2) max|d| s <= 2^15, so every pass-1
+// output of a unit-norm vector stays below 2^15 (Cauchy-Schwarz over the
+// column's N2 terms, with a factor 2 for rounding of the norm).  part holds
+// kHalfScaleParts floats of scratch.  Graph-capturable (two launches, no
+// memset).
+constexpr int kHalfScaleParts = 256;
+hipError_t launch_half_scale(const float2* d, int64_t n, int n2, float* part, float* hs, hipStream_t stream);
 
 // Launch pass 1 / pass 2 on `stream`.  Return hipSuccess or the launch error.
 hipError_t launch_pass1(const PassArgs& a, InKind in, hipStream_t stream);
