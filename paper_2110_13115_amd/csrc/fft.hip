@@ -168,6 +168,12 @@ struct ColLayout {
 };
 // columns per pass-1 workgroup: one 128-byte row segment
 template <class V> struct Cols { static constexpr int value = 128 / sizeof(V); };
+// ... of the stored intermediate: 32 columns of FP16 pairs for IN_CORR_H
+// (while the L x 32 complex64 LDS tile fits), else one segment of V
+template <class V, int L, int IN>
+struct Cols1 {
+  static constexpr int value = (IN == IN_CORR_H && L <= 256) ? 32 : Cols<V>::value;
+};
 // Row layout (pass 2): F FFTs, element (f, pos) at f * (L + L/8) + pos + pos/8
 // (one pad slot every 8 elements keeps the radix-8/16 scatter conflict-free).
 template <int L>
@@ -294,7 +300,7 @@ __device__ __forceinline__ float2 unpack_f16x2(uint32_t w) {
 template <class V, int L, int R1, int R2, int R3, int IN, int S>
 __global__ __launch_bounds__(NT) void k_pass1(PassArgs a) {
   using T = typename Re<V>::T;
-  constexpr int C = Cols<V>::value;
+  constexpr int C = Cols1<V, L, IN>::value;
   using Lay = ColLayout<L, C>;
   __shared__ V lds[Lay::SIZE];
   const int tid = threadIdx.x;
@@ -754,7 +760,7 @@ template <> struct Radices<2048> { static constexpr int r1 = 16, r2 = 16, r3 = 8
 template <class V, int L, int IN, int S>
 hipError_t go1(const PassArgs& a, hipStream_t st) {
   using Rd = Radices<L>;
-  dim3 grid(a.g.N1 / Cols<V>::value, a.nvec);
+  dim3 grid(a.g.N1 / Cols1<V, L, IN>::value, a.nvec);
   hipLaunchKernelGGL((k_pass1<V, L, Rd::r1, Rd::r2, Rd::r3, IN, S>), grid, dim3(NT), 0, st, a);
   return hipGetLastError();
 }
