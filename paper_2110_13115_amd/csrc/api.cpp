@@ -168,6 +168,7 @@ struct rb_ctx_s {
   // dspec is rewritten by each spectrum (dspec_gen counts them); the FP16
   // intermediate's scale in hscale belongs to spectrum hscale_gen
   uint64_t dspec_gen = 0, hscale_gen = ~uint64_t(0);
+  int hscale_n2 = 0;
   int64_t gfold_N = 0;             // grid and bin width of the table in gfold
   int gfold_w = 0;
   hipEvent_t ev[8] = {};
@@ -560,6 +561,20 @@ rb_status pass_pairs(rb_ctx ctx, PassArgs a, int64_t nvec, InKind in, OutKind ou
   return RB_OK;
 }
 
+// The FP16 intermediate's {s, 1 / s} for the current spectrum in ctx->dspec
+// (computed once per spectrum; the bound depends on the split's N2).
+rb_status half_scale(rb_ctx ctx, rb_bank bank, const FftGeom& g, const float** hs) {
+  if (ctx->hscale_gen != ctx->dspec_gen || ctx->hscale_n2 != g.N2) {
+    RB_TRY(ctx->hscale.ensure((size_t)(2 + kHalfScaleParts) * 4));
+    RB_HIP(launch_half_scale(ctx->dspec.as<float2>(), bank->nbs, g.N2, ctx->hscale.as<float>() + 2,
+                             ctx->hscale.as<float>(), ctx->stream));
+    ctx->hscale_gen = ctx->dspec_gen;
+    ctx->hscale_n2 = g.N2;
+  }
+  *hs = ctx->hscale.as<float>();
+  return RB_OK;
+}
+
 // a2 + a3: Z = IFFT(d conj(P_k)) for all basis vectors, planar storage
 // (the basis's storage type, or FP32 into ctx->z32 when force_f32).  For
 // BF16 / FP16 storage the four-step intermediate between the passes is kept
@@ -590,13 +605,7 @@ rb_status step_basis_outputs(rb_ctx ctx, rb_basis basis, const FftGeom& g, const
   a.zdtype = (int)dt;
   a.zplane = (int64_t)2 * Kp * g.N;
   if (dt == RB_BF16 || dt == RB_F16) {
-    if (ctx->hscale_gen != ctx->dspec_gen) {
-      RB_TRY(ctx->hscale.ensure((size_t)(2 + kHalfScaleParts) * 4));
-      RB_HIP(launch_half_scale(ctx->dspec.as<float2>(), bank->nbs, g.N2, ctx->hscale.as<float>() + 2,
-                               ctx->hscale.as<float>(), ctx->stream));
-      ctx->hscale_gen = ctx->dspec_gen;
-    }
-    a.hscale = ctx->hscale.as<float>();
+    RB_TRY(half_scale(ctx, bank, g, &a.hscale));
     return pass_pairs(ctx, a, K, IN_CORR_H, OUT_Z16_H);
   }
   return pass_pairs(ctx, a, K, IN_CORR, dt == RB_F32 ? OUT_Z32 : OUT_Z16);
@@ -642,11 +651,14 @@ rb_status step_basis_outputs_binned(rb_ctx ctx, rb_basis basis, const FftGeom& g
   a.zpart = G < w ? ctx->zpart.as<float2>() : nullptr;
   a.bin_g = G;
   a.bin_w = w;
+  // 16-bit storage: the FP16 intermediate, as in step_basis_outputs
+  const bool h = dt == RB_BF16 || dt == RB_F16;
+  if (h) RB_TRY(half_scale(ctx, bank, g, &a.hscale));
   for (int v0 = 0; v0 < K; v0 += B) {
     a.vec_base = v0;
     a.nvec = std::min(B, K - v0);
-    RB_HIP(launch_pass1(a, IN_CORR, ctx->stream));
-    RB_HIP(launch_pass2(a, OUT_ZBIN, ctx->stream));
+    RB_HIP(launch_pass1(a, h ? IN_CORR_H : IN_CORR, ctx->stream));
+    RB_HIP(launch_pass2(a, h ? OUT_ZBIN_H : OUT_ZBIN, ctx->stream));
   }
   if (G == w) return RB_OK;   // the pass wrote the bin means itself
   BinReduceArgs r;

@@ -480,7 +480,7 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
         int f, j;
         Lay::template split<R1>(b, f, j);
         V x[R1];
-        if constexpr (OUT == OUT_Z16_H) {
+        if constexpr (OUT == OUT_Z16_H || OUT == OUT_ZBIN_H) {
           const uint32_t* rowh =
               reinterpret_cast<const uint32_t*>(a.work) + (int64_t)bv * a.g.N + (int64_t)(row0 + f) * L;
 #pragma unroll
@@ -607,7 +607,7 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
       const int64_t n = (int64_t)(row0 + f) + (int64_t)N2 * n1;
       o[n] = make_float2(val.x, val.y);
     });
-  } else if constexpr (OUT == OUT_ZBIN) {
+  } else if constexpr (OUT == OUT_ZBIN || OUT == OUT_ZBIN_H) {
     // Binned first stage.  The block holds F consecutive rows (samples
     // row0 .. row0 + F - 1 of every n1 slice).  After the final stage the
     // outputs go back to LDS as X[e], e = n1 F + f (one pad slot every 32
@@ -624,7 +624,12 @@ __global__ __launch_bounds__(NT) void k_pass2(PassArgs a) {
     constexpr int NBF = F * L / RL;
     constexpr int PERF = (NBF + NT - 1) / NT;
     V keep[PERF * RL];
-    final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int, int, V val, int idx) { keep[idx] = val; });
+    if constexpr (OUT == OUT_ZBIN_H) {   // remove the FP16 intermediate's scale (a power of two: exact)
+      const float is = a.hscale[1];
+      final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int, int, V val, int idx) { keep[idx] = mk<V>(val.x * is, val.y * is); });
+    } else {
+      final_stage<Lay, L, RL, S>(lds, pyr, tid, [&](int, int, V val, int idx) { keep[idx] = val; });
+    }
     __syncthreads();
     auto xa = [](int e) { return e + (e >> 5); };
 #pragma unroll
@@ -841,6 +846,7 @@ hipError_t launch_pass2(const PassArgs& a, OutKind out, hipStream_t st) {
     case OUT_NATURAL:
       return a.sign > 0 ? disp2<float2, OUT_NATURAL, 1>(a, st) : disp2<float2, OUT_NATURAL, -1>(a, st);
     case OUT_ZBIN: return disp2<float2, OUT_ZBIN, 1>(a, st);
+    case OUT_ZBIN_H: return a.hscale ? disp2<float2, OUT_ZBIN_H, 1>(a, st) : hipErrorInvalidValue;
     case OUT_TRANSPOSED:
       return a.sign > 0 ? disp2<float2, OUT_TRANSPOSED, 1>(a, st) : disp2<float2, OUT_TRANSPOSED, -1>(a, st);
     case OUT_SPECTRUM: return disp2<double2, OUT_SPECTRUM, -1>(a, st);

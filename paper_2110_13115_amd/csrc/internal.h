@@ -66,7 +66,8 @@ enum OutKind {
                      // means in zout (planar, zdtype, plane stride N / bin_w) when
                      // bin_g == bin_w, else partial sums in zpart ([N2 / bin_g][N1]
                      // complex64 per vector)
-  OUT_Z16_H = 7      // OUT_Z16 from the FP16 intermediate of IN_CORR_H (its scale removed)
+  OUT_Z16_H = 7,     // OUT_Z16 from the FP16 intermediate of IN_CORR_H (its scale removed)
+  OUT_ZBIN_H = 8     // OUT_ZBIN from the FP16 intermediate of IN_CORR_H (its scale removed)
 };
 
 struct TrigRec {     // device trigger record before sorting
