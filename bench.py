@@ -228,13 +228,15 @@ def binned_runs(ctx, wl, bank_def, bank, bases_by_dt, sd, out, mf_trig, t_mf, si
     res["sweep_w"] = sweep
     fold_ok = wl.N // wl.bin_w >= 4096
     for dt, bs in bases_by_dt.items():
-        runs = [(rbmf.RB_STAGE2_RECON, "recon", 0), (rbmf.RB_STAGE2_SPARSE, "sparse", 0)]
+        runs = [(rbmf.RB_STAGE2_RECON, "recon", 0, 0), (rbmf.RB_STAGE2_SPARSE, "sparse", 0, 0)]
         if fold_ok:   # the averaged series from the templates (Sec. III.D), the basis for the fine stage
-            runs.append((rbmf.RB_STAGE2_RECON, "fold_recon", 1))
-        for mode, name, src in runs:
+            runs.append((rbmf.RB_STAGE2_RECON, "fold_recon", 1, 0))
+        if dt in ("bf16", "f16"):   # with the FP16 FFT intermediate option (rb_filter_opts.flags)
+            runs.append((rbmf.RB_STAGE2_RECON, "recon_fp16_intermediate", 0, rbmf.RB_OPT_FP16_INTERMEDIATE))
+        for mode, name, src, flags in runs:
             def call():
                 n, _, st = rbmf.rb_filter(ctx, bs, bank, sd, wl.thr1, wl.thr2, stage2=mode, bin_w=wl.bin_w,
-                                          thr_bin=thr_bin, bin_source=src, out=out)
+                                          thr_bin=thr_bin, bin_source=src, out=out, flags=flags)
                 return n, st
             t, (n, st) = time_calls(call, args.steps, args.warmup, torch)
             tr = out[:n].cpu().numpy().view(rbmf.TRIGGER_NP).reshape(-1)
@@ -649,6 +651,8 @@ def main():
     ap.add_argument("--skip-16bit", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline rb_filter call (for profiler runs)")
+    ap.add_argument("--fp16-intermediate", action="store_true",
+                    help="--headline-only: 16-bit bases with the FP16 FFT intermediate (RB_OPT_FP16_INTERMEDIATE)")
     ap.add_argument("--headline-dtype", default="f32", choices=["f32", "bf16", "f16", "bf16x3"],
                     help="storage type of the bases of --headline-only (for profiler runs)")
     ap.add_argument("--mf-only", action="store_true",
@@ -742,7 +746,8 @@ def main():
     gemm_ms, z_ms, s1, nref, issued, s2_ms = [], [], [], [], [], []
 
     def rb_timed():
-        n, _, st = rbmf.rb_filter(ctx, bases, bank, sd, wl.thr1, wl.thr2, stage2=rbmf.RB_STAGE2_SPARSE, out=out)
+        n, _, st = rbmf.rb_filter(ctx, bases, bank, sd, wl.thr1, wl.thr2, stage2=rbmf.RB_STAGE2_SPARSE, out=out,
+                                  flags=rbmf.RB_OPT_FP16_INTERMEDIATE if args.fp16_intermediate else 0)
         gemm_ms.append(st.ms[2])
         issued.append(st.gemm_mfma_flop)
         z_ms.append(st.ms[1])
@@ -821,6 +826,21 @@ def main():
                                  "gemm_mfma_issued_frac": float(np.mean(i16)) / (gm * 1e-3) / 1e12 / PEAK["bf16"],
                                  "stage_ms": [round(x, 4) for x in st16.ms[:7]]}
             log(f"rb_filter {dt}: {t16 * 1e3:.2f} ms/step, gemm {gm:.3f} ms")
+            if dt in ("bf16", "f16"):
+                # the FP16 FFT intermediate option (rb_filter_opts.flags): half the Z stage's
+                # round-trip traffic, for an error floor that scales with the loudest signal
+                def f16h():
+                    n, _, st = rbmf.rb_filter(ctx, b16, bank, sd, wl.thr1, wl.thr2, stage2=rbmf.RB_STAGE2_SPARSE,
+                                              out=out, flags=rbmf.RB_OPT_FP16_INTERMEDIATE)
+                    return n, st
+                th, (nh, sth) = time_calls(f16h, args.steps, args.warmup, torch)
+                trh = out[:nh].cpu().numpy().view(rbmf.TRIGGER_NP).reshape(-1)
+                okh = nh == n_mf and np.array_equal(trh[["tmpl", "sample"]], mf_trig[["tmpl", "sample"]])
+                extra[f"rb_{dt}_sparse_stage2_fp16_intermediate"] = {
+                    "value": seg / th, "ms_per_step": th * 1e3, "rb_over_mf": t_mf / th,
+                    "final_triggers_equal_mf": bool(okh), "vs_oracle": oracle_agreement(trh, ora, wl.thr2, wl.N),
+                    "stage_ms": [round(x, 4) for x in sth.ms[:7]]}
+                log(f"rb_filter {dt} with the FP16 intermediate: {th * 1e3:.2f} ms/step")
             for b in b16:
                 b.close()
 

@@ -167,8 +167,20 @@ typedef struct {
                               template's band product folded onto N/bin_w
                               bins and inverse transformed; the exact bin
                               means; needs N / bin_w >= 4096)                */
-  int32_t reserved;        /* must be 0                                      */
+  int32_t flags;           /* 0, or RB_OPT_FP16_INTERMEDIATE                 */
 } rb_filter_opts;
+
+/* rb_filter_opts.flags.  RB_OPT_FP16_INTERMEDIATE: for BF16 and FP16 bases,
+ * the four-step FFT intermediate between the passes that produce beta is
+ * kept as FP16 pairs scaled by a power of two chosen from max |d| of the
+ * segment (by Cauchy-Schwarz no pass-1 output of a unit-norm basis vector
+ * reaches 2^15, so none overflows), halving that round trip's HBM traffic.
+ * Its rounding (2^-11 of each intermediate element) spreads over the whole
+ * segment: next to a signal of SNR 4000 the first-stage error at quiet
+ * samples reaches 2.3e-2 of sum_k |c_jk| |beta_k(n)| (about 0.1 in |rho_RB|),
+ * so thr2 - thr1 must cover it.  Ignored for FP32 and split-BF16 bases;
+ * other bits are RB_ERR_ARG. */
+#define RB_OPT_FP16_INTERMEDIATE 1
 
 /* Bank source.  Fills out[(t1-t0) * (k1-k0) * 2] with the complex128 values
  * h_j[k] (interleaved re, im; row-major over templates) of templates

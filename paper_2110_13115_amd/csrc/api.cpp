@@ -576,14 +576,14 @@ rb_status half_scale(rb_ctx ctx, rb_bank bank, const FftGeom& g, const float** h
 }
 
 // a2 + a3: Z = IFFT(d conj(P_k)) for all basis vectors, planar storage
-// (the basis's storage type, or FP32 into ctx->z32 when force_f32).  For
-// BF16 / FP16 storage the four-step intermediate between the passes is kept
-// as FP16 pairs scaled by a power of two chosen from max |d| (no overflow for
-// unit-norm vectors; relative rounding 2^-11 per element, below the 16-bit
-// storage rounding of Z itself), half the intermediate's HBM traffic; the
-// split-BF16 form, whose Z carries FP32-level accuracy, keeps it in FP32.
+// (the basis's storage type, or FP32 into ctx->z32 when force_f32).  With
+// fp16_inter and BF16 / FP16 storage the four-step intermediate between the
+// passes is kept as FP16 pairs scaled by a power of two chosen from max |d|
+// (no overflow for unit-norm vectors), half the intermediate's HBM traffic;
+// its rounding spreads over the segment (an error floor that scales with the
+// loudest signal), so it is the caller's option, not the default.
 rb_status step_basis_outputs(rb_ctx ctx, rb_basis basis, const FftGeom& g, const FftTables& tw,
-                             bool force_f32 = false) {
+                             bool force_f32 = false, bool fp16_inter = false) {
   rb_bank bank = basis->bank;
   const int K = basis->K, Kp = force_f32 ? basis->K : basis->Kp;
   const rb_dtype dt = force_f32 ? RB_F32 : basis->dtype;
@@ -604,7 +604,7 @@ rb_status step_basis_outputs(rb_ctx ctx, rb_basis basis, const FftGeom& g, const
   a.zout = zb.as<float>();
   a.zdtype = (int)dt;
   a.zplane = (int64_t)2 * Kp * g.N;
-  if (dt == RB_BF16 || dt == RB_F16) {
+  if (fp16_inter && (dt == RB_BF16 || dt == RB_F16)) {
     RB_TRY(half_scale(ctx, bank, g, &a.hscale));
     return pass_pairs(ctx, a, K, IN_CORR_H, OUT_Z16_H);
   }
@@ -617,7 +617,8 @@ int64_t trig_capacity(const DevBuf& b) { return (int64_t)(b.bytes / sizeof(TrigR
 // OUT_ZBIN layout (ctx->zfine, read by the fine reconstruction) and the bin
 // means beta_avg in the reconstruction dtype (ctx->z, planar [2Kp][N/w], the
 // GEMM's operand), from partial sums written by the same pass-2 launch.
-rb_status step_basis_outputs_binned(rb_ctx ctx, rb_basis basis, const FftGeom& g, const FftTables& tw, int w) {
+rb_status step_basis_outputs_binned(rb_ctx ctx, rb_basis basis, const FftGeom& g, const FftTables& tw, int w,
+                                    bool fp16_inter = false) {
   rb_bank bank = basis->bank;
   const int K = basis->K, Kp = basis->Kp;
   const rb_dtype dt = basis->dtype;
@@ -652,7 +653,7 @@ rb_status step_basis_outputs_binned(rb_ctx ctx, rb_basis basis, const FftGeom& g
   a.bin_g = G;
   a.bin_w = w;
   // 16-bit storage: the FP16 intermediate, as in step_basis_outputs
-  const bool h = dt == RB_BF16 || dt == RB_F16;
+  const bool h = fp16_inter && (dt == RB_BF16 || dt == RB_F16);
   if (h) RB_TRY(half_scale(ctx, bank, g, &a.hscale));
   for (int v0 = 0; v0 < K; v0 += B) {
     a.vec_base = v0;
@@ -1965,7 +1966,7 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
   RB_CHECK(w == 1 || (std::isfinite(opts->thr_bin) && opts->thr_bin > 0), RB_ERR_ARG, "thr_bin must be > 0");
   RB_CHECK(opts->bin_source == 0 || (opts->bin_source == 1 && w > 1), RB_ERR_ARG,
            "bin_source must be 0, or 1 with bin_w >= 2");
-  RB_CHECK(opts->reserved == 0, RB_ERR_ARG, "reserved must be 0");
+  RB_CHECK((opts->flags & ~RB_OPT_FP16_INTERMEDIATE) == 0, RB_ERR_ARG, "unknown opts flag");
   const bool fold = opts->bin_source == 1;
   FftGeom gM{};
   if (fold) {
@@ -2032,20 +2033,21 @@ extern "C" rb_status rb_filter(rb_ctx ctx, const rb_basis* bases, int32_t nbases
       RB_TRY(fill32(ctx, ctx->counters.as<unsigned long long>() + 2, 0u, 2));
       RB_TRY(fill32(ctx, ctx->cntB.p, 0u, T));
     }
+    const bool h16 = (opts->flags & RB_OPT_FP16_INTERMEDIATE) != 0;
     for (int32_t m = 0; m < nbases; ++m) {
       if (w == 1) {
-        RB_TRY(step_basis_outputs(ctx, bases[m], g, tw));
+        RB_TRY(step_basis_outputs(ctx, bases[m], g, tw, false, h16));
         if (tm) RB_TRY(event(ctx, 2 + 2 * (size_t)m));
         RB_TRY(stage1_gemm(ctx, bases[m], g, thr1sq, nullptr));
       } else if (fold) {   // the basis serves the fine stage only
-        RB_TRY(step_basis_outputs_binned(ctx, bases[m], gb, tw, w));
+        RB_TRY(step_basis_outputs_binned(ctx, bases[m], gb, tw, w, h16));
         if (tm) RB_TRY(event(ctx, 2 + 2 * (size_t)m));
         if (tm) RB_TRY(event(ctx, e_end + 1 + (size_t)m));
         const int t0 = bases[m]->t0, t1 = t0 + bases[m]->T;
         RB_TRY(step_fine(ctx, bases[m], gb, w, thr1sq, nullptr, ctx->recsB.as<TrigRec>(), offB[t0],
                          (int64_t)offB[t1 - 1] + cntB[t1 - 1]));
       } else {
-        RB_TRY(step_basis_outputs_binned(ctx, bases[m], gb, tw, w));
+        RB_TRY(step_basis_outputs_binned(ctx, bases[m], gb, tw, w, h16));
         if (tm) RB_TRY(event(ctx, 2 + 2 * (size_t)m));
         unsigned long long* snap = ctx->snap.as<unsigned long long>() + m;
         RB_HIP(launch_copy_u64(ctx->counters.as<unsigned long long>() + 2, snap, ctx->stream));
@@ -2821,7 +2823,7 @@ rb_status enqueue_item(rb_ctx ctx, const rb_batch_item& it, const rb_filter_opts
     RB_TRY(fill32(ctx, ctx->cntB.p, 0u, T));
     RB_TRY(ctx->snap.ensure((size_t)it.nbases * 8));
     for (int32_t m = 0; m < it.nbases; ++m) {
-      RB_TRY(step_basis_outputs_binned(ctx, it.bases[m], gb, tw, w));
+      RB_TRY(step_basis_outputs_binned(ctx, it.bases[m], gb, tw, w, (opts->flags & RB_OPT_FP16_INTERMEDIATE) != 0));
       unsigned long long* snap = ctx->snap.as<unsigned long long>() + m;
       RB_HIP(launch_copy_u64(ctx->counters.as<unsigned long long>() + 2, snap, ctx->stream));
       RB_TRY(stage1_gemm(ctx, it.bases[m], gb, (float)(opts->thr_bin * opts->thr_bin), nullptr, w));
@@ -2831,7 +2833,7 @@ rb_status enqueue_item(rb_ctx ctx, const rb_batch_item& it, const rb_filter_opts
                            ctx->stream));
   } else {
     for (int32_t m = 0; m < it.nbases; ++m) {
-      RB_TRY(step_basis_outputs(ctx, it.bases[m], g, tw));
+      RB_TRY(step_basis_outputs(ctx, it.bases[m], g, tw, false, (opts->flags & RB_OPT_FP16_INTERMEDIATE) != 0));
       RB_TRY(stage1_gemm(ctx, it.bases[m], g, thr1sq, nullptr));
     }
   }
@@ -2922,7 +2924,7 @@ extern "C" rb_status rb_filter_batch(rb_ctx ctx, int32_t nitems, const rb_batch_
   RB_CHECK(opts->bin_source == 0, RB_ERR_UNSUPPORTED, "the batch search takes bin_source 0");
   RB_CHECK(opts->stage2 == RB_STAGE2_FULL || opts->stage2 == RB_STAGE2_SPARSE || opts->stage2 == RB_STAGE2_RECON,
            RB_ERR_ARG, "bad stage2 mode");
-  RB_CHECK(opts->reserved == 0, RB_ERR_ARG, "reserved must be 0");
+  RB_CHECK((opts->flags & ~RB_OPT_FP16_INTERMEDIATE) == 0, RB_ERR_ARG, "unknown opts flag");
   {
     const int w = opts->bin_w >= 2 ? opts->bin_w : 1;
     RB_CHECK(opts->bin_w >= 0 && opts->bin_w <= 64 && (w & (w - 1)) == 0, RB_ERR_ARG,

@@ -22,6 +22,7 @@ RB_OK, RB_ERR_ARG, RB_ERR_OOM, RB_ERR_DEVICE, RB_ERR_CAPACITY, RB_ERR_NUMERIC, R
 RB_F32, RB_BF16, RB_F16, RB_BF16X3 = 0, 1, 2, 3
 RB_STAGE2_FULL, RB_STAGE2_SPARSE, RB_STAGE2_AUTO, RB_STAGE2_RECON = 0, 1, 2, 3
 RB_EIG_SUBSPACE, RB_EIG_LANCZOS = 0, 1
+RB_OPT_FP16_INTERMEDIATE = 1   # rb_filter_opts.flags
 SOLVERS = {"subspace": RB_EIG_SUBSPACE, "lanczos": RB_EIG_LANCZOS}
 DTYPES = {"f32": RB_F32, "bf16": RB_BF16, "f16": RB_F16, "bf16x3": RB_BF16X3}
 
@@ -53,7 +54,7 @@ class Stats(C.Structure):
 class FilterOpts(C.Structure):
     _fields_ = [("thr1", C.c_double), ("thr2", C.c_double), ("stage2", C.c_int32),
                 ("bin_w", C.c_int32), ("thr_bin", C.c_double), ("bin_source", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("flags", C.c_int32)]
 
 
 TRIGGER_NP = np.dtype([("tmpl", np.int32), ("sample", np.int32), ("snr", np.float32),
@@ -339,16 +340,16 @@ def subbank_bases(ctx: Context, bank: Bank, bounds, rank=0, tol: float = 1e-3, d
 
 def rb_filter(ctx: Context, bases, bank: Bank, strain, thr1: float, thr2: float,
               stage2: int = RB_STAGE2_FULL, cap: int = 1 << 20, peaks: bool = False,
-              out=None, bin_w: int = 0, thr_bin: float = 0.0, bin_source: int = 0):
+              out=None, bin_w: int = 0, thr_bin: float = 0.0, bin_source: int = 0, flags: int = 0):
     """bases: one Basis or a list partitioning the bank.  bin_w >= 2 selects the
     binned first stage with threshold thr_bin on the averaged SNR, taken from
-    the basis (bin_source 0) or from the templates (bin_source 1).  Returns
-    (triggers as a TRIGGER_NP array, or their count when `out` is a device
-    buffer; peaks or None; Stats)."""
+    the basis (bin_source 0) or from the templates (bin_source 1).  flags:
+    RB_OPT_FP16_INTERMEDIATE or 0.  Returns (triggers as a TRIGGER_NP array,
+    or their count when `out` is a device buffer; peaks or None; Stats)."""
     if isinstance(bases, Basis):
         bases = [bases]
     arr = (C.c_void_p * len(bases))(*[b.h.value for b in bases])
-    o = FilterOpts(thr1, thr2, stage2, int(bin_w), float(thr_bin), int(bin_source), 0)
+    o = FilterOpts(thr1, thr2, stage2, int(bin_w), float(thr_bin), int(bin_source), int(flags))
     dev = out is not None and not isinstance(out, np.ndarray)
     buf = out if out is not None else _triggers_out(cap, False)
     cap = buf.shape[0]
@@ -489,7 +490,7 @@ class BatchItem(C.Structure):
 
 def rb_filter_batch(ctx: Context, items, thr1: float, thr2: float, use_graph: bool = True,
                     cap_item: int = 1 << 16, out=None, stage2: int = RB_STAGE2_FULL, bin_w: int = 0,
-                    thr_bin: float = 0.0):
+                    thr_bin: float = 0.0, flags: int = 0):
     """items: list of (device strain tensor, Bank, [Basis, ...]).  Returns
     (list of per-item TRIGGER_NP arrays, Stats); with a device `out` buffer
     (nitems * cap_item x 4 int32) returns (counts, Stats) instead."""
@@ -502,7 +503,7 @@ def rb_filter_batch(ctx: Context, items, thr1: float, thr2: float, use_graph: bo
         bp = (C.c_void_p * len(bases))(*[b.h.value for b in bases])
         keep.append(bp)
         arr[i] = BatchItem(_ptr(s), bank.h.value, C.cast(bp, C.POINTER(C.c_void_p)), len(bases))
-    o = FilterOpts(thr1, thr2, stage2, int(bin_w), float(thr_bin), 0, 0)
+    o = FilterOpts(thr1, thr2, stage2, int(bin_w), float(thr_bin), 0, int(flags))
     dev = out is not None and not isinstance(out, np.ndarray)
     buf = out if out is not None else np.empty(max(1, n * cap_item), dtype=TRIGGER_NP)
     counts = (C.c_int64 * n)()
