@@ -235,8 +235,6 @@ def test_binned_16bit_storage(ctx, bcase, dtype):
     err = (np.abs(got_avg - ref_avg) / np.maximum(np.abs(ref_avg), 1.0)).max()
     log(dtype, "rho_avg max err", err)
     assert err <= tol
-    got, _, st = rbmf.rb_filter(ctx, b16, bank, case.strain, thr1, thr2, stage2=rbmf.RB_STAGE2_RECON,
-                                bin_w=w, thr_bin=thr_bin)
     a_avg = np.abs(ref_avg)
     a_rb = np.abs(ob.rb_snr(beta, c))
     band = lambda x, t: np.abs(x / t - 1) <= tol
@@ -246,13 +244,17 @@ def test_binned_16bit_storage(ctx, bcase, dtype):
     maybe = (on | amb) & (a_rb >= thr1 * (1 - tol)) & ~sure
     definite = sure & (a_rb >= thr2) & ~band(a_rb, thr2)
     possible = (sure | maybe) & (a_rb >= thr2 * (1 - tol))
-    G = np.zeros_like(definite)
-    G[got["tmpl"], got["sample"]] = True
-    log(dtype, "final", len(got), "oracle", int(definite.sum()))
     assert definite.sum() > 10
-    assert not (definite & ~G).any() and not (G & ~possible).any()
-    rel = np.abs(got["snr"] - a_rb[got["tmpl"], got["sample"]]) / a_rb[got["tmpl"], got["sample"]]
-    assert rel.max() <= tol
+    # BF16 / FP16 also with the FP16 FFT intermediate option (fine Z and bin means from it)
+    for flags in ((0,) if dtype == "bf16x3" else (0, rbmf.RB_OPT_FP16_INTERMEDIATE)):
+        got, _, st = rbmf.rb_filter(ctx, b16, bank, case.strain, thr1, thr2, stage2=rbmf.RB_STAGE2_RECON,
+                                    bin_w=w, thr_bin=thr_bin, flags=flags)
+        G = np.zeros_like(definite)
+        G[got["tmpl"], got["sample"]] = True
+        log(dtype, "flags", flags, "final", len(got), "oracle", int(definite.sum()))
+        assert not (definite & ~G).any() and not (G & ~possible).any()
+        rel = np.abs(got["snr"] - a_rb[got["tmpl"], got["sample"]]) / a_rb[got["tmpl"], got["sample"]]
+        assert rel.max() <= tol
     b16.close()
 
 
